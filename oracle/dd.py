@@ -1,0 +1,525 @@
+"""Domain decomposition for entropic unbalanced OT on 2-D grids (oracle, FP64).
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+Follows Sec. 3 (Definitions basic/composite partitions and cell subproblem,
+Algorithm 3 sequential and Algorithm 4 parallel DomDecIter, Algorithm 2 outer
+loop) and Sec. 4.1/4.4 (cell Sinkhorn with the Newton Y-update, nu_{-J} from the
+aggregated Y-marginal, truncation of basic-cell marginals, bounding boxes,
+padded B partition, PD stopping rule, GetWeights variants of Sec. 3.4).
+
+Every cell problem is solved densely: an explicit |X_J| x |box_J| cost matrix
+and library log-sum-exp.  Readings of points the paper leaves open (all of
+them also fixed in the design notes):
+
+  R1 grid: x = h (i1, i2); cost c = |x - y|^2, so c = h^2 |i - j|^2.
+  R2 partitions: basic cells are s1 x s2 blocks; partition A groups 2 x 2
+     basic cells from the origin, B is offset by one basic cell; the B cells
+     at the border contain only the basic cells that exist (padding of X only).
+     An axis with a single basic cell is not paired.
+  R3 state: the basic-cell Y-marginals nu_i stored on bounding boxes, plus the
+     X-marginal P_X pi, plus per basic cell a tracked score Hbar_i and the
+     last cell potential alpha (stitched).
+  R4 cell Y-box: bbox of the union of the basic boxes of J, dilated by a
+     margin m = min(M, (cap - U) // 2) per axis (U = union extent), clipped to
+     the grid.  A union wider than cap makes the cell overflow: it is skipped
+     (its basic cells keep their old state).  An all-empty union uses the X
+     rectangle of J instead.
+  R5 warm start: beta^0 = -lam log(P_Y pi / nu) on the box (0 where P_Y pi = 0),
+     i.e. the Y optimality condition eq. (optimality-conditions-KL) evaluated
+     for the current plan.
+  R6 inner loop: X-half, then repeat {Y-half (Newton), X-half, PD check};
+     the cell solve ends after a Y-half, the final pair is the alpha used in
+     that Y-half and the new beta.  Stop when PD_J / lam <= Err |mu_J|
+     (per-cell rule), or after exactly `fixed_iters` Y-halves (parity mode),
+     or at `max_iter`.
+  R7 truncation: after the re-split and again after mixing, entries below
+     `trunc` are set to 0 and the box shrinks to the bbox of the nonzeros.
+  R8 tracked score: Ebar = sum_i Hbar_i + lam KL(P_Y pi | nu); Hbar_i is the
+     exact cell-restricted score of a diagonal-scaling plan and is mixed with
+     the same weights as the plans, so Ebar >= E with equality after greedy
+     steps (convexity of each term).
+  R9 GetWeights: greedy theta = 1; safe theta = 1/n with n the number of cells
+     updated in the step; swift takes greedy iff
+     Ebar_greedy <= Ebar_cur + lenience |Ebar_cur|, else safe.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import uot
+
+
+# --------------------------------------------------------------------------
+# problem, options, partitions
+# --------------------------------------------------------------------------
+@dataclass
+class Problem:
+    mu: np.ndarray            # (n1, n2) point masses, > 0
+    nu: np.ndarray            # (n1, n2) point masses, > 0
+    eps: float
+    lam: float
+    h: float
+    s1: int                   # basic cell sides
+    s2: int
+
+    @property
+    def n1(self):
+        return self.mu.shape[0]
+
+    @property
+    def n2(self):
+        return self.mu.shape[1]
+
+    @property
+    def nb1(self):
+        return self.n1 // self.s1
+
+    @property
+    def nb2(self):
+        return self.n2 // self.s2
+
+
+@dataclass
+class Options:
+    err: float = 2e-5          # Err of Sec. 4.4
+    max_iter: int = 1000
+    fixed_iters: int = 0       # > 0: exactly this many Y-halves per cell
+    trunc: float = 1e-15       # Sec. 4.4
+    lenience: float = 0.0      # 0.005 in Sec. 4.4; 0 = strict
+    margin: int = 2
+    cap: int = 64              # maximal Y-box side
+    getweights: str = "swift"  # greedy | safe | swift
+
+
+def make_problem(mu, nu, eps, lam, h, s1, s2=None) -> Problem:
+    s2 = s1 if s2 is None else s2
+    mu = np.asarray(mu, dtype=np.float64)
+    nu = np.asarray(nu, dtype=np.float64)
+    if mu.shape != nu.shape or mu.ndim != 2:
+        raise ValueError("mu and nu must be 2-D arrays of one shape")
+    if not (np.all(mu > 0) and np.all(nu > 0)):
+        raise ValueError("full support required (Assumption 2)")
+    n1, n2 = mu.shape
+    if n1 % s1 or n2 % s2:
+        raise ValueError("grid not divisible by the basic cell size")
+    return Problem(mu, nu, float(eps), float(lam), float(h), int(s1), int(s2))
+
+
+def basic_rect(p: Problem, b: int):
+    """X rectangle (o1, o2, l1, l2) of basic cell b = b1*nb2 + b2."""
+    b1, b2 = divmod(b, p.nb2)
+    return (b1 * p.s1, b2 * p.s2, p.s1, p.s2)
+
+
+def _axis_groups(nb: int, offset: bool):
+    """Groups of basic indices along one axis: pairs from 0 (A) or pairs
+    offset by one with singletons at both ends (B).  A single basic cell is
+    never paired."""
+    if nb == 1:
+        return [[0]]
+    if not offset:
+        return [[2 * a, 2 * a + 1] for a in range(nb // 2)]
+    groups = []
+    for c in range(nb // 2 + 1):
+        g = [b for b in (2 * c - 1, 2 * c) if 0 <= b < nb]
+        groups.append(g)
+    return groups
+
+
+def composite_cells(p: Problem, part: str):
+    """Composite cells of partition 'A' or 'B' in row-major order.  Each is a
+    dict with the ordered basic ids and the X rectangle (o1, o2, l1, l2)."""
+    off = part == "B"
+    g1 = _axis_groups(p.nb1, off)
+    g2 = _axis_groups(p.nb2, off)
+    cells = []
+    for r in g1:
+        for c in g2:
+            basic = [b1 * p.nb2 + b2 for b1 in r for b2 in c]
+            rect = (r[0] * p.s1, c[0] * p.s2, len(r) * p.s1, len(c) * p.s2)
+            cells.append(dict(basic=basic, rect=rect))
+    return cells
+
+
+def rect_index(rect, n2):
+    """Flat grid indices of a rectangle, row-major."""
+    o1, o2, l1, l2 = rect
+    i1, i2 = np.meshgrid(np.arange(o1, o1 + l1), np.arange(o2, o2 + l2), indexing="ij")
+    return (i1 * n2 + i2).ravel()
+
+
+def rect_coords(rect, h):
+    o1, o2, l1, l2 = rect
+    i1, i2 = np.meshgrid(np.arange(o1, o1 + l1), np.arange(o2, o2 + l2), indexing="ij")
+    return h * np.stack([i1.ravel(), i2.ravel()], axis=1).astype(np.float64)
+
+
+def rect_cost(p: Problem, xrect, yrect):
+    """Dense cost matrix c(x, y) = |x - y|^2 between two rectangles."""
+    return uot.sq_cost(rect_coords(xrect, p.h), rect_coords(yrect, p.h))
+
+
+# --------------------------------------------------------------------------
+# state
+# --------------------------------------------------------------------------
+@dataclass
+class State:
+    boxes: list               # per basic cell: (o1, o2, arr (L1, L2))
+    px: np.ndarray            # (n1, n2) X-marginal of the plan
+    hbar: np.ndarray          # (nbasic,) tracked cell-restricted scores
+    abar: np.ndarray          # (n1, n2) last cell potential alpha
+    plan: np.ndarray | None = None   # dense plan (tiny problems only)
+    k: int = 0                # half-iterations done
+    force_greedy: bool = False
+    history: list = field(default_factory=list)
+
+
+def cell_piece(pi_box, mu_x, nu_box, nu_total, c_box, eps, lam) -> float:
+    """Score of a cell-restricted plan supported on X_i x box (definition):
+    <c,pi> + eps KL(pi | mu_i x nu) + lam KL(P_X pi | mu_i), where the KL over
+    X_i x Y counts the "+1" term mu_i(x) nu(y) also outside the box."""
+    prod = np.outer(mu_x, nu_box)
+    outside = mu_x.sum() * (nu_total - nu_box.sum())
+    return (float((c_box * pi_box).sum()) + eps * (uot.kl(pi_box, prod) + outside)
+            + lam * uot.kl(pi_box.sum(1), mu_x))
+
+
+def _embed_full(p: Problem, rect, arr):
+    full = np.zeros((p.n1, p.n2))
+    o1, o2, l1, l2 = rect
+    full[o1:o1 + l1, o2:o2 + l2] = arr
+    return full
+
+
+def init_product(p: Problem, dense_plan: bool = False) -> State:
+    """pi^0 = mu x nu (the toy initialisation of Sec. 4.2): nu_i = |mu_i| nu on
+    the whole grid, P_X pi = |nu| mu."""
+    nbasic = p.nb1 * p.nb2
+    nu_tot = p.nu.sum()
+    full = (0, 0, p.n1, p.n2)
+    boxes, hbar = [], np.zeros(nbasic)
+    for b in range(nbasic):
+        rect = basic_rect(p, b)
+        mu_x = p.mu.ravel()[rect_index(rect, p.n2)]
+        boxes.append((0, 0, mu_x.sum() * p.nu.copy()))
+        pi_box = np.outer(mu_x, p.nu.ravel())
+        hbar[b] = cell_piece(pi_box, mu_x, p.nu.ravel(), nu_tot,
+                             rect_cost(p, rect, full), p.eps, p.lam)
+    st = State(boxes, nu_tot * p.mu.copy(), hbar, np.zeros_like(p.mu))
+    if dense_plan:
+        st.plan = np.outer(p.mu.ravel(), p.nu.ravel())
+    return st
+
+
+def init_block(p: Problem, dense_plan: bool = False) -> State:
+    """Block-diagonal start: pi^0 restricted to X_i x Y is mu_i x (nu on X_i)
+    divided by |mu_i|, so nu_i = nu restricted to the block X_i (box = block),
+    P_Y pi = nu, and P_X pi = mu |nu(X_i)| / |mu_i| on X_i."""
+    nbasic = p.nb1 * p.nb2
+    nu_tot = p.nu.sum()
+    boxes, hbar = [], np.zeros(nbasic)
+    px = np.zeros_like(p.mu)
+    plan = np.zeros((p.n1 * p.n2, p.n1 * p.n2)) if dense_plan else None
+    for b in range(nbasic):
+        rect = basic_rect(p, b)
+        o1, o2, l1, l2 = rect
+        idx = rect_index(rect, p.n2)
+        mu_x = p.mu.ravel()[idx]
+        nu_b = p.nu.ravel()[idx]
+        boxes.append((o1, o2, p.nu[o1:o1 + l1, o2:o2 + l2].copy()))
+        pi_box = np.outer(mu_x, nu_b) / mu_x.sum()
+        px.ravel()[idx] = pi_box.sum(1)
+        hbar[b] = cell_piece(pi_box, mu_x, nu_b, nu_tot, rect_cost(p, rect, rect),
+                             p.eps, p.lam)
+        if plan is not None:
+            plan[np.ix_(idx, idx)] = pi_box
+    return State(boxes, px, hbar, np.zeros_like(p.mu), plan)
+
+
+def aggregate(p: Problem, boxes) -> np.ndarray:
+    """P_Y pi = sum_i nu_i (Sec. 4.1, computing nu_{-J})."""
+    P = np.zeros((p.n1, p.n2))
+    for o1, o2, arr in boxes:
+        P[o1:o1 + arr.shape[0], o2:o2 + arr.shape[1]] += arr
+    return P
+
+
+def tracked_score(p: Problem, st: State, P=None) -> float:
+    """Ebar = sum_i Hbar_i + lam KL(P_Y pi | nu)   (reading R8)."""
+    if P is None:
+        P = aggregate(p, st.boxes)
+    return float(st.hbar.sum()) + p.lam * uot.kl(P, p.nu)
+
+
+def exact_score(p: Problem, st: State) -> float:
+    """E(pi) of the dense plan (Definition unbalanced-entropic-transport)."""
+    c = uot.sq_cost(uot.grid_points(p.n1, p.n2, p.h), uot.grid_points(p.n1, p.n2, p.h))
+    return uot.primal(st.plan, p.mu, p.nu, c, p.eps, p.lam)
+
+
+# --------------------------------------------------------------------------
+# one cell
+# --------------------------------------------------------------------------
+def cell_box(p: Problem, cell, boxes, opt: Options):
+    """Y-box of composite cell J (reading R4).  Returns (o1, o2, L1, L2) or None
+    on overflow."""
+    rect = cell["rect"]
+    los, his = [], []
+    for b in cell["basic"]:
+        o1, o2, arr = boxes[b]
+        if arr.size:
+            los.append((o1, o2))
+            his.append((o1 + arr.shape[0], o2 + arr.shape[1]))
+    if los:
+        lo = [min(v[0] for v in los), min(v[1] for v in los)]
+        hi = [max(v[0] for v in his), max(v[1] for v in his)]
+    else:
+        lo = [rect[0], rect[1]]
+        hi = [rect[0] + rect[2], rect[1] + rect[3]]
+    out = []
+    for ax, n in ((0, p.n1), (1, p.n2)):
+        U = hi[ax] - lo[ax]
+        if U > opt.cap:
+            return None
+        m = min(opt.margin, (opt.cap - U) // 2)
+        out.append((max(lo[ax] - m, 0), min(hi[ax] + m, n)))
+    return (out[0][0], out[1][0], out[0][1] - out[0][0], out[1][1] - out[1][0])
+
+
+def solve_cell(mu_x, nu_y, r_y, beta0, C, eps, lam, tol, opt: Options):
+    """Cell Sinkhorn of Sec. 4.1 (reading R6).
+
+    alpha from eq. (sinkhorn-X-iteration); beta from eq. (proxdiv-problem)
+    with r = d nu_{-J} / d nu; PD from eq. (PD-gap-KL).
+    Returns dict(alpha, beta, px, iters, converged, pd)."""
+    with np.errstate(divide="ignore"):
+        lr = np.log(r_y)
+    beta = beta0.copy()
+    alpha = uot.x_update(beta, nu_y, C, eps, lam)
+    it, pd, conv = 0, np.inf, False
+    while True:
+        it += 1
+        z = uot.y_log_integral(alpha, mu_x, C, eps)
+        beta, _ = uot.y_update_root(z, lr, eps, lam)
+        alpha_next = uot.x_update(beta, nu_y, C, eps, lam)
+        px = uot.plan(alpha, beta, mu_x, nu_y, C, eps).sum(1)
+        pd = uot.pd_gap_kl(alpha, px, mu_x, lam) / lam
+        conv = pd <= tol
+        if opt.fixed_iters > 0:
+            if it >= opt.fixed_iters:
+                break
+        elif conv or it >= opt.max_iter:
+            break
+        alpha = alpha_next
+    return dict(alpha=alpha, beta=beta, px=px, iters=it, converged=bool(conv), pd=pd)
+
+
+def cell_inputs(p: Problem, cell, box, boxes, P):
+    """nu_J, nu_{-J} = P_Y pi - nu_J (Sec. 4.1, clamped at 0), r = nu_{-J}/nu and
+    the warm start beta^0 of reading R5, all on the cell Y-box."""
+    o1, o2, L1, L2 = box
+    nuJ = np.zeros((L1, L2))
+    for b in cell["basic"]:
+        bo1, bo2, arr = boxes[b]
+        if arr.size:
+            nuJ[bo1 - o1:bo1 - o1 + arr.shape[0], bo2 - o2:bo2 - o2 + arr.shape[1]] += arr
+    Pb = P[o1:o1 + L1, o2:o2 + L2]
+    nub = p.nu[o1:o1 + L1, o2:o2 + L2]
+    r = np.maximum(Pb - nuJ, 0.0) / nub
+    with np.errstate(divide="ignore"):
+        beta0 = np.where(Pb > 0, -p.lam * np.log(Pb / nub), 0.0)
+    return r.ravel(), beta0.ravel()
+
+
+def process_cell(p: Problem, cell, boxes, P, opt: Options):
+    """Solve one composite cell and re-split its plan into basic cells.
+
+    Returns None on overflow, else dict with the box, the cell potentials, the
+    candidate basic marginals (untruncated and truncated), their pieces
+    H_i (definition cell_piece), P_X of the cell plan, iteration count."""
+    box = cell_box(p, cell, boxes, opt)
+    if box is None:
+        return None
+    rect = cell["rect"]
+    xi = rect_index(rect, p.n2)
+    yi = rect_index(box, p.n2)
+    mu_x = p.mu.ravel()[xi]
+    nu_y = p.nu.ravel()[yi]
+    C = rect_cost(p, rect, box)
+    r, beta0 = cell_inputs(p, cell, box, boxes, P)
+    tol = opt.err * mu_x.sum()
+    sol = solve_cell(mu_x, nu_y, r, beta0, C, p.eps, p.lam, tol, opt)
+    pi = uot.plan(sol["alpha"], sol["beta"], mu_x, nu_y, C, p.eps)
+    nu_tot = p.nu.sum()
+    cand, pieces = {}, {}
+    for b in cell["basic"]:
+        brect = basic_rect(p, b)
+        rows = np.isin(xi, rect_index(brect, p.n2))
+        pib = pi[rows]
+        nut = pib.sum(0).reshape(box[2], box[3])
+        pieces[b] = cell_piece(pib, mu_x[rows], nu_y, nu_tot, C[rows], p.eps, p.lam)
+        cand[b] = nut
+    return dict(box=box, rect=rect, xi=xi, yi=yi, alpha=sol["alpha"], beta=sol["beta"],
+                px=pi.sum(1), pi=pi, cand=cand, pieces=pieces, iters=sol["iters"],
+                converged=sol["converged"], pd=sol["pd"])
+
+
+def truncate_to_box(o1, o2, arr, trunc):
+    """Entries below `trunc` -> 0, then shrink to the bbox of the nonzeros
+    (reading R7).  An all-zero array becomes an empty box at (o1, o2)."""
+    arr = np.where(arr < trunc, 0.0, arr)
+    nz = np.argwhere(arr > 0)
+    if nz.size == 0:
+        return (o1, o2, np.zeros((0, 0)))
+    a1, a2 = nz.min(0)
+    b1, b2 = nz.max(0) + 1
+    return (o1 + int(a1), o2 + int(a2), arr[a1:b1, a2:b2].copy())
+
+
+def _on_box(entry, box):
+    o1, o2, L1, L2 = box
+    out = np.zeros((L1, L2))
+    bo1, bo2, arr = entry
+    if arr.size:
+        out[bo1 - o1:bo1 - o1 + arr.shape[0], bo2 - o2:bo2 - o2 + arr.shape[1]] = arr
+    return out
+
+
+# --------------------------------------------------------------------------
+# Algorithm 4 (parallel) and Algorithm 3 (sequential)
+# --------------------------------------------------------------------------
+def half_iteration(p: Problem, st: State, part: str, opt: Options) -> dict:
+    """One parallel DomDecIter (Algorithm 4) over partition `part`, with
+    GetWeights per reading R9.  Mutates `st`; returns the step's statistics."""
+    cells = composite_cells(p, part)
+    P = aggregate(p, st.boxes)
+    results = [process_cell(p, c, st.boxes, P, opt) for c in cells]
+    upd = [(c, r) for c, r in zip(cells, results) if r is not None]
+    n_upd = len(upd)
+
+    # candidate state for the greedy choice
+    cand_boxes = list(st.boxes)
+    htil = st.hbar.copy()
+    for c, r in upd:
+        o1, o2 = r["box"][0], r["box"][1]
+        for b in c["basic"]:
+            cand_boxes[b] = truncate_to_box(o1, o2, r["cand"][b], opt.trunc)
+            htil[b] = r["pieces"][b]
+    Pg = aggregate(p, cand_boxes)
+    e_cur = float(st.hbar.sum()) + p.lam * uot.kl(P, p.nu)
+    e_grd = float(htil.sum()) + p.lam * uot.kl(Pg, p.nu)
+
+    if opt.getweights == "greedy" or st.force_greedy:
+        theta = 1.0
+    elif opt.getweights == "safe":
+        theta = 1.0 / max(n_upd, 1)
+    elif opt.getweights == "swift":
+        theta = 1.0 if e_grd <= e_cur + opt.lenience * abs(e_cur) else 1.0 / max(n_upd, 1)
+    else:
+        raise ValueError(opt.getweights)
+    st.force_greedy = False
+
+    # Algorithm 4: pi' = sum_J (1 - theta) pi_J + theta pi~_J
+    for c, r in upd:
+        box = r["box"]
+        for b in c["basic"]:
+            v = (1.0 - theta) * _on_box(st.boxes[b], box) + theta * _on_box(cand_boxes[b], box)
+            st.boxes[b] = truncate_to_box(box[0], box[1], v, opt.trunc)
+            st.hbar[b] = (1.0 - theta) * st.hbar[b] + theta * htil[b]
+        pxf = st.px.ravel()
+        pxf[r["xi"]] = (1.0 - theta) * pxf[r["xi"]] + theta * r["px"]
+        st.abar.ravel()[r["xi"]] = r["alpha"]
+        if st.plan is not None:
+            rows = r["xi"]
+            new = np.zeros((rows.size, p.n1 * p.n2))
+            new[:, r["yi"]] = r["pi"]
+            st.plan[rows] = (1.0 - theta) * st.plan[rows] + theta * new
+    st.k += 1
+    stats = dict(part=part, theta=theta, e_cur=e_cur, e_greedy=e_grd, n_cells=len(cells),
+                 n_updated=n_upd, n_overflow=len(cells) - n_upd,
+                 iters=[r["iters"] for _, r in upd],
+                 n_unconverged=sum(1 for _, r in upd if not r["converged"]),
+                 point_iters=sum(r["iters"] * r["xi"].size for _, r in upd))
+    st.history.append(stats)
+    return stats
+
+
+def half_iteration_sequential(p: Problem, st: State, part: str, opt: Options) -> dict:
+    """Sequential DomDecIter (Algorithm 3): cells in order, each solved against
+    the plan updated by all previous cells."""
+    cells = composite_cells(p, part)
+    iters = []
+    for c in cells:
+        P = aggregate(p, st.boxes)
+        r = process_cell(p, c, st.boxes, P, opt)
+        if r is None:
+            continue
+        iters.append(r["iters"])
+        o1, o2 = r["box"][0], r["box"][1]
+        for b in c["basic"]:
+            st.boxes[b] = truncate_to_box(o1, o2, r["cand"][b], opt.trunc)
+            st.hbar[b] = r["pieces"][b]
+        st.px.ravel()[r["xi"]] = r["px"]
+        st.abar.ravel()[r["xi"]] = r["alpha"]
+        if st.plan is not None:
+            new = np.zeros((r["xi"].size, p.n1 * p.n2))
+            new[:, r["yi"]] = r["pi"]
+            st.plan[r["xi"]] = new
+    st.k += 1
+    stats = dict(part=part, theta=1.0, iters=iters)
+    st.history.append(stats)
+    return stats
+
+
+def run(p: Problem, st: State, n_half: int, opt: Options, sequential=False, single=False):
+    """Algorithm 2: k odd -> partition A, k even -> B (k counted from 1).
+    `single` uses partition A only (Remark on one partition)."""
+    out = []
+    for _ in range(n_half):
+        part = "A" if (single or st.k % 2 == 0) else "B"
+        f = half_iteration_sequential if sequential else half_iteration
+        out.append(f(p, st, part, opt))
+    return out
+
+
+def set_eps(p: Problem, st: State, eps: float):
+    """Next epsilon stage (Sec. 4.4 epsilon-scaling).  The tracked pieces were
+    computed for the old eps, so the next half-iteration is taken greedily,
+    which makes every Hbar_i exact again."""
+    p.eps = float(eps)
+    st.force_greedy = True
+
+
+# --------------------------------------------------------------------------
+# certificate (global primal-dual gap of a DD state)
+# --------------------------------------------------------------------------
+def certificate(p: Problem, abar) -> dict:
+    """Dual candidate alpha_bar (stitched cell potentials) -> beta_hat by one
+    global Y-update with nu_- = 0 (eq. sinkhorn-iters-ot) -> pi_hat; the gap is
+    PD = lam KL(P_X pi_hat | exp(-alpha/lam) mu), exact by eq. (PD-gap-KL) with
+    J = I.  Dense: for small grids only.  Also returns primal and dual."""
+    pts = uot.grid_points(p.n1, p.n2, p.h)
+    C = uot.sq_cost(pts, pts)
+    a = np.ravel(abar)
+    kappa = p.lam / (p.lam + p.eps)
+    z = uot.y_log_integral(a, p.mu, C, p.eps)
+    bhat = -p.eps * kappa * z
+    pi = uot.plan(a, bhat, p.mu, p.nu, C, p.eps)
+    px, py = pi.sum(1), pi.sum(0)
+    pd = uot.pd_gap_kl(a, px, p.mu, p.lam)
+    D = uot.dual(a, bhat, p.mu, p.nu, C, p.eps, p.lam)
+    E = uot.primal(pi, p.mu, p.nu, C, p.eps, p.lam)
+    return dict(pd=pd, dual=D, primal=E, rel=pd / D, beta_hat=bhat.reshape(p.mu.shape),
+                px=px.reshape(p.mu.shape), py=py.reshape(p.mu.shape),
+                l1_x=float(np.abs(px - np.exp(-a / p.lam) * p.mu.ravel()).sum()))
+
+
+def beta_hat_at(p: Problem, abar, y_flat) -> np.ndarray:
+    """beta_hat at selected grid points (dense over all x); for large grids."""
+    pts = uot.grid_points(p.n1, p.n2, p.h)
+    C = uot.sq_cost(pts, pts[np.asarray(y_flat)])
+    kappa = p.lam / (p.lam + p.eps)
+    return -p.eps * kappa * uot.y_log_integral(np.ravel(abar), p.mu, C, p.eps)

@@ -1,0 +1,231 @@
+"""Pins of the domain-decomposition oracle (Sec. 3, Sec. 4)."""
+import numpy as np
+import pytest
+
+from oracle import dd, uot
+from paper_2410_08859_amd.inputs import gaussian_mixture, uniform_masses
+
+
+def small_problem(n=8, s=2, eps_h2=4.0, lam=1.0, seed=1, h=None):
+    mu = gaussian_mixture(n, n, 3, 1e-3, 1.0, 10 * seed + 1)
+    nu = gaussian_mixture(n, n, 3, 1e-3, 1.3, 10 * seed + 2)
+    hh = 1.0 / n if h is None else h
+    return dd.make_problem(mu, nu, eps_h2 / n ** 2, lam, hh, s)
+
+
+def global_optimum(p):
+    pts = uot.grid_points(p.n1, p.n2, p.h)
+    C = uot.sq_cost(pts, pts)
+    sol = uot.sinkhorn(p.mu, p.nu, C, p.eps, p.lam, tol=None, step_tol=1e-15)
+    pi = uot.plan(sol["alpha"], sol["beta"], p.mu, p.nu, C, p.eps)
+    return pi, sol, C
+
+
+def test_partitions_cover_basic_cells_once():
+    p = small_problem(16, 2)
+    for part, ncell in (("A", 16), ("B", 25)):
+        cells = dd.composite_cells(p, part)
+        assert len(cells) == ncell
+        ids = sorted(b for c in cells for b in c["basic"])
+        assert ids == list(range(p.nb1 * p.nb2))
+        for c in cells:
+            o1, o2, l1, l2 = c["rect"]
+            idx = set(dd.rect_index(c["rect"], p.n2).tolist())
+            assert idx == set(np.concatenate([dd.rect_index(dd.basic_rect(p, b), p.n2)
+                                              for b in c["basic"]]).tolist())
+
+
+def test_toy_partition_has_singletons():
+    mu = uniform_masses(1, 32, 1.0)
+    p = dd.make_problem(mu, mu.copy(), 2.0 / 32 ** 2, 1.0, 1.0 / 32, 1, 1)
+    B = dd.composite_cells(p, "B")
+    assert [len(c["basic"]) for c in B] == [1] + [2] * 15 + [1]
+    assert len(dd.composite_cells(p, "A")) == 16
+
+
+def test_init_marginals():
+    p = small_problem()
+    st = dd.init_block(p)
+    np.testing.assert_allclose(dd.aggregate(p, st.boxes), p.nu, rtol=1e-15)
+    st = dd.init_product(p)
+    np.testing.assert_allclose(dd.aggregate(p, st.boxes), p.mu.sum() * p.nu, rtol=1e-14)
+    np.testing.assert_allclose(st.px, p.nu.sum() * p.mu, rtol=1e-15)
+
+
+def test_block_init_piece_closed_form():
+    # H_i of the block start written out: <c,pi> + eps[|nu(X_i)|(-log|mu_i| - 1) +
+    # |mu_i||nu|] + lam |mu_i| (t log t - t + 1), t = |nu(X_i)|/|mu_i|
+    p = small_problem(8, 2)
+    st = dd.init_block(p)
+    for b in range(p.nb1 * p.nb2):
+        rect = dd.basic_rect(p, b)
+        idx = dd.rect_index(rect, p.n2)
+        m, v = p.mu.ravel()[idx], p.nu.ravel()[idx]
+        C = dd.rect_cost(p, rect, rect)
+        t = v.sum() / m.sum()
+        h = ((C * np.outer(m, v)).sum() / m.sum()
+             + p.eps * (v.sum() * (-np.log(m.sum()) - 1) + m.sum() * p.nu.sum())
+             + p.lam * m.sum() * (t * np.log(t) - t + 1))
+        assert st.hbar[b] == pytest.approx(h, rel=1e-13)
+
+
+def test_cell_piece_formula_for_diagonal_scaling_plan():
+    # For pi = exp((a + b - c)/eps) mu x nu on X_i x box:
+    # <c,pi> + eps KL(pi|mu_i x nu) = <a, P_X pi> + <b, P_Y pi> - eps|pi| + eps|mu_i||nu|
+    p = small_problem(8, 2)
+    rng = np.random.default_rng(3)
+    rect, box = (2, 2, 2, 2), (1, 0, 5, 6)
+    xi, yi = dd.rect_index(rect, p.n2), dd.rect_index(box, p.n2)
+    mu_x, nu_y = p.mu.ravel()[xi], p.nu.ravel()[yi]
+    C = dd.rect_cost(p, rect, box)
+    a = rng.normal(0, 0.01, xi.size)
+    b = rng.normal(0, 0.01, yi.size)
+    pi = uot.plan(a, b, mu_x, nu_y, C, p.eps)
+    px, py = pi.sum(1), pi.sum(0)
+    formula = ((a * px).sum() + (b * py).sum() - p.eps * pi.sum()
+               + p.eps * mu_x.sum() * p.nu.sum() + p.lam * uot.kl(px, mu_x))
+    definition = dd.cell_piece(pi, mu_x, nu_y, p.nu.sum(), C, p.eps, p.lam)
+    assert formula == pytest.approx(definition, rel=1e-12)
+
+
+def test_resplit_sums():
+    p = small_problem(8, 2)
+    st = dd.init_block(p)
+    opt = dd.Options(margin=2, cap=8, trunc=0.0)
+    P = dd.aggregate(p, st.boxes)
+    for cell in dd.composite_cells(p, "B"):
+        r = dd.process_cell(p, cell, st.boxes, P, opt)
+        tot = sum(r["cand"][b] for b in cell["basic"])
+        np.testing.assert_allclose(tot.ravel(), r["pi"].sum(0), rtol=1e-13)
+        for b in cell["basic"]:
+            rows = np.isin(r["xi"], dd.rect_index(dd.basic_rect(p, b), p.n2))
+            assert r["cand"][b].sum() == pytest.approx(r["px"][rows].sum(), rel=1e-13)
+
+
+def test_global_optimum_is_a_fixed_point_of_the_cell_step():
+    # nu_{-J} = P_Y pi - nu_J at the optimum: the cell problem returns pi^dagger
+    # restricted to X_J x Y (Sec. 3.1, cell subproblem)
+    p = small_problem(8, 2)
+    pi, _, _ = global_optimum(p)
+    st = dd.init_product(p)
+    for b in range(p.nb1 * p.nb2):
+        rows = dd.rect_index(dd.basic_rect(p, b), p.n2)
+        st.boxes[b] = (0, 0, pi[rows].sum(0).reshape(p.n1, p.n2))
+    opt = dd.Options(cap=8, trunc=0.0, getweights="greedy", err=1e-14, max_iter=5000)
+    ref = [arr.copy() for _, _, arr in st.boxes]
+    dd.half_iteration(p, st, "A", opt)
+    for b in range(p.nb1 * p.nb2):
+        np.testing.assert_allclose(st.boxes[b][2], ref[b], rtol=1e-6, atol=1e-14)
+    np.testing.assert_allclose(st.px, pi.sum(1).reshape(p.mu.shape), rtol=1e-6)
+
+
+@pytest.mark.parametrize("gw", ["swift", "safe"])
+def test_monotone_scores(gw):
+    # Safe decrement proof (Sec. 3.4): with safe weights the exact score of the
+    # mixed plan never rises.  The tracked score Ebar (reading R8) bounds E from
+    # above and never rises under safe or swift; swift compares tracked scores,
+    # so after a safe step it may accept a greedy plan whose exact score lies
+    # above the (smaller) exact score of the mixture.
+    p = small_problem(8, 2)
+    st = dd.init_product(p, dense_plan=True)
+    opt = dd.Options(cap=8, trunc=0.0, getweights=gw, err=1e-13, max_iter=5000)
+    E = [dd.exact_score(p, st)]
+    Eb = [dd.tracked_score(p, st)]
+    assert Eb[0] == pytest.approx(E[0], rel=1e-13)
+    for _ in range(8):
+        dd.run(p, st, 1, opt)
+        E.append(dd.exact_score(p, st))
+        Eb.append(dd.tracked_score(p, st))
+    E, Eb = np.array(E), np.array(Eb)
+    if gw == "safe":
+        assert np.all(np.diff(E) <= 1e-12 * np.abs(E[:-1]))
+    assert np.all(np.diff(Eb) <= 1e-12 * np.abs(Eb[:-1]))
+    assert np.all(E <= Eb + 1e-12 * np.abs(Eb))
+    if gw == "swift":
+        greedy_steps = [h["theta"] == 1.0 for h in st.history]
+        # after a greedy step the tracked score is exact
+        for k, g in enumerate(greedy_steps):
+            if g:
+                assert Eb[k + 1] == pytest.approx(E[k + 1], rel=1e-11)
+
+
+def test_sequential_monotone():
+    p = small_problem(8, 2)
+    st = dd.init_product(p, dense_plan=True)
+    opt = dd.Options(cap=8, trunc=0.0, err=1e-13, max_iter=5000)
+    E = [dd.exact_score(p, st)]
+    for _ in range(4):
+        dd.run(p, st, 1, opt, sequential=True)
+        E.append(dd.exact_score(p, st))
+    assert np.all(np.diff(E) <= 1e-12 * np.abs(E[0]))
+
+
+def test_dd_converges_to_global_optimum():
+    # Props. (convergence, parallel) + unique optimum: DD limit = pi^dagger
+    p = small_problem(8, 2)
+    pi, sol, C = global_optimum(p)
+    st = dd.init_product(p, dense_plan=True)
+    opt = dd.Options(cap=8, trunc=0.0, getweights="swift", err=1e-15, max_iter=20000)
+    dd.run(p, st, 160, opt)
+    np.testing.assert_allclose(st.plan, pi, rtol=5e-6, atol=1e-15)
+    np.testing.assert_allclose(st.px.ravel(), pi.sum(1), rtol=5e-6)
+    np.testing.assert_allclose(dd.aggregate(p, st.boxes).ravel(), pi.sum(0), rtol=5e-6)
+    cert = dd.certificate(p, st.abar)
+    W = uot.primal(pi, p.mu, p.nu, C, p.eps, p.lam)
+    assert cert["rel"] < 1e-12
+    assert cert["dual"] <= W * (1 + 1e-13) and cert["primal"] >= W * (1 - 1e-13)
+    assert dd.tracked_score(p, st) == pytest.approx(W, rel=1e-9)
+
+
+def test_certificate_gap_identity():
+    # PD of the certificate pair equals E(pi_hat) - D(alpha_bar, beta_hat)
+    p = small_problem(8, 2)
+    st = dd.init_block(p)
+    dd.run(p, st, 3, dd.Options(cap=8, margin=2))
+    cert = dd.certificate(p, st.abar)
+    assert cert["primal"] - cert["dual"] == pytest.approx(cert["pd"], rel=1e-8)
+    assert cert["pd"] > 0
+
+
+def test_zero_cost_dd_reaches_product_plan():
+    # h = 0 makes c = 0; the optimum is s mu x nu, s = (|mu||nu|)^(-lam/(eps+2lam))
+    p = small_problem(8, 2, h=0.0)
+    p.eps = 4.0 / 64
+    st = dd.init_product(p, dense_plan=True)
+    dd.run(p, st, 40, dd.Options(cap=8, trunc=0.0, err=1e-15, max_iter=20000))
+    s = (p.mu.sum() * p.nu.sum()) ** (-p.lam / (p.eps + 2 * p.lam))
+    np.testing.assert_allclose(st.plan, s * np.outer(p.mu.ravel(), p.nu.ravel()), rtol=1e-8)
+
+
+def toy(gw, iters):
+    # Sec. 4.2 toy: N = 32 on {0, 1/N, ..}, mu = nu uniform, lam = 1, eps = 2/N^2,
+    # A = pairs, B = staggered with two singletons, start mu x nu
+    N = 32
+    mu = uniform_masses(1, N, 1.0)
+    p = dd.make_problem(mu, mu.copy(), 2.0 / N ** 2, 1.0, 1.0 / N, 1, 1)
+    st = dd.init_product(p, dense_plan=True)
+    opt = dd.Options(cap=64, trunc=0.0, getweights=gw, err=1e-7, max_iter=1500)
+    E = [dd.exact_score(p, st)]
+    for _ in range(iters):
+        dd.run(p, st, 1, opt)
+        E.append(dd.exact_score(p, st))
+    return np.array(E), p
+
+
+def test_toy_getweights_behaviour():
+    # Sec. 4.2: greedy does not converge (cells overshoot together and the
+    # score rises), safe is very slow, swift makes steady progress.
+    # Qualitative only: the paper's figures carry no numbers.
+    Eg, p = toy("greedy", 4)
+    Es, _ = toy("safe", 8)
+    Ew, _ = toy("swift", 8)
+    pts = uot.grid_points(p.n1, p.n2, p.h)
+    C = uot.sq_cost(pts, pts)
+    sol = uot.sinkhorn(p.mu, p.nu, C, p.eps, p.lam, tol=None, step_tol=1e-14)
+    W = uot.primal(uot.plan(sol["alpha"], sol["beta"], p.mu, p.nu, C, p.eps),
+                   p.mu, p.nu, C, p.eps, p.lam)
+    gap_g, gap_s, gap_w = Eg - W, Es - W, Ew - W
+    assert np.any(np.diff(Eg) > 0)             # greedy raises the score
+    assert gap_w[-1] < 0.1 * gap_w[0]          # swift converges
+    assert gap_s[-1] > 3 * gap_w[-1]           # safe lags behind
+    assert gap_g[-1] > 10 * gap_w[-1]          # greedy does not converge
