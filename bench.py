@@ -1,0 +1,154 @@
+"""Throughput of the domain-decomposition hot path on one MI355X.
+
+A step is one parallel DomDecIter half-iteration over every composite cell of
+one partition (aggregation of the basic Y-marginals, cell inputs, the cell
+Sinkhorn solves with the Newton Y-update and the PD stopping rule, re-split,
+score pieces, GetWeights, update), alternating A and B.  The metric counts
+grid points times inner Sinkhorn iterations: sum over solved cells of
+|X_J| * (Y-halves of that cell), divided by the wall time of the timed steps.
+
+Prints one JSON line.  `--gpus` above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2410_08859_amd import binding as B  # noqa: E402
+from paper_2410_08859_amd.inputs import WORKLOADS, workload_marginals  # noqa: E402
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 9.83e13 FP32 lane-ops/s;
+# v_exp_f32 runs at a quarter of that rate.
+EXP_PEAK = 256 * 64 * 2.4e9 / 4.0
+HBM_PEAK = 8.0e12
+
+
+def workload_config(name, precision, max_inner, cap):
+    w = WORKLOADS[name]
+    n = w["n"]
+    return B.dd_uot_default_config(
+        n1=n, n2=n, h=1.0 / n, eps=w["eps_h2"] / n ** 2, lam=w["lam"], cell=w["cell"],
+        precision=precision, init=B.INIT_BLOCK, getweights=B.GW_SWIFT,
+        sinkhorn_err=2e-5, sinkhorn_max_iter=max_inner, trunc=1e-15, lenience=0.005,
+        box_margin=2, box_cap=cap)
+
+
+def cpu_baseline(name, max_inner, budget_s=15.0):
+    """The oracle timed on a bounded sample of the same workload: the cell
+    solves of the first A cells of the first half-iteration, until the budget
+    is spent.  Single-threaded numpy."""
+    from oracle import dd
+    w = WORKLOADS[name]
+    n = w["n"]
+    mu, nu = workload_marginals(name)
+    p = dd.make_problem(mu, nu, w["eps_h2"] / n ** 2, w["lam"], 1.0 / n, w["cell"])
+    st = dd.init_block(p)
+    opt = dd.Options(err=2e-5, max_iter=max_inner, trunc=1e-15, lenience=0.005, margin=2, cap=64)
+    P = dd.aggregate(p, st.boxes)
+    cells = dd.composite_cells(p, "A")
+    t0 = time.perf_counter()
+    pts = 0
+    done = 0
+    for c in cells:
+        r = dd.process_cell(p, c, st.boxes, P, opt)
+        pts += r["iters"] * r["xi"].size
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": pts / dt, "unit": "grid-pts*iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of {len(cells)} partition-A cell solves of the first half-iteration "
+                      f"({n}x{n}, FP64 dense numpy, Err 2e-5, max {max_inner} inner iterations)"}
+
+
+def run(args):
+    import torch
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    mu, nu = workload_marginals(args.workload)
+    cfg = workload_config(args.workload, args.precision, args.max_inner, args.cap)
+    stream = torch.cuda.current_stream(dev)
+    h = B.dd_uot_init(cfg, mu, nu, stream=stream.cuda_stream)
+    try:
+        B.dd_uot_iterate(h, args.warmup, stats=False)
+        torch.cuda.synchronize()
+        B.dd_uot_set_timing(h, True)
+        rec0 = len(B.dd_uot_history(h, 0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.dd_uot_iterate(h, args.steps, stats=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        launches, kms, kbytes = B.dd_uot_kernel_time(h)
+        B.dd_uot_set_timing(h, False)
+        hist = B.dd_uot_history(h, 0)[rec0:]
+        point_iters = hist[:, 4].sum()
+        terms = hist[:, 10].sum()
+        score = B.dd_uot_score(h, 0)
+    finally:
+        B.dd_uot_destroy(h)
+    avg_ms = kms / max(launches, 1)
+    exp_rate = terms / launches / (avg_ms * 1e-3)
+    hbm_rate = kbytes / launches / (avg_ms * 1e-3)
+    out = {
+        "metric": "grid-pts\u00b7iters/s and time to PD-gap 1e-6, 1024\u00b2 UOT, FP32 vs FP64 on 1 GPU",
+        "value": point_iters / dt,
+        "unit": "grid-pts\u00b7iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == 32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": cfg.n1, "cell": cfg.cell, "lambda": cfg.lambda_,
+                   "eps": cfg.eps, "precision": args.precision, "max_inner": args.max_inner,
+                   "box_cap": cfg.box_cap, "start": "block"},
+        "roofline": {"bound": "alu", "achieved": exp_rate / 1e12, "peak": EXP_PEAK / 1e12,
+                     "unit": "Texp/s", "frac": exp_rate / EXP_PEAK, "traffic": None,
+                     "kernel": "k_cell_solve", "avg_launch_ms": avg_ms,
+                     "hbm_algorithmic_GBps": hbm_rate / 1e9, "hbm_frac": hbm_rate / HBM_PEAK},
+        "inner": {"point_iters": float(point_iters), "mean_inner_per_cell":
+                  float(hist[:, 8].sum() / max(hist[:, 3].sum(), 1)),
+                  "unconverged_cells": float(hist[:, 6].sum()),
+                  "overflow_cells": float(hist[:, 7].sum()),
+                  "safe_steps": int((hist[:, 0] < 1).sum())},
+        "state_after": {"rel_pd_gap": score["rel_pd_gap"], "tracked_score": score["tracked"],
+                        "half_iters": score["half_iters"]},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.max_inner, args.cpu_budget)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--workload", default="grid1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
+    ap.add_argument("--max-inner", type=int, default=100)
+    ap.add_argument("--cap", type=int, default=48)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build",
+              file=sys.stderr)
+        sys.exit(2)
+    print(json.dumps(run(args)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

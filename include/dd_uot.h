@@ -1,0 +1,185 @@
+/*
+ * dd_uot.h -- C ABI of the MI355X domain-decomposition solver for entropic
+ * unbalanced optimal transport on 2-D grids (Medina, Nguyen, Schmitzer,
+ * "Domain decomposition for entropic unbalanced optimal transport").
+ *
+ * Problem (Definition unbalanced-entropic-transport, Sec. 2.2; choices of
+ * Sec. 4.1): point masses mu, nu > 0 on the same n1 x n2 grid x = h (i1, i2),
+ * cost c(x, y) = |x - y|^2, entropic strength eps, marginal penalties
+ * D1 = D2 = lambda KL.  The solver runs Algorithm 2 (alternating composite
+ * partitions A and B) with the parallel DomDecIter of Algorithm 4: every
+ * composite cell of a partition is solved at once by the unbalanced Sinkhorn
+ * iteration of Sec. 4.1 (X-update eq. sinkhorn-X-iteration, Y-update
+ * eq. proxdiv-problem by Newton, stopping rule eq. PD-gap-KL), the basic-cell
+ * Y-marginals are stored on bounding boxes truncated at `trunc` (Sec. 4.4),
+ * and the step weights come from GetWeights (Proposition converging-getweights).
+ *
+ * Conventions for every function:
+ *  - return 0 (DDUOT_OK) or a negative DDUOT_E* code; no C++ exception
+ *    crosses the ABI; dd_uot_last_error() gives the calling thread's text;
+ *  - arrays are row-major n1 x n2 double (index i1 * n2 + i2) in HOST memory;
+ *    inputs are copied, outputs are written into caller-owned buffers of the
+ *    stated size;
+ *  - a handle owns all device memory it allocates and is not thread-safe:
+ *    use one handle per host thread / stream;
+ *  - work is queued on the HIP stream given at init (NULL = default stream);
+ *    dd_uot_iterate is asynchronous unless it is asked for statistics.
+ */
+#ifndef DD_UOT_H
+#define DD_UOT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DDUOT_OK = 0,
+  DDUOT_EINVAL = -1,   /* bad argument: sizes, non-finite or non-positive masses
+                          (full-support assumption, Sec. 3.2), eps/lambda <= 0 */
+  DDUOT_ENOMEM = -2,   /* device allocation failed */
+  DDUOT_EHIP = -3,     /* HIP runtime error (text kept in dd_uot_last_error) */
+  DDUOT_ESLOT = -4,    /* a cell's Y-box exceeded box_cap (reported, not fatal) */
+  DDUOT_ESTATE = -5    /* call not valid in the handle's state */
+};
+
+enum { DDUOT_GW_GREEDY = 0, DDUOT_GW_SAFE = 1, DDUOT_GW_SWIFT = 2 };
+enum { DDUOT_INIT_BLOCK = 0, DDUOT_INIT_PRODUCT = 1 };
+
+typedef struct dduot_handle dduot_handle;
+
+typedef struct {
+  int32_t n1, n2;            /* grid; each divisible by 2*cell */
+  double h;                  /* grid spacing (>= 0; 0 makes the cost vanish) */
+  double lambda, eps;        /* > 0 */
+  int32_t cell;              /* basic cell side s; composite = 2 x 2 basic cells,
+                                partition B offset by s (Sec. 4.4); 2*s <= 16 */
+  int32_t precision;         /* 64: FP64 cell arithmetic; 32: FP32 log-sum-exp
+                                on per-cell re-centred residuals, FP64 bases,
+                                reductions and scores */
+  int32_t getweights;        /* DDUOT_GW_* ; swift is the default */
+  int32_t init;              /* DDUOT_INIT_BLOCK (nu_i = nu on block i) or
+                                DDUOT_INIT_PRODUCT (pi = mu x nu, Sec. 4.2) */
+  double sinkhorn_err;       /* Err: a cell stops at PD/lambda <= Err |mu_J|
+                                (Sec. 4.4: 2e-5) */
+  int32_t sinkhorn_max_iter; /* cap on Y-halves per cell solve */
+  int32_t fixed_inner_iters; /* > 0: exactly this many Y-halves per cell */
+  double trunc;              /* basic-marginal truncation (Sec. 4.4: 1e-15) */
+  double lenience;           /* swift accepts greedy if the tracked score rises
+                                by at most lenience*|score| (Sec. 4.4: 0.005) */
+  int32_t box_margin;        /* Y-box of a cell = bbox of its basic boxes
+                                dilated by this margin, clipped to the grid */
+  int32_t box_cap;           /* maximal Y-box side (device slot capacity) */
+} dduot_config;
+
+/* Per call of dd_uot_iterate, summed over all problems of the handle. */
+typedef struct {
+  int32_t half_iters;        /* half-iterations run by the call */
+  int32_t n_safe;            /* (problem, half-iteration) pairs that took the
+                                safe weights */
+  int64_t inner_iters;       /* sum over solved cells of Y-halves */
+  int64_t point_iters;       /* sum over solved cells of |X_J| * Y-halves */
+  int32_t max_inner;         /* largest Y-half count of one cell */
+  int32_t n_unconverged;     /* cells that hit the iteration cap */
+  int32_t n_overflow;        /* cells skipped because the Y-box exceeded box_cap */
+  int32_t n_cells;           /* cells solved (all half-iterations) */
+} dduot_iter_stats;
+
+typedef struct {
+  double tracked;            /* tracked score sum_i Hbar_i + lambda KL(P_Y pi|nu):
+                                an upper bound of E(pi), exact after greedy steps */
+  double primal;             /* E(pi_hat) of the certificate plan */
+  double dual;               /* D(alpha_bar, beta_hat) */
+  double pd_gap;             /* primal - dual = lambda KL(P_X pi_hat | e^{-alpha/lambda} mu),
+                                eq. PD-gap-KL with J = I */
+  double rel_pd_gap;         /* pd_gap / dual (Sec. 4.4 solution quality) */
+  double l1_err_x;           /* || P_X pi - e^{-alpha_bar/lambda} mu ||_1 (state plan) */
+  double l1_err_y;           /* || P_Y pi - e^{-beta_hat/lambda} nu ||_1 (state plan) */
+  double mass_x, mass_y;     /* |P_X pi|, |P_Y pi| of the state plan */
+  int64_t half_iters;        /* half-iterations done so far */
+  int32_t overflow;          /* nonzero if any cell ever overflowed */
+} dduot_score;
+
+/* Fill *cfg with the paper's defaults (Err 2e-5, trunc 1e-15, lenience 0.005,
+   swift, FP32, block start, margin 2, cap 64, max 1000 inner iterations). */
+void dd_uot_default_config(dduot_config* cfg);
+
+/* Create a solver for one problem.  mu, nu: host, n1*n2 each, every entry
+   finite and > 0 (Assumption full support, Sec. 3.2) else DDUOT_EINVAL.
+   hip_stream: a hipStream_t or NULL.  The start plan is cfg->init. */
+int dd_uot_init(const dduot_config* cfg, const double* mu, const double* nu,
+                void* hip_stream, dduot_handle** out);
+
+/* Create one solver holding nprob independent problems (sizes and parameters
+   may differ); every kernel launch covers all problems' cells at once, and
+   GetWeights decides per problem.  mus[k], nus[k]: host arrays of problem k. */
+int dd_uot_init_batch(int32_t nprob, const dduot_config* cfgs, const double* const* mus,
+                      const double* const* nus, void* hip_stream, dduot_handle** out);
+
+/* Set eps of problem `prob` (epsilon-scaling, Sec. 4.4).  The tracked scores
+   were computed for the old eps, so the next half-iteration of that problem
+   takes greedy weights, which makes them exact again. */
+int dd_uot_set_eps(dduot_handle* h, int32_t prob, double eps);
+
+/* Run n_half_iters parallel DomDecIter steps (Algorithm 4), alternating
+   partitions A and B (Algorithm 2; the first step after init uses A).
+   stats == NULL: asynchronous on the handle's stream.  Otherwise the call
+   synchronises and fills *stats for the steps of this call. */
+int dd_uot_iterate(dduot_handle* h, int32_t n_half_iters, dduot_iter_stats* stats);
+
+/* Per half-iteration record of problem `prob`, oldest first, at most `max`
+   records of 11 doubles: theta, tracked score before, tracked score of the
+   greedy candidate, cells updated, sum |X_J| * inner iterations, max inner
+   iterations, unconverged cells, overflowed cells, inner iterations,
+   algorithmic bytes of the cell solves, log-sum-exp terms of the cell solves.
+   Returns the number of records written (>= 0) or an error code.
+   Synchronises. */
+int dd_uot_history(dduot_handle* h, int32_t prob, int32_t max, double* out);
+
+/* Primal-dual certificate of the current state of problem `prob`: the
+   stitched cell potentials alpha_bar (last solve of each cell), one global
+   Y-update with nu_- = 0 (eq. sinkhorn-iters-ot) giving beta_hat, and the
+   gap of eq. PD-gap-KL for the plan pi_hat they define.  Synchronises. */
+int dd_uot_score(dduot_handle* h, int32_t prob, dduot_score* out);
+
+/* X- and Y-marginal of the current state plan (P_X pi and sum_i nu_i).
+   px, py: host, n1*n2 doubles each (either may be NULL).  Synchronises. */
+int dd_uot_marginals(dduot_handle* h, int32_t prob, double* px, double* py);
+
+/* Stored Y-marginal nu_i of basic cell `basic` (row-major ids over the
+   (n1/cell) x (n2/cell) blocks).  box[4] receives (o1, o2, L1, L2); values
+   receives L1*L2 doubles if L1*L2 <= cap, else DDUOT_EINVAL.  Synchronises. */
+int dd_uot_basic_marginal(dduot_handle* h, int32_t prob, int32_t basic, int32_t box[4],
+                          double* values, int64_t cap);
+
+/* alpha_bar (stitched cell potentials) and, after dd_uot_score, beta_hat.
+   Either pointer may be NULL; n1*n2 doubles each.  Synchronises. */
+int dd_uot_potentials(dduot_handle* h, int32_t prob, double* alpha, double* beta_hat);
+
+/* Gradient of the optimal value W(mu, nu) at the certificate pair (envelope
+   theorem on the dual of Definition unbalanced-entropic-transport):
+   dW/dmu = eps|nu| - eps P_X pi_hat/mu - lambda (e^{-alpha/lambda} - 1),
+   dW/dnu = eps|mu| - eps P_Y pi_hat/nu - lambda (e^{-beta/lambda} - 1),
+   scaled by gout.  Exact at the optimum; call after dd_uot_score.
+   dmu, dnu: host, n1*n2 doubles each (either may be NULL). */
+int dd_uot_backward(dduot_handle* h, int32_t prob, double gout, double* dmu, double* dnu);
+
+/* Cell-kernel timing with HIP events recorded on the handle's stream around
+   every cell-solve launch (enable != 0 turns it on and clears the totals).
+   dd_uot_kernel_time returns the number of timed launches and their summed
+   duration in milliseconds, and the summed algorithmic bytes of those
+   launches.  Synchronises. */
+int dd_uot_set_timing(dduot_handle* h, int32_t enable);
+int dd_uot_kernel_time(dduot_handle* h, int64_t* launches, double* total_ms,
+                       double* algo_bytes);
+
+int dd_uot_synchronize(dduot_handle* h);
+int32_t dd_uot_num_problems(const dduot_handle* h);
+void dd_uot_destroy(dduot_handle* h);
+const char* dd_uot_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DD_UOT_H */

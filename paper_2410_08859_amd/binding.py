@@ -1,0 +1,232 @@
+"""ctypes binding of libdd_uot.so: the C ABI of include/dd_uot.h, same names.
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdd_uot.so")
+
+OK, EINVAL, ENOMEM, EHIP, ESLOT, ESTATE = 0, -1, -2, -3, -4, -5
+GW_GREEDY, GW_SAFE, GW_SWIFT = 0, 1, 2
+INIT_BLOCK, INIT_PRODUCT = 0, 1
+HIST_FIELDS = ("theta", "e_cur", "e_greedy", "n_updated", "point_iters", "max_inner",
+               "n_unconverged", "n_overflow", "inner_iters", "algo_bytes", "lse_terms")
+
+EXPORTED = (
+    "dd_uot_default_config", "dd_uot_init", "dd_uot_init_batch", "dd_uot_set_eps",
+    "dd_uot_iterate", "dd_uot_history", "dd_uot_score", "dd_uot_marginals",
+    "dd_uot_basic_marginal", "dd_uot_potentials", "dd_uot_backward", "dd_uot_set_timing",
+    "dd_uot_kernel_time", "dd_uot_synchronize", "dd_uot_num_problems", "dd_uot_destroy",
+    "dd_uot_last_error",
+)
+
+
+class dduot_config(C.Structure):
+    _fields_ = [
+        ("n1", C.c_int32), ("n2", C.c_int32),
+        ("h", C.c_double),
+        ("lambda_", C.c_double), ("eps", C.c_double),
+        ("cell", C.c_int32), ("precision", C.c_int32), ("getweights", C.c_int32),
+        ("init", C.c_int32),
+        ("sinkhorn_err", C.c_double),
+        ("sinkhorn_max_iter", C.c_int32), ("fixed_inner_iters", C.c_int32),
+        ("trunc", C.c_double), ("lenience", C.c_double),
+        ("box_margin", C.c_int32), ("box_cap", C.c_int32),
+    ]
+
+
+class dduot_iter_stats(C.Structure):
+    _fields_ = [
+        ("half_iters", C.c_int32), ("n_safe", C.c_int32),
+        ("inner_iters", C.c_int64), ("point_iters", C.c_int64),
+        ("max_inner", C.c_int32), ("n_unconverged", C.c_int32), ("n_overflow", C.c_int32),
+        ("n_cells", C.c_int32),
+    ]
+
+
+class dduot_score(C.Structure):
+    _fields_ = [
+        ("tracked", C.c_double), ("primal", C.c_double), ("dual", C.c_double),
+        ("pd_gap", C.c_double), ("rel_pd_gap", C.c_double),
+        ("l1_err_x", C.c_double), ("l1_err_y", C.c_double),
+        ("mass_x", C.c_double), ("mass_y", C.c_double),
+        ("half_iters", C.c_int64), ("overflow", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load the HIP library (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not built; run paper_2410_08859_amd/build.py "
+                           "(or __graft_entry__.build())")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    dp = P(C.c_double)
+    H = C.c_void_p
+    sig = {
+        "dd_uot_default_config": (None, [P(dduot_config)]),
+        "dd_uot_init": (C.c_int, [P(dduot_config), dp, dp, C.c_void_p, P(H)]),
+        "dd_uot_init_batch": (C.c_int, [C.c_int32, P(dduot_config), P(dp), P(dp), C.c_void_p, P(H)]),
+        "dd_uot_set_eps": (C.c_int, [H, C.c_int32, C.c_double]),
+        "dd_uot_iterate": (C.c_int, [H, C.c_int32, P(dduot_iter_stats)]),
+        "dd_uot_history": (C.c_int, [H, C.c_int32, C.c_int32, dp]),
+        "dd_uot_score": (C.c_int, [H, C.c_int32, P(dduot_score)]),
+        "dd_uot_marginals": (C.c_int, [H, C.c_int32, dp, dp]),
+        "dd_uot_basic_marginal": (C.c_int, [H, C.c_int32, C.c_int32, P(C.c_int32), dp, C.c_int64]),
+        "dd_uot_potentials": (C.c_int, [H, C.c_int32, dp, dp]),
+        "dd_uot_backward": (C.c_int, [H, C.c_int32, C.c_double, dp, dp]),
+        "dd_uot_set_timing": (C.c_int, [H, C.c_int32]),
+        "dd_uot_kernel_time": (C.c_int, [H, P(C.c_int64), dp, dp]),
+        "dd_uot_synchronize": (C.c_int, [H]),
+        "dd_uot_num_problems": (C.c_int32, [H]),
+        "dd_uot_destroy": (None, [H]),
+        "dd_uot_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class DDUOTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dd_uot error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc < 0:
+        raise DDUOTError(rc, load().dd_uot_last_error().decode())
+    return rc
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def dd_uot_default_config(**kw) -> dduot_config:
+    cfg = dduot_config()
+    load().dd_uot_default_config(C.byref(cfg))
+    for k, v in kw.items():
+        setattr(cfg, "lambda_" if k == "lam" else k, v)
+    return cfg
+
+
+def _grid(a, n1, n2):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.size != n1 * n2:
+        raise ValueError("marginal size does not match the grid")
+    return a
+
+
+def dd_uot_init(cfg: dduot_config, mu, nu, stream=None):
+    mu = _grid(mu, cfg.n1, cfg.n2)
+    nu = _grid(nu, cfg.n1, cfg.n2)
+    h = C.c_void_p()
+    _check(load().dd_uot_init(C.byref(cfg), _dptr(mu), _dptr(nu), stream, C.byref(h)))
+    return h
+
+
+def dd_uot_init_batch(cfgs, mus, nus, stream=None):
+    n = len(cfgs)
+    arr = (dduot_config * n)(*cfgs)
+    mus = [_grid(m, c.n1, c.n2) for m, c in zip(mus, cfgs)]
+    nus = [_grid(v, c.n1, c.n2) for v, c in zip(nus, cfgs)]
+    pm = (C.POINTER(C.c_double) * n)(*[_dptr(m) for m in mus])
+    pn = (C.POINTER(C.c_double) * n)(*[_dptr(v) for v in nus])
+    h = C.c_void_p()
+    _check(load().dd_uot_init_batch(n, arr, pm, pn, stream, C.byref(h)))
+    return h
+
+
+def dd_uot_set_eps(h, prob, eps):
+    _check(load().dd_uot_set_eps(h, prob, eps))
+
+
+def dd_uot_iterate(h, n_half_iters, stats=True):
+    st = dduot_iter_stats() if stats else None
+    _check(load().dd_uot_iterate(h, n_half_iters, C.byref(st) if st is not None else None))
+    if st is None:
+        return None
+    return {f: getattr(st, f) for f, _ in dduot_iter_stats._fields_}
+
+
+def dd_uot_history(h, prob, max_records=4096):
+    out = np.zeros((max_records, len(HIST_FIELDS)))
+    n = _check(load().dd_uot_history(h, prob, max_records, _dptr(out)))
+    return out[:n]
+
+
+def dd_uot_score(h, prob=0):
+    s = dduot_score()
+    _check(load().dd_uot_score(h, prob, C.byref(s)))
+    return {f: getattr(s, f) for f, _ in dduot_score._fields_}
+
+
+def dd_uot_marginals(h, prob, n1, n2):
+    px = np.zeros(n1 * n2)
+    py = np.zeros(n1 * n2)
+    _check(load().dd_uot_marginals(h, prob, _dptr(px), _dptr(py)))
+    return px.reshape(n1, n2), py.reshape(n1, n2)
+
+
+def dd_uot_basic_marginal(h, prob, basic, cap=1 << 16):
+    box = (C.c_int32 * 4)()
+    vals = np.zeros(cap)
+    _check(load().dd_uot_basic_marginal(h, prob, basic, box, _dptr(vals), cap))
+    o1, o2, l1, l2 = list(box)
+    return (o1, o2, vals[: l1 * l2].reshape(l1, l2).copy())
+
+
+def dd_uot_potentials(h, prob, n1, n2, beta=True):
+    a = np.zeros(n1 * n2)
+    b = np.zeros(n1 * n2) if beta else None
+    _check(load().dd_uot_potentials(h, prob, _dptr(a), _dptr(b) if beta else None))
+    return a.reshape(n1, n2), (b.reshape(n1, n2) if beta else None)
+
+
+def dd_uot_backward(h, prob, n1, n2, gout=1.0):
+    dmu = np.zeros(n1 * n2)
+    dnu = np.zeros(n1 * n2)
+    _check(load().dd_uot_backward(h, prob, gout, _dptr(dmu), _dptr(dnu)))
+    return dmu.reshape(n1, n2), dnu.reshape(n1, n2)
+
+
+def dd_uot_set_timing(h, enable=True):
+    _check(load().dd_uot_set_timing(h, 1 if enable else 0))
+
+
+def dd_uot_kernel_time(h):
+    n = C.c_int64()
+    ms = C.c_double()
+    by = C.c_double()
+    _check(load().dd_uot_kernel_time(h, C.byref(n), C.byref(ms), C.byref(by)))
+    return n.value, ms.value, by.value
+
+
+def dd_uot_synchronize(h):
+    _check(load().dd_uot_synchronize(h))
+
+
+def dd_uot_num_problems(h):
+    return load().dd_uot_num_problems(h)
+
+
+def dd_uot_destroy(h):
+    if h:
+        load().dd_uot_destroy(h)

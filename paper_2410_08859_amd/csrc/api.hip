@@ -1,0 +1,772 @@
+// Host driver and C ABI (include/dd_uot.h).
+#include "../../include/dd_uot.h"
+#include "dd_types.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+namespace dduot {
+hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int precision,
+                             hipStream_t st);
+hipError_t set_cell_lds_limit(size_t bytes);
+size_t cell_lds_bytes(int cap, int precision);
+hipError_t launch_fill(double* p, long n, double v, hipStream_t st);
+hipError_t launch_aggregate(const Box* box, const double* vals, long cap2, const int* basic_prob,
+                            const Prob* probs, double* P, int nbasic, hipStream_t st);
+hipError_t launch_kl_chunks(const int* cp, const int* cs, const int* cl, const Prob* probs,
+                            const double* P, const double* Pg, const double* nu, double* part,
+                            int nchunk, hipStream_t st);
+hipError_t launch_getweights(const Dev& d, int part, int rec, int nprob, hipStream_t st);
+hipError_t launch_mix(const Dev& d, int part, int nbasic, int cap, hipStream_t st);
+hipError_t set_mix_lds_limit(size_t bytes);
+hipError_t launch_certificate(const Prob& p, const double* alpha, const double* mu, const double* nu,
+                              const double* px, const double* P, double* bhat, double* dmu,
+                              double* dnu, double* scratch, double* part, int nblk, hipStream_t st);
+hipError_t set_rows_lds_limit(size_t bytes);
+hipError_t launch_scatter_slots(const double* src, const long* off, double* vals, long cap2, int nbasic,
+                                hipStream_t st);
+}  // namespace dduot
+
+using namespace dduot;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(DDUOT_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+static const int kChunk = 16384;
+static const int kCertBlocks = 1024;
+
+struct dduot_handle {
+  int nprob = 0;
+  int precision = 32;
+  int cap = 0;
+  long cap2 = 0;
+  hipStream_t stream = nullptr;
+  std::vector<Prob> probs;
+  std::vector<Cell> cells;
+  int ncell[2] = {0, 0};
+  int nbasic = 0;
+  long ngrid = 0;
+  long maxgrid = 0;
+  int nchunk = 0;
+  long long k = 0;     // half-iterations done
+  int hist_cap = 4096;
+  // device memory
+  std::vector<void*> allocs;
+  Dev d{};
+  Prob* d_probs = nullptr;
+  Cell* d_cells = nullptr;
+  int* d_basic_prob = nullptr;
+  int2* d_basic_xy = nullptr;
+  int* d_basic_cell[2] = {nullptr, nullptr};
+  double *d_mu = nullptr, *d_nu = nullptr, *d_P = nullptr, *d_Pg = nullptr, *d_px = nullptr,
+         *d_pxc = nullptr, *d_abar = nullptr;
+  Box *d_box = nullptr, *d_cbox = nullptr;
+  double *d_vals = nullptr, *d_cand = nullptr, *d_hbar = nullptr, *d_htil = nullptr;
+  int *d_iters = nullptr, *d_conv = nullptr;
+  double* d_bytes = nullptr;
+  double* d_terms = nullptr;
+  int *d_chunk_prob = nullptr, *d_chunk_start = nullptr, *d_chunk_len = nullptr;
+  double* d_chunk_part = nullptr;
+  double *d_theta = nullptr, *d_hist = nullptr;
+  int *d_overflow = nullptr, *d_force = nullptr;
+  double *d_bhat = nullptr, *d_dmu = nullptr, *d_dnu = nullptr, *d_scratch = nullptr,
+         *d_cpart = nullptr;
+  bool have_cert_prob[1] = {false};
+  std::vector<int> cert_done;   // per problem: certificate arrays valid
+  // timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  std::vector<long long> timed_recs;
+};
+
+template <typename T>
+static int dalloc(dduot_handle* h, T** p, size_t count) {
+  if (count == 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, sizeof(T) * count);
+  if (e != hipSuccess) return fail(DDUOT_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  h->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return DDUOT_OK;
+}
+
+#define CHK(x)            \
+  do {                    \
+    int r_ = (x);         \
+    if (r_ != DDUOT_OK) { \
+      return r_;          \
+    }                     \
+  } while (0)
+
+extern "C" void dd_uot_default_config(dduot_config* c) {
+  memset(c, 0, sizeof(*c));
+  c->h = 0.0;
+  c->lambda = 1.0;
+  c->eps = 0.0;
+  c->cell = 4;
+  c->precision = 32;
+  c->getweights = DDUOT_GW_SWIFT;
+  c->init = DDUOT_INIT_BLOCK;
+  c->sinkhorn_err = 2e-5;
+  c->sinkhorn_max_iter = 1000;
+  c->fixed_inner_iters = 0;
+  c->trunc = 1e-15;
+  c->lenience = 0.005;
+  c->box_margin = 2;
+  c->box_cap = 64;
+}
+
+extern "C" const char* dd_uot_last_error(void) { return g_err.c_str(); }
+
+static int validate(const dduot_config* c, const double* mu, const double* nu, int idx) {
+  const std::string pre = "problem " + std::to_string(idx) + ": ";
+  if (!c || !mu || !nu) return fail(DDUOT_EINVAL, pre + "null config or marginal");
+  if (c->n1 <= 0 || c->n2 <= 0) return fail(DDUOT_EINVAL, pre + "grid sides must be positive");
+  if (c->cell < 1 || 2 * c->cell > kMaxTile)
+    return fail(DDUOT_EINVAL, pre + "basic cell side must be in [1, 8]");
+  if (c->n1 % (2 * c->cell) || c->n2 % (2 * c->cell))
+    return fail(DDUOT_EINVAL, pre + "grid sides must be divisible by 2*cell");
+  if (!(c->lambda > 0.0) || !isfinite(c->lambda)) return fail(DDUOT_EINVAL, pre + "lambda must be > 0");
+  if (!(c->eps > 0.0) || !isfinite(c->eps)) return fail(DDUOT_EINVAL, pre + "eps must be > 0");
+  if (!(c->h >= 0.0) || !isfinite(c->h)) return fail(DDUOT_EINVAL, pre + "h must be >= 0");
+  if (c->precision != 32 && c->precision != 64)
+    return fail(DDUOT_EINVAL, pre + "precision must be 32 or 64");
+  if (c->getweights < 0 || c->getweights > 2) return fail(DDUOT_EINVAL, pre + "bad getweights");
+  if (c->init != DDUOT_INIT_BLOCK && c->init != DDUOT_INIT_PRODUCT)
+    return fail(DDUOT_EINVAL, pre + "bad init");
+  if (!(c->sinkhorn_err >= 0.0)) return fail(DDUOT_EINVAL, pre + "sinkhorn_err must be >= 0");
+  if (c->sinkhorn_max_iter < 1) return fail(DDUOT_EINVAL, pre + "sinkhorn_max_iter must be >= 1");
+  if (c->fixed_inner_iters < 0) return fail(DDUOT_EINVAL, pre + "fixed_inner_iters must be >= 0");
+  if (!(c->trunc >= 0.0)) return fail(DDUOT_EINVAL, pre + "trunc must be >= 0");
+  if (!(c->lenience >= 0.0)) return fail(DDUOT_EINVAL, pre + "lenience must be >= 0");
+  if (c->box_margin < 0) return fail(DDUOT_EINVAL, pre + "box_margin must be >= 0");
+  if (c->box_cap < 2 * c->cell || c->box_cap > 128)
+    return fail(DDUOT_EINVAL, pre + "box_cap must be in [2*cell, 128]");
+  if (c->init == DDUOT_INIT_PRODUCT && (c->box_cap < c->n1 || c->box_cap < c->n2))
+    return fail(DDUOT_EINVAL, pre + "product start needs box_cap >= grid side");
+  const long n = (long)c->n1 * c->n2;
+  for (long i = 0; i < n; ++i) {
+    if (!(mu[i] > 0.0) || !isfinite(mu[i]) || !(nu[i] > 0.0) || !isfinite(nu[i]))
+      return fail(DDUOT_EINVAL, pre + "masses must be finite and > 0 (full support)");
+  }
+  return DDUOT_OK;
+}
+
+// groups of basic indices along one axis: pairs from 0 (A) or offset pairs (B)
+static std::vector<std::vector<int>> axis_groups(int nb, bool offset) {
+  std::vector<std::vector<int>> g;
+  if (!offset) {
+    for (int a = 0; a < nb / 2; ++a) g.push_back({2 * a, 2 * a + 1});
+  } else {
+    for (int c = 0; c < nb / 2 + 1; ++c) {
+      std::vector<int> v;
+      for (int b : {2 * c - 1, 2 * c})
+        if (b >= 0 && b < nb) v.push_back(b);
+      g.push_back(v);
+    }
+  }
+  return g;
+}
+
+static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const double* const* mus,
+                 const double* const* nus) {
+  for (int k = 0; k < nprob; ++k) CHK(validate(&cfgs[k], mus[k], nus[k], k));
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  int max_lds = 0;
+  HIPCHK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  h->nprob = nprob;
+  h->precision = cfgs[0].precision;
+  h->cap = 0;
+  for (int k = 0; k < nprob; ++k) {
+    if (cfgs[k].precision != h->precision)
+      return fail(DDUOT_EINVAL, "all problems of a handle must share one precision");
+    h->cap = std::max(h->cap, cfgs[k].box_cap);
+  }
+  h->cap2 = (long)h->cap * h->cap;
+  const size_t lds_cell = cell_lds_bytes(h->cap, h->precision);
+  const size_t lds_mix = sizeof(double) * h->cap2;
+  if ((long)lds_cell > max_lds || (long)lds_mix > max_lds)
+    return fail(DDUOT_EINVAL, "box_cap too large for the LDS of one workgroup");
+  HIPCHK(set_cell_lds_limit(lds_cell));
+  HIPCHK(set_mix_lds_limit(lds_mix));
+
+  // problems, basic cells, composite cells
+  std::vector<int> basic_prob;
+  std::vector<int2> basic_xy;
+  std::vector<Cell> cellsA, cellsB;
+  std::vector<int> chunk_prob, chunk_start, chunk_len;
+  long goff = 0;
+  for (int k = 0; k < nprob; ++k) {
+    const dduot_config& c = cfgs[k];
+    Prob p{};
+    p.n1 = c.n1; p.n2 = c.n2; p.s = c.cell;
+    p.nb1 = c.n1 / c.cell; p.nb2 = c.n2 / c.cell;
+    p.h = c.h; p.eps = c.eps; p.lam = c.lambda;
+    p.kappa = c.lambda / (c.lambda + c.eps);
+    p.K = c.lambda / c.eps;
+    p.ch = c.h * c.h / c.eps;
+    p.err = c.sinkhorn_err; p.trunc = c.trunc; p.lenience = c.lenience;
+    p.getweights = c.getweights; p.fixed_iters = c.fixed_inner_iters; p.max_iter = c.sinkhorn_max_iter;
+    p.margin = c.box_margin; p.cap = c.box_cap; p.precision = c.precision;
+    p.grid_off = (int)goff;
+    p.basic_off = (int)basic_prob.size();
+    p.nbasic = p.nb1 * p.nb2;
+    const long n = (long)c.n1 * c.n2;
+    double mm = 0.0, mn = 0.0;
+    for (long i = 0; i < n; ++i) { mm += mus[k][i]; mn += nus[k][i]; }
+    p.mass_mu = mm; p.mass_nu = mn;
+    for (int b1 = 0; b1 < p.nb1; ++b1)
+      for (int b2 = 0; b2 < p.nb2; ++b2) {
+        basic_prob.push_back(k);
+        basic_xy.push_back(make_int2(b1 * p.s, b2 * p.s));
+      }
+    for (int part = 0; part < 2; ++part) {
+      auto g1 = axis_groups(p.nb1, part == 1), g2 = axis_groups(p.nb2, part == 1);
+      auto& out = part == 0 ? cellsA : cellsB;
+      p.cell_off[part] = (int)out.size();   // fixed up below for B
+      for (auto& r : g1)
+        for (auto& cc : g2) {
+          Cell C{};
+          C.prob = k;
+          C.nb = 0;
+          for (int b1 : r)
+            for (int b2 : cc) C.basic[C.nb++] = p.basic_off + b1 * p.nb2 + b2;
+          C.x1 = r[0] * p.s; C.x2 = cc[0] * p.s;
+          C.lx1 = (int)r.size() * p.s; C.lx2 = (int)cc.size() * p.s;
+          out.push_back(C);
+        }
+      p.ncell[part] = (int)out.size() - p.cell_off[part];
+    }
+    p.chunk_off = (int)chunk_prob.size();
+    for (long s0 = 0; s0 < n; s0 += kChunk) {
+      chunk_prob.push_back(k);
+      chunk_start.push_back((int)s0);
+      chunk_len.push_back((int)std::min<long>(kChunk, n - s0));
+    }
+    p.nchunk = (int)chunk_prob.size() - p.chunk_off;
+    h->probs.push_back(p);
+    goff += n;
+    h->maxgrid = std::max(h->maxgrid, n);
+  }
+  h->ngrid = goff;
+  h->ncell[0] = (int)cellsA.size();
+  h->ncell[1] = (int)cellsB.size();
+  for (auto& p : h->probs) p.cell_off[1] += h->ncell[0];
+  h->cells = cellsA;
+  h->cells.insert(h->cells.end(), cellsB.begin(), cellsB.end());
+  h->nbasic = (int)basic_prob.size();
+  h->nchunk = (int)chunk_prob.size();
+  std::vector<int> bcell[2];
+  for (int part = 0; part < 2; ++part) {
+    bcell[part].assign(h->nbasic, -1);
+    const int base = part == 0 ? 0 : h->ncell[0];
+    for (int c = 0; c < h->ncell[part]; ++c) {
+      const Cell& C = h->cells[base + c];
+      for (int q = 0; q < C.nb; ++q) bcell[part][C.basic[q]] = base + c;
+    }
+  }
+
+  // host start state (Sec. 4.2 product start, or the block start)
+  std::vector<double> mu_all(h->ngrid), nu_all(h->ngrid), px(h->ngrid), hbar(h->nbasic);
+  std::vector<Box> box(h->nbasic);
+  for (int k = 0; k < nprob; ++k) {
+    const Prob& p = h->probs[k];
+    const long n = (long)p.n1 * p.n2;
+    std::copy(mus[k], mus[k] + n, mu_all.begin() + p.grid_off);
+    std::copy(nus[k], nus[k] + n, nu_all.begin() + p.grid_off);
+    const double* mu = mus[k];
+    const double* nu = nus[k];
+    const double h2 = p.h * p.h;
+    // moments of nu over the whole grid (product start)
+    double N0 = 0, N1a = 0, N1b = 0, N2 = 0;
+    if (cfgs[k].init == DDUOT_INIT_PRODUCT) {
+      for (int i1 = 0; i1 < p.n1; ++i1)
+        for (int i2 = 0; i2 < p.n2; ++i2) {
+          const double v = nu[(long)i1 * p.n2 + i2];
+          N0 += v; N1a += v * i1; N1b += v * i2; N2 += v * ((double)i1 * i1 + (double)i2 * i2);
+        }
+    }
+    for (int b = 0; b < p.nbasic; ++b) {
+      const int gb = p.basic_off + b;
+      const int x1 = basic_xy[gb].x, x2 = basic_xy[gb].y;
+      // block moments (local coordinates) of mu and nu
+      double m0 = 0, m1a = 0, m1b = 0, m2 = 0, v0 = 0, v1a = 0, v1b = 0, v2 = 0;
+      double g1 = 0, g1b = 0, g2 = 0;   // global-coordinate moments of mu (product start)
+      for (int i1 = 0; i1 < p.s; ++i1)
+        for (int i2 = 0; i2 < p.s; ++i2) {
+          const long g = (long)(x1 + i1) * p.n2 + (x2 + i2);
+          const double m = mu[g], v = nu[g];
+          m0 += m; m1a += m * i1; m1b += m * i2; m2 += m * ((double)i1 * i1 + (double)i2 * i2);
+          v0 += v; v1a += v * i1; v1b += v * i2; v2 += v * ((double)i1 * i1 + (double)i2 * i2);
+          const double a1 = x1 + i1, a2 = x2 + i2;
+          g1 += m * a1; g1b += m * a2; g2 += m * (a1 * a1 + a2 * a2);
+        }
+      if (cfgs[k].init == DDUOT_INIT_BLOCK) {
+        // pi_i = mu_i x (nu on X_i) / |mu_i|
+        const double cost = h2 * (v0 * m2 + m0 * v2 - 2.0 * (m1a * v1a + m1b * v1b)) / m0;
+        const double t = v0 / m0;
+        hbar[gb] = cost + p.eps * (v0 * (-log(m0) - 1.0) + m0 * p.mass_nu) +
+                   p.lam * m0 * (t * log(t) - t + 1.0);
+        box[gb] = Box{x1, x2, p.s, p.s};
+        for (int i1 = 0; i1 < p.s; ++i1)
+          for (int i2 = 0; i2 < p.s; ++i2) {
+            const long g = (long)(x1 + i1) * p.n2 + (x2 + i2);
+            px[p.grid_off + g] = mu[g] * t;
+          }
+      } else {
+        // pi = mu x nu: nu_i = |mu_i| nu, P_X = |nu| mu
+        const double cost = h2 * (N0 * g2 + m0 * N2 - 2.0 * (g1 * N1a + g1b * N1b));
+        const double t = p.mass_nu;
+        hbar[gb] = cost + p.lam * m0 * (t * log(t) - t + 1.0);
+        box[gb] = Box{0, 0, p.n1, p.n2};
+        for (int i1 = 0; i1 < p.s; ++i1)
+          for (int i2 = 0; i2 < p.s; ++i2) {
+            const long g = (long)(x1 + i1) * p.n2 + (x2 + i2);
+            px[p.grid_off + g] = mu[g] * t;
+          }
+      }
+    }
+  }
+
+  // device buffers
+  CHK(dalloc(h, &h->d_probs, nprob));
+  CHK(dalloc(h, &h->d_cells, h->cells.size()));
+  CHK(dalloc(h, &h->d_basic_prob, h->nbasic));
+  CHK(dalloc(h, &h->d_basic_xy, h->nbasic));
+  CHK(dalloc(h, &h->d_basic_cell[0], h->nbasic));
+  CHK(dalloc(h, &h->d_basic_cell[1], h->nbasic));
+  CHK(dalloc(h, &h->d_mu, h->ngrid));
+  CHK(dalloc(h, &h->d_nu, h->ngrid));
+  CHK(dalloc(h, &h->d_P, h->ngrid));
+  CHK(dalloc(h, &h->d_Pg, h->ngrid));
+  CHK(dalloc(h, &h->d_px, h->ngrid));
+  CHK(dalloc(h, &h->d_pxc, h->ngrid));
+  CHK(dalloc(h, &h->d_abar, h->ngrid));
+  CHK(dalloc(h, &h->d_box, h->nbasic));
+  CHK(dalloc(h, &h->d_cbox, h->nbasic));
+  CHK(dalloc(h, &h->d_vals, (size_t)h->nbasic * h->cap2));
+  CHK(dalloc(h, &h->d_cand, (size_t)h->nbasic * h->cap2));
+  CHK(dalloc(h, &h->d_hbar, h->nbasic));
+  CHK(dalloc(h, &h->d_htil, h->nbasic));
+  CHK(dalloc(h, &h->d_iters, h->cells.size()));
+  CHK(dalloc(h, &h->d_conv, h->cells.size()));
+  CHK(dalloc(h, &h->d_bytes, h->cells.size()));
+  CHK(dalloc(h, &h->d_terms, h->cells.size()));
+  CHK(dalloc(h, &h->d_chunk_prob, h->nchunk));
+  CHK(dalloc(h, &h->d_chunk_start, h->nchunk));
+  CHK(dalloc(h, &h->d_chunk_len, h->nchunk));
+  CHK(dalloc(h, &h->d_chunk_part, 2 * (size_t)h->nchunk));
+  CHK(dalloc(h, &h->d_theta, nprob));
+  CHK(dalloc(h, &h->d_hist, (size_t)nprob * h->hist_cap * kHistFields));
+  CHK(dalloc(h, &h->d_overflow, nprob));
+  CHK(dalloc(h, &h->d_force, nprob));
+  CHK(dalloc(h, &h->d_bhat, h->ngrid));
+  CHK(dalloc(h, &h->d_dmu, h->ngrid));
+  CHK(dalloc(h, &h->d_dnu, h->ngrid));
+  CHK(dalloc(h, &h->d_scratch, 5 * (size_t)h->maxgrid));
+  CHK(dalloc(h, &h->d_cpart, (size_t)kCertBlocks * 8));
+  h->cert_done.assign(nprob, 0);
+
+  hipStream_t st = h->stream;
+  HIPCHK(hipMemcpyAsync(h->d_probs, h->probs.data(), sizeof(Prob) * nprob, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_cells, h->cells.data(), sizeof(Cell) * h->cells.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_basic_prob, basic_prob.data(), sizeof(int) * h->nbasic, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_basic_xy, basic_xy.data(), sizeof(int2) * h->nbasic, hipMemcpyHostToDevice, st));
+  for (int part = 0; part < 2; ++part)
+    HIPCHK(hipMemcpyAsync(h->d_basic_cell[part], bcell[part].data(), sizeof(int) * h->nbasic, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_mu, mu_all.data(), sizeof(double) * h->ngrid, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_nu, nu_all.data(), sizeof(double) * h->ngrid, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_px, px.data(), sizeof(double) * h->ngrid, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_hbar, hbar.data(), sizeof(double) * h->nbasic, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_box, box.data(), sizeof(Box) * h->nbasic, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_chunk_prob, chunk_prob.data(), sizeof(int) * h->nchunk, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_chunk_start, chunk_start.data(), sizeof(int) * h->nchunk, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_chunk_len, chunk_len.data(), sizeof(int) * h->nchunk, hipMemcpyHostToDevice, st));
+  HIPCHK(launch_fill(h->d_abar, h->ngrid, 0.0, st));
+  HIPCHK(launch_fill(h->d_hist, (long)nprob * h->hist_cap * kHistFields, 0.0, st));
+  std::vector<int> zeros(nprob, 0);
+  HIPCHK(hipMemcpyAsync(h->d_overflow, zeros.data(), sizeof(int) * nprob, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_force, zeros.data(), sizeof(int) * nprob, hipMemcpyHostToDevice, st));
+
+  // state slots: block start = nu on the block; product start = |mu_i| nu.
+  // Staged compactly on the host, scattered into the fixed-capacity slots.
+  {
+    std::vector<long> off(h->nbasic + 1, 0);
+    for (int b = 0; b < h->nbasic; ++b) off[b + 1] = off[b] + (long)box[b].l1 * box[b].l2;
+    std::vector<double> stage(off[h->nbasic]);
+    for (int k = 0; k < nprob; ++k) {
+      const Prob& p = h->probs[k];
+      for (int b = 0; b < p.nbasic; ++b) {
+        const int gb = p.basic_off + b;
+        const Box& bx = box[gb];
+        double m0 = 0.0;
+        if (cfgs[k].init == DDUOT_INIT_PRODUCT)
+          for (int i1 = 0; i1 < p.s; ++i1)
+            for (int i2 = 0; i2 < p.s; ++i2)
+              m0 += mus[k][(long)(basic_xy[gb].x + i1) * p.n2 + (basic_xy[gb].y + i2)];
+        double* dst = stage.data() + off[gb];
+        for (int a1 = 0; a1 < bx.l1; ++a1)
+          for (int a2 = 0; a2 < bx.l2; ++a2) {
+            const double v = nus[k][(long)(bx.o1 + a1) * p.n2 + (bx.o2 + a2)];
+            dst[(size_t)a1 * bx.l2 + a2] = cfgs[k].init == DDUOT_INIT_PRODUCT ? m0 * v : v;
+          }
+      }
+    }
+    double* d_stage = nullptr;
+    long* d_off = nullptr;
+    HIPCHK(hipMalloc(&d_stage, sizeof(double) * std::max<size_t>(stage.size(), 1)));
+    HIPCHK(hipMalloc(&d_off, sizeof(long) * off.size()));
+    HIPCHK(hipMemcpyAsync(d_stage, stage.data(), sizeof(double) * stage.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_off, off.data(), sizeof(long) * off.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_scatter_slots(d_stage, d_off, h->d_vals, h->cap2, h->nbasic, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipFree(d_stage));
+    HIPCHK(hipFree(d_off));
+  }
+
+  Dev& d = h->d;
+  d.probs = h->d_probs;
+  d.cells = h->d_cells;
+  d.basic_prob = h->d_basic_prob;
+  d.basic_xy = h->d_basic_xy;
+  d.basic_cell[0] = h->d_basic_cell[0];
+  d.basic_cell[1] = h->d_basic_cell[1];
+  d.mu = h->d_mu;
+  d.nu = h->d_nu;
+  d.P = h->d_P;
+  d.Pg = h->d_Pg;
+  d.px = h->d_px;
+  d.pxc = h->d_pxc;
+  d.abar = h->d_abar;
+  d.box = h->d_box;
+  d.vals = h->d_vals;
+  d.cbox = h->d_cbox;
+  d.cand = h->d_cand;
+  d.hbar = h->d_hbar;
+  d.htil = h->d_htil;
+  d.cell_iters = h->d_iters;
+  d.cell_conv = h->d_conv;
+  d.cell_bytes = h->d_bytes;
+  d.cell_terms = h->d_terms;
+  d.chunk_part = h->d_chunk_part;
+  d.theta = h->d_theta;
+  d.hist = h->d_hist;
+  d.overflow_any = h->d_overflow;
+  d.force_greedy = h->d_force;
+  d.hist_cap = h->hist_cap;
+  d.cap2 = h->cap2;
+  HIPCHK(hipStreamSynchronize(st));
+  return DDUOT_OK;
+}
+
+static void release(dduot_handle* h) {
+  if (!h) return;
+  for (auto& e : h->events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (void* p : h->allocs) (void)hipFree(p);
+  delete h;
+}
+
+extern "C" int dd_uot_init_batch(int32_t nprob, const dduot_config* cfgs, const double* const* mus,
+                                 const double* const* nus, void* hip_stream, dduot_handle** out) {
+  if (!out) return fail(DDUOT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nprob < 1 || !cfgs || !mus || !nus) return fail(DDUOT_EINVAL, "need at least one problem");
+  dduot_handle* h = new dduot_handle();
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  int r = build(h, nprob, cfgs, mus, nus);
+  if (r != DDUOT_OK) {
+    std::string keep = g_err;
+    release(h);
+    g_err = keep;
+    return r;
+  }
+  *out = h;
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_init(const dduot_config* cfg, const double* mu, const double* nu,
+                           void* hip_stream, dduot_handle** out) {
+  return dd_uot_init_batch(1, cfg, &mu, &nu, hip_stream, out);
+}
+
+extern "C" void dd_uot_destroy(dduot_handle* h) {
+  if (h) (void)hipStreamSynchronize(h->stream);
+  release(h);
+}
+
+extern "C" int32_t dd_uot_num_problems(const dduot_handle* h) { return h ? h->nprob : 0; }
+
+extern "C" int dd_uot_synchronize(dduot_handle* h) {
+  if (!h) return fail(DDUOT_EINVAL, "null handle");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_set_eps(dduot_handle* h, int32_t prob, double eps) {
+  if (!h || prob < 0 || prob >= h->nprob) return fail(DDUOT_EINVAL, "bad handle or problem");
+  if (!(eps > 0.0) || !isfinite(eps)) return fail(DDUOT_EINVAL, "eps must be > 0");
+  Prob& p = h->probs[prob];
+  p.eps = eps;
+  p.kappa = p.lam / (p.lam + eps);
+  p.K = p.lam / eps;
+  p.ch = p.h * p.h / eps;
+  HIPCHK(hipMemcpyAsync(h->d_probs + prob, &p, sizeof(Prob), hipMemcpyHostToDevice, h->stream));
+  static const int one = 1;
+  HIPCHK(hipMemcpyAsync(h->d_force + prob, &one, sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->cert_done[prob] = 0;
+  return DDUOT_OK;
+}
+
+// One half-iteration over partition `part` for all problems.
+static int half_iteration(dduot_handle* h, int part) {
+  hipStream_t st = h->stream;
+  const Dev& d = h->d;
+  HIPCHK(launch_fill(h->d_P, h->ngrid, 0.0, st));
+  HIPCHK(launch_aggregate(h->d_box, h->d_vals, h->cap2, h->d_basic_prob, h->d_probs, h->d_P, h->nbasic, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->timing) {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+  }
+  const int base = part == 0 ? 0 : h->ncell[0];
+  HIPCHK(launch_cell_solve(d, base, h->ncell[part], h->cap, h->precision, st));
+  if (h->timing) {
+    HIPCHK(hipEventRecord(e1, st));
+    h->events.push_back({e0, e1});
+    h->timed_recs.push_back(h->k);
+  }
+  HIPCHK(launch_fill(h->d_Pg, h->ngrid, 0.0, st));
+  HIPCHK(launch_aggregate(h->d_cbox, h->d_cand, h->cap2, h->d_basic_prob, h->d_probs, h->d_Pg, h->nbasic, st));
+  HIPCHK(launch_kl_chunks(h->d_chunk_prob, h->d_chunk_start, h->d_chunk_len, h->d_probs, h->d_P,
+                          h->d_Pg, h->d_nu, h->d_chunk_part, h->nchunk, st));
+  HIPCHK(launch_getweights(d, part, (int)(h->k % h->hist_cap), h->nprob, st));
+  HIPCHK(launch_mix(d, part, h->nbasic, h->cap, st));
+  h->k += 1;
+  return DDUOT_OK;
+}
+
+static int read_records(dduot_handle* h, int prob, long long from, long long to, std::vector<double>& out) {
+  out.clear();
+  if (to <= from) return DDUOT_OK;
+  std::vector<double> all((size_t)h->hist_cap * kHistFields);
+  HIPCHK(hipMemcpy(all.data(), h->d_hist + (size_t)prob * h->hist_cap * kHistFields,
+                   sizeof(double) * all.size(), hipMemcpyDeviceToHost));
+  for (long long r = std::max(from, to - h->hist_cap); r < to; ++r) {
+    const double* rec = all.data() + (size_t)(r % h->hist_cap) * kHistFields;
+    out.insert(out.end(), rec, rec + kHistFields);
+  }
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_iterate(dduot_handle* h, int32_t n_half_iters, dduot_iter_stats* stats) {
+  if (!h) return fail(DDUOT_EINVAL, "null handle");
+  if (n_half_iters < 0) return fail(DDUOT_EINVAL, "n_half_iters must be >= 0");
+  const long long k0 = h->k;
+  for (int i = 0; i < n_half_iters; ++i) CHK(half_iteration(h, (int)(h->k % 2)));
+  for (int p = 0; p < h->nprob; ++p) h->cert_done[p] = 0;
+  if (stats) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    memset(stats, 0, sizeof(*stats));
+    stats->half_iters = n_half_iters;
+    std::vector<double> rec;
+    for (int p = 0; p < h->nprob; ++p) {
+      CHK(read_records(h, p, k0, h->k, rec));
+      for (size_t r = 0; r + kHistFields <= rec.size(); r += kHistFields) {
+        const double* x = rec.data() + r;
+        if (x[0] < 1.0) stats->n_safe += 1;
+        stats->n_cells += (int32_t)x[3];
+        stats->point_iters += (int64_t)x[4];
+        stats->max_inner = std::max(stats->max_inner, (int32_t)x[5]);
+        stats->n_unconverged += (int32_t)x[6];
+        stats->n_overflow += (int32_t)x[7];
+        stats->inner_iters += (int64_t)x[8];
+      }
+    }
+  }
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_history(dduot_handle* h, int32_t prob, int32_t max, double* out) {
+  if (!h || prob < 0 || prob >= h->nprob || max < 0 || (!out && max > 0))
+    return fail(DDUOT_EINVAL, "bad arguments");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  std::vector<double> rec;
+  CHK(read_records(h, prob, 0, h->k, rec));
+  const int n = (int)(rec.size() / kHistFields);
+  const int m = std::min(n, (int)max);
+  std::copy(rec.begin(), rec.begin() + (size_t)m * kHistFields, out);
+  return m;
+}
+
+// Re-aggregate the current state into d_P (the state Y-marginal).
+static int refresh_state_marginal(dduot_handle* h) {
+  HIPCHK(launch_fill(h->d_P, h->ngrid, 0.0, h->stream));
+  HIPCHK(launch_aggregate(h->d_box, h->d_vals, h->cap2, h->d_basic_prob, h->d_probs, h->d_P, h->nbasic,
+                          h->stream));
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_score(dduot_handle* h, int32_t prob, dduot_score* out) {
+  if (!h || !out || prob < 0 || prob >= h->nprob) return fail(DDUOT_EINVAL, "bad arguments");
+  const Prob& p = h->probs[prob];
+  hipStream_t st = h->stream;
+  CHK(refresh_state_marginal(h));
+  HIPCHK(launch_kl_chunks(h->d_chunk_prob, h->d_chunk_start, h->d_chunk_len, h->d_probs, h->d_P,
+                          h->d_P, h->d_nu, h->d_chunk_part, h->nchunk, st));
+  const long g = p.grid_off;
+  const long n = (long)p.n1 * p.n2;
+  const size_t rows = sizeof(double) * std::max(p.n1, p.n2);
+  HIPCHK(set_rows_lds_limit(std::max<size_t>(rows, 1024)));
+  HIPCHK(launch_certificate(p, h->d_abar + g, h->d_mu + g, h->d_nu + g, h->d_px + g, h->d_P + g,
+                            h->d_bhat + g, h->d_dmu + g, h->d_dnu + g, h->d_scratch, h->d_cpart,
+                            kCertBlocks, st));
+  std::vector<double> part((size_t)kCertBlocks * 8), chunks(2 * (size_t)h->nchunk), hb(p.nbasic);
+  HIPCHK(hipMemcpyAsync(part.data(), h->d_cpart, sizeof(double) * part.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(chunks.data(), h->d_chunk_part, sizeof(double) * chunks.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hb.data(), h->d_hbar + p.basic_off, sizeof(double) * p.nbasic, hipMemcpyDeviceToHost, st));
+  int ovf = 0;
+  HIPCHK(hipMemcpyAsync(&ovf, h->d_overflow + prob, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < kCertBlocks; ++b)
+    for (int k = 0; k < 8; ++k) s[k] += part[(size_t)b * 8 + k];
+  double klp = 0.0;
+  for (int c = 0; c < p.nchunk; ++c) klp += chunks[2 * (size_t)(p.chunk_off + c)];
+  double hs = 0.0;
+  for (double v : hb) hs += v;
+  const double pd = p.lam * s[0];
+  const double dual = p.eps * (p.mass_mu * p.mass_nu - s[1]) - s[2] - s[3];
+  out->tracked = hs + p.lam * klp;
+  out->pd_gap = pd;
+  out->dual = dual;
+  out->primal = dual + pd;
+  out->rel_pd_gap = pd / dual;
+  out->l1_err_x = s[4];
+  out->l1_err_y = s[5];
+  out->mass_x = s[6];
+  out->mass_y = s[7];
+  out->half_iters = h->k;
+  out->overflow = ovf;
+  h->cert_done[prob] = 1;
+  (void)n;
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_marginals(dduot_handle* h, int32_t prob, double* px, double* py) {
+  if (!h || prob < 0 || prob >= h->nprob) return fail(DDUOT_EINVAL, "bad arguments");
+  const Prob& p = h->probs[prob];
+  const long n = (long)p.n1 * p.n2;
+  CHK(refresh_state_marginal(h));
+  if (px) HIPCHK(hipMemcpyAsync(px, h->d_px + p.grid_off, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+  if (py) HIPCHK(hipMemcpyAsync(py, h->d_P + p.grid_off, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_basic_marginal(dduot_handle* h, int32_t prob, int32_t basic, int32_t box[4],
+                                     double* values, int64_t cap) {
+  if (!h || !box || prob < 0 || prob >= h->nprob) return fail(DDUOT_EINVAL, "bad arguments");
+  const Prob& p = h->probs[prob];
+  if (basic < 0 || basic >= p.nbasic) return fail(DDUOT_EINVAL, "basic cell out of range");
+  const int gb = p.basic_off + basic;
+  Box b;
+  HIPCHK(hipMemcpyAsync(&b, h->d_box + gb, sizeof(Box), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  box[0] = b.o1; box[1] = b.o2; box[2] = b.l1; box[3] = b.l2;
+  const int64_t n = (int64_t)b.l1 * b.l2;
+  if (n > cap) return fail(DDUOT_EINVAL, "values buffer too small");
+  if (n > 0 && values) {
+    HIPCHK(hipMemcpyAsync(values, h->d_vals + (size_t)gb * h->cap2, sizeof(double) * n,
+                          hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_potentials(dduot_handle* h, int32_t prob, double* alpha, double* beta_hat) {
+  if (!h || prob < 0 || prob >= h->nprob) return fail(DDUOT_EINVAL, "bad arguments");
+  const Prob& p = h->probs[prob];
+  const long n = (long)p.n1 * p.n2;
+  if (beta_hat && !h->cert_done[prob]) return fail(DDUOT_ESTATE, "beta_hat needs dd_uot_score first");
+  if (alpha) HIPCHK(hipMemcpyAsync(alpha, h->d_abar + p.grid_off, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+  if (beta_hat) HIPCHK(hipMemcpyAsync(beta_hat, h->d_bhat + p.grid_off, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_backward(dduot_handle* h, int32_t prob, double gout, double* dmu, double* dnu) {
+  if (!h || prob < 0 || prob >= h->nprob) return fail(DDUOT_EINVAL, "bad arguments");
+  if (!h->cert_done[prob]) return fail(DDUOT_ESTATE, "call dd_uot_score before dd_uot_backward");
+  const Prob& p = h->probs[prob];
+  const long n = (long)p.n1 * p.n2;
+  std::vector<double> tmp;
+  if (dmu) {
+    HIPCHK(hipMemcpyAsync(dmu, h->d_dmu + p.grid_off, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+  }
+  if (dnu) {
+    HIPCHK(hipMemcpyAsync(dnu, h->d_dnu + p.grid_off, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (gout != 1.0) {
+    for (long i = 0; dmu && i < n; ++i) dmu[i] *= gout;
+    for (long i = 0; dnu && i < n; ++i) dnu[i] *= gout;
+  }
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_set_timing(dduot_handle* h, int32_t enable) {
+  if (!h) return fail(DDUOT_EINVAL, "null handle");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (auto& e : h->events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  h->events.clear();
+  h->timed_recs.clear();
+  h->timing = enable != 0;
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_kernel_time(dduot_handle* h, int64_t* launches, double* total_ms, double* algo_bytes) {
+  if (!h) return fail(DDUOT_EINVAL, "null handle");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  double ms = 0.0;
+  for (auto& e : h->events) {
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, e.first, e.second));
+    ms += t;
+  }
+  double bytes = 0.0;
+  for (int p = 0; p < h->nprob; ++p) {
+    std::vector<double> all((size_t)h->hist_cap * kHistFields);
+    HIPCHK(hipMemcpy(all.data(), h->d_hist + (size_t)p * h->hist_cap * kHistFields,
+                     sizeof(double) * all.size(), hipMemcpyDeviceToHost));
+    for (long long r : h->timed_recs) bytes += all[(size_t)(r % h->hist_cap) * kHistFields + 9];
+  }
+  if (launches) *launches = (int64_t)h->events.size();
+  if (total_ms) *total_ms = ms;
+  if (algo_bytes) *algo_bytes = bytes;
+  return DDUOT_OK;
+}

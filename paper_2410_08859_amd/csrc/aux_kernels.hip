@@ -1,0 +1,407 @@
+// Kernels around the cell solve: aggregation of basic Y-marginals, the
+// GetWeights decision, the convex-combination update with truncation, and the
+// global primal-dual certificate.
+#include "dd_types.h"
+
+#include <limits.h>
+#include <math.h>
+
+namespace dduot {
+
+__global__ void k_fill(double* p, long n, double v) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// P_Y pi = sum_i nu_i (Sec. 4.1): one workgroup per basic cell scatters its box.
+__global__ __launch_bounds__(kBlock) void k_aggregate(const Box* box, const double* vals, long cap2,
+                                                      const int* basic_prob, const Prob* probs,
+                                                      double* P) {
+  const int b = blockIdx.x;
+  const Box bx = box[b];
+  if (bx.l1 <= 0 || bx.l2 <= 0) return;
+  const Prob& p = probs[basic_prob[b]];
+  const long n = (long)bx.l1 * bx.l2;
+  const double* v = vals + b * cap2;
+  double* out = P + p.grid_off;
+  for (long o = threadIdx.x; o < n; o += kBlock) {
+    const int j1 = (int)(o / bx.l2), j2 = (int)(o - (long)j1 * bx.l2);
+    const double x = v[o];
+    if (x != 0.0) unsafeAtomicAdd(out + (long)(bx.o1 + j1) * p.n2 + (bx.o2 + j2), x);
+  }
+}
+
+__device__ __forceinline__ double kl_term(double p, double q) {
+  return p > 0.0 ? p * (log(p) - log(q)) - p + q : q;
+}
+
+template <int N>
+__device__ __forceinline__ void block_sum_aux(double (&v)[N], double* red) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    v[k] = x;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0)
+    for (int k = 0; k < N; ++k) red[w * N + k] = v[k];
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    double s = 0.0;
+    for (int ww = 0; ww < kBlock / 64; ++ww) s += red[ww * N + k];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// KL(P|nu) and KL(Pg|nu) per reduction chunk (fixed order, deterministic).
+__global__ __launch_bounds__(kBlock) void k_kl_chunks(const int* chunk_prob, const int* chunk_start,
+                                                      const int* chunk_len, const Prob* probs,
+                                                      const double* P, const double* Pg,
+                                                      const double* nu, double* part) {
+  __shared__ double red[4 * 2];
+  const int c = blockIdx.x;
+  const Prob& p = probs[chunk_prob[c]];
+  const long base = p.grid_off + (long)chunk_start[c];
+  double acc[2] = {0.0, 0.0};
+  for (int o = threadIdx.x; o < chunk_len[c]; o += kBlock) {
+    const double q = nu[base + o];
+    acc[0] += kl_term(P[base + o], q);
+    acc[1] += kl_term(Pg[base + o], q);
+  }
+  block_sum_aux<2>(acc, red);
+  if (threadIdx.x == 0) {
+    part[2 * c] = acc[0];
+    part[2 * c + 1] = acc[1];
+  }
+}
+
+// GetWeights (Proposition converging-getweights) with tracked scores:
+// E_cur = sum Hbar + lam KL(P|nu), E_greedy = sum Htil + lam KL(Pg|nu);
+// greedy theta = 1, safe theta = 1/n (n = cells updated), swift = greedy iff
+// E_greedy <= E_cur + lenience |E_cur|.  One workgroup per problem.
+__global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int rec) {
+  __shared__ double red[4 * 9];
+  const int pi = blockIdx.x;
+  const Prob p = d.probs[pi];
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // [0] sum hbar, [1] sum htil, [2] cells updated, [3] point iters, [4] unconverged,
+  // [5] overflow, [6] inner iters, [7] bytes, [8] log-sum-exp terms
+  for (int b = threadIdx.x; b < p.nbasic; b += kBlock) {
+    acc[0] += d.hbar[p.basic_off + b];
+    acc[1] += d.htil[p.basic_off + b];
+  }
+  int maxit = 0;
+  const int c0 = p.cell_off[part], nc = p.ncell[part];
+  for (int c = threadIdx.x; c < nc; c += kBlock) {
+    const int it = d.cell_iters[c0 + c];
+    const Cell C = d.cells[c0 + c];
+    if (it >= 0) {
+      acc[2] += 1.0;
+      acc[3] += (double)it * C.lx1 * C.lx2;
+      acc[4] += d.cell_conv[c0 + c] ? 0.0 : 1.0;
+      acc[6] += it;
+      acc[7] += d.cell_bytes[c0 + c];
+      acc[8] += d.cell_terms[c0 + c];
+      maxit = max(maxit, it);
+    } else {
+      acc[5] += 1.0;
+    }
+  }
+  block_sum_aux<9>(acc, red);
+  __shared__ int mred[4];
+  for (int o = 32; o > 0; o >>= 1) maxit = max(maxit, __shfl_down(maxit, o, 64));
+  if ((threadIdx.x & 63) == 0) mred[threadIdx.x >> 6] = maxit;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    maxit = max(max(mred[0], mred[1]), max(mred[2], mred[3]));
+    double kp = 0.0, kg = 0.0;
+    for (int c = 0; c < p.nchunk; ++c) {
+      kp += d.chunk_part[2 * (p.chunk_off + c)];
+      kg += d.chunk_part[2 * (p.chunk_off + c) + 1];
+    }
+    const double ecur = acc[0] + p.lam * kp;
+    const double egr = acc[1] + p.lam * kg;
+    const double n = acc[2] > 0.0 ? acc[2] : 1.0;
+    double th;
+    if (d.force_greedy[pi] || p.getweights == 0) th = 1.0;
+    else if (p.getweights == 1) th = 1.0 / n;
+    else th = (egr <= ecur + p.lenience * fabs(ecur)) ? 1.0 : 1.0 / n;
+    d.force_greedy[pi] = 0;
+    d.theta[pi] = th;
+    double* r = d.hist + ((long)pi * d.hist_cap + (rec % d.hist_cap)) * kHistFields;
+    r[0] = th;
+    r[1] = ecur;
+    r[2] = egr;
+    r[3] = acc[2];
+    r[4] = acc[3];
+    r[5] = (double)maxit;
+    r[6] = acc[4];
+    r[7] = acc[5];
+    r[8] = acc[6];
+    r[9] = acc[7];
+    r[10] = acc[8];
+  }
+}
+
+// Algorithm 4 update: nu_i <- (1 - theta) nu_i + theta nu~_i on the cell box,
+// truncation below `trunc`, shrink to the bbox of the nonzeros; the tracked
+// piece and the X-marginal are mixed with the same weight.
+__global__ __launch_bounds__(kBlock) void k_mix(Dev d, int part) {
+  extern __shared__ __align__(16) double vbuf[];
+  __shared__ int ired[4 * 4];
+  const int b = blockIdx.x;
+  const int pi = d.basic_prob[b];
+  const Prob& p = d.probs[pi];
+  const int J = d.basic_cell[part][b];
+  if (d.cell_iters[J] < 0) return;
+  const double th = d.theta[pi];
+  const Box cb = d.cbox[b];
+  const Box ob = d.box[b];
+  const long n = (long)cb.l1 * cb.l2;
+  const double* cv = d.cand + b * d.cap2;
+  double* sv = d.vals + b * d.cap2;
+  int lo1 = INT_MAX, lo2 = INT_MAX, hi1 = INT_MIN, hi2 = INT_MIN;
+  for (long o = threadIdx.x; o < n; o += kBlock) {
+    const int j1 = (int)(o / cb.l2), j2 = (int)(o - (long)j1 * cb.l2);
+    double v = cv[o];
+    if (th != 1.0) {
+      const int a1 = cb.o1 + j1 - ob.o1, a2 = cb.o2 + j2 - ob.o2;
+      double old = 0.0;
+      if (a1 >= 0 && a1 < ob.l1 && a2 >= 0 && a2 < ob.l2) old = sv[(long)a1 * ob.l2 + a2];
+      v = (1.0 - th) * old + th * v;
+    }
+    if (v < p.trunc) v = 0.0;
+    vbuf[o] = v;
+    if (v > 0.0) {
+      lo1 = min(lo1, j1); hi1 = max(hi1, j1 + 1);
+      lo2 = min(lo2, j2); hi2 = max(hi2, j2 + 1);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo1 = min(lo1, __shfl_down(lo1, o, 64));
+    lo2 = min(lo2, __shfl_down(lo2, o, 64));
+    hi1 = max(hi1, __shfl_down(hi1, o, 64));
+    hi2 = max(hi2, __shfl_down(hi2, o, 64));
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    ired[w * 4 + 0] = lo1; ired[w * 4 + 1] = lo2; ired[w * 4 + 2] = hi1; ired[w * 4 + 3] = hi2;
+  }
+  __syncthreads();
+  lo1 = INT_MAX; lo2 = INT_MAX; hi1 = INT_MIN; hi2 = INT_MIN;
+  for (int ww = 0; ww < kBlock / 64; ++ww) {
+    lo1 = min(lo1, ired[ww * 4 + 0]); lo2 = min(lo2, ired[ww * 4 + 1]);
+    hi1 = max(hi1, ired[ww * 4 + 2]); hi2 = max(hi2, ired[ww * 4 + 3]);
+  }
+  Box nb;
+  if (lo1 == INT_MAX) {
+    nb.o1 = cb.o1; nb.o2 = cb.o2; nb.l1 = 0; nb.l2 = 0;
+  } else {
+    nb.o1 = cb.o1 + lo1; nb.o2 = cb.o2 + lo2; nb.l1 = hi1 - lo1; nb.l2 = hi2 - lo2;
+  }
+  const long nn = (long)nb.l1 * nb.l2;
+  for (long o = threadIdx.x; o < nn; o += kBlock) {
+    const int a1 = (int)(o / nb.l2), a2 = (int)(o - (long)a1 * nb.l2);
+    sv[o] = vbuf[(long)(a1 + lo1) * cb.l2 + (a2 + lo2)];
+  }
+  if (threadIdx.x == 0) {
+    d.box[b] = nb;
+    d.hbar[b] = (1.0 - th) * d.hbar[b] + th * d.htil[b];
+  }
+  const int2 xy = d.basic_xy[b];
+  for (int o = threadIdx.x; o < p.s * p.s; o += kBlock) {
+    const int i1 = o / p.s, i2 = o - i1 * p.s;
+    const long g = p.grid_off + (long)(xy.x + i1) * p.n2 + (xy.y + i2);
+    d.px[g] = th == 1.0 ? d.pxc[g] : (1.0 - th) * d.px[g] + th * d.pxc[g];
+  }
+}
+
+// ---- certificate: separable global log-sum-exp on one problem's grid --------
+// out[r, k] = LSE_c in[r, c] - ch (c - k)^2, one workgroup per row r.
+__global__ __launch_bounds__(kBlock) void k_lse_rows(const double* in, double* out, int n2, double ch) {
+  extern __shared__ __align__(16) double row[];
+  const int r = blockIdx.x;
+  for (int c = threadIdx.x; c < n2; c += kBlock) row[c] = in[(long)r * n2 + c];
+  __syncthreads();
+  for (int k = threadIdx.x; k < n2; k += kBlock) {
+    double m = -INFINITY;
+    for (int c = 0; c < n2; ++c) {
+      const double dd = double(c - k);
+      const double t = row[c] - ch * dd * dd;
+      m = t > m ? t : m;
+    }
+    double s = 0.0;
+    for (int c = 0; c < n2; ++c) {
+      const double dd = double(c - k);
+      s += exp(row[c] - ch * dd * dd - m);
+    }
+    out[(long)r * n2 + k] = m + log(s);
+  }
+}
+
+__global__ void k_transpose(const double* in, double* out, int n1, int n2) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
+    const int r = by + j, c = bx + threadIdx.x;
+    if (r < n1 && c < n2) tile[j][threadIdx.x] = in[(long)r * n2 + c];
+  }
+  __syncthreads();
+  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
+    const int c = bx + j, r = by + threadIdx.x;
+    if (r < n1 && c < n2) out[(long)c * n1 + r] = tile[threadIdx.x][j];
+  }
+}
+
+// a(x) = alpha(x)/eps + log mu(x)
+__global__ void k_prep_alpha(const double* alpha, const double* mu, double* a, long n, double inv_eps) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    a[i] = alpha[i] * inv_eps + log(mu[i]);
+}
+
+// beta_hat = -eps kappa z ; b(y) = beta_hat/eps + log nu(y)
+__global__ void k_prep_beta(const double* z, const double* nu, double* bhat, double* b, long n,
+                            double eps, double kappa) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    bhat[i] = -eps * kappa * z[i];
+    b[i] = bhat[i] / eps + log(nu[i]);
+  }
+}
+
+// Per-point certificate terms and gradients.  Partial sums per workgroup:
+// [0] PD/lam terms, [1] |pi_hat|, [2] sum lam (e^{-a/lam} - 1) mu,
+// [3] sum lam (e^{-b/lam} - 1) nu, [4] l1 X error (state), [5] l1 Y error (state),
+// [6] |P_X pi| (state), [7] |P_Y pi| (state)
+__global__ __launch_bounds__(kBlock) void k_cert_terms(const double* alpha, const double* bhat,
+                                                       const double* S, const double* z,
+                                                       const double* mu, const double* nu,
+                                                       const double* px, const double* P, long n,
+                                                       double eps, double lam, double mass_mu,
+                                                       double mass_nu, double* dmu, double* dnu,
+                                                       double* part) {
+  __shared__ double red[4 * 8];
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long i = blockIdx.x * (long)kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+    const double a = alpha[i], m = mu[i];
+    const double lp = a / eps + S[i];
+    const double pxh = m * exp(lp);
+    const double aol = a / lam;
+    const double ea = exp(-aol);
+    acc[0] += pxh * (lp + aol) - pxh + m * ea;
+    acc[1] += pxh;
+    acc[2] += lam * (ea - 1.0) * m;
+    const double b = bhat[i], v = nu[i];
+    const double eb = exp(-b / lam);
+    const double pyh = v * exp(b / eps + z[i]);
+    acc[3] += lam * (eb - 1.0) * v;
+    acc[4] += fabs(px[i] - ea * m);
+    acc[5] += fabs(P[i] - eb * v);
+    acc[6] += px[i];
+    acc[7] += P[i];
+    dmu[i] = eps * mass_nu - eps * pxh / m - lam * (ea - 1.0);
+    dnu[i] = eps * mass_mu - eps * pyh / v - lam * (eb - 1.0);
+  }
+  block_sum_aux<8>(acc, red);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 8; ++k) part[blockIdx.x * 8 + k] = acc[k];
+}
+
+// Copy compactly staged slot contents into the fixed-capacity slots.
+__global__ void k_scatter_slots(const double* src, const long* off, double* vals, long cap2) {
+  const int b = blockIdx.x;
+  const long n = off[b + 1] - off[b];
+  for (long o = threadIdx.x; o < n; o += blockDim.x) vals[b * cap2 + o] = src[off[b] + o];
+}
+
+hipError_t launch_scatter_slots(const double* src, const long* off, double* vals, long cap2, int nbasic,
+                                hipStream_t st) {
+  if (nbasic <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_slots, dim3(nbasic), dim3(256), 0, st, src, off, vals, cap2);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_fill(double* p, long n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)min((n + 255) / 256, (long)4096);
+  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_aggregate(const Box* box, const double* vals, long cap2, const int* basic_prob,
+                            const Prob* probs, double* P, int nbasic, hipStream_t st) {
+  if (nbasic <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_aggregate, dim3(nbasic), dim3(kBlock), 0, st, box, vals, cap2, basic_prob,
+                     probs, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_kl_chunks(const int* cp, const int* cs, const int* cl, const Prob* probs,
+                            const double* P, const double* Pg, const double* nu, double* part,
+                            int nchunk, hipStream_t st) {
+  hipLaunchKernelGGL(k_kl_chunks, dim3(nchunk), dim3(kBlock), 0, st, cp, cs, cl, probs, P, Pg, nu,
+                     part);
+  return hipGetLastError();
+}
+
+hipError_t launch_getweights(const Dev& d, int part, int rec, int nprob, hipStream_t st) {
+  hipLaunchKernelGGL(k_getweights, dim3(nprob), dim3(kBlock), 0, st, d, part, rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_mix(const Dev& d, int part, int nbasic, int cap, hipStream_t st) {
+  if (nbasic <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mix, dim3(nbasic), dim3(kBlock), sizeof(double) * (size_t)cap * cap, st, d,
+                     part);
+  return hipGetLastError();
+}
+
+hipError_t set_mix_lds_limit(size_t bytes) {
+  return hipFuncSetAttribute((const void*)k_mix, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+// out = LSE over the grid of in(x) - ch |x - y|^2 (two separable passes).
+static hipError_t gauss_lse2d(const double* in, double* out, double* tmp, int n1, int n2, double ch,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_lse_rows, dim3(n1), dim3(kBlock), sizeof(double) * n2, st, in, tmp, n2, ch);
+  dim3 tb(32, 8);
+  hipLaunchKernelGGL(k_transpose, dim3((n2 + 31) / 32, (n1 + 31) / 32), tb, 0, st, tmp, out, n1, n2);
+  hipLaunchKernelGGL(k_lse_rows, dim3(n2), dim3(kBlock), sizeof(double) * n1, st, out, tmp, n1, ch);
+  hipLaunchKernelGGL(k_transpose, dim3((n1 + 31) / 32, (n2 + 31) / 32), tb, 0, st, tmp, out, n2, n1);
+  return hipGetLastError();
+}
+
+// Certificate of one problem; scratch holds 5 grids.  Partial sums go to part
+// (nblk x 8 doubles).
+hipError_t launch_certificate(const Prob& p, const double* alpha, const double* mu, const double* nu,
+                              const double* px, const double* P, double* bhat, double* dmu,
+                              double* dnu, double* scratch, double* part, int nblk, hipStream_t st) {
+  const long n = (long)p.n1 * p.n2;
+  double* a = scratch;
+  double* z = scratch + n;
+  double* tmp = scratch + 2 * n;
+  double* b = scratch + 3 * n;
+  double* S = scratch + 4 * n;
+  const int eb = (int)min((n + 255) / 256, (long)4096);
+  hipLaunchKernelGGL(k_prep_alpha, dim3(eb), dim3(256), 0, st, alpha, mu, a, n, 1.0 / p.eps);
+  hipError_t e = gauss_lse2d(a, z, tmp, p.n1, p.n2, p.ch, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prep_beta, dim3(eb), dim3(256), 0, st, z, nu, bhat, b, n, p.eps, p.kappa);
+  e = gauss_lse2d(b, S, tmp, p.n1, p.n2, p.ch, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cert_terms, dim3(nblk), dim3(kBlock), 0, st, alpha, bhat, S, z, mu, nu, px, P,
+                     n, p.eps, p.lam, p.mass_mu, p.mass_nu, dmu, dnu, part);
+  return hipGetLastError();
+}
+
+hipError_t set_rows_lds_limit(size_t bytes) {
+  return hipFuncSetAttribute((const void*)k_lse_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+}  // namespace dduot
