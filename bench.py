@@ -122,7 +122,8 @@ def run(args):
                   float(hist[:, 8].sum() / max(hist[:, 3].sum(), 1)),
                   "unconverged_cells": float(hist[:, 6].sum()),
                   "overflow_cells": float(hist[:, 7].sum()),
-                  "safe_steps": int((hist[:, 0] < 1).sum())},
+                  "safe_steps": int((hist[:, 0] < 1).sum()),
+                  "fp64_fallbacks": float(hist[:, 11].sum())},
         "state_after": {"rel_pd_gap": score["rel_pd_gap"], "tracked_score": score["tracked"],
                         "half_iters": score["half_iters"]},
     }

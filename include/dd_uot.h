@@ -71,6 +71,11 @@ typedef struct {
   int32_t box_margin;        /* Y-box of a cell = bbox of its basic boxes
                                 dilated by this margin, clipped to the grid */
   int32_t box_cap;           /* maximal Y-box side (device slot capacity) */
+  int32_t translate;         /* 1: before every Y-half, maximise the cell dual
+                                exactly along (alpha + s, beta - s) (closed
+                                form, removes the slowly contracting constant
+                                mode; not in the paper); 0: the paper's plain
+                                Sinkhorn iteration */
 } dduot_config;
 
 /* Per call of dd_uot_iterate, summed over all problems of the handle. */
@@ -102,7 +107,8 @@ typedef struct {
 } dduot_score;
 
 /* Fill *cfg with the paper's defaults (Err 2e-5, trunc 1e-15, lenience 0.005,
-   swift, FP32, block start, margin 2, cap 64, max 1000 inner iterations). */
+   swift, FP32, block start, margin 2, cap 64, max 1000 inner iterations,
+   translation step on). */
 void dd_uot_default_config(dduot_config* cfg);
 
 /* Create a solver for one problem.  mu, nu: host, n1*n2 each, every entry
@@ -129,10 +135,11 @@ int dd_uot_set_eps(dduot_handle* h, int32_t prob, double eps);
 int dd_uot_iterate(dduot_handle* h, int32_t n_half_iters, dduot_iter_stats* stats);
 
 /* Per half-iteration record of problem `prob`, oldest first, at most `max`
-   records of 11 doubles: theta, tracked score before, tracked score of the
+   records of 12 doubles: theta, tracked score before, tracked score of the
    greedy candidate, cells updated, sum |X_J| * inner iterations, max inner
    iterations, unconverged cells, overflowed cells, inner iterations,
-   algorithmic bytes of the cell solves, log-sum-exp terms of the cell solves.
+   algorithmic bytes of the cell solves, log-sum-exp terms of the cell solves,
+   pass outputs recomputed in FP64 after an underflow.
    Returns the number of records written (>= 0) or an error code.
    Synchronises. */
 int dd_uot_history(dduot_handle* h, int32_t prob, int32_t max, double* out);

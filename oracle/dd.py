@@ -29,6 +29,11 @@ them also fixed in the design notes):
      i.e. the Y optimality condition eq. (optimality-conditions-KL) evaluated
      for the current plan.
   R6 inner loop: X-half, then repeat {Y-half (Newton), X-half, PD check};
+     with `translate`, every Y-half is preceded by the exact maximisation of
+     the cell dual along (alpha + s, beta - s), which has the closed form
+     e^{s/lam} = (R + sqrt(R^2 + 4AB)) / (2B), A = sum e^{-alpha/lam} mu_J,
+     B = sum e^{-beta/lam} nu, R = |nu_{-J}| (a dual ascent step that removes
+     the slowly contracting constant mode; not part of the paper);
      the cell solve ends after a Y-half, the final pair is the alpha used in
      that Y-half and the new beta.  Stop when PD_J / lam <= Err |mu_J|
      (per-cell rule), or after exactly `fixed_iters` Y-halves (parity mode),
@@ -92,6 +97,7 @@ class Options:
     margin: int = 2
     cap: int = 64              # maximal Y-box side
     getweights: str = "swift"  # greedy | safe | swift
+    translate: bool = False    # dual line search along (alpha + s, beta - s)
 
 
 def make_problem(mu, nu, eps, lam, h, s1, s2=None) -> Problem:
@@ -289,6 +295,18 @@ def cell_box(p: Problem, cell, boxes, opt: Options):
     return (out[0][0], out[1][0], out[0][1] - out[0][0], out[1][1] - out[1][0])
 
 
+def translation_shift(alpha, beta, mu_x, nu_y, r_y, lam):
+    """Maximiser s of the cell dual D_J(alpha + s, beta - s | nu_{-J}).  Along
+    this direction the plan is fixed and D changes by
+    -lam (e^{-s/lam} - 1) A - lam (e^{s/lam} - 1) B + s R, whose stationary
+    point solves B w^2 - R w - A = 0 for w = e^{s/lam}."""
+    A = float((np.exp(-alpha / lam) * mu_x).sum())
+    B = float((np.exp(-beta / lam) * nu_y).sum())
+    R = float((r_y * nu_y).sum())
+    w = (R + np.sqrt(R * R + 4.0 * A * B)) / (2.0 * B)
+    return lam * np.log(w)
+
+
 def solve_cell(mu_x, nu_y, r_y, beta0, C, eps, lam, tol, opt: Options):
     """Cell Sinkhorn of Sec. 4.1 (reading R6).
 
@@ -302,6 +320,10 @@ def solve_cell(mu_x, nu_y, r_y, beta0, C, eps, lam, tol, opt: Options):
     it, pd, conv = 0, np.inf, False
     while True:
         it += 1
+        if opt.translate:
+            sh = translation_shift(alpha, beta, mu_x, nu_y, r_y, lam)
+            alpha = alpha + sh
+            beta = beta - sh
         z = uot.y_log_integral(alpha, mu_x, C, eps)
         beta, _ = uot.y_update_root(z, lr, eps, lam)
         alpha_next = uot.x_update(beta, nu_y, C, eps, lam)

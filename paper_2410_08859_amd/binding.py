@@ -17,7 +17,8 @@ OK, EINVAL, ENOMEM, EHIP, ESLOT, ESTATE = 0, -1, -2, -3, -4, -5
 GW_GREEDY, GW_SAFE, GW_SWIFT = 0, 1, 2
 INIT_BLOCK, INIT_PRODUCT = 0, 1
 HIST_FIELDS = ("theta", "e_cur", "e_greedy", "n_updated", "point_iters", "max_inner",
-               "n_unconverged", "n_overflow", "inner_iters", "algo_bytes", "lse_terms")
+               "n_unconverged", "n_overflow", "inner_iters", "algo_bytes", "lse_terms",
+               "fallbacks")
 
 EXPORTED = (
     "dd_uot_default_config", "dd_uot_init", "dd_uot_init_batch", "dd_uot_set_eps",
@@ -39,6 +40,7 @@ class dduot_config(C.Structure):
         ("sinkhorn_max_iter", C.c_int32), ("fixed_inner_iters", C.c_int32),
         ("trunc", C.c_double), ("lenience", C.c_double),
         ("box_margin", C.c_int32), ("box_cap", C.c_int32),
+        ("translate", C.c_int32),
     ]
 
 

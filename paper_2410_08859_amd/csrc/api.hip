@@ -81,6 +81,8 @@ struct dduot_handle {
   int *d_iters = nullptr, *d_conv = nullptr;
   double* d_bytes = nullptr;
   double* d_terms = nullptr;
+  double* d_fall = nullptr;
+  double *d_ws_lnv = nullptr, *d_ws_lrr = nullptr;
   int *d_chunk_prob = nullptr, *d_chunk_start = nullptr, *d_chunk_len = nullptr;
   double* d_chunk_part = nullptr;
   double *d_theta = nullptr, *d_hist = nullptr;
@@ -130,6 +132,7 @@ extern "C" void dd_uot_default_config(dduot_config* c) {
   c->lenience = 0.005;
   c->box_margin = 2;
   c->box_cap = 64;
+  c->translate = 1;
 }
 
 extern "C" const char* dd_uot_last_error(void) { return g_err.c_str(); }
@@ -156,6 +159,7 @@ static int validate(const dduot_config* c, const double* mu, const double* nu, i
   if (!(c->trunc >= 0.0)) return fail(DDUOT_EINVAL, pre + "trunc must be >= 0");
   if (!(c->lenience >= 0.0)) return fail(DDUOT_EINVAL, pre + "lenience must be >= 0");
   if (c->box_margin < 0) return fail(DDUOT_EINVAL, pre + "box_margin must be >= 0");
+  if (c->translate != 0 && c->translate != 1) return fail(DDUOT_EINVAL, pre + "translate must be 0 or 1");
   if (c->box_cap < 2 * c->cell || c->box_cap > 128)
     return fail(DDUOT_EINVAL, pre + "box_cap must be in [2*cell, 128]");
   if (c->init == DDUOT_INIT_PRODUCT && (c->box_cap < c->n1 || c->box_cap < c->n2))
@@ -225,6 +229,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
     p.err = c.sinkhorn_err; p.trunc = c.trunc; p.lenience = c.lenience;
     p.getweights = c.getweights; p.fixed_iters = c.fixed_inner_iters; p.max_iter = c.sinkhorn_max_iter;
     p.margin = c.box_margin; p.cap = c.box_cap; p.precision = c.precision;
+    p.translate = c.translate;
     p.grid_off = (int)goff;
     p.basic_off = (int)basic_prob.size();
     p.nbasic = p.nb1 * p.nb2;
@@ -369,6 +374,9 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_conv, h->cells.size()));
   CHK(dalloc(h, &h->d_bytes, h->cells.size()));
   CHK(dalloc(h, &h->d_terms, h->cells.size()));
+  CHK(dalloc(h, &h->d_fall, h->cells.size()));
+  CHK(dalloc(h, &h->d_ws_lnv, h->cells.size() * (size_t)h->cap2));
+  CHK(dalloc(h, &h->d_ws_lrr, h->cells.size() * (size_t)h->cap2));
   CHK(dalloc(h, &h->d_chunk_prob, h->nchunk));
   CHK(dalloc(h, &h->d_chunk_start, h->nchunk));
   CHK(dalloc(h, &h->d_chunk_len, h->nchunk));
@@ -465,6 +473,9 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   d.cell_conv = h->d_conv;
   d.cell_bytes = h->d_bytes;
   d.cell_terms = h->d_terms;
+  d.cell_fall = h->d_fall;
+  d.ws_lnv = h->d_ws_lnv;
+  d.ws_lrr = h->d_ws_lrr;
   d.chunk_part = h->d_chunk_part;
   d.theta = h->d_theta;
   d.hist = h->d_hist;

@@ -84,10 +84,10 @@ __global__ __launch_bounds__(kBlock) void k_kl_chunks(const int* chunk_prob, con
 // greedy theta = 1, safe theta = 1/n (n = cells updated), swift = greedy iff
 // E_greedy <= E_cur + lenience |E_cur|.  One workgroup per problem.
 __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int rec) {
-  __shared__ double red[4 * 9];
+  __shared__ double red[4 * 10];
   const int pi = blockIdx.x;
   const Prob p = d.probs[pi];
-  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   // [0] sum hbar, [1] sum htil, [2] cells updated, [3] point iters, [4] unconverged,
   // [5] overflow, [6] inner iters, [7] bytes, [8] log-sum-exp terms
   for (int b = threadIdx.x; b < p.nbasic; b += kBlock) {
@@ -106,12 +106,13 @@ __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int rec)
       acc[6] += it;
       acc[7] += d.cell_bytes[c0 + c];
       acc[8] += d.cell_terms[c0 + c];
+      acc[9] += d.cell_fall[c0 + c];
       maxit = max(maxit, it);
     } else {
       acc[5] += 1.0;
     }
   }
-  block_sum_aux<9>(acc, red);
+  block_sum_aux<10>(acc, red);
   __shared__ int mred[4];
   for (int o = 32; o > 0; o >>= 1) maxit = max(maxit, __shfl_down(maxit, o, 64));
   if ((threadIdx.x & 63) == 0) mred[threadIdx.x >> 6] = maxit;
@@ -144,6 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int rec)
     r[8] = acc[6];
     r[9] = acc[7];
     r[10] = acc[8];
+    r[11] = acc[9];
   }
 }
 

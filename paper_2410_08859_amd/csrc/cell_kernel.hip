@@ -14,16 +14,22 @@
 //     basic cells, X-marginal, and the cell-restricted score pieces
 //     H_i = <alpha, P_X> + <beta, nu_i> - eps |nu_i| + eps |mu_i||nu| + lam KL(P_X|mu_i).
 //
-// The cost |x - y|^2 / eps = ch |i - j|^2 is separable, so every log-sum-exp
-// over the X tile (lx1 x lx2) or the Y box (L1 x L2) is done as two 1-D passes
-// over LDS-resident arrays.  Potentials are kept as an FP64 affine base plus a
-// residual array of type R (float or double):
-//     beta/eps  = B0 + p . j + b~(j)        (j: box-local index)
-//     alpha/eps = A0 + g . i + a~(i)        (i: tile-local index)
-// The linear part of the base is folded into the Gaussian kernel by completing
-// the square, p . j - ch |j - D|^2 = -ch |j - D - delta|^2 + p . D + ch |delta|^2
-// with delta = p / (2 ch), so the FP32 passes only see residuals and kernel
-// centres of moderate size while the large affine parts stay in FP64.
+// Numerics.  The potentials live in LDS in FP64 as b(y) = beta/eps + log nu
+// and a(x) = alpha/eps + log mu.  Near the optimum beta/eps ~ -(lam/eps)
+// log(P_Y pi / nu) has magnitude and curvature scaled by lam/eps (~1e6 on
+// fine grids), far beyond what FP32 can hold, so FP32 never sees them.  The
+// cost |x - y|^2/eps = ch |i - j|^2 is separable: each log-sum-exp over the
+// tile (lx1 x lx2) or the box (L1 x L2) is two 1-D passes.  Every pass output
+// is evaluated as
+//     out = s + log sum_k exp(R(base_k - s) - ch (k - c)^2)
+// with an FP64 shift s equal to the same output's value at the previous
+// Sinkhorn iteration (so the sum is O(1)), the subtraction base_k - s in FP64
+// and exp / accumulation in the kernel precision R.  Terms provably below
+// e^-W of the output are skipped (window from the row maximum).  When the sum
+// leaves [e^-60, e^60] (first iteration, large change) the output is
+// recomputed exactly by a max pass and a sum pass.
+// The Newton solve works in R on the log cell share relative to the FP64
+// reference z/(1+K) (the root when nu_{-J} = 0), finished in FP64.
 #include "dd_types.h"
 
 #include <float.h>
@@ -39,14 +45,12 @@ struct M<float> {
   static __device__ __forceinline__ float ex(float x) { return __expf(x); }
   static __device__ __forceinline__ float lg(float x) { return __logf(x); }
   static __device__ __forceinline__ float lg1p(float x) { return log1pf(x); }
-  static __device__ __forceinline__ float ninf() { return -INFINITY; }
 };
 template <>
 struct M<double> {
   static __device__ __forceinline__ double ex(double x) { return exp(x); }
   static __device__ __forceinline__ double lg(double x) { return log(x); }
   static __device__ __forceinline__ double lg1p(double x) { return log1p(x); }
-  static __device__ __forceinline__ double ninf() { return -INFINITY; }
 };
 
 // Sum N doubles over the workgroup in a fixed order (deterministic).
@@ -75,44 +79,142 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
   __syncthreads();
 }
 
-// log-sum-exp over n terms  base[k*stride] - ch (k0 + k - c)^2,  k in [0, n).
+// Y-update, eq. proxdiv-problem, at one point.  With q = -beta/lam,
+// q_ref = z/(1+K) (the root when nu_{-J} = 0), a = log r - q_ref and the unknown
+// v = -K (q - q_ref) (log of the cell's share of P_Y at the point, up to q_ref),
+// the equation reads  G(v) = v + K logaddexp(a, v) = 0;  G is increasing and
+// convex, so Newton from any start converges (a step from the left lands right
+// of the root, from where the iterates decrease monotonically).  v is O(10), so
+// its R rounding is harmless: beta/eps = -K q_ref + v.  In FP32 the root is
+// finished by one FP64 Newton step (K logaddexp amplifies FP32 rounding).
 template <typename R>
-__device__ __forceinline__ R lse_gauss(const R* base, int stride, int n, int k0, R c, R ch) {
-  R m = M<R>::ninf();
-  for (int k = 0; k < n; ++k) {
-    const R d = R(k0 + k) - c;
-    const R t = base[k * stride] - ch * d * d;
-    m = t > m ? t : m;
-  }
-  R s = R(0);
-  for (int k = 0; k < n; ++k) {
-    const R d = R(k0 + k) - c;
-    s += M<R>::ex(base[k * stride] - ch * d * d - m);
-  }
-  return m + M<R>::lg(s);
-}
-
-// Root of F(v) = logaddexp(A, zt + v) + v/K (convex, increasing) by Newton
-// from the upper bound min(-K A, -kappa zt); see eq. proxdiv-problem with
-// beta/eps = v - kappa z_aff and q = -beta/lam = c0 - v/K.
-template <typename R>
-__device__ __forceinline__ R newton_v(R zt, R A, R K, R kappa, R tol, int maxit) {
-  const R invK = R(1) / K;
-  R v = -kappa * zt;
-  const R vb = -K * A;
-  v = vb < v ? vb : v;
+__device__ __forceinline__ double newton_v(double a, double v0, double K, R tol, int maxit) {
+  if (!(a > -INFINITY)) return 0.0;
+  const R aR = R(a), KR = R(K);
+  R v = R(v0);
   for (int it = 0; it < maxit; ++it) {
-    const R w = zt + v;
-    const R mx = A > w ? A : w;
-    const R e = M<R>::ex(-fabs(A - w));
-    const R la = mx + M<R>::lg1p(e);   // logaddexp(A, w); A = -inf gives w
-    const R F = la + v * invK;
-    const R sig = M<R>::ex(w - la);
-    const R dv = F / (sig + invK);
+    R la, sig;
+    if (v >= aR) {
+      const R e = M<R>::ex(aR - v);
+      la = v + M<R>::lg1p(e);
+      sig = R(1) / (R(1) + e);
+    } else {
+      const R e = M<R>::ex(v - aR);
+      la = aR + M<R>::lg1p(e);
+      sig = e / (R(1) + e);
+    }
+    const R dv = (v + KR * la) / (R(1) + KR * sig);
     v -= dv;
     if (!(fabs(dv) > tol * (R(1) + fabs(v)))) break;
   }
-  return v;
+  double vd = (double)v;
+  if (sizeof(R) == 4) {
+    double la, sig;
+    if (vd >= a) {
+      const double e = exp(a - vd);
+      la = vd + log1p(e);
+      sig = 1.0 / (1.0 + e);
+    } else {
+      const double e = exp(vd - a);
+      la = a + log1p(e);
+      sig = e / (1.0 + e);
+    }
+    vd -= (vd + K * la) / (1.0 + K * sig);
+  }
+  return vd;
+}
+
+// One pass output: LSE over k in [k0, k1) of base[k*stride] - ch (k - c)^2.
+// `shift` is an FP64 estimate of the result (have_shift false: none); `bmax`
+// bounds base over [k0, k1) from above (window).  Counts exact recomputations
+// in nfall.
+template <typename R>
+__device__ __forceinline__ double lse_pass(const double* base, int stride, int k0, int k1, double c,
+                                           double ch, bool have_shift, double shift, double bmax,
+                                           double& nfall) {
+  constexpr double W = sizeof(R) == 8 ? 745.0 : 104.0;   // e^-W below the R range
+  if (have_shift) {
+    int a = k0, b = k1;
+    if (ch > 0.0) {
+      const double r2 = (bmax - shift + W) / ch;
+      if (r2 < 0.0) {
+        a = b = k0;   // every term is below e^-W of the shift: recompute
+      } else {
+        const double rr = sqrt(r2);
+        a = max(k0, (int)ceil(c - rr));
+        b = min(k1, (int)floor(c + rr) + 1);
+      }
+    }
+    R acc = R(0);
+    const R cR = R(c), chR = R(ch);
+    for (int k = a; k < b; ++k) {
+      const R d = R(k) - cR;
+      acc += M<R>::ex(R(base[k * stride] - shift) - chR * d * d);
+    }
+    if (acc > R(8.7e-27) && acc < R(1.1e26)) return shift + (double)M<R>::lg(acc);
+  }
+  nfall += 1.0;
+  // exact: max pass in FP64, then sum pass with R exponentials of FP64 differences
+  double m = -INFINITY;
+  for (int k = k0; k < k1; ++k) {
+    const double d = k - c;
+    const double t = base[k * stride] - ch * d * d;
+    m = t > m ? t : m;
+  }
+  if (!(m > -INFINITY)) return m;
+  int a = k0, b = k1;
+  if (ch > 0.0) {
+    const double rr = sqrt((bmax - m + W) / ch);
+    a = max(k0, (int)ceil(c - rr));
+    b = min(k1, (int)floor(c + rr) + 1);
+  }
+  R acc = R(0);
+  for (int k = a; k < b; ++k) {
+    const double d = k - c;
+    acc += M<R>::ex(R(base[k * stride] - ch * d * d - m));
+  }
+  return m + (double)M<R>::lg(acc);
+}
+
+template <typename R>
+struct CellLds {
+  double* bd;    // b(y) = beta/eps + log nu                      [cmax^2]
+  double* zp;    // z(y) of the last Y-half                       [cmax^2]
+  double* Tt;    // X pass 1 output / re-split half 1             [16*cmax]
+  double* Ud;    // Y pass 1 output                               [16*cmax]
+  double* Mr;    // row maxima of b                               [cmax]
+  double* MU;    // column maxima of Ud                           [cmax]
+  double* Mc;    // column maxima of Tt                           [16]
+  double* adr;   // a(x) = alpha/eps + log mu                     [256]
+  double* Ma;    // row maxima of adr                             [16]
+  double* red;   // reductions                                    [4*24]
+};
+
+template <typename R>
+__host__ __device__ inline size_t cell_lds_layout(int cmax, CellLds<R>* L, unsigned char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = (off + bytes + 15) & ~size_t(15);
+    return o;
+  };
+  const size_t n2 = (size_t)cmax * cmax, nt = (size_t)cmax * kMaxTile;
+  size_t o_bd = take(8 * n2), o_zp = take(8 * n2), o_Tt = take(8 * nt), o_Ud = take(8 * nt);
+  size_t o_Mr = take(8 * cmax), o_MU = take(8 * cmax), o_Mc = take(8 * kMaxTile);
+  size_t o_adr = take(8 * kBlock), o_Ma = take(8 * kMaxTile), o_red = take(8 * 4 * 24);
+  if (L) {
+    L->bd = (double*)(base + o_bd);
+    L->zp = (double*)(base + o_zp);
+    L->Tt = (double*)(base + o_Tt);
+    L->Ud = (double*)(base + o_Ud);
+    L->Mr = (double*)(base + o_Mr);
+    L->MU = (double*)(base + o_MU);
+    L->Mc = (double*)(base + o_Mc);
+    L->adr = (double*)(base + o_adr);
+    L->Ma = (double*)(base + o_Ma);
+    L->red = (double*)(base + o_red);
+  }
+  return off;
 }
 
 template <typename R>
@@ -124,7 +226,6 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
   const Prob P = d.probs[C.prob];
   const int cap = P.cap;
   const long cap2 = d.cap2;
-  const int cmax = P.cap;   // LDS layout of this problem (allocation covers the largest cap)
 
   // ---- Y-box of the cell: bbox of the basic boxes, dilated, clipped -------
   int lo1 = INT_MAX, lo2 = INT_MAX, hi1 = INT_MIN, hi2 = INT_MIN;
@@ -165,6 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
       d.cell_conv[ci] = 0;
       d.cell_bytes[ci] = 0.0;
       d.cell_terms[ci] = 0.0;
+      d.cell_fall[ci] = 0.0;
       d.overflow_any[C.prob] = 1;
     }
     return;
@@ -174,41 +276,34 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
   const int L1 = min(hi1 + m1, P.n1) - o1, L2 = min(hi2 + m2, P.n2) - o2;
   const int NY = L1 * L2;
 
-  // ---- LDS carve-up --------------------------------------------------------
-  R* bl = reinterpret_cast<R*>(smem_raw);        // b~ + log nu      [cmax^2]
-  R* lnv = bl + cmax * cmax;                      // log nu           [cmax^2]
-  R* lrr = lnv + cmax * cmax;                     // log r            [cmax^2]
-  R* T = lrr + cmax * cmax;                       // X pass 1         [cmax*16]
-  R* U0 = T + cmax * kMaxTile;                    // Y pass 1         [16*cmax]
-  R* U1a = U0 + cmax * kMaxTile;                  // Y pass 1, half 1 [16*cmax]
-  R* al = U1a + cmax * kMaxTile;                  // a~ + log mu      [256]
-  R* lnm = al + kBlock;                           // log mu           [256]
-  const size_t rbytes = ((size_t)(3 * cmax * cmax + 3 * cmax * kMaxTile + 2 * kBlock) * sizeof(R) + 15) & ~size_t(15);
-  double* red = reinterpret_cast<double*>(smem_raw + rbytes);  // 4 waves x 24
+  CellLds<R> S;
+  cell_lds_layout<R>(cap, &S, smem_raw);
+  double* red = S.red;
 
   const double eps = P.eps, lam = P.lam, kap = P.kappa, K = P.K, ch = P.ch;
-  const R chR = R(ch);
   const int D1 = C.x1 - o1, D2 = C.x2 - o2;      // tile origin in box coordinates
   const double* nu = d.nu + P.grid_off;
   const double* mu = d.mu + P.grid_off;
-  const double* Pg = d.P + P.grid_off;
+  const double* Pst = d.P + P.grid_off;
+  double* wlnv = d.ws_lnv + (long)ci * cap2;
+  double* wlrr = d.ws_lrr + (long)ci * cap2;
 
-  // ---- X tile inputs -------------------------------------------------------
+  // ---- X tile inputs (thread t owns tile point t) --------------------------
   const int ti1 = t < lx ? t / lx2 : 0, ti2 = t < lx ? t - ti1 * lx2 : 0;
   const long gx = (long)(C.x1 + ti1) * P.n2 + (C.x2 + ti2);
-  double mux = 0.0;
+  double mux = 0.0, lmux = 0.0;
   if (t < lx) {
     mux = mu[gx];
-    lnm[t] = R(log(mux));
+    lmux = log(mux);
   }
 
-  // ---- Y box inputs: nu_{-J}, r, log nu, warm start (affine fit) ----------
-  double fit[4] = {0.0, 0.0, 0.0, mux};
+  // ---- Y box inputs: nu_{-J}, r, log nu, warm start -------------------------
+  double acc0[2] = {mux, 0.0};
   for (int o = t; o < NY; o += kBlock) {
     const int j1 = o / L2, j2 = o - j1 * L2;
     const int y1 = o1 + j1, y2 = o2 + j2;
     const long g = (long)y1 * P.n2 + y2;
-    const double pv = Pg[g], nv = nu[g];
+    const double pv = Pst[g], nv = nu[g];
     double nj = 0.0;
     for (int k = 0; k < C.nb; ++k) {
       const Box b = d.box[C.basic[k]];
@@ -217,105 +312,133 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
         nj += d.vals[C.basic[k] * cap2 + (long)a1 * b.l2 + a2];
     }
     const double r = fmax(pv - nj, 0.0) / nv;
-    lrr[o] = r > 0.0 ? R(log(r)) : M<R>::ninf();
-    lnv[o] = R(log(nv));
-    const double f = pv > 0.0 ? -K * log(pv / nv) : 0.0;
-    fit[0] += f;
-    fit[1] += j1 * f;
-    fit[2] += j2 * f;
+    acc0[1] += r * nv;
+    const double lnv = log(nv);
+    wlrr[o] = r > 0.0 ? log(r) : -INFINITY;
+    wlnv[o] = lnv;
+    // beta^0/eps = -K log(P/nu); b = beta/eps + log nu
+    S.bd[o] = (pv > 0.0 ? -K * log(pv / nv) : 0.0) + lnv;
   }
-  block_sum<4>(fit, red);
-  const double muJ = fit[3];
-  double B0, p1 = 0.0, p2 = 0.0;
-  {
-    const double N = double(NY), jb1 = 0.5 * (L1 - 1), jb2 = 0.5 * (L2 - 1);
-    if (ch > 0.0) {
-      if (L1 > 1) p1 = (fit[1] - jb1 * fit[0]) / (L2 * (double)L1 * ((double)L1 * L1 - 1.0) / 12.0);
-      if (L2 > 1) p2 = (fit[2] - jb2 * fit[0]) / (L1 * (double)L2 * ((double)L2 * L2 - 1.0) / 12.0);
-    }
-    B0 = fit[0] / N - p1 * jb1 - p2 * jb2;
-  }
-  for (int o = t; o < NY; o += kBlock) {
-    const int j1 = o / L2, j2 = o - j1 * L2;
-    const long g = (long)(o1 + j1) * P.n2 + (o2 + j2);
-    const double pv = Pg[g], nv = nu[g];
-    const double f = pv > 0.0 ? -K * log(pv / nv) : 0.0;
-    bl[o] = R(f - B0 - p1 * j1 - p2 * j2) + lnv[o];
-  }
-  __syncthreads();
+  block_sum<2>(acc0, red);
+  const double muJ = acc0[0];
+  const double Rmass = acc0[1];   // |nu_{-J}| on the box
+  double nfall = 0.0;             // pass outputs recomputed exactly
 
-  // ---- X-half: S~(i) = LSE_j [b~ + log nu - ch |j - (D + delta + i)|^2] ----
-  auto x_half = [&](double b0, double q1, double q2, double& a0n, double& g1n, double& g2n) -> R {
-    const double dl1 = ch > 0.0 ? q1 / (2.0 * ch) : 0.0;
-    const double dl2 = ch > 0.0 ? q2 / (2.0 * ch) : 0.0;
-    const double c1o = D1 + dl1, c2o = D2 + dl2;
+  // ---- X-half: S(i) = LSE_j [b(j) - ch |j - (D + i)|^2], in place over Tt ----
+  // Returns S for the thread's point; sprev is that point's previous S.
+  bool have_x = false;
+  auto x_half = [&](double sprev) -> double {
+    for (int j1 = t; j1 < L1; j1 += kBlock) {
+      double m = -INFINITY;
+      for (int j2 = 0; j2 < L2; ++j2) m = fmax(m, S.bd[j1 * L2 + j2]);
+      S.Mr[j1] = m;
+    }
+    __syncthreads();
     for (int o = t; o < L1 * lx2; o += kBlock) {
       const int j1 = o / lx2, i2 = o - j1 * lx2;
-      T[o] = lse_gauss<R>(bl + j1 * L2, 1, L2, 0, R(c2o + i2), chR);
+      S.Tt[o] = lse_pass<R>(S.bd + j1 * L2, 1, 0, L2, (double)(D2 + i2), ch, have_x, S.Tt[o],
+                            S.Mr[j1], nfall);
     }
     __syncthreads();
-    R st = R(0);
-    if (t < lx) st = lse_gauss<R>(T + ti2, lx2, L1, 0, R(c1o + ti1), chR);
-    __syncthreads();
-    a0n = -kap * (b0 + q1 * D1 + q2 * D2 + ch * (dl1 * dl1 + dl2 * dl2));
-    g1n = -kap * q1;
-    g2n = -kap * q2;
-    return st;
-  };
-
-  // Y pass 1 over columns [ib, ie) of the tile for a given alpha base.
-  auto y_pass1 = [&](R* Uo, int ib, int ie, double d2o) {
-    for (int o = t; o < lx1 * L2; o += kBlock) {
-      const int i1 = o / L2, j2 = o - i1 * L2;
-      Uo[o] = lse_gauss<R>(al + i1 * lx2 + ib, 1, ie - ib, ib, R(d2o + j2), chR);
+    for (int i2 = t; i2 < lx2; i2 += kBlock) {
+      double m = -INFINITY;
+      for (int j1 = 0; j1 < L1; ++j1) m = fmax(m, S.Tt[j1 * lx2 + i2]);
+      S.Mc[i2] = m;
     }
+    __syncthreads();
+    double sv = 0.0;
+    if (t < lx)
+      sv = lse_pass<R>(S.Tt + ti2, lx2, 0, L1, (double)(D1 + ti1), ch, have_x, sprev, S.Mc[ti2],
+                       nfall);
+    have_x = true;
+    __syncthreads();
+    return sv;
   };
 
-  double A0, g1, g2;
-  R at = x_half(B0, p1, p2, A0, g1, g2);
-  if (t < lx) {
-    at = -R(kap) * at;
-    al[t] = at + lnm[t];
-  }
-  __syncthreads();
+  double Sx = x_half(0.0);
+  double aeps = -kap * Sx;   // alpha/eps of the thread's point
 
   const double tol = P.err * muJ;
-  const R newton_tol = sizeof(R) == 8 ? R(1e-14) : R(2e-6);
+  const R newton_tol = sizeof(R) == 8 ? R(1e-14) : R(1e-6);
   const int newton_max = sizeof(R) == 8 ? 100 : 60;
-  double B0n = 0.0, pn1 = 0.0, pn2 = 0.0;
   double pxv = 0.0, lpv = 0.0;
   int it = 0;
   bool conv = false;
+  bool have_y = false;
+  double ushift = 0.0;   // shift applied to alpha since the last Y-half (eps units)
+
+  // ---- Y-half pieces -------------------------------------------------------
+  auto y_prepare = [&]() {
+    if (t < lx) S.adr[t] = aeps + lmux;
+    __syncthreads();
+    for (int i1 = t; i1 < lx1; i1 += kBlock) {
+      double m = -INFINITY;
+      for (int i2 = 0; i2 < lx2; ++i2) m = fmax(m, S.adr[i1 * lx2 + i2]);
+      S.Ma[i1] = m;
+    }
+    __syncthreads();
+  };
+  // Y pass 1 over tile columns [ib, ie): Uo(i1, j2) = LSE_i2 [a - ch (i2 - (j2 - D2))^2]
+  auto y_pass1 = [&](double* Uo, int ib, int ie, bool have, double extra) {
+    for (int o = t; o < lx1 * L2; o += kBlock) {
+      const int i1 = o / L2, j2 = o - i1 * L2;
+      Uo[o] = lse_pass<R>(S.adr + i1 * lx2, 1, ib, ie, (double)(j2 - D2), ch, have, Uo[o] + extra,
+                          S.Ma[i1], nfall);
+    }
+    __syncthreads();
+    for (int j2 = t; j2 < L2; j2 += kBlock) {
+      double m = -INFINITY;
+      for (int i1 = 0; i1 < lx1; ++i1) m = fmax(m, Uo[i1 * L2 + j2]);
+      S.MU[j2] = m;
+    }
+    __syncthreads();
+  };
+
   for (;;) {
     ++it;
-    // ---- Y-half: z~(j) by two passes, then Newton per point ---------------
-    const double dq1 = ch > 0.0 ? g1 / (2.0 * ch) : 0.0;
-    const double dq2 = ch > 0.0 ? g2 / (2.0 * ch) : 0.0;
-    const double d1o = -D1 + dq1, d2o = -D2 + dq2;
-    y_pass1(U0, 0, lx2, d2o);
-    __syncthreads();
-    const double Z0 = A0 - g1 * D1 - g2 * D2 + ch * (dq1 * dq1 + dq2 * dq2);
+    if (P.translate) {
+      // exact maximisation of the cell dual along (alpha + s, beta - s):
+      // e^{s/lam} = (R + sqrt(R^2 + 4AB)) / (2B); FP64 sums (the shift in
+      // eps units is K log w, so w must be exact to ~1/K)
+      double ab[2] = {0.0, 0.0};
+      if (t < lx) ab[0] = mux * exp(-aeps / K);
+      for (int o = t; o < NY; o += kBlock) {
+        const double lnv = wlnv[o];
+        ab[1] += exp(lnv - (S.bd[o] - lnv) / K);
+      }
+      block_sum<2>(ab, red);
+      const double w = (Rmass + sqrt(Rmass * Rmass + 4.0 * ab[0] * ab[1])) / (2.0 * ab[1]);
+      const double sh = K * log(w);   // s/eps
+      aeps += sh;
+      ushift += sh;
+      for (int o = t; o < NY; o += kBlock) S.bd[o] -= sh;
+      __syncthreads();
+    }
+    // ---- Y-half: z by two passes, Newton per point --------------------------
+    y_prepare();
+    y_pass1(S.Ud, 0, lx2, have_y, ushift);
     for (int o = t; o < NY; o += kBlock) {
       const int j1 = o / L2, j2 = o - j1 * L2;
-      const R zt = lse_gauss<R>(U0 + j2, L2, lx1, 0, R(d1o + j1), chR);
-      const double c0 = (1.0 - kap) * (Z0 + g1 * j1 + g2 * j2);
-      const R A = R(double(lrr[o]) - c0);
-      const R v = newton_v<R>(zt, A, R(K), R(kap), newton_tol, newton_max);
-      bl[o] = v + lnv[o];
+      const double z = lse_pass<R>(S.Ud + j2, L2, 0, lx1, (double)(j1 - D1), ch, have_y,
+                                   S.zp[o] + ushift, S.MU[j2], nfall);
+      S.zp[o] = z;
+      const double lnv = wlnv[o];
+      const double qref = z / (K + 1.0);
+      // warm start: the previous beta/eps = bd - log nu, i.e. v0 = bd - lnv + K qref
+      const double v0 = S.bd[o] - lnv + K * qref;
+      const double v = newton_v<R>(wlrr[o] - qref, v0, K, newton_tol, newton_max);
+      S.bd[o] = -K * qref + v + lnv;
     }
-    B0n = -kap * Z0;
-    pn1 = -kap * g1;
-    pn2 = -kap * g2;
+    have_y = true;
+    ushift = 0.0;
     __syncthreads();
 
-    // ---- next X-half (gives P_X of the pair for the stopping rule) --------
-    double A0n, g1n, g2n;
-    R atn = x_half(B0n, pn1, pn2, A0n, g1n, g2n);
+    // ---- next X-half (gives P_X of the pair for the stopping rule) ----------
+    const double Sn = x_half(Sx);
     double term = 0.0;
     if (t < lx) {
-      lpv = (A0 - A0n / kap) + (g1 - g1n / kap) * ti1 + (g2 - g2n / kap) * ti2 + double(at) +
-            double(atn);
-      const double aol = (A0 + g1 * ti1 + g2 * ti2 + double(at)) / K;   // alpha / lam
+      lpv = aeps + Sn;               // log(P_X / mu)
+      const double aol = aeps / K;   // alpha/lam
       pxv = mux * exp(lpv);
       term = pxv * (lpv + aol) - pxv + mux * exp(-aol);
     }
@@ -324,25 +447,14 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
     conv = pdv[0] <= tol;
     const bool done = P.fixed_iters > 0 ? (it >= P.fixed_iters) : (conv || it >= P.max_iter);
     if (done) break;
-    A0 = A0n;
-    g1 = g1n;
-    g2 = g2n;
-    if (t < lx) {
-      at = -R(kap) * atn;
-      al[t] = at + lnm[t];
-    }
-    __syncthreads();
+    Sx = Sn;
+    aeps = -kap * Sn;
   }
 
-  // ---- re-split into the basic cells of J --------------------------------
-  const double dq1 = ch > 0.0 ? g1 / (2.0 * ch) : 0.0;
-  const double dq2 = ch > 0.0 ? g2 / (2.0 * ch) : 0.0;
-  const double d1o = -D1 + dq1, d2o = -D2 + dq2;
-  const double Z0 = A0 - g1 * D1 - g2 * D2 + ch * (dq1 * dq1 + dq2 * dq2);
+  // ---- re-split into the basic cells of J ----------------------------------
+  // The final pair is (alpha of the last Y-half, beta = eps (b - log nu)); adr,
+  // Ma and zp still hold that alpha's values.
   const int nc = lx2 / s;
-  y_pass1(U0, 0, s, d2o);
-  if (nc > 1) y_pass1(U1a, s, 2 * s, d2o);
-  __syncthreads();
   int kr[4], kc[4];
   for (int k = 0; k < C.nb; ++k) {
     const int2 bx = d.basic_xy[C.basic[k]];
@@ -350,36 +462,39 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
     kc[k] = (bx.y - C.x2) / s;
   }
   // sums: [0..3] <beta, nu_k>, [4..7] |nu_k|, [8..11] <alpha, px>, [12..15] KL terms,
-  // [16..19] |mu_k|
-  double acc[20];
+  // [16..19] |mu_k|, [20] exact recomputations
+  double acc[21];
 #pragma unroll
-  for (int k = 0; k < 20; ++k) acc[k] = 0.0;
-  for (int o = t; o < NY; o += kBlock) {
-    const int j1 = o / L2, j2 = o - j1 * L2;
-    const long g = (long)(o1 + j1) * P.n2 + (o2 + j2);
-    const double v = double(bl[o]) - double(lnv[o]);
-    const double c0 = (1.0 - kap) * (Z0 + g1 * j1 + g2 * j2);
-    const double beta = eps * (B0n + pn1 * j1 + pn2 * j2 + v);
-    const double base = log(nu[g]) + v + c0;
-    for (int k = 0; k < C.nb; ++k) {
-      const R* Ub = (kc[k] == 0 ? U0 : U1a) + (long)(kr[k] * s) * L2 + j2;
-      const R zk = lse_gauss<R>(Ub, L2, s, kr[k] * s, R(d1o + j1), chR);
-      const double nt = exp(base + double(zk));
-      acc[k] += beta * nt;
-      acc[4 + k] += nt;
-      d.cand[(long)C.basic[k] * cap2 + o] = nt < P.trunc ? 0.0 : nt;
+  for (int k = 0; k < 21; ++k) acc[k] = 0.0;
+  for (int c = 0; c < nc; ++c) {
+    double* Uo = c == 0 ? S.Ud : S.Tt;
+    y_pass1(Uo, c * s, (c + 1) * s, false, 0.0);
+    for (int o = t; o < NY; o += kBlock) {
+      const int j1 = o / L2, j2 = o - j1 * L2;
+      const double beta = eps * (S.bd[o] - wlnv[o]);
+      for (int k = 0; k < C.nb; ++k) {
+        if (kc[k] != c) continue;
+        const double zk = lse_pass<R>(Uo + j2, L2, kr[k] * s, (kr[k] + 1) * s, (double)(j1 - D1), ch,
+                                      true, S.zp[o], S.MU[j2], nfall);
+        const double nt = exp(S.bd[o] + zk);   // nu e^{beta/eps} e^{z_k}
+        acc[k] += beta * nt;
+        acc[4 + k] += nt;
+        d.cand[(long)C.basic[k] * cap2 + o] = nt < P.trunc ? 0.0 : nt;
+      }
     }
+    __syncthreads();
   }
   if (t < lx) {
     const int k = (ti1 / s) * nc + (ti2 / s);
-    const double alpha = eps * (A0 + g1 * ti1 + g2 * ti2 + double(at));
+    const double alpha = eps * aeps;
     acc[8 + k] = alpha * pxv;
     acc[12 + k] = mux * (exp(lpv) * lpv - exp(lpv) + 1.0);
     acc[16 + k] = mux;
     d.pxc[P.grid_off + gx] = pxv;
     d.abar[P.grid_off + gx] = alpha;
   }
-  block_sum<20>(acc, red);
+  acc[20] = nfall;
+  block_sum<21>(acc, red);
   if (t == 0) {
     double bytes = 8.0 * (2.0 * NY + 3.0 * lx + (double)C.nb * NY);
     for (int k = 0; k < C.nb; ++k) {
@@ -392,8 +507,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
       nb.o1 = o1; nb.o2 = o2; nb.l1 = L1; nb.l2 = L2;
       d.cbox[b] = nb;
     }
-    // exps of the log-sum-exp passes: every Y-half and X-half of the loop, the
-    // first X-half, and the re-split passes
+    // log-sum-exp terms of the separable passes: every Y-half and X-half of
+    // the loop, the first X-half, and the re-split passes
     const double xh = (double)L1 * lx2 * L2 + (double)lx * L1;
     const double yh = (double)lx1 * L2 * lx2 + (double)NY * lx1;
     const double rs = (double)lx1 * L2 * lx2 + (double)NY * s * C.nb;
@@ -401,15 +516,13 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
     d.cell_conv[ci] = conv ? 1 : 0;
     d.cell_bytes[ci] = bytes;
     d.cell_terms[ci] = it * (xh + yh) + xh + rs;
+    d.cell_fall[ci] = acc[20];
   }
 }
 
 size_t cell_lds_bytes(int cap, int precision) {
-  const size_t rs = precision == 64 ? 8 : 4;
-  const size_t n = 3 * (size_t)cap * cap + 3 * (size_t)cap * kMaxTile + 2 * kBlock;
-  size_t bytes = rs * n;
-  bytes = (bytes + 15) & ~size_t(15);
-  return bytes + sizeof(double) * 4 * 24;
+  if (precision == 64) return cell_lds_layout<double>(cap, nullptr, nullptr);
+  return cell_lds_layout<float>(cap, nullptr, nullptr);
 }
 
 hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int precision,

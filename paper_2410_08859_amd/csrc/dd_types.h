@@ -7,7 +7,7 @@ namespace dduot {
 
 constexpr int kBlock = 256;        // threads per workgroup of the cell kernels
 constexpr int kMaxTile = 16;       // maximal X tile side (2 * basic cell side)
-constexpr int kHistFields = 11;    // doubles per half-iteration record
+constexpr int kHistFields = 12;    // doubles per half-iteration record
 
 // One transport problem of a (possibly batched) handle.
 struct Prob {
@@ -19,6 +19,7 @@ struct Prob {
   double err, trunc, lenience;
   int getweights, fixed_iters, max_iter;
   int margin, cap;
+  int translate;
   int precision;
   int grid_off;     // offset of this problem's grid arrays
   int basic_off, nbasic;
@@ -60,7 +61,10 @@ struct Dev {
   int* cell_iters;            // Y-halves of the last solve of each cell (-1: skipped)
   int* cell_conv;             // converged flag of the last solve
   double* cell_bytes;         // algorithmic bytes of the last solve
-  double* cell_terms;         // log-sum-exp terms (one exp each) of the last solve
+  double* cell_terms;         // log-sum-exp terms of the last solve
+  double* cell_fall;          // pass outputs recomputed in FP64 (underflow) in the last solve
+  double* ws_lnv;             // per cell: log nu on the Y-box (cap2 entries)
+  double* ws_lrr;             // per cell: log(nu_{-J}/nu) on the Y-box (cap2 entries)
   double* chunk_part;         // 2 doubles per reduction chunk
   double* theta;              // per problem
   double* hist;               // per problem ring of records

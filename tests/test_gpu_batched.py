@@ -1,0 +1,105 @@
+"""Several independent problems of different sizes in one handle: every launch
+covers all problems' cells, GetWeights decides per problem.  Each problem must
+follow its own oracle trajectory, and match a handle that holds it alone."""
+import numpy as np
+import pytest
+
+from oracle import dd
+from paper_2410_08859_amd import binding as B
+from paper_2410_08859_amd.inputs import batched_problems, gaussian_mixture
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [  # (n, s, lam, eps_h2, init)
+    (16, 2, 0.5, 4.0, B.INIT_PRODUCT),
+    (32, 4, 1.0, 4.0, B.INIT_PRODUCT),
+    (32, 4, 5.0, 2.0, B.INIT_PRODUCT),
+    (24, 2, 2.0, 3.0, B.INIT_PRODUCT),
+]
+
+
+def problem_data(k, n):
+    mu = gaussian_mixture(n, n, 3, 1e-3, 1.0, 700 + 2 * k)
+    nu = gaussian_mixture(n, n, 3, 1e-3, 1.2, 701 + 2 * k)
+    return mu, nu
+
+
+def make_cfgs(precision, fixed=8):
+    cfgs = []
+    for (n, s, lam, e, init) in SPECS:
+        cfgs.append(B.dd_uot_default_config(
+            n1=n, n2=n, h=1.0 / n, eps=e / n ** 2, lam=lam, cell=s, precision=precision,
+            init=init, fixed_inner_iters=fixed, lenience=0.0, box_cap=32, getweights=B.GW_SWIFT))
+    return cfgs
+
+
+def test_batched_fp64_follows_each_oracle():
+    cfgs = make_cfgs(64)
+    data = [problem_data(k, c.n1) for k, c in enumerate(cfgs)]
+    h = B.dd_uot_init_batch(cfgs, [d[0] for d in data], [d[1] for d in data])
+    try:
+        assert B.dd_uot_num_problems(h) == len(cfgs)
+        probs, states = [], []
+        for k, c in enumerate(cfgs):
+            p = dd.make_problem(data[k][0], data[k][1], c.eps, c.lambda_, c.h, c.cell)
+            probs.append(p)
+            states.append(dd.init_product(p))
+        opt = dd.Options(fixed_iters=8, lenience=0.0, cap=32, trunc=1e-15, margin=2, translate=True)
+        for step in range(4):
+            print(f"[batched] step {step}", flush=True)
+            B.dd_uot_iterate(h, 1)
+            for k, (p, st) in enumerate(zip(probs, states)):
+                ost = dd.half_iteration(p, st, "A" if step % 2 == 0 else "B", opt)
+                rec = B.dd_uot_history(h, k)[-1]
+                assert rec[0] == ost["theta"]
+                assert rec[1] == pytest.approx(ost["e_cur"], rel=1e-10)
+                assert rec[2] == pytest.approx(ost["e_greedy"], rel=1e-10)
+                px, py = B.dd_uot_marginals(h, k, p.n1, p.n2)
+                np.testing.assert_allclose(px, st.px, rtol=0, atol=1e-10 * st.px.max())
+                P = dd.aggregate(p, st.boxes)
+                np.testing.assert_allclose(py, P, rtol=0, atol=1e-10 * P.max())
+    finally:
+        B.dd_uot_destroy(h)
+
+
+def test_batched_matches_single_handles_fp32():
+    cfgs = make_cfgs(32)
+    data = [problem_data(k, c.n1) for k, c in enumerate(cfgs)]
+    hb = B.dd_uot_init_batch(cfgs, [d[0] for d in data], [d[1] for d in data])
+    singles = [B.dd_uot_init(c, d[0], d[1]) for c, d in zip(cfgs, data)]
+    try:
+        B.dd_uot_iterate(hb, 5)
+        for k, hs in enumerate(singles):
+            B.dd_uot_iterate(hs, 5)
+            n = cfgs[k].n1
+            pb = B.dd_uot_marginals(hb, k, n, n)
+            ps = B.dd_uot_marginals(hs, 0, n, n)
+            # FP64 atomics in the aggregation make the last bit of P_Y depend on
+            # the order of the adds, which FP32 arithmetic amplifies to ~1e-7 per step
+            for a, b in zip(pb, ps):
+                np.testing.assert_allclose(a, b, rtol=0, atol=1e-5 * b.max())
+            np.testing.assert_allclose(B.dd_uot_history(hb, k)[:, :3], B.dd_uot_history(hs, 0)[:, :3],
+                                       rtol=1e-5)
+    finally:
+        B.dd_uot_destroy(hb)
+        for hs in singles:
+            B.dd_uot_destroy(hs)
+
+
+def test_batched_workload_64_problems_runs():
+    # the batched workload: 64 problems, sides 64..512, lambda in [0.1, 10], FP32
+    probs = batched_problems(64)
+    cfgs = [B.dd_uot_default_config(n1=q["n"], n2=q["n"], h=1.0 / q["n"], eps=1.0 / q["n"] ** 2,
+                                    lam=q["lam"], cell=4, precision=32, sinkhorn_max_iter=50,
+                                    box_cap=48) for q in probs]
+    h = B.dd_uot_init_batch(cfgs, [q["mu"] for q in probs], [q["nu"] for q in probs])
+    try:
+        st = B.dd_uot_iterate(h, 4)
+        assert st["n_cells"] > 0
+        assert st["n_overflow"] == sum(B.dd_uot_history(h, k)[:, 7].sum() for k in range(64))
+        for k in (0, 17, 63):
+            s = B.dd_uot_score(h, k)
+            assert np.isfinite(s["tracked"]) and s["pd_gap"] >= -1e-12 * abs(s["dual"])
+            assert abs(s["mass_x"] - s["mass_y"]) <= 1e-5 * s["mass_x"]
+    finally:
+        B.dd_uot_destroy(h)

@@ -1,0 +1,117 @@
+"""Full-size checks in the bench's launch configuration (1024 x 1024, cells
+8 x 8, FP32 cell arithmetic, Y-box cap 48).
+
+The oracle cannot run all 4096 cell problems of a half-iteration in seconds,
+so the first half-iteration is checked on sampled cells (whose inputs the
+oracle derives itself from the start plan), and later half-iterations on
+properties that hold at any size.
+"""
+import numpy as np
+import pytest
+
+from oracle import dd
+from paper_2410_08859_amd import binding as B
+from paper_2410_08859_amd.inputs import WORKLOADS, workload_marginals
+
+pytestmark = pytest.mark.gpu
+
+N = 1024
+S = 8
+CAP = 48
+MAX_INNER = 100
+
+
+def cfg_for(precision, getweights, lenience=0.005):
+    w = WORKLOADS["grid1024"]
+    return B.dd_uot_default_config(n1=N, n2=N, h=1.0 / N, eps=w["eps_h2"] / N ** 2, lam=w["lam"],
+                                   cell=S, precision=precision, init=B.INIT_BLOCK,
+                                   getweights=getweights, sinkhorn_err=2e-5,
+                                   sinkhorn_max_iter=MAX_INNER, trunc=1e-15, lenience=lenience,
+                                   box_margin=2, box_cap=CAP)
+
+
+@pytest.fixture(scope="module")
+def marg():
+    return workload_marginals("grid1024")
+
+
+@pytest.fixture(scope="module")
+def oracle_problem(marg):
+    mu, nu = marg
+    w = WORKLOADS["grid1024"]
+    p = dd.make_problem(mu, nu, w["eps_h2"] / N ** 2, w["lam"], 1.0 / N, S)
+    st = dd.init_block(p)
+    return p, st
+
+
+# sampled A cells: corners, edges, interior (row-major ids over 64 x 64 cells)
+SAMPLE = [0, 63, 64 * 63, 64 * 64 - 1, 64 * 20 + 31, 64 * 32 + 32, 64 * 45 + 7, 64 * 5 + 50]
+
+
+# FP64: potentials of magnitude K = lam/eps ~ 1e6 carry an absolute rounding of
+# K * 1.1e-16 ~ 1e-10 into every exponent, so the FP64 bar here is K * 1e-15.
+@pytest.mark.parametrize("precision,rtol", [(32, 1e-5), (64, 1e-9)])
+def test_first_half_iteration_sampled_cells(marg, oracle_problem, precision, rtol):
+    mu, nu = marg
+    p, st = oracle_problem
+    cfg = cfg_for(precision, B.GW_GREEDY)
+    opt = dd.Options(err=cfg.sinkhorn_err, max_iter=MAX_INNER, trunc=cfg.trunc,
+                     lenience=cfg.lenience, margin=cfg.box_margin, cap=CAP, getweights="greedy",
+                     translate=bool(cfg.translate))
+    print(f"[fullsize] 1024^2 first half-iteration, precision {precision}", flush=True)
+    h = B.dd_uot_init(cfg, mu, nu)
+    try:
+        B.dd_uot_iterate(h, 1)
+        rec = B.dd_uot_history(h, 0)[-1]
+        assert rec[0] == 1.0 and rec[3] == 4096 and rec[7] == 0
+        px, _ = B.dd_uot_marginals(h, 0, N, N)
+        alpha, _ = B.dd_uot_potentials(h, 0, N, N, beta=False)
+        P = dd.aggregate(p, st.boxes)
+        cells = dd.composite_cells(p, "A")
+        for ci in SAMPLE:
+            c = cells[ci]
+            r = dd.process_cell(p, c, st.boxes, P, opt)
+            xi = r["xi"]
+            e_px = np.abs(px.ravel()[xi] - r["px"]).sum() / r["px"].sum()
+            assert e_px < rtol, f"cell {ci}: P_X rel L1 {e_px:.2e}"
+            if precision == 64:
+                e_a = np.abs(alpha.ravel()[xi] - r["alpha"]).max() / np.abs(r["alpha"]).max()
+                assert e_a < rtol, f"cell {ci}: alpha {e_a:.2e}"
+            for b in c["basic"]:
+                o1, o2, arr = B.dd_uot_basic_marginal(h, 0, b)
+                ref = dd.truncate_to_box(r["box"][0], r["box"][1], r["cand"][b], cfg.trunc)
+                if precision == 64:
+                    assert (o1, o2, arr.shape) == (ref[0], ref[1], ref[2].shape), f"box {b}"
+                    np.testing.assert_allclose(arr, ref[2], rtol=0, atol=rtol * ref[2].max())
+                else:
+                    # FP32 may flip truncation of entries near 1e-15; compare on the cell box
+                    box = r["box"]
+                    full = np.zeros((N, N))
+                    full[o1:o1 + arr.shape[0], o2:o2 + arr.shape[1]] = arr
+                    got = full[box[0]:box[0] + box[2], box[1]:box[1] + box[3]]
+                    e = np.abs(got - r["cand"][b]).sum() / r["cand"][b].sum()
+                    assert e < rtol, f"basic {b}: nu rel L1 {e:.2e}"
+    finally:
+        B.dd_uot_destroy(h)
+
+
+def test_invariants_over_several_half_iterations(marg):
+    # every cell plan is a diagonal scaling, so |P_X pi| = |P_Y pi| up to
+    # truncated entries (also after safe mixing, which is linear); the
+    # certificate gap is nonnegative.
+    mu, nu = marg
+    cfg = cfg_for(32, B.GW_SWIFT)
+    h = B.dd_uot_init(cfg, mu, nu)
+    try:
+        for k in range(6):
+            B.dd_uot_iterate(h, 1)
+            s = B.dd_uot_score(h, 0)
+            rec = B.dd_uot_history(h, 0)[-1]
+            print(f"[fullsize] step {k}: theta {rec[0]:.3g} tracked {s['tracked']:.9e} rel PD "
+                  f"{s['rel_pd_gap']:.3e} mean inner {rec[8] / max(rec[3], 1):.1f} "
+                  f"fallbacks {rec[11]:.0f}", flush=True)
+            assert s["pd_gap"] >= -1e-12 * abs(s["dual"])
+            assert abs(s["mass_x"] - s["mass_y"]) <= 1e-6 * s["mass_x"]
+            assert np.isfinite(s["tracked"])
+    finally:
+        B.dd_uot_destroy(h)

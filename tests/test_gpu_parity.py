@@ -23,7 +23,8 @@ def config(n, s, eps, lam, h, **kw):
 def oracle_options(cfg):
     return dd.Options(err=cfg.sinkhorn_err, max_iter=cfg.sinkhorn_max_iter,
                       fixed_iters=cfg.fixed_inner_iters, trunc=cfg.trunc, lenience=cfg.lenience,
-                      margin=cfg.box_margin, cap=cfg.box_cap, getweights=GW[cfg.getweights])
+                      margin=cfg.box_margin, cap=cfg.box_cap, getweights=GW[cfg.getweights],
+                      translate=bool(cfg.translate))
 
 
 def oracle_start(p, cfg):
@@ -94,11 +95,12 @@ def grid32():
     return mu, nu
 
 
-def test_fp64_product_start_fixed_inner(grid32):
+@pytest.mark.parametrize("translate", [0, 1])
+def test_fp64_product_start_fixed_inner(grid32, translate):
     mu, nu = grid32
     n = 32
     cfg = config(n, 4, 4.0 / n ** 2, 1.0, 1.0 / n, precision=64, init=B.INIT_PRODUCT,
-                 fixed_inner_iters=20, lenience=0.0, box_cap=32)
+                 fixed_inner_iters=20, lenience=0.0, box_cap=32, translate=translate)
     h, p, st = run_pair(mu, nu, cfg, 6)
     try:
         compare_boxes(h, p, st, 1e-10)

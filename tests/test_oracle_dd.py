@@ -229,3 +229,29 @@ def test_toy_getweights_behaviour():
     assert gap_w[-1] < 0.1 * gap_w[0]          # swift converges
     assert gap_s[-1] > 3 * gap_w[-1]           # safe lags behind
     assert gap_g[-1] > 10 * gap_w[-1]          # greedy does not converge
+
+
+def test_translation_shift_is_the_line_maximiser_and_keeps_the_solution():
+    p = small_problem(16, 4, eps_h2=1.0, lam=1.0)
+    st = dd.init_block(p)
+    opt = dd.Options(margin=2, cap=16)
+    P = dd.aggregate(p, st.boxes)
+    cell = dd.composite_cells(p, "A")[1]
+    box = dd.cell_box(p, cell, st.boxes, opt)
+    xi, yi = dd.rect_index(cell["rect"], p.n2), dd.rect_index(box, p.n2)
+    mu_x, nu_y = p.mu.ravel()[xi], p.nu.ravel()[yi]
+    C = dd.rect_cost(p, cell["rect"], box)
+    r, beta0 = dd.cell_inputs(p, cell, box, st.boxes, P)
+    alpha = uot.x_update(beta0, nu_y, C, p.eps, p.lam)
+    s = dd.translation_shift(alpha, beta0, mu_x, nu_y, r, p.lam)
+    D = lambda d_: uot.dual(alpha + s + d_, beta0 - s - d_, mu_x, nu_y, C, p.eps, p.lam, r * nu_y)
+    for d_ in (1e-3, -1e-3, 1e-5, -1e-5):
+        assert D(d_) <= D(0.0)
+    assert D(0.0) >= uot.dual(alpha, beta0, mu_x, nu_y, C, p.eps, p.lam, r * nu_y)
+    # same converged cell solution with and without the step
+    sols = []
+    for tr in (False, True):
+        o = dd.Options(margin=2, cap=16, translate=tr, err=1e-14, max_iter=200000)
+        sols.append(dd.solve_cell(mu_x, nu_y, r, beta0, C, p.eps, p.lam, 1e-14 * mu_x.sum(), o))
+    assert sols[1]["iters"] < sols[0]["iters"]
+    np.testing.assert_allclose(sols[1]["px"], sols[0]["px"], rtol=1e-6)
