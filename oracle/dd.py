@@ -69,6 +69,7 @@ class Problem:
     h: float
     s1: int                   # basic cell sides
     s2: int
+    ypos: np.ndarray | None = None   # (n1, n2, 2) moved Y points y'; None = the grid
 
     @property
     def n1(self):
@@ -100,7 +101,10 @@ class Options:
     translate: bool = False    # dual line search along (alpha + s, beta - s)
 
 
-def make_problem(mu, nu, eps, lam, h, s1, s2=None) -> Problem:
+def make_problem(mu, nu, eps, lam, h, s1, s2=None, ypos=None) -> Problem:
+    """ypos: optional (n1, n2, 2) coordinates y' of the Y points (a displaced
+    support, cost |x - y'|^2); the index structure (boxes, cells) stays that
+    of the grid."""
     s2 = s1 if s2 is None else s2
     mu = np.asarray(mu, dtype=np.float64)
     nu = np.asarray(nu, dtype=np.float64)
@@ -111,7 +115,11 @@ def make_problem(mu, nu, eps, lam, h, s1, s2=None) -> Problem:
     n1, n2 = mu.shape
     if n1 % s1 or n2 % s2:
         raise ValueError("grid not divisible by the basic cell size")
-    return Problem(mu, nu, float(eps), float(lam), float(h), int(s1), int(s2))
+    if ypos is not None:
+        ypos = np.asarray(ypos, dtype=np.float64)
+        if ypos.shape != (n1, n2, 2):
+            raise ValueError("ypos must have shape (n1, n2, 2)")
+    return Problem(mu, nu, float(eps), float(lam), float(h), int(s1), int(s2), ypos)
 
 
 def basic_rect(p: Problem, b: int):
@@ -163,9 +171,24 @@ def rect_coords(rect, h):
     return h * np.stack([i1.ravel(), i2.ravel()], axis=1).astype(np.float64)
 
 
+def y_coords(p: Problem, yrect):
+    """Coordinates of the Y points of a rectangle: the grid, or the moved
+    points y' when the problem has them."""
+    if p.ypos is None:
+        return rect_coords(yrect, p.h)
+    o1, o2, l1, l2 = yrect
+    return p.ypos[o1:o1 + l1, o2:o2 + l2].reshape(-1, 2)
+
+
 def rect_cost(p: Problem, xrect, yrect):
     """Dense cost matrix c(x, y) = |x - y|^2 between two rectangles."""
-    return uot.sq_cost(rect_coords(xrect, p.h), rect_coords(yrect, p.h))
+    return uot.sq_cost(rect_coords(xrect, p.h), y_coords(p, yrect))
+
+
+def full_cost(p: Problem):
+    """Dense cost between all X and all Y points (small grids only)."""
+    full = (0, 0, p.n1, p.n2)
+    return rect_cost(p, full, full)
 
 
 # --------------------------------------------------------------------------
@@ -262,7 +285,7 @@ def tracked_score(p: Problem, st: State, P=None) -> float:
 
 def exact_score(p: Problem, st: State) -> float:
     """E(pi) of the dense plan (Definition unbalanced-entropic-transport)."""
-    c = uot.sq_cost(uot.grid_points(p.n1, p.n2, p.h), uot.grid_points(p.n1, p.n2, p.h))
+    c = full_cost(p)
     return uot.primal(st.plan, p.mu, p.nu, c, p.eps, p.lam)
 
 
@@ -523,8 +546,7 @@ def certificate(p: Problem, abar) -> dict:
     global Y-update with nu_- = 0 (eq. sinkhorn-iters-ot) -> pi_hat; the gap is
     PD = lam KL(P_X pi_hat | exp(-alpha/lam) mu), exact by eq. (PD-gap-KL) with
     J = I.  Dense: for small grids only.  Also returns primal and dual."""
-    pts = uot.grid_points(p.n1, p.n2, p.h)
-    C = uot.sq_cost(pts, pts)
+    C = full_cost(p)
     a = np.ravel(abar)
     kappa = p.lam / (p.lam + p.eps)
     z = uot.y_log_integral(a, p.mu, C, p.eps)
@@ -534,7 +556,7 @@ def certificate(p: Problem, abar) -> dict:
     pd = uot.pd_gap_kl(a, px, p.mu, p.lam)
     D = uot.dual(a, bhat, p.mu, p.nu, C, p.eps, p.lam)
     E = uot.primal(pi, p.mu, p.nu, C, p.eps, p.lam)
-    return dict(pd=pd, dual=D, primal=E, rel=pd / D, beta_hat=bhat.reshape(p.mu.shape),
+    return dict(pd=pd, dual=D, primal=E, rel=pd / abs(D), beta_hat=bhat.reshape(p.mu.shape),
                 px=px.reshape(p.mu.shape), py=py.reshape(p.mu.shape),
                 l1_x=float(np.abs(px - np.exp(-a / p.lam) * p.mu.ravel()).sum()))
 
@@ -542,6 +564,7 @@ def certificate(p: Problem, abar) -> dict:
 def beta_hat_at(p: Problem, abar, y_flat) -> np.ndarray:
     """beta_hat at selected grid points (dense over all x); for large grids."""
     pts = uot.grid_points(p.n1, p.n2, p.h)
-    C = uot.sq_cost(pts, pts[np.asarray(y_flat)])
+    ys = pts if p.ypos is None else p.ypos.reshape(-1, 2)
+    C = uot.sq_cost(pts, ys[np.asarray(y_flat)])
     kappa = p.lam / (p.lam + p.eps)
     return -p.eps * kappa * uot.y_log_integral(np.ravel(abar), p.mu, C, p.eps)

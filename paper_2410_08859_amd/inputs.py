@@ -81,3 +81,49 @@ def batched_problems(count: int = 64, seed: int = 4999, sides=(64, 128, 256, 512
         nu = gaussian_mixture(n, n, 3, 1e-3, 1.0, 4001 + 2 * k)
         out.append(dict(n=n, lam=lam, mu=mu, nu=nu))
     return out
+
+
+# --------------------------------------------------------------------------
+# Displaced Y support: y' = y + u_theta(y) with a smooth seeded field
+# --------------------------------------------------------------------------
+def cubic_bspline(t: np.ndarray) -> np.ndarray:
+    """Centred uniform cubic B-spline kernel (support |t| < 2, partition of unity)."""
+    a = np.abs(np.asarray(t, dtype=np.float64))
+    out = np.zeros_like(a)
+    m1 = a < 1.0
+    m2 = (a >= 1.0) & (a < 2.0)
+    out[m1] = 2.0 / 3.0 - a[m1] ** 2 + 0.5 * a[m1] ** 3
+    out[m2] = (2.0 - a[m2]) ** 3 / 6.0
+    return out
+
+
+def displacement_basis(n: int, controls: int = 8) -> np.ndarray:
+    """(n, controls) matrix B with B[i, a] the weight of control point a at the
+    grid coordinate i/n: uniform cubic B-spline on [0, 1] with `controls`
+    control points, the first and last lying one knot spacing outside [0, 1]
+    (spacing 1/(controls - 3)), so that the rows sum to 1."""
+    if controls < 4:
+        raise ValueError("a cubic B-spline needs at least 4 control points")
+    step = 1.0 / (controls - 3)
+    x = np.arange(n, dtype=np.float64) / n
+    a = np.arange(controls, dtype=np.float64)
+    return cubic_bspline((x[:, None] - (a[None, :] - 1.0) * step) / step)
+
+
+def displacement_theta(seed: int, h: float, controls: int = 8) -> np.ndarray:
+    """Seeded control values theta, shape (2, controls, controls), U(-2h, 2h)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-2.0 * h, 2.0 * h, size=(2, controls, controls))
+
+
+def displaced_points(n1: int, n2: int, h: float, theta: np.ndarray) -> np.ndarray:
+    """y' = h (j1, j2) + u_theta(j), u_c = B1 theta_c B2^T; shape (n1, n2, 2).
+    Since the basis rows sum to 1 and are nonnegative, |u_c| <= max |theta_c|."""
+    G = theta.shape[1]
+    B1 = displacement_basis(n1, G)
+    B2 = displacement_basis(n2, G)
+    j1, j2 = np.meshgrid(np.arange(n1), np.arange(n2), indexing="ij")
+    y = np.stack([h * j1, h * j2], axis=-1).astype(np.float64)
+    y[..., 0] += B1 @ theta[0] @ B2.T
+    y[..., 1] += B1 @ theta[1] @ B2.T
+    return y

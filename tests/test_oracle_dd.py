@@ -255,3 +255,26 @@ def test_translation_shift_is_the_line_maximiser_and_keeps_the_solution():
         sols.append(dd.solve_cell(mu_x, nu_y, r, beta0, C, p.eps, p.lam, 1e-14 * mu_x.sum(), o))
     assert sols[1]["iters"] < sols[0]["iters"]
     np.testing.assert_allclose(sols[1]["px"], sols[0]["px"], rtol=1e-6)
+
+
+def test_dd_with_displaced_support_converges_to_global_optimum():
+    # moved Y points y' (cost |x - y'|^2, no longer separable): the DD limit is
+    # still the unique optimum of the global problem with the same cost
+    from paper_2410_08859_amd.inputs import displaced_points, displacement_theta
+    n = 8
+    p0 = small_problem(n, 2)
+    y = displaced_points(n, n, 1.0 / n, displacement_theta(53, 1.0 / n))
+    p = dd.make_problem(p0.mu, p0.nu, p0.eps, p0.lam, p0.h, 2, ypos=y)
+    C = dd.full_cost(p)
+    pts = uot.grid_points(n, n, p.h)
+    np.testing.assert_allclose(C, uot.sq_cost(pts, y.reshape(-1, 2)))
+    assert not np.allclose(C, uot.sq_cost(pts, pts))
+    sol = uot.sinkhorn(p.mu, p.nu, C, p.eps, p.lam, tol=None, step_tol=1e-15)
+    pi = uot.plan(sol["alpha"], sol["beta"], p.mu, p.nu, C, p.eps)
+    st = dd.init_product(p, dense_plan=True)
+    opt = dd.Options(cap=8, trunc=0.0, getweights="swift", err=1e-15, max_iter=20000,
+                     translate=True)
+    dd.run(p, st, 160, opt)
+    np.testing.assert_allclose(st.plan, pi, rtol=5e-6, atol=1e-15)
+    cert = dd.certificate(p, st.abar)
+    assert cert["rel"] < 1e-12
