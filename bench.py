@@ -41,7 +41,7 @@ def workload_config(name, precision, max_inner, cap):
         box_margin=2, box_cap=cap)
 
 
-def cpu_baseline(name, max_inner, budget_s=15.0):
+def cpu_baseline(name, max_inner, cap, budget_s=15.0):
     """The oracle timed on a bounded sample of the same workload: the cell
     solves of the first A cells of the first half-iteration, until the budget
     is spent.  Single-threaded numpy."""
@@ -51,7 +51,8 @@ def cpu_baseline(name, max_inner, budget_s=15.0):
     mu, nu = workload_marginals(name)
     p = dd.make_problem(mu, nu, w["eps_h2"] / n ** 2, w["lam"], 1.0 / n, w["cell"])
     st = dd.init_block(p)
-    opt = dd.Options(err=2e-5, max_iter=max_inner, trunc=1e-15, lenience=0.005, margin=2, cap=64)
+    opt = dd.Options(err=2e-5, max_iter=max_inner, trunc=1e-15, lenience=0.005, margin=2, cap=cap,
+                     translate=True)
     P = dd.aggregate(p, st.boxes)
     cells = dd.composite_cells(p, "A")
     t0 = time.perf_counter()
@@ -69,10 +70,25 @@ def cpu_baseline(name, max_inner, budget_s=15.0):
                       f"({n}x{n}, FP64 dense numpy, Err 2e-5, max {max_inner} inner iterations)"}
 
 
+def copy_probe(mib):
+    """One plain device copy of `mib` MiB (a reference dispatch of known HBM
+    traffic for the profiler's FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def run(args):
     import torch
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
     mu, nu = workload_marginals(args.workload)
     cfg = workload_config(args.workload, args.precision, args.max_inner, args.cap)
     stream = torch.cuda.current_stream(dev)
@@ -128,7 +144,7 @@ def run(args):
                         "half_iters": score["half_iters"]},
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.max_inner, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.max_inner, args.cap, args.cpu_budget)
     return out
 
 
@@ -143,6 +159,8 @@ def main():
     ap.add_argument("--cap", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="MiB of a plain device copy run once before the solver (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build",

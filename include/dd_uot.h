@@ -55,9 +55,10 @@ typedef struct {
   double lambda, eps;        /* > 0 */
   int32_t cell;              /* basic cell side s; composite = 2 x 2 basic cells,
                                 partition B offset by s (Sec. 4.4); 2*s <= 16 */
-  int32_t precision;         /* 64: FP64 cell arithmetic; 32: FP32 log-sum-exp
-                                on per-cell re-centred residuals, FP64 bases,
-                                reductions and scores */
+  int32_t precision;         /* 64: FP64 cell arithmetic; 32: cell potentials
+                                in FP64, FP32 exponentials of FP64 differences
+                                to a per-output shift, FP32 Newton; FP64
+                                reductions, scores and certificate */
   int32_t getweights;        /* DDUOT_GW_* ; swift is the default */
   int32_t init;              /* DDUOT_INIT_BLOCK (nu_i = nu on block i) or
                                 DDUOT_INIT_PRODUCT (pi = mu x nu, Sec. 4.2) */
@@ -98,7 +99,7 @@ typedef struct {
   double dual;               /* D(alpha_bar, beta_hat) */
   double pd_gap;             /* primal - dual = lambda KL(P_X pi_hat | e^{-alpha/lambda} mu),
                                 eq. PD-gap-KL with J = I */
-  double rel_pd_gap;         /* pd_gap / dual (Sec. 4.4 solution quality) */
+  double rel_pd_gap;         /* pd_gap / |dual| (Sec. 4.4 solution quality) */
   double l1_err_x;           /* || P_X pi - e^{-alpha_bar/lambda} mu ||_1 (state plan) */
   double l1_err_y;           /* || P_Y pi - e^{-beta_hat/lambda} nu ||_1 (state plan) */
   double mass_x, mass_y;     /* |P_X pi|, |P_Y pi| of the state plan */
@@ -122,6 +123,20 @@ int dd_uot_init(const dduot_config* cfg, const double* mu, const double* nu,
    GetWeights decides per problem.  mus[k], nus[k]: host arrays of problem k. */
 int dd_uot_init_batch(int32_t nprob, const dduot_config* cfgs, const double* const* mus,
                       const double* const* nus, void* hip_stream, dduot_handle** out);
+
+/* Moved Y points (the differentiable form): the Y masses sit at y' instead of
+   the grid, cost c(x, y') = |x - y'|^2, which is no longer separable, so the
+   cell solves and the certificate use dense sums over explicit point pairs.
+   ypos: host, n1*n2*2 doubles (y'_1, y'_2 of grid point j, row-major), finite;
+   needs h > 0.  Boxes and partitions stay those of the grid indices, so
+   displacements should be small against the cell size.
+   dd_uot_init_batch_moved: ypos[k] for every problem, or ypos == NULL for
+   none (all problems of a handle share one kind). */
+int dd_uot_init_moved(const dduot_config* cfg, const double* mu, const double* nu,
+                      const double* ypos, void* hip_stream, dduot_handle** out);
+int dd_uot_init_batch_moved(int32_t nprob, const dduot_config* cfgs, const double* const* mus,
+                            const double* const* nus, const double* const* ypos,
+                            void* hip_stream, dduot_handle** out);
 
 /* Set eps of problem `prob` (epsilon-scaling, Sec. 4.4).  The tracked scores
    were computed for the old eps, so the next half-iteration of that problem
@@ -172,6 +187,14 @@ int dd_uot_potentials(dduot_handle* h, int32_t prob, double* alpha, double* beta
    dmu, dnu: host, n1*n2 doubles each (either may be NULL). */
 int dd_uot_backward(dduot_handle* h, int32_t prob, double gout, double* dmu, double* dnu);
 
+/* Gradient of the optimal value with respect to the Y positions at the
+   certificate plan pi_hat: dW/dy'(y) = sum_x pi_hat(x, y) 2 (y' - x) (the
+   cost derivative integrated against the plan; exact at the optimum), for
+   the grid or the moved points, scaled by gout.  The plan is recomputed on
+   the fly by dense pruned sums (no stored plan).  Call after dd_uot_score.
+   dypos: host, n1*n2*2 doubles.  Needs h > 0. */
+int dd_uot_backward_ypos(dduot_handle* h, int32_t prob, double gout, double* dypos);
+
 /* Cell-kernel timing with HIP events recorded on the handle's stream around
    every cell-solve launch (enable != 0 turns it on and clears the totals).
    dd_uot_kernel_time returns the number of timed launches and their summed
@@ -180,6 +203,54 @@ int dd_uot_backward(dduot_handle* h, int32_t prob, double gout, double* dmu, dou
 int dd_uot_set_timing(dduot_handle* h, int32_t enable);
 int dd_uot_kernel_time(dduot_handle* h, int64_t* launches, double* total_ms,
                        double* algo_bytes);
+
+/* ---- Multiscale (Sec. 4.4 "Multi-scale and eps-scaling") ----------------- */
+
+/* New handle for the grid with twice the points per axis, started from the
+   refined state of the single problem of `coarse`: every coarse plan entry
+   is split in proportion to the fine masses inside its 2 x 2 points, a fine
+   basic cell takes the share |mu(X_i)| / |mu(X_I)| of the refined Y-marginal
+   of its coarse basic cell I (boxes double, then truncate at cfg->trunc and
+   shrink; a box wider than box_cap keeps its central box_cap rows/columns,
+   see dd_uot_refine_clipped).  cfg: the fine problem (n = 2 n_coarse,
+   cell = coarse cell or twice it, same precision); mu, nu: host fine
+   marginals, whose 2 x 2 sums should be the coarse ones.  The first
+   half-iteration of the new handle is greedy (the tracked pieces are
+   estimates until then).  `coarse` is left unchanged. */
+int dd_uot_refine(dduot_handle* coarse, const dduot_config* cfg, const double* mu,
+                  const double* nu, void* hip_stream, dduot_handle** out);
+/* Basic boxes clipped by the refinement that created h (0 otherwise). */
+int32_t dd_uot_refine_clipped(const dduot_handle* h);
+
+typedef struct {
+  int32_t levels;            /* layers; the coarsest has n / 2^(levels-1) points per axis */
+  int32_t coarse_cell;       /* basic cell side on all but the finest layer */
+  double eps_start_h2;       /* eps at the start of a layer, in units of its h^2 (paper: 2) */
+  double eps_end_h2;         /* eps at the end of a coarser layer, same units (paper: 1/2);
+                                eps halves between, with halves_per_stage steps each */
+  int32_t halves_per_stage;  /* half-iterations per eps stage */
+  int32_t final_max_halves;  /* cap on half-iterations after the finest stage */
+  int32_t check_every;       /* certificate (dd_uot_score) every this many */
+  double target_rel_gap;     /* stop once the relative primal-dual gap is below */
+} dduot_multiscale;
+
+/* levels 6, coarse_cell 4, eps 2 h^2 -> h^2/2 per layer, 4 half-iterations per
+   stage, at most 200 final half-iterations, certificate every 4, target 1e-6. */
+void dd_uot_default_multiscale(dduot_multiscale* m);
+
+/* Coarse-to-fine solve with eps-scaling: coarsen (mu, nu) by 2 x 2 sums to
+   `levels` layers; on the coarsest start from the product plan if it fits
+   box_cap, else the block start; on every layer run the eps stages, then
+   refine (dd_uot_refine); on the finest layer continue to cfg->eps and then
+   iterate until the certificate's relative gap is <= target_rel_gap or
+   final_max_halves are done.  trace (nullable, trace_cap triples): one
+   (total half-iterations, elapsed ms since the call, relative gap) per
+   certificate of the final stage; *trace_len gets their count.  *out
+   receives the finest handle (its state, score, backward). */
+int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_multiscale* ms,
+                            const double* mu, const double* nu, void* hip_stream,
+                            dduot_handle** out, double* trace, int32_t trace_cap,
+                            int32_t* trace_len);
 
 int dd_uot_synchronize(dduot_handle* h);
 int32_t dd_uot_num_problems(const dduot_handle* h);

@@ -47,6 +47,7 @@ them also fixed in the design notes):
   R9 GetWeights: greedy theta = 1; safe theta = 1/n with n the number of cells
      updated in the step; swift takes greedy iff
      Ebar_greedy <= Ebar_cur + lenience |Ebar_cur|, else safe.
+  R10 multiscale refinement (warm start of a finer layer): see `refine`.
 """
 from __future__ import annotations
 
@@ -536,6 +537,58 @@ def set_eps(p: Problem, st: State, eps: float):
     which makes every Hbar_i exact again."""
     p.eps = float(eps)
     st.force_greedy = True
+
+
+# --------------------------------------------------------------------------
+# multiscale (Sec. 4.4 "Multi-scale and eps-scaling")
+# --------------------------------------------------------------------------
+def coarsen(a):
+    """Masses of the next coarser layer: sums over 2 x 2 blocks of points."""
+    n1, n2 = a.shape
+    return a.reshape(n1 // 2, 2, n2 // 2, 2).sum(axis=(1, 3))
+
+
+def refine(pc: Problem, stc: State, pf: Problem, trunc: float, cap: int) -> State:
+    """Warm start of the finer layer from a coarse DD state.
+
+    Reading R10: the coarse plan is carried to the fine grid by splitting each
+    entry pi_c(X, Y) in proportion to the fine masses inside the 2 x 2 blocks
+    X and Y; the state keeps only basic-cell Y-marginals, so a fine basic
+    cell i inside the coarse basic cell I takes the share |mu_f(X_i)| /
+    |mu_c(X_I)| of the refined marginal of I.  Boxes double, then entries
+    below `trunc` are dropped and the box shrinks (R7); a box wider than
+    `cap` keeps its central `cap` rows / columns.  The tracked pieces are
+    scaled alike (estimates: the next step is forced greedy)."""
+    ones = np.ones((2, 2))
+    nbasic = pf.nb1 * pf.nb2
+    boxes, hbar = [], np.zeros(nbasic)
+    for b in range(nbasic):
+        rect = basic_rect(pf, b)
+        x1, x2 = rect[0], rect[1]
+        I1, I2 = (x1 // 2) // pc.s1, (x2 // 2) // pc.s2
+        I = I1 * pc.nb2 + I2
+        crect = basic_rect(pc, I)
+        f = pf.mu[x1:x1 + rect[2], x2:x2 + rect[3]].sum() / \
+            pc.mu[crect[0]:crect[0] + crect[2], crect[1]:crect[1] + crect[3]].sum()
+        hbar[b] = f * stc.hbar[I]
+        o1, o2, arr = stc.boxes[I]
+        if arr.size == 0:
+            boxes.append((2 * o1, 2 * o2, np.zeros((0, 0))))
+            continue
+        l1, l2 = arr.shape
+        fine = np.kron(arr / pc.nu[o1:o1 + l1, o2:o2 + l2], ones) * \
+            pf.nu[2 * o1:2 * (o1 + l1), 2 * o2:2 * (o2 + l2)] * f
+        t1, t2, tarr = truncate_to_box(2 * o1, 2 * o2, fine, trunc)
+        if tarr.shape[0] > cap:
+            k = (tarr.shape[0] - cap) // 2
+            t1, tarr = t1 + k, tarr[k:k + cap]
+        if tarr.shape[1] > cap:
+            k = (tarr.shape[1] - cap) // 2
+            t2, tarr = t2 + k, tarr[:, k:k + cap]
+        boxes.append((t1, t2, tarr.copy()))
+    px = np.kron(stc.px / pc.mu, ones) * pf.mu
+    abar = np.kron(stc.abar, ones)
+    return State(boxes, px, hbar, abar, force_greedy=True)
 
 
 # --------------------------------------------------------------------------

@@ -25,7 +25,9 @@ EXPORTED = (
     "dd_uot_iterate", "dd_uot_history", "dd_uot_score", "dd_uot_marginals",
     "dd_uot_basic_marginal", "dd_uot_potentials", "dd_uot_backward", "dd_uot_set_timing",
     "dd_uot_kernel_time", "dd_uot_synchronize", "dd_uot_num_problems", "dd_uot_destroy",
-    "dd_uot_last_error",
+    "dd_uot_last_error", "dd_uot_refine", "dd_uot_refine_clipped", "dd_uot_default_multiscale",
+    "dd_uot_solve_multiscale", "dd_uot_init_moved", "dd_uot_init_batch_moved",
+    "dd_uot_backward_ypos",
 )
 
 
@@ -63,6 +65,16 @@ class dduot_score(C.Structure):
     ]
 
 
+class dduot_multiscale(C.Structure):
+    _fields_ = [
+        ("levels", C.c_int32), ("coarse_cell", C.c_int32),
+        ("eps_start_h2", C.c_double), ("eps_end_h2", C.c_double),
+        ("halves_per_stage", C.c_int32), ("final_max_halves", C.c_int32),
+        ("check_every", C.c_int32),
+        ("target_rel_gap", C.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -74,6 +86,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not built; run paper_2410_08859_amd/build.py "
                            "(or __graft_entry__.build())")
+    # One HIP runtime per process: when PyTorch is installed its runtime
+    # (same soname) is loaded first, so the library and torch share it.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     P = C.POINTER
     dp = P(C.c_double)
@@ -96,6 +114,15 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dd_uot_num_problems": (C.c_int32, [H]),
         "dd_uot_destroy": (None, [H]),
         "dd_uot_last_error": (C.c_char_p, []),
+        "dd_uot_refine": (C.c_int, [H, P(dduot_config), dp, dp, C.c_void_p, P(H)]),
+        "dd_uot_init_moved": (C.c_int, [P(dduot_config), dp, dp, dp, C.c_void_p, P(H)]),
+        "dd_uot_init_batch_moved": (C.c_int, [C.c_int32, P(dduot_config), P(dp), P(dp), P(dp),
+                                              C.c_void_p, P(H)]),
+        "dd_uot_backward_ypos": (C.c_int, [H, C.c_int32, C.c_double, dp]),
+        "dd_uot_refine_clipped": (C.c_int32, [H]),
+        "dd_uot_default_multiscale": (None, [P(dduot_multiscale)]),
+        "dd_uot_solve_multiscale": (C.c_int, [P(dduot_config), P(dduot_multiscale), dp, dp,
+                                              C.c_void_p, P(H), dp, C.c_int32, P(C.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -232,3 +259,69 @@ def dd_uot_num_problems(h):
 def dd_uot_destroy(h):
     if h:
         load().dd_uot_destroy(h)
+
+
+def dd_uot_refine(coarse, cfg: dduot_config, mu, nu, stream=None):
+    mu = _grid(mu, cfg.n1, cfg.n2)
+    nu = _grid(nu, cfg.n1, cfg.n2)
+    h = C.c_void_p()
+    _check(load().dd_uot_refine(coarse, C.byref(cfg), _dptr(mu), _dptr(nu), stream, C.byref(h)))
+    return h
+
+
+def dd_uot_refine_clipped(h):
+    return load().dd_uot_refine_clipped(h)
+
+
+def dd_uot_default_multiscale(**kw) -> dduot_multiscale:
+    m = dduot_multiscale()
+    load().dd_uot_default_multiscale(C.byref(m))
+    for k, v in kw.items():
+        setattr(m, k, v)
+    return m
+
+
+def dd_uot_solve_multiscale(cfg: dduot_config, ms: dduot_multiscale, mu, nu, stream=None,
+                            trace_cap=1024):
+    """Returns (handle, trace) with trace rows (half-iterations, elapsed ms, rel gap)."""
+    mu = _grid(mu, cfg.n1, cfg.n2)
+    nu = _grid(nu, cfg.n1, cfg.n2)
+    h = C.c_void_p()
+    tr = np.zeros(3 * trace_cap)
+    n = C.c_int32()
+    _check(load().dd_uot_solve_multiscale(C.byref(cfg), C.byref(ms), _dptr(mu), _dptr(nu), stream,
+                                          C.byref(h), _dptr(tr), trace_cap, C.byref(n)))
+    return h, tr[: 3 * n.value].reshape(-1, 3)
+
+
+def dd_uot_init_moved(cfg: dduot_config, mu, nu, ypos, stream=None):
+    """ypos: (n1, n2, 2) coordinates y' of the Y points."""
+    mu = _grid(mu, cfg.n1, cfg.n2)
+    nu = _grid(nu, cfg.n1, cfg.n2)
+    yp = np.ascontiguousarray(ypos, dtype=np.float64)
+    if yp.size != 2 * cfg.n1 * cfg.n2:
+        raise ValueError("ypos must hold n1*n2*2 coordinates")
+    h = C.c_void_p()
+    _check(load().dd_uot_init_moved(C.byref(cfg), _dptr(mu), _dptr(nu), _dptr(yp), stream,
+                                    C.byref(h)))
+    return h
+
+
+def dd_uot_init_batch_moved(cfgs, mus, nus, yposs, stream=None):
+    n = len(cfgs)
+    arr = (dduot_config * n)(*cfgs)
+    mus = [_grid(m, c.n1, c.n2) for m, c in zip(mus, cfgs)]
+    nus = [_grid(v, c.n1, c.n2) for v, c in zip(nus, cfgs)]
+    yps = [np.ascontiguousarray(y, dtype=np.float64) for y in yposs]
+    pm = (C.POINTER(C.c_double) * n)(*[_dptr(m) for m in mus])
+    pn = (C.POINTER(C.c_double) * n)(*[_dptr(v) for v in nus])
+    py = (C.POINTER(C.c_double) * n)(*[_dptr(y) for y in yps])
+    h = C.c_void_p()
+    _check(load().dd_uot_init_batch_moved(n, arr, pm, pn, py, stream, C.byref(h)))
+    return h
+
+
+def dd_uot_backward_ypos(h, prob, n1, n2, gout=1.0):
+    out = np.zeros(2 * n1 * n2)
+    _check(load().dd_uot_backward_ypos(h, prob, gout, _dptr(out)))
+    return out.reshape(n1, n2, 2)

@@ -7,14 +7,15 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <string>
 #include <vector>
 
 namespace dduot {
 hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int precision,
-                             hipStream_t st);
+                             bool moved, hipStream_t st);
 hipError_t set_cell_lds_limit(size_t bytes);
-size_t cell_lds_bytes(int cap, int precision);
+size_t cell_lds_bytes(int cap, int precision, bool moved);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st);
 hipError_t launch_aggregate(const Box* box, const double* vals, long cap2, const int* basic_prob,
                             const Prob* probs, double* P, int nbasic, hipStream_t st);
@@ -25,11 +26,36 @@ hipError_t launch_getweights(const Dev& d, int part, int rec, int nprob, hipStre
 hipError_t launch_mix(const Dev& d, int part, int nbasic, int cap, hipStream_t st);
 hipError_t set_mix_lds_limit(size_t bytes);
 hipError_t launch_certificate(const Prob& p, const double* alpha, const double* mu, const double* nu,
-                              const double* px, const double* P, double* bhat, double* dmu,
-                              double* dnu, double* scratch, double* part, int nblk, hipStream_t st);
+                              const double* px, const double* P, const double* ydel, double* bhat,
+                              double* dmu, double* dnu, double* scratch, double* part, int nblk,
+                              hipStream_t st);
+hipError_t launch_grad_ypos(const Prob& p, const double* alpha, const double* mu, const double* nu,
+                            const double* ydel, const double* bhat, double gout, double* scratch,
+                            double* mom, double* out, hipStream_t st);
 hipError_t set_rows_lds_limit(size_t bytes);
 hipError_t launch_scatter_slots(const double* src, const long* off, double* vals, long cap2, int nbasic,
                                 hipStream_t st);
+struct RefineArgs {
+  const Box* cbox;
+  const double* cvals;
+  long ccap2;
+  const double* mu_c;
+  const double* nu_c;
+  const double* chbar;
+  int cn2, cs, cnb2;
+  const int2* fxy;
+  const double* mu_f;
+  const double* nu_f;
+  int fn2, fs, fcap;
+  long fcap2;
+  double trunc;
+  Box* fbox;
+  double* fvals;
+  double* fhbar;
+  int* nclip;
+};
+hipError_t launch_refine(const RefineArgs& A, int fnbasic, const double* px_c, const double* abar_c,
+                         double* px_f, double* abar_f, int fn1, hipStream_t st);
 }  // namespace dduot
 
 using namespace dduot;
@@ -83,6 +109,9 @@ struct dduot_handle {
   double* d_terms = nullptr;
   double* d_fall = nullptr;
   double *d_ws_lnv = nullptr, *d_ws_lrr = nullptr;
+  double* d_ydel = nullptr;
+  double *d_mom = nullptr, *d_dy = nullptr;   // Y-position gradient (allocated on first use)
+  bool moved = false;
   int *d_chunk_prob = nullptr, *d_chunk_start = nullptr, *d_chunk_len = nullptr;
   double* d_chunk_part = nullptr;
   double *d_theta = nullptr, *d_hist = nullptr;
@@ -92,6 +121,7 @@ struct dduot_handle {
   bool have_cert_prob[1] = {false};
   std::vector<int> cert_done;   // per problem: certificate arrays valid
   // timing
+  int clipped = 0;      // refined basic boxes clipped to the slot size
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   std::vector<long long> timed_recs;
@@ -189,8 +219,19 @@ static std::vector<std::vector<int>> axis_groups(int nb, bool offset) {
 }
 
 static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const double* const* mus,
-                 const double* const* nus) {
+                 const double* const* nus, const double* const* yps) {
   for (int k = 0; k < nprob; ++k) CHK(validate(&cfgs[k], mus[k], nus[k], k));
+  // moved Y points: all problems of a handle or none (one kernel variant)
+  h->moved = yps && yps[0];
+  for (int k = 0; k < nprob; ++k) {
+    const bool mk = yps && yps[k];
+    if (mk != h->moved) return fail(DDUOT_EINVAL, "moved Y points: give them for all problems or none");
+    if (!mk) continue;
+    if (!(cfgs[k].h > 0.0)) return fail(DDUOT_EINVAL, "moved Y points need h > 0");
+    const long n = 2L * cfgs[k].n1 * cfgs[k].n2;
+    for (long i = 0; i < n; ++i)
+      if (!isfinite(yps[k][i])) return fail(DDUOT_EINVAL, "moved Y points must be finite");
+  }
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   int max_lds = 0;
@@ -204,7 +245,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
     h->cap = std::max(h->cap, cfgs[k].box_cap);
   }
   h->cap2 = (long)h->cap * h->cap;
-  const size_t lds_cell = cell_lds_bytes(h->cap, h->precision);
+  const size_t lds_cell = cell_lds_bytes(h->cap, h->precision, h->moved);
   const size_t lds_mix = sizeof(double) * h->cap2;
   if ((long)lds_cell > max_lds || (long)lds_mix > max_lds)
     return fail(DDUOT_EINVAL, "box_cap too large for the LDS of one workgroup");
@@ -230,6 +271,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
     p.getweights = c.getweights; p.fixed_iters = c.fixed_inner_iters; p.max_iter = c.sinkhorn_max_iter;
     p.margin = c.box_margin; p.cap = c.box_cap; p.precision = c.precision;
     p.translate = c.translate;
+    p.moved = h->moved ? 1 : 0;
     p.grid_off = (int)goff;
     p.basic_off = (int)basic_prob.size();
     p.nbasic = p.nb1 * p.nb2;
@@ -290,6 +332,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
 
   // host start state (Sec. 4.2 product start, or the block start)
   std::vector<double> mu_all(h->ngrid), nu_all(h->ngrid), px(h->ngrid), hbar(h->nbasic);
+  std::vector<double> ydel_all(h->moved ? 2 * (size_t)h->ngrid : 0);
   std::vector<Box> box(h->nbasic);
   for (int k = 0; k < nprob; ++k) {
     const Prob& p = h->probs[k];
@@ -299,13 +342,17 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
     const double* mu = mus[k];
     const double* nu = nus[k];
     const double h2 = p.h * p.h;
+    // Y coordinates in pixel units: the grid index, or y'/h for moved points
+    const double* yp = h->moved ? yps[k] : nullptr;
+    auto yc = [&](long g, int ax, int idx) -> double { return yp ? yp[2 * g + ax] / p.h : (double)idx; };
     // moments of nu over the whole grid (product start)
     double N0 = 0, N1a = 0, N1b = 0, N2 = 0;
     if (cfgs[k].init == DDUOT_INIT_PRODUCT) {
       for (int i1 = 0; i1 < p.n1; ++i1)
         for (int i2 = 0; i2 < p.n2; ++i2) {
-          const double v = nu[(long)i1 * p.n2 + i2];
-          N0 += v; N1a += v * i1; N1b += v * i2; N2 += v * ((double)i1 * i1 + (double)i2 * i2);
+          const long g = (long)i1 * p.n2 + i2;
+          const double v = nu[g], u1 = yc(g, 0, i1), u2 = yc(g, 1, i2);
+          N0 += v; N1a += v * u1; N1b += v * u2; N2 += v * (u1 * u1 + u2 * u2);
         }
     }
     for (int b = 0; b < p.nbasic; ++b) {
@@ -318,8 +365,9 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
         for (int i2 = 0; i2 < p.s; ++i2) {
           const long g = (long)(x1 + i1) * p.n2 + (x2 + i2);
           const double m = mu[g], v = nu[g];
+          const double u1 = yc(g, 0, x1 + i1) - x1, u2 = yc(g, 1, x2 + i2) - x2;
           m0 += m; m1a += m * i1; m1b += m * i2; m2 += m * ((double)i1 * i1 + (double)i2 * i2);
-          v0 += v; v1a += v * i1; v1b += v * i2; v2 += v * ((double)i1 * i1 + (double)i2 * i2);
+          v0 += v; v1a += v * u1; v1b += v * u2; v2 += v * (u1 * u1 + u2 * u2);
           const double a1 = x1 + i1, a2 = x2 + i2;
           g1 += m * a1; g1b += m * a2; g2 += m * (a1 * a1 + a2 * a2);
         }
@@ -357,6 +405,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_basic_xy, h->nbasic));
   CHK(dalloc(h, &h->d_basic_cell[0], h->nbasic));
   CHK(dalloc(h, &h->d_basic_cell[1], h->nbasic));
+  CHK(dalloc(h, &h->d_ydel, h->moved ? 2 * (size_t)h->ngrid : 1));
   CHK(dalloc(h, &h->d_mu, h->ngrid));
   CHK(dalloc(h, &h->d_nu, h->ngrid));
   CHK(dalloc(h, &h->d_P, h->ngrid));
@@ -375,8 +424,10 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_bytes, h->cells.size()));
   CHK(dalloc(h, &h->d_terms, h->cells.size()));
   CHK(dalloc(h, &h->d_fall, h->cells.size()));
-  CHK(dalloc(h, &h->d_ws_lnv, h->cells.size() * (size_t)h->cap2));
-  CHK(dalloc(h, &h->d_ws_lrr, h->cells.size() * (size_t)h->cap2));
+  // per-cell FP64 workspace of log nu and log r (FP32 kernels keep them in LDS)
+  const size_t ws = h->precision == 64 ? h->cells.size() * (size_t)h->cap2 : 1;
+  CHK(dalloc(h, &h->d_ws_lnv, ws));
+  CHK(dalloc(h, &h->d_ws_lrr, ws));
   CHK(dalloc(h, &h->d_chunk_prob, h->nchunk));
   CHK(dalloc(h, &h->d_chunk_start, h->nchunk));
   CHK(dalloc(h, &h->d_chunk_len, h->nchunk));
@@ -388,7 +439,8 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_bhat, h->ngrid));
   CHK(dalloc(h, &h->d_dmu, h->ngrid));
   CHK(dalloc(h, &h->d_dnu, h->ngrid));
-  CHK(dalloc(h, &h->d_scratch, 5 * (size_t)h->maxgrid));
+  // certificate scratch: 5 grids, then the per-block table of the dense sums
+  CHK(dalloc(h, &h->d_scratch, 6 * (size_t)h->maxgrid + 4096));
   CHK(dalloc(h, &h->d_cpart, (size_t)kCertBlocks * 8));
   h->cert_done.assign(nprob, 0);
 
@@ -401,6 +453,20 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
     HIPCHK(hipMemcpyAsync(h->d_basic_cell[part], bcell[part].data(), sizeof(int) * h->nbasic, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h->d_mu, mu_all.data(), sizeof(double) * h->ngrid, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h->d_nu, nu_all.data(), sizeof(double) * h->ngrid, hipMemcpyHostToDevice, st));
+  if (h->moved) {
+    // displacement in pixel units, y'/h - j, per grid point
+    for (int k = 0; k < nprob; ++k) {
+      const Prob& p = h->probs[k];
+      for (int i1 = 0; i1 < p.n1; ++i1)
+        for (int i2 = 0; i2 < p.n2; ++i2) {
+          const long g = (long)i1 * p.n2 + i2;
+          ydel_all[2 * (p.grid_off + g)] = yps[k][2 * g] / p.h - i1;
+          ydel_all[2 * (p.grid_off + g) + 1] = yps[k][2 * g + 1] / p.h - i2;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(h->d_ydel, ydel_all.data(), sizeof(double) * ydel_all.size(),
+                          hipMemcpyHostToDevice, st));
+  }
   HIPCHK(hipMemcpyAsync(h->d_px, px.data(), sizeof(double) * h->ngrid, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h->d_hbar, hbar.data(), sizeof(double) * h->nbasic, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h->d_box, box.data(), sizeof(Box) * h->nbasic, hipMemcpyHostToDevice, st));
@@ -476,6 +542,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   d.cell_fall = h->d_fall;
   d.ws_lnv = h->d_ws_lnv;
   d.ws_lrr = h->d_ws_lrr;
+  d.ydel = h->d_ydel;
   d.chunk_part = h->d_chunk_part;
   d.theta = h->d_theta;
   d.hist = h->d_hist;
@@ -497,14 +564,16 @@ static void release(dduot_handle* h) {
   delete h;
 }
 
-extern "C" int dd_uot_init_batch(int32_t nprob, const dduot_config* cfgs, const double* const* mus,
-                                 const double* const* nus, void* hip_stream, dduot_handle** out) {
+extern "C" int dd_uot_init_batch_moved(int32_t nprob, const dduot_config* cfgs,
+                                       const double* const* mus, const double* const* nus,
+                                       const double* const* ypos, void* hip_stream,
+                                       dduot_handle** out) {
   if (!out) return fail(DDUOT_EINVAL, "out is NULL");
   *out = nullptr;
   if (nprob < 1 || !cfgs || !mus || !nus) return fail(DDUOT_EINVAL, "need at least one problem");
   dduot_handle* h = new dduot_handle();
   h->stream = static_cast<hipStream_t>(hip_stream);
-  int r = build(h, nprob, cfgs, mus, nus);
+  int r = build(h, nprob, cfgs, mus, nus, ypos);
   if (r != DDUOT_OK) {
     std::string keep = g_err;
     release(h);
@@ -515,9 +584,20 @@ extern "C" int dd_uot_init_batch(int32_t nprob, const dduot_config* cfgs, const 
   return DDUOT_OK;
 }
 
+extern "C" int dd_uot_init_batch(int32_t nprob, const dduot_config* cfgs, const double* const* mus,
+                                 const double* const* nus, void* hip_stream, dduot_handle** out) {
+  return dd_uot_init_batch_moved(nprob, cfgs, mus, nus, nullptr, hip_stream, out);
+}
+
 extern "C" int dd_uot_init(const dduot_config* cfg, const double* mu, const double* nu,
                            void* hip_stream, dduot_handle** out) {
-  return dd_uot_init_batch(1, cfg, &mu, &nu, hip_stream, out);
+  return dd_uot_init_batch_moved(1, cfg, &mu, &nu, nullptr, hip_stream, out);
+}
+
+extern "C" int dd_uot_init_moved(const dduot_config* cfg, const double* mu, const double* nu,
+                                 const double* ypos, void* hip_stream, dduot_handle** out) {
+  if (!ypos) return fail(DDUOT_EINVAL, "ypos is NULL");
+  return dd_uot_init_batch_moved(1, cfg, &mu, &nu, &ypos, hip_stream, out);
 }
 
 extern "C" void dd_uot_destroy(dduot_handle* h) {
@@ -562,7 +642,7 @@ static int half_iteration(dduot_handle* h, int part) {
     HIPCHK(hipEventRecord(e0, st));
   }
   const int base = part == 0 ? 0 : h->ncell[0];
-  HIPCHK(launch_cell_solve(d, base, h->ncell[part], h->cap, h->precision, st));
+  HIPCHK(launch_cell_solve(d, base, h->ncell[part], h->cap, h->precision, h->moved, st));
   if (h->timing) {
     HIPCHK(hipEventRecord(e1, st));
     h->events.push_back({e0, e1});
@@ -651,8 +731,8 @@ extern "C" int dd_uot_score(dduot_handle* h, int32_t prob, dduot_score* out) {
   const size_t rows = sizeof(double) * std::max(p.n1, p.n2);
   HIPCHK(set_rows_lds_limit(std::max<size_t>(rows, 1024)));
   HIPCHK(launch_certificate(p, h->d_abar + g, h->d_mu + g, h->d_nu + g, h->d_px + g, h->d_P + g,
-                            h->d_bhat + g, h->d_dmu + g, h->d_dnu + g, h->d_scratch, h->d_cpart,
-                            kCertBlocks, st));
+                            h->moved ? h->d_ydel + 2 * g : nullptr, h->d_bhat + g, h->d_dmu + g,
+                            h->d_dnu + g, h->d_scratch, h->d_cpart, kCertBlocks, st));
   std::vector<double> part((size_t)kCertBlocks * 8), chunks(2 * (size_t)h->nchunk), hb(p.nbasic);
   HIPCHK(hipMemcpyAsync(part.data(), h->d_cpart, sizeof(double) * part.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(chunks.data(), h->d_chunk_part, sizeof(double) * chunks.size(), hipMemcpyDeviceToHost, st));
@@ -673,7 +753,7 @@ extern "C" int dd_uot_score(dduot_handle* h, int32_t prob, dduot_score* out) {
   out->pd_gap = pd;
   out->dual = dual;
   out->primal = dual + pd;
-  out->rel_pd_gap = pd / dual;
+  out->rel_pd_gap = pd / fabs(dual);
   out->l1_err_x = s[4];
   out->l1_err_y = s[5];
   out->mass_x = s[6];
@@ -747,6 +827,23 @@ extern "C" int dd_uot_backward(dduot_handle* h, int32_t prob, double gout, doubl
   return DDUOT_OK;
 }
 
+extern "C" int dd_uot_backward_ypos(dduot_handle* h, int32_t prob, double gout, double* dypos) {
+  if (!h || !dypos || prob < 0 || prob >= h->nprob) return fail(DDUOT_EINVAL, "bad arguments");
+  if (!h->cert_done[prob]) return fail(DDUOT_ESTATE, "call dd_uot_score before dd_uot_backward_ypos");
+  const Prob& p = h->probs[prob];
+  if (!(p.h > 0.0)) return fail(DDUOT_EINVAL, "the Y-position gradient needs h > 0");
+  const long n = (long)p.n1 * p.n2;
+  const long g = p.grid_off;
+  if (!h->d_mom) CHK(dalloc(h, &h->d_mom, 2 * (size_t)h->maxgrid));
+  if (!h->d_dy) CHK(dalloc(h, &h->d_dy, 2 * (size_t)h->maxgrid));
+  HIPCHK(launch_grad_ypos(p, h->d_abar + g, h->d_mu + g, h->d_nu + g,
+                          h->moved ? h->d_ydel + 2 * g : nullptr, h->d_bhat + g, gout, h->d_scratch,
+                          h->d_mom, h->d_dy, h->stream));
+  HIPCHK(hipMemcpyAsync(dypos, h->d_dy, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DDUOT_OK;
+}
+
 extern "C" int dd_uot_set_timing(dduot_handle* h, int32_t enable) {
   if (!h) return fail(DDUOT_EINVAL, "null handle");
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -779,5 +876,216 @@ extern "C" int dd_uot_kernel_time(dduot_handle* h, int64_t* launches, double* to
   if (launches) *launches = (int64_t)h->events.size();
   if (total_ms) *total_ms = ms;
   if (algo_bytes) *algo_bytes = bytes;
+  return DDUOT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Multiscale: refinement of a state to the next finer grid, and the driver
+// ---------------------------------------------------------------------------
+extern "C" int dd_uot_refine(dduot_handle* coarse, const dduot_config* cfg, const double* mu,
+                             const double* nu, void* hip_stream, dduot_handle** out) {
+  if (!out) return fail(DDUOT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!coarse || !cfg) return fail(DDUOT_EINVAL, "null handle or config");
+  if (coarse->nprob != 1) return fail(DDUOT_EINVAL, "refinement needs a single-problem handle");
+  if (coarse->moved) return fail(DDUOT_EINVAL, "refinement of moved Y points is not supported");
+  const Prob& pc = coarse->probs[0];
+  if (cfg->n1 != 2 * pc.n1 || cfg->n2 != 2 * pc.n2)
+    return fail(DDUOT_EINVAL, "the fine grid must have twice the coarse points per axis");
+  if (cfg->cell != pc.s && cfg->cell != 2 * pc.s)
+    return fail(DDUOT_EINVAL, "the fine basic cell side must be the coarse one or twice it");
+  if (cfg->precision != coarse->precision)
+    return fail(DDUOT_EINVAL, "coarse and fine precision differ");
+  dduot_config c = *cfg;
+  c.init = DDUOT_INIT_BLOCK;   // placeholder state, overwritten below
+  dduot_handle* h = nullptr;
+  CHK(dd_uot_init(&c, mu, nu, hip_stream, &h));
+  // the coarse work must be complete before the fine stream reads its state
+  if (coarse->stream != h->stream) {
+    hipError_t e = hipStreamSynchronize(coarse->stream);
+    if (e != hipSuccess) {
+      dd_uot_destroy(h);
+      return fail(DDUOT_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    }
+  }
+  int* d_nclip = nullptr;
+  auto body = [&]() -> int {
+    hipStream_t st = h->stream;
+    const Prob& pf = h->probs[0];
+    CHK(dalloc(h, &d_nclip, 1));
+    static const int zero = 0;
+    HIPCHK(hipMemcpyAsync(d_nclip, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+    RefineArgs A{};
+    A.cbox = coarse->d_box;
+    A.cvals = coarse->d_vals;
+    A.ccap2 = coarse->cap2;
+    A.mu_c = coarse->d_mu;
+    A.nu_c = coarse->d_nu;
+    A.chbar = coarse->d_hbar;
+    A.cn2 = pc.n2;
+    A.cs = pc.s;
+    A.cnb2 = pc.nb2;
+    A.fxy = h->d_basic_xy;
+    A.mu_f = h->d_mu;
+    A.nu_f = h->d_nu;
+    A.fn2 = pf.n2;
+    A.fs = pf.s;
+    A.fcap = h->cap;
+    A.fcap2 = h->cap2;
+    A.trunc = pf.trunc;
+    A.fbox = h->d_box;
+    A.fvals = h->d_vals;
+    A.fhbar = h->d_hbar;
+    A.nclip = d_nclip;
+    HIPCHK(launch_refine(A, pf.nbasic, coarse->d_px, coarse->d_abar, h->d_px, h->d_abar, pf.n1, st));
+    // the tracked pieces of the refined state are only estimates: the next
+    // half-iteration is greedy, which recomputes them
+    static const int one = 1;
+    HIPCHK(hipMemcpyAsync(h->d_force, &one, sizeof(int), hipMemcpyHostToDevice, st));
+    int nclip = 0;
+    HIPCHK(hipMemcpyAsync(&nclip, d_nclip, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    h->clipped = nclip;
+    return DDUOT_OK;
+  };
+  int r = body();
+  if (r != DDUOT_OK) {
+    std::string keep = g_err;
+    dd_uot_destroy(h);
+    g_err = keep;
+    return r;
+  }
+  *out = h;
+  return DDUOT_OK;
+}
+
+extern "C" int32_t dd_uot_refine_clipped(const dduot_handle* h) { return h ? h->clipped : 0; }
+
+extern "C" void dd_uot_default_multiscale(dduot_multiscale* m) {
+  memset(m, 0, sizeof(*m));
+  m->levels = 6;
+  m->coarse_cell = 4;
+  m->eps_start_h2 = 2.0;
+  m->eps_end_h2 = 0.5;
+  m->halves_per_stage = 4;
+  m->final_max_halves = 200;
+  m->check_every = 4;
+  m->target_rel_gap = 1e-6;
+}
+
+static double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_multiscale* ms,
+                                       const double* mu, const double* nu, void* hip_stream,
+                                       dduot_handle** out, double* trace, int32_t trace_cap,
+                                       int32_t* trace_len) {
+  if (!out) return fail(DDUOT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (trace_len) *trace_len = 0;
+  if (!cfg || !ms || !mu || !nu) return fail(DDUOT_EINVAL, "null argument");
+  if (trace_cap < 0 || (trace_cap > 0 && !trace)) return fail(DDUOT_EINVAL, "bad trace buffer");
+  const int L = ms->levels;
+  if (L < 1 || L > 12) return fail(DDUOT_EINVAL, "levels must be in [1, 12]");
+  if (!(ms->eps_start_h2 > 0.0) || !(ms->eps_end_h2 > 0.0) || ms->eps_end_h2 > ms->eps_start_h2)
+    return fail(DDUOT_EINVAL, "need 0 < eps_end_h2 <= eps_start_h2");
+  if (ms->halves_per_stage < 1 || ms->final_max_halves < 0 || ms->check_every < 1)
+    return fail(DDUOT_EINVAL, "bad iteration counts");
+  if (cfg->n1 % (1 << (L - 1)) || cfg->n2 % (1 << (L - 1)))
+    return fail(DDUOT_EINVAL, "grid sides must be divisible by 2^(levels-1)");
+  const double t0 = now_ms();
+  // marginals of every layer: 2 x 2 sums of the next finer one
+  std::vector<std::vector<double>> mus(L), nus(L);
+  std::vector<int> n1s(L), n2s(L);
+  mus[L - 1].assign(mu, mu + (size_t)cfg->n1 * cfg->n2);
+  nus[L - 1].assign(nu, nu + (size_t)cfg->n1 * cfg->n2);
+  n1s[L - 1] = cfg->n1;
+  n2s[L - 1] = cfg->n2;
+  for (int l = L - 2; l >= 0; --l) {
+    const int a1 = n1s[l + 1] / 2, a2 = n2s[l + 1] / 2, f2 = n2s[l + 1];
+    n1s[l] = a1;
+    n2s[l] = a2;
+    mus[l].assign((size_t)a1 * a2, 0.0);
+    nus[l].assign((size_t)a1 * a2, 0.0);
+    for (int i1 = 0; i1 < a1; ++i1)
+      for (int i2 = 0; i2 < a2; ++i2)
+        for (int q = 0; q < 4; ++q) {
+          const size_t g = (size_t)(2 * i1 + q / 2) * f2 + (2 * i2 + q % 2);
+          mus[l][(size_t)i1 * a2 + i2] += mus[l + 1][g];
+          nus[l][(size_t)i1 * a2 + i2] += nus[l + 1][g];
+        }
+  }
+  int tl = 0;
+  long long halves_before = 0;   // half-iterations of the coarser layers
+  auto record = [&](dduot_handle* h, double rel) {
+    if (tl < trace_cap) {
+      trace[3 * tl + 0] = (double)(halves_before + h->k);
+      trace[3 * tl + 1] = now_ms() - t0;
+      trace[3 * tl + 2] = rel;
+      ++tl;
+    }
+  };
+  dduot_handle* h = nullptr;
+  for (int l = 0; l < L; ++l) {
+    const double scale = (double)(1 << (L - 1 - l));
+    dduot_config c = *cfg;
+    c.n1 = n1s[l];
+    c.n2 = n2s[l];
+    c.h = cfg->h * scale;
+    c.cell = l == L - 1 ? cfg->cell : std::min(cfg->cell, ms->coarse_cell);
+    const double h2 = c.h * c.h;
+    c.eps = ms->eps_start_h2 * h2;
+    dduot_handle* nh = nullptr;
+    if (l == 0) {
+      c.init = (c.box_cap >= c.n1 && c.box_cap >= c.n2) ? DDUOT_INIT_PRODUCT : DDUOT_INIT_BLOCK;
+      CHK(dd_uot_init(&c, mus[l].data(), nus[l].data(), hip_stream, &nh));
+    } else {
+      const int r = dd_uot_refine(h, &c, mus[l].data(), nus[l].data(), hip_stream, &nh);
+      halves_before += h->k;
+      dd_uot_destroy(h);
+      h = nullptr;
+      if (r != DDUOT_OK) return r;
+    }
+    h = nh;
+    // eps stages of this layer: halve from eps_start down to eps_end (the
+    // finest layer continues to cfg->eps)
+    const double e_end = l == L - 1 ? cfg->eps : ms->eps_end_h2 * h2;
+    double e = c.eps;
+    auto fail_out = [&](int r) {
+      std::string keep = g_err;
+      dd_uot_destroy(h);
+      g_err = keep;
+      return r;
+    };
+    for (;;) {
+      int r = dd_uot_iterate(h, ms->halves_per_stage, nullptr);
+      if (r != DDUOT_OK) return fail_out(r);
+      if (e <= e_end * (1.0 + 1e-12)) break;
+      e = std::max(e * 0.5, e_end);
+      r = dd_uot_set_eps(h, 0, e);
+      if (r != DDUOT_OK) return fail_out(r);
+    }
+    if (l == L - 1) {
+      // final stage: iterate, certificate every check_every half-iterations
+      dduot_score sc;
+      int r = dd_uot_score(h, 0, &sc);
+      if (r != DDUOT_OK) return fail_out(r);
+      record(h, sc.rel_pd_gap);
+      int done = 0;
+      while (!(sc.rel_pd_gap <= ms->target_rel_gap) && done < ms->final_max_halves) {
+        const int k = std::min(ms->check_every, ms->final_max_halves - done);
+        r = dd_uot_iterate(h, k, nullptr);
+        if (r != DDUOT_OK) return fail_out(r);
+        done += k;
+        r = dd_uot_score(h, 0, &sc);
+        if (r != DDUOT_OK) return fail_out(r);
+        record(h, sc.rel_pd_gap);
+      }
+    }
+  }
+  if (trace_len) *trace_len = tl;
+  *out = h;
   return DDUOT_OK;
 }

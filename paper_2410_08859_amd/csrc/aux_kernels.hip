@@ -378,11 +378,16 @@ static hipError_t gauss_lse2d(const double* in, double* out, double* tmp, int n1
   return hipGetLastError();
 }
 
+hipError_t dense_lse(const double* v, const double* qdel, const double* pdel, int n1, int n2,
+                     double ch, double* info, double* out, double* mom, hipStream_t st);
+
 // Certificate of one problem; scratch holds 5 grids.  Partial sums go to part
-// (nblk x 8 doubles).
+// (nblk x 8 doubles).  ydel (moved Y points, else NULL): the cost is not
+// separable and both global log-sum-exps are dense (pruned exactly).
 hipError_t launch_certificate(const Prob& p, const double* alpha, const double* mu, const double* nu,
-                              const double* px, const double* P, double* bhat, double* dmu,
-                              double* dnu, double* scratch, double* part, int nblk, hipStream_t st) {
+                              const double* px, const double* P, const double* ydel, double* bhat,
+                              double* dmu, double* dnu, double* scratch, double* part, int nblk,
+                              hipStream_t st) {
   const long n = (long)p.n1 * p.n2;
   double* a = scratch;
   double* z = scratch + n;
@@ -391,13 +396,50 @@ hipError_t launch_certificate(const Prob& p, const double* alpha, const double* 
   double* S = scratch + 4 * n;
   const int eb = (int)min((n + 255) / 256, (long)4096);
   hipLaunchKernelGGL(k_prep_alpha, dim3(eb), dim3(256), 0, st, alpha, mu, a, n, 1.0 / p.eps);
-  hipError_t e = gauss_lse2d(a, z, tmp, p.n1, p.n2, p.ch, st);
+  double* info = scratch + 5 * n;   // block table of the dense sums
+  hipError_t e = ydel ? dense_lse(a, nullptr, ydel, p.n1, p.n2, p.ch, info, z, nullptr, st)
+                      : gauss_lse2d(a, z, tmp, p.n1, p.n2, p.ch, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_prep_beta, dim3(eb), dim3(256), 0, st, z, nu, bhat, b, n, p.eps, p.kappa);
-  e = gauss_lse2d(b, S, tmp, p.n1, p.n2, p.ch, st);
+  e = ydel ? dense_lse(b, ydel, nullptr, p.n1, p.n2, p.ch, info, S, nullptr, st)
+           : gauss_lse2d(b, S, tmp, p.n1, p.n2, p.ch, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cert_terms, dim3(nblk), dim3(kBlock), 0, st, alpha, bhat, S, z, mu, nu, px, P,
                      n, p.eps, p.lam, p.mass_mu, p.mass_nu, dmu, dnu, part);
+  return hipGetLastError();
+}
+
+// dW/dy' = sum_x pi_hat(x, y) 2 (y' - x) = 2 h P_Y pi_hat(y) (y'/h - E[x | y]) with
+// the conditional mean E[x | y] (pixel units) from the moments of the Y-update sum.
+__global__ void k_grad_ypos(const double* mom, const double* z, const double* bhat, const double* nu,
+                            const double* ydel, int n1, int n2, double eps, double h, double gout,
+                            double* out) {
+  const long n = (long)n1 * n2;
+  for (long g = blockIdx.x * (long)blockDim.x + threadIdx.x; g < n; g += (long)gridDim.x * blockDim.x) {
+    const int j1 = (int)(g / n2), j2 = (int)(g - (long)j1 * n2);
+    const double y1 = ydel ? j1 + ydel[2 * g] : (double)j1;
+    const double y2 = ydel ? j2 + ydel[2 * g + 1] : (double)j2;
+    const double py = nu[g] * exp(bhat[g] / eps + z[g]);
+    out[2 * g] = gout * 2.0 * h * py * (y1 - mom[2 * g]);
+    out[2 * g + 1] = gout * 2.0 * h * py * (y2 - mom[2 * g + 1]);
+  }
+}
+
+// Gradient with respect to the Y positions at the certificate pair (after
+// launch_certificate: bhat set); scratch as above, mom 2 grids.
+hipError_t launch_grad_ypos(const Prob& p, const double* alpha, const double* mu, const double* nu,
+                            const double* ydel, const double* bhat, double gout, double* scratch,
+                            double* mom, double* out, hipStream_t st) {
+  const long n = (long)p.n1 * p.n2;
+  double* a = scratch;
+  double* z = scratch + n;
+  double* info = scratch + 5 * n;
+  const int eb = (int)min((n + 255) / 256, (long)4096);
+  hipLaunchKernelGGL(k_prep_alpha, dim3(eb), dim3(256), 0, st, alpha, mu, a, n, 1.0 / p.eps);
+  hipError_t e = dense_lse(a, nullptr, ydel, p.n1, p.n2, p.ch, info, z, mom, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grad_ypos, dim3(eb), dim3(256), 0, st, mom, z, bhat, nu, ydel, p.n1, p.n2,
+                     p.eps, p.h, gout, out);
   return hipGetLastError();
 }
 

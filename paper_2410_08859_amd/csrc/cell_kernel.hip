@@ -25,11 +25,14 @@
 // with an FP64 shift s equal to the same output's value at the previous
 // Sinkhorn iteration (so the sum is O(1)), the subtraction base_k - s in FP64
 // and exp / accumulation in the kernel precision R.  Terms provably below
-// e^-W of the output are skipped (window from the row maximum).  When the sum
-// leaves [e^-60, e^60] (first iteration, large change) the output is
-// recomputed exactly by a max pass and a sum pass.
+// e^-W of the shift are skipped (window from the row maximum).  When the sum
+// leaves [e^-22, e^60] it is redone once with the shift corrected by its log;
+// when it is not representable (first iteration, very large change) the
+// output is recomputed exactly by a max pass and a sum pass.
 // The Newton solve works in R on the log cell share relative to the FP64
-// reference z/(1+K) (the root when nu_{-J} = 0), finished in FP64.
+// reference z/(1+K) (the root when nu_{-J} = 0).  In FP32 kernels log nu and
+// log r live in LDS as FP32 (a relative perturbation of nu below 1e-6); FP64
+// kernels read them from a per-cell FP64 workspace.
 #include "dd_types.h"
 
 #include <float.h>
@@ -42,12 +45,16 @@ template <typename R>
 struct M;
 template <>
 struct M<float> {
+  static constexpr float kScale = 1.4426950408889634f;   // log2(e): exp(x) = 2^(x log2 e)
+  static __device__ __forceinline__ float ex2s(float x) { return __builtin_amdgcn_exp2f(x); }
   static __device__ __forceinline__ float ex(float x) { return __expf(x); }
   static __device__ __forceinline__ float lg(float x) { return __logf(x); }
   static __device__ __forceinline__ float lg1p(float x) { return log1pf(x); }
 };
 template <>
 struct M<double> {
+  static constexpr double kScale = 1.0;
+  static __device__ __forceinline__ double ex2s(double x) { return exp(x); }
   static __device__ __forceinline__ double ex(double x) { return exp(x); }
   static __device__ __forceinline__ double lg(double x) { return log(x); }
   static __device__ __forceinline__ double lg1p(double x) { return log1p(x); }
@@ -79,19 +86,39 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
   __syncthreads();
 }
 
+// out[r] = max_c a[r*rs + c*cs] for r < rows, c < cols: G consecutive lanes
+// share a row and combine by butterfly shuffles (G divides 64).
+template <int G>
+__device__ __forceinline__ void seg_max(const double* a, int rows, int cols, int rs, int cs,
+                                        double* out) {
+  const int g = threadIdx.x % G;
+  for (int r0 = 0; r0 < rows; r0 += kBlock / G) {
+    const int r = r0 + threadIdx.x / G;
+    double m = -INFINITY;
+    if (r < rows)
+      for (int c = g; c < cols; c += G) m = fmax(m, a[r * rs + c * cs]);
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (g == 0 && r < rows) out[r] = m;
+  }
+}
+
 // Y-update, eq. proxdiv-problem, at one point.  With q = -beta/lam,
 // q_ref = z/(1+K) (the root when nu_{-J} = 0), a = log r - q_ref and the unknown
 // v = -K (q - q_ref) (log of the cell's share of P_Y at the point, up to q_ref),
 // the equation reads  G(v) = v + K logaddexp(a, v) = 0;  G is increasing and
 // convex, so Newton from any start converges (a step from the left lands right
 // of the root, from where the iterates decrease monotonically).  v is O(10), so
-// its R rounding is harmless: beta/eps = -K q_ref + v.  In FP32 the root is
-// finished by one FP64 Newton step (K logaddexp amplifies FP32 rounding).
+// its R rounding is harmless: beta/eps = -K q_ref + v.  The R rounding of a
+// and v puts a floor of about K ulp on G, i.e. 1/(1 + K sigma) ulp on v where
+// sigma is the cell's share: the error of the plan at a point is inversely
+// proportional to the share, its mass proportional to it.
 template <typename R>
 __device__ __forceinline__ double newton_v(double a, double v0, double K, R tol, int maxit) {
   if (!(a > -INFINITY)) return 0.0;
   const R aR = R(a), KR = R(K);
   R v = R(v0);
+  R prev = R(INFINITY);
   for (int it = 0; it < maxit; ++it) {
     R la, sig;
     if (v >= aR) {
@@ -105,23 +132,13 @@ __device__ __forceinline__ double newton_v(double a, double v0, double K, R tol,
     }
     const R dv = (v + KR * la) / (R(1) + KR * sig);
     v -= dv;
-    if (!(fabs(dv) > tol * (R(1) + fabs(v)))) break;
+    // converged, or at the rounding floor of K logaddexp (the step stopped
+    // shrinking): further steps only move v inside that floor
+    const R adv = fabs(dv);
+    if (!(adv > tol * (R(1) + fabs(v))) || !(adv < prev)) break;
+    prev = adv;
   }
-  double vd = (double)v;
-  if (sizeof(R) == 4) {
-    double la, sig;
-    if (vd >= a) {
-      const double e = exp(a - vd);
-      la = vd + log1p(e);
-      sig = 1.0 / (1.0 + e);
-    } else {
-      const double e = exp(vd - a);
-      la = a + log1p(e);
-      sig = e / (1.0 + e);
-    }
-    vd -= (vd + K * la) / (1.0 + K * sig);
-  }
-  return vd;
+  return (double)v;
 }
 
 // One pass output: LSE over k in [k0, k1) of base[k*stride] - ch (k - c)^2.
@@ -132,8 +149,13 @@ template <typename R>
 __device__ __forceinline__ double lse_pass(const double* base, int stride, int k0, int k1, double c,
                                            double ch, bool have_shift, double shift, double bmax,
                                            double& nfall) {
-  constexpr double W = sizeof(R) == 8 ? 745.0 : 104.0;   // e^-W below the R range
-  if (have_shift) {
+  // Terms more than W below the shift are skipped; an output is accepted when
+  // its shifted sum stays above e^-22, so every skipped term is below e^-(W-22)
+  // of the output (e^-18 in FP32, e^-38 in FP64), i.e. under the R rounding.
+  constexpr double W = sizeof(R) == 8 ? 60.0 : 40.0;
+  // A sum outside the accepted range but still representable says where the
+  // output moved: one more windowed pass with the shift corrected by its log.
+  for (int attempt = 0; have_shift && attempt < 2; ++attempt) {
     int a = k0, b = k1;
     if (ch > 0.0) {
       const double r2 = (bmax - shift + W) / ch;
@@ -145,13 +167,28 @@ __device__ __forceinline__ double lse_pass(const double* base, int stride, int k
         b = min(k1, (int)floor(c + rr) + 1);
       }
     }
-    R acc = R(0);
-    const R cR = R(c), chR = R(ch);
-    for (int k = a; k < b; ++k) {
-      const R d = R(k) - cR;
-      acc += M<R>::ex(R(base[k * stride] - shift) - chR * d * d);
+    // Terms are evaluated as 2^(sc (base_k - shift) - sc ch d^2) in FP32 (sc =
+    // log2 e, one v_exp_f32 each) and as exp() in FP64; four terms per trip
+    // with their LDS reads issued together.
+    const R sc = M<R>::kScale;
+    const R chs = R(ch) * sc;
+    R acc0 = R(0), acc1 = R(0);
+    R dk = R(a) - R(c);   // integer-valued: exact
+    const double* p = base + (long)a * stride;
+    int k = a;
+    for (; k + 4 <= b; k += 4, p += 4 * stride, dk += R(4)) {
+      const double v0 = p[0], v1 = p[stride], v2 = p[2 * stride], v3 = p[3 * stride];
+      const R d1 = dk + R(1), d2 = dk + R(2), d3 = dk + R(3);
+      acc0 += M<R>::ex2s(R(v0 - shift) * sc - chs * dk * dk);
+      acc1 += M<R>::ex2s(R(v1 - shift) * sc - chs * d1 * d1);
+      acc0 += M<R>::ex2s(R(v2 - shift) * sc - chs * d2 * d2);
+      acc1 += M<R>::ex2s(R(v3 - shift) * sc - chs * d3 * d3);
     }
-    if (acc > R(8.7e-27) && acc < R(1.1e26)) return shift + (double)M<R>::lg(acc);
+    for (; k < b; ++k, p += stride, dk += R(1)) acc0 += M<R>::ex2s(R(p[0] - shift) * sc - chs * dk * dk);
+    const R acc = acc0 + acc1;
+    if (acc > R(2.8e-10) && acc < R(1.1e26)) return shift + (double)M<R>::lg(acc);   // e^-22 .. e^60
+    if (!(acc > R(0)) || !(acc < R(INFINITY))) break;
+    shift += (double)M<R>::lg(acc);
   }
   nfall += 1.0;
   // exact: max pass in FP64, then sum pass with R exponentials of FP64 differences
@@ -187,11 +224,17 @@ struct CellLds {
   double* Mc;    // column maxima of Tt                           [16]
   double* adr;   // a(x) = alpha/eps + log mu                     [256]
   double* Ma;    // row maxima of adr                             [16]
-  double* red;   // reductions                                    [4*24]
+  double* red;   // reductions                                    [4*16]
+  float* lnvf;   // FP32 kernels: log nu on the box                [cmax^2]
+  float* lrf;    // FP32 kernels: log r on the box                 [cmax^2]
+  R* dl1;        // moved Y: displacement (pixels) on the box      [cmax^2]
+  R* dl2;
+  double* mx;    // moved Y: partial sums, shifts, flags           [3*256]
 };
 
 template <typename R>
-__host__ __device__ inline size_t cell_lds_layout(int cmax, CellLds<R>* L, unsigned char* base) {
+__host__ __device__ inline size_t cell_lds_layout(int cmax, bool moved, CellLds<R>* L,
+                                                  unsigned char* base) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -201,7 +244,12 @@ __host__ __device__ inline size_t cell_lds_layout(int cmax, CellLds<R>* L, unsig
   const size_t n2 = (size_t)cmax * cmax, nt = (size_t)cmax * kMaxTile;
   size_t o_bd = take(8 * n2), o_zp = take(8 * n2), o_Tt = take(8 * nt), o_Ud = take(8 * nt);
   size_t o_Mr = take(8 * cmax), o_MU = take(8 * cmax), o_Mc = take(8 * kMaxTile);
-  size_t o_adr = take(8 * kBlock), o_Ma = take(8 * kMaxTile), o_red = take(8 * 4 * 24);
+  size_t o_adr = take(8 * kBlock), o_Ma = take(8 * kMaxTile), o_red = take(8 * 4 * 16);
+  // FP32 kernels keep log nu and log r in LDS (FP64 kernels use the global
+  // per-cell workspace, whose full precision the FP64 parity needs)
+  const size_t o_lnv = sizeof(R) == 4 ? take(4 * n2) : 0, o_lr = sizeof(R) == 4 ? take(4 * n2) : 0;
+  const size_t o_d1 = moved ? take(sizeof(R) * n2) : 0, o_d2 = moved ? take(sizeof(R) * n2) : 0;
+  const size_t o_mx = moved ? take(8 * 3 * kBlock) : 0;
   if (L) {
     L->bd = (double*)(base + o_bd);
     L->zp = (double*)(base + o_zp);
@@ -213,11 +261,109 @@ __host__ __device__ inline size_t cell_lds_layout(int cmax, CellLds<R>* L, unsig
     L->adr = (double*)(base + o_adr);
     L->Ma = (double*)(base + o_Ma);
     L->red = (double*)(base + o_red);
+    L->lnvf = sizeof(R) == 4 ? (float*)(base + o_lnv) : nullptr;
+    L->lrf = sizeof(R) == 4 ? (float*)(base + o_lr) : nullptr;
+    L->dl1 = moved ? (R*)(base + o_d1) : nullptr;
+    L->dl2 = moved ? (R*)(base + o_d2) : nullptr;
+    L->mx = moved ? (double*)(base + o_mx) : nullptr;
   }
   return off;
 }
 
+// ---- moved Y points: the cost ch |(x - j) - delta_j|^2 is not separable ----
+// Dense sums over explicit (x, y) pairs, FP64 argument, R exponential.
+
+// sum over box points j in [ja, jb) (row-major, row length L2) of
+// exp(b_j - shift - ch |c - j - delta_j|^2) for one tile point c (box coordinates)
 template <typename R>
+__device__ __forceinline__ R dense_x_sum(const double* bd, const R* dl1, const R* dl2, int L2, int ja,
+                                         int jb, double c1, double c2, double ch, double shift) {
+  const R sc = M<R>::kScale;
+  R acc0 = R(0), acc1 = R(0);
+  int r = ja / L2, c = ja - r * L2;
+  int j = ja;
+  for (; j + 2 <= jb; j += 2) {
+    const double e1 = (c1 - r) - (double)dl1[j], e2 = (c2 - c) - (double)dl2[j];
+    acc0 += M<R>::ex2s(R((bd[j] - shift) - ch * (e1 * e1 + e2 * e2)) * sc);
+    if (++c == L2) { c = 0; ++r; }
+    const double f1 = (c1 - r) - (double)dl1[j + 1], f2 = (c2 - c) - (double)dl2[j + 1];
+    acc1 += M<R>::ex2s(R((bd[j + 1] - shift) - ch * (f1 * f1 + f2 * f2)) * sc);
+    if (++c == L2) { c = 0; ++r; }
+  }
+  if (j < jb) {
+    const double e1 = (c1 - r) - (double)dl1[j], e2 = (c2 - c) - (double)dl2[j];
+    acc0 += M<R>::ex2s(R((bd[j] - shift) - ch * (e1 * e1 + e2 * e2)) * sc);
+  }
+  return acc0 + acc1;
+}
+
+template <typename R>
+__device__ __forceinline__ double dense_x_max(const double* bd, const R* dl1, const R* dl2, int L2,
+                                              int ja, int jb, double c1, double c2, double ch) {
+  double m = -INFINITY;
+  int r = ja / L2, c = ja - r * L2;
+  for (int j = ja; j < jb; ++j) {
+    const double e1 = (c1 - r) - (double)dl1[j], e2 = (c2 - c) - (double)dl2[j];
+    m = fmax(m, bd[j] - ch * (e1 * e1 + e2 * e2));
+    if (++c == L2) { c = 0; ++r; }
+  }
+  return m;
+}
+
+// sum over tile points x in [xa1, xb1) x [xa2, xb2) (row length lx2) of
+// exp(a_x - shift - ch |(D + x) - y|^2) for one moved point y (box coordinates)
+template <typename R>
+__device__ __forceinline__ R dense_y_sum(const double* adr, const double* Ma, int lx2, int xa1,
+                                         int xb1, int xa2, int xb2, double D1, double D2, double y1,
+                                         double y2, double ch, double shift, double W) {
+  const R sc = M<R>::kScale;
+  R acc = R(0);
+  for (int x1 = xa1; x1 < xb1; ++x1) {
+    const double e1 = (D1 + x1) - y1;
+    const double q1 = ch * e1 * e1;
+    if (Ma[x1] - shift - q1 < -W) continue;   // every term of the row is below e^-W
+    const double* row = adr + x1 * lx2;
+    for (int x2 = xa2; x2 < xb2; ++x2) {
+      const double e2 = (D2 + x2) - y2;
+      acc += M<R>::ex2s(R((row[x2] - shift) - q1 - ch * e2 * e2) * sc);
+    }
+  }
+  return acc;
+}
+
+template <typename R>
+__device__ __forceinline__ double dense_y_max(const double* adr, int lx2, int xa1, int xb1, int xa2,
+                                              int xb2, double D1, double D2, double y1, double y2,
+                                              double ch) {
+  double m = -INFINITY;
+  for (int x1 = xa1; x1 < xb1; ++x1) {
+    const double e1 = (D1 + x1) - y1;
+    for (int x2 = xa2; x2 < xb2; ++x2) {
+      const double e2 = (D2 + x2) - y2;
+      m = fmax(m, adr[x1 * lx2 + x2] - ch * (e1 * e1 + e2 * e2));
+    }
+  }
+  return m;
+}
+
+// z(y) over the whole tile: shifted sum, else exact max + sum
+template <typename R>
+__device__ __forceinline__ double dense_y_lse(const double* adr, const double* Ma, int lx1, int lx2,
+                                              double D1, double D2, double y1, double y2, double ch,
+                                              bool have, double shift, double& nfall) {
+  constexpr double W = sizeof(R) == 8 ? 60.0 : 40.0;
+  if (have) {
+    const R acc = dense_y_sum<R>(adr, Ma, lx2, 0, lx1, 0, lx2, D1, D2, y1, y2, ch, shift, W);
+    if (acc > R(2.8e-10) && acc < R(1.1e26)) return shift + (double)M<R>::lg(acc);
+  }
+  nfall += 1.0;
+  const double m = dense_y_max<R>(adr, lx2, 0, lx1, 0, lx2, D1, D2, y1, y2, ch);
+  if (!(m > -INFINITY)) return m;
+  const R acc = dense_y_sum<R>(adr, Ma, lx2, 0, lx1, 0, lx2, D1, D2, y1, y2, ch, m, 745.0);
+  return m + (double)M<R>::lg(acc);
+}
+
+template <typename R, bool kMoved>
 __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int t = threadIdx.x;
@@ -277,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
   const int NY = L1 * L2;
 
   CellLds<R> S;
-  cell_lds_layout<R>(cap, &S, smem_raw);
+  cell_lds_layout<R>(cap, kMoved, &S, smem_raw);
   double* red = S.red;
 
   const double eps = P.eps, lam = P.lam, kap = P.kappa, K = P.K, ch = P.ch;
@@ -298,7 +444,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
   }
 
   // ---- Y box inputs: nu_{-J}, r, log nu, warm start -------------------------
-  double acc0[2] = {mux, 0.0};
+  double acc0[3] = {mux, 0.0, 0.0};
   for (int o = t; o < NY; o += kBlock) {
     const int j1 = o / L2, j2 = o - j1 * L2;
     const int y1 = o1 + j1, y2 = o2 + j2;
@@ -313,46 +459,112 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
     }
     const double r = fmax(pv - nj, 0.0) / nv;
     acc0[1] += r * nv;
-    const double lnv = log(nv);
-    wlrr[o] = r > 0.0 ? log(r) : -INFINITY;
-    wlnv[o] = lnv;
+    acc0[2] += pv > 0.0 ? pv : nv;
+    double lnv = log(nv);
+    const double lr = r > 0.0 ? log(r) : -INFINITY;
+    if constexpr (sizeof(R) == 4) {
+      S.lnvf[o] = (float)lnv;
+      S.lrf[o] = (float)lr;
+      lnv = (double)(float)lnv;   // b carries the same rounded log nu
+    } else {
+      wlrr[o] = lr;
+      wlnv[o] = lnv;
+    }
     // beta^0/eps = -K log(P/nu); b = beta/eps + log nu
     S.bd[o] = (pv > 0.0 ? -K * log(pv / nv) : 0.0) + lnv;
+    if constexpr (kMoved) {
+      S.dl1[o] = R(d.ydel[2 * (P.grid_off + g)]);
+      S.dl2[o] = R(d.ydel[2 * (P.grid_off + g) + 1]);
+    }
   }
-  block_sum<2>(acc0, red);
+  block_sum<3>(acc0, red);
   const double muJ = acc0[0];
-  const double Rmass = acc0[1];   // |nu_{-J}| on the box
+  const double Rmass = acc0[1];    // |nu_{-J}| on the box
+  const double B0mass = acc0[2];   // sum of e^{-beta0/lam} nu on the box
+  double pxsum = 0.0;              // |P_X pi| of the last evaluated pair
   double nfall = 0.0;             // pass outputs recomputed exactly
 
   // ---- X-half: S(i) = LSE_j [b(j) - ch |j - (D + i)|^2], in place over Tt ----
   // Returns S for the thread's point; sprev is that point's previous S.
   bool have_x = false;
   auto x_half = [&](double sprev) -> double {
-    for (int j1 = t; j1 < L1; j1 += kBlock) {
-      double m = -INFINITY;
-      for (int j2 = 0; j2 < L2; ++j2) m = fmax(m, S.bd[j1 * L2 + j2]);
-      S.Mr[j1] = m;
+    if constexpr (kMoved) {
+      // dense: tile point xi summed over the box by np threads, each over a
+      // contiguous part of the box; partial sums, shifts and flags meet in mx
+      const int np = max(1, kBlock / lx);
+      const int xi = t % lx, part = t / lx;
+      const bool act = part < np;
+      const int ja = (int)((long)NY * part / np), jb = (int)((long)NY * (part + 1) / np);
+      const double c1 = D1 + xi / lx2, c2 = D2 + xi % lx2;
+      double* pt = S.mx;                  // [np * lx] partial sums / maxima
+      double* sh = S.mx + kBlock;         // [lx] shift, then result
+      double* need = S.mx + 2 * kBlock;   // [lx] exact recomputation flag
+      if (t < lx) sh[t] = sprev;
+      __syncthreads();
+      if (have_x) {
+        if (act)
+          pt[part * lx + xi] =
+              (double)dense_x_sum<R>(S.bd, S.dl1, S.dl2, L2, ja, jb, c1, c2, ch, sh[xi]);
+        __syncthreads();
+        if (t < lx) {
+          double a = 0.0;
+          for (int q = 0; q < np; ++q) a += pt[q * lx + t];
+          const bool ok = a > 2.8e-10 && a < 1.1e26;
+          need[t] = ok ? 0.0 : 1.0;
+          if (ok) sh[t] = sprev + log(a);
+        }
+      } else if (t < lx) {
+        need[t] = 1.0;
+      }
+      __syncthreads();
+      int any = 0;
+      if (t < lx) any = need[t] != 0.0;
+      if (__syncthreads_or(any)) {
+        // exact: maximum over the parts, then the shifted sum
+        const bool my = act && need[xi] != 0.0;
+        if (my) pt[part * lx + xi] = dense_x_max<R>(S.bd, S.dl1, S.dl2, L2, ja, jb, c1, c2, ch);
+        __syncthreads();
+        double m = -INFINITY;
+        if (my)
+          for (int q = 0; q < np; ++q) m = fmax(m, pt[q * lx + xi]);
+        __syncthreads();
+        if (my)
+          pt[part * lx + xi] =
+              m > -INFINITY ? (double)dense_x_sum<R>(S.bd, S.dl1, S.dl2, L2, ja, jb, c1, c2, ch, m)
+                            : 0.0;
+        __syncthreads();
+        if (t < lx && need[t] != 0.0) {
+          double a = 0.0, mm = -INFINITY;
+          for (int q = 0; q < np; ++q) a += pt[q * lx + t];
+          mm = m;   // thread t is part 0 of tile point t
+          sh[t] = mm > -INFINITY ? mm + log(a) : mm;
+          nfall += 1.0;
+        }
+      }
+      __syncthreads();
+      const double sv = t < lx ? sh[t] : 0.0;
+      have_x = true;
+      __syncthreads();
+      return sv;
+    } else {
+      seg_max<8>(S.bd, L1, L2, L2, 1, S.Mr);
+      __syncthreads();
+      for (int o = t; o < L1 * lx2; o += kBlock) {
+        const int j1 = o / lx2, i2 = o - j1 * lx2;
+        S.Tt[o] = lse_pass<R>(S.bd + j1 * L2, 1, 0, L2, (double)(D2 + i2), ch, have_x, S.Tt[o],
+                              S.Mr[j1], nfall);
+      }
+      __syncthreads();
+      seg_max<16>(S.Tt, lx2, L1, 1, lx2, S.Mc);
+      __syncthreads();
+      double sv = 0.0;
+      if (t < lx)
+        sv = lse_pass<R>(S.Tt + ti2, lx2, 0, L1, (double)(D1 + ti1), ch, have_x, sprev, S.Mc[ti2],
+                         nfall);
+      have_x = true;
+      __syncthreads();
+      return sv;
     }
-    __syncthreads();
-    for (int o = t; o < L1 * lx2; o += kBlock) {
-      const int j1 = o / lx2, i2 = o - j1 * lx2;
-      S.Tt[o] = lse_pass<R>(S.bd + j1 * L2, 1, 0, L2, (double)(D2 + i2), ch, have_x, S.Tt[o],
-                            S.Mr[j1], nfall);
-    }
-    __syncthreads();
-    for (int i2 = t; i2 < lx2; i2 += kBlock) {
-      double m = -INFINITY;
-      for (int j1 = 0; j1 < L1; ++j1) m = fmax(m, S.Tt[j1 * lx2 + i2]);
-      S.Mc[i2] = m;
-    }
-    __syncthreads();
-    double sv = 0.0;
-    if (t < lx)
-      sv = lse_pass<R>(S.Tt + ti2, lx2, 0, L1, (double)(D1 + ti1), ch, have_x, sprev, S.Mc[ti2],
-                       nfall);
-    have_x = true;
-    __syncthreads();
-    return sv;
   };
 
   double Sx = x_half(0.0);
@@ -371,11 +583,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
   auto y_prepare = [&]() {
     if (t < lx) S.adr[t] = aeps + lmux;
     __syncthreads();
-    for (int i1 = t; i1 < lx1; i1 += kBlock) {
-      double m = -INFINITY;
-      for (int i2 = 0; i2 < lx2; ++i2) m = fmax(m, S.adr[i1 * lx2 + i2]);
-      S.Ma[i1] = m;
-    }
+    seg_max<16>(S.adr, lx1, lx2, lx2, 1, S.Ma);
     __syncthreads();
   };
   // Y pass 1 over tile columns [ib, ie): Uo(i1, j2) = LSE_i2 [a - ch (i2 - (j2 - D2))^2]
@@ -386,11 +594,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
                           S.Ma[i1], nfall);
     }
     __syncthreads();
-    for (int j2 = t; j2 < L2; j2 += kBlock) {
-      double m = -INFINITY;
-      for (int i1 = 0; i1 < lx1; ++i1) m = fmax(m, Uo[i1 * L2 + j2]);
-      S.MU[j2] = m;
-    }
+    seg_max<8>(Uo, L2, lx1, 1, L2, S.MU);
     __syncthreads();
   };
 
@@ -398,16 +602,17 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
     ++it;
     if (P.translate) {
       // exact maximisation of the cell dual along (alpha + s, beta - s):
-      // e^{s/lam} = (R + sqrt(R^2 + 4AB)) / (2B); FP64 sums (the shift in
-      // eps units is K log w, so w must be exact to ~1/K)
-      double ab[2] = {0.0, 0.0};
+      // e^{s/lam} = (R + sqrt(R^2 + 4AB)) / (2B), A = sum e^{-alpha/lam} mu,
+      // B = sum e^{-beta/lam} nu.  After a Y-update e^{-beta/lam} nu =
+      // P_Y pi + nu_{-J} pointwise, so B = |P_X pi of the last pair| + R (and
+      // B = |P_Y pi| of the state before the first Y-half, where
+      // e^{-beta0/lam} nu = P_Y pi).  The plan is invariant along this
+      // direction, so R-level relative accuracy of w suffices.
+      double ab[1] = {0.0};
       if (t < lx) ab[0] = mux * exp(-aeps / K);
-      for (int o = t; o < NY; o += kBlock) {
-        const double lnv = wlnv[o];
-        ab[1] += exp(lnv - (S.bd[o] - lnv) / K);
-      }
-      block_sum<2>(ab, red);
-      const double w = (Rmass + sqrt(Rmass * Rmass + 4.0 * ab[0] * ab[1])) / (2.0 * ab[1]);
+      block_sum<1>(ab, red);
+      const double Bsum = it == 1 ? B0mass : pxsum + Rmass;
+      const double w = (Rmass + sqrt(Rmass * Rmass + 4.0 * ab[0] * Bsum)) / (2.0 * Bsum);
       const double sh = K * log(w);   // s/eps
       aeps += sh;
       ushift += sh;
@@ -416,17 +621,29 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
     }
     // ---- Y-half: z by two passes, Newton per point --------------------------
     y_prepare();
-    y_pass1(S.Ud, 0, lx2, have_y, ushift);
+    if constexpr (!kMoved) y_pass1(S.Ud, 0, lx2, have_y, ushift);
     for (int o = t; o < NY; o += kBlock) {
       const int j1 = o / L2, j2 = o - j1 * L2;
-      const double z = lse_pass<R>(S.Ud + j2, L2, 0, lx1, (double)(j1 - D1), ch, have_y,
-                                   S.zp[o] + ushift, S.MU[j2], nfall);
+      double z;
+      if constexpr (kMoved)
+        z = dense_y_lse<R>(S.adr, S.Ma, lx1, lx2, (double)D1, (double)D2, j1 + (double)S.dl1[o],
+                           j2 + (double)S.dl2[o], ch, have_y, S.zp[o] + ushift, nfall);
+      else
+        z = lse_pass<R>(S.Ud + j2, L2, 0, lx1, (double)(j1 - D1), ch, have_y, S.zp[o] + ushift,
+                        S.MU[j2], nfall);
       S.zp[o] = z;
-      const double lnv = wlnv[o];
+      double lnv, lrr;
+      if constexpr (sizeof(R) == 4) {
+        lnv = (double)S.lnvf[o];
+        lrr = (double)S.lrf[o];
+      } else {
+        lnv = wlnv[o];
+        lrr = wlrr[o];
+      }
       const double qref = z / (K + 1.0);
       // warm start: the previous beta/eps = bd - log nu, i.e. v0 = bd - lnv + K qref
       const double v0 = S.bd[o] - lnv + K * qref;
-      const double v = newton_v<R>(wlrr[o] - qref, v0, K, newton_tol, newton_max);
+      const double v = newton_v<R>(lrr - qref, v0, K, newton_tol, newton_max);
       S.bd[o] = -K * qref + v + lnv;
     }
     have_y = true;
@@ -442,9 +659,10 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
       pxv = mux * exp(lpv);
       term = pxv * (lpv + aol) - pxv + mux * exp(-aol);
     }
-    double pdv[1] = {term};
-    block_sum<1>(pdv, red);
+    double pdv[2] = {term, pxv};
+    block_sum<2>(pdv, red);
     conv = pdv[0] <= tol;
+    pxsum = pdv[1];
     const bool done = P.fixed_iters > 0 ? (it >= P.fixed_iters) : (conv || it >= P.max_iter);
     if (done) break;
     Sx = Sn;
@@ -461,88 +679,117 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
     kr[k] = (bx.x - C.x1) / s;
     kc[k] = (bx.y - C.x2) / s;
   }
-  // sums: [0..3] <beta, nu_k>, [4..7] |nu_k|, [8..11] <alpha, px>, [12..15] KL terms,
-  // [16..19] |mu_k|, [20] exact recomputations
-  double acc[21];
+  // Y sums per basic cell k: <beta, nu_k>, |nu_k|
+  double accy[8];
 #pragma unroll
-  for (int k = 0; k < 21; ++k) acc[k] = 0.0;
+  for (int k = 0; k < 8; ++k) accy[k] = 0.0;
   for (int c = 0; c < nc; ++c) {
     double* Uo = c == 0 ? S.Ud : S.Tt;
-    y_pass1(Uo, c * s, (c + 1) * s, false, 0.0);
+    if constexpr (!kMoved) y_pass1(Uo, c * s, (c + 1) * s, false, 0.0);
     for (int o = t; o < NY; o += kBlock) {
       const int j1 = o / L2, j2 = o - j1 * L2;
-      const double beta = eps * (S.bd[o] - wlnv[o]);
-      for (int k = 0; k < C.nb; ++k) {
-        if (kc[k] != c) continue;
-        const double zk = lse_pass<R>(Uo + j2, L2, kr[k] * s, (kr[k] + 1) * s, (double)(j1 - D1), ch,
-                                      true, S.zp[o], S.MU[j2], nfall);
+      const double beta =
+          eps * (S.bd[o] - (sizeof(R) == 4 ? (double)S.lnvf[o] : wlnv[o]));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k >= C.nb || kc[k] != c) continue;
+        double zk;
+        if constexpr (kMoved) {
+          const R a = dense_y_sum<R>(S.adr, S.Ma, lx2, kr[k] * s, (kr[k] + 1) * s, kc[k] * s,
+                                     (kc[k] + 1) * s, (double)D1, (double)D2,
+                                     j1 + (double)S.dl1[o], j2 + (double)S.dl2[o], ch, S.zp[o],
+                                     sizeof(R) == 8 ? 60.0 : 40.0);
+          zk = a > R(0) ? S.zp[o] + (double)M<R>::lg(a) : -INFINITY;
+        } else {
+          zk = lse_pass<R>(Uo + j2, L2, kr[k] * s, (kr[k] + 1) * s, (double)(j1 - D1), ch, true,
+                           S.zp[o], S.MU[j2], nfall);
+        }
         const double nt = exp(S.bd[o] + zk);   // nu e^{beta/eps} e^{z_k}
-        acc[k] += beta * nt;
-        acc[4 + k] += nt;
+        accy[k] += beta * nt;
+        accy[4 + k] += nt;
         d.cand[(long)C.basic[k] * cap2 + o] = nt < P.trunc ? 0.0 : nt;
       }
     }
     __syncthreads();
   }
+  block_sum<8>(accy, red);
+  // X sums per basic cell k: <alpha, px>, KL terms, |mu_k|; then the count of
+  // exact recomputations
+  double accx[13];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) accx[k] = 0.0;
   if (t < lx) {
     const int k = (ti1 / s) * nc + (ti2 / s);
     const double alpha = eps * aeps;
-    acc[8 + k] = alpha * pxv;
-    acc[12 + k] = mux * (exp(lpv) * lpv - exp(lpv) + 1.0);
-    acc[16 + k] = mux;
+    const double e = exp(lpv);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q != k) continue;
+      accx[q] = alpha * pxv;
+      accx[4 + q] = mux * (e * lpv - e + 1.0);
+      accx[8 + q] = mux;
+    }
     d.pxc[P.grid_off + gx] = pxv;
     d.abar[P.grid_off + gx] = alpha;
   }
-  acc[20] = nfall;
-  block_sum<21>(acc, red);
+  accx[12] = nfall;
+  block_sum<13>(accx, red);
   if (t == 0) {
     double bytes = 8.0 * (2.0 * NY + 3.0 * lx + (double)C.nb * NY);
     for (int k = 0; k < C.nb; ++k) {
       const int b = C.basic[k];
       const Box ob = d.box[b];
       bytes += 8.0 * ob.l1 * ob.l2;
-      d.htil[b] = acc[8 + k] + acc[k] - eps * acc[4 + k] + eps * acc[16 + k] * P.mass_nu +
-                  lam * acc[12 + k];
+      d.htil[b] = accx[k] + accy[k] - eps * accy[4 + k] + eps * accx[8 + k] * P.mass_nu +
+                  lam * accx[4 + k];
       Box nb;
       nb.o1 = o1; nb.o2 = o2; nb.l1 = L1; nb.l2 = L2;
       d.cbox[b] = nb;
     }
     // log-sum-exp terms of the separable passes: every Y-half and X-half of
     // the loop, the first X-half, and the re-split passes
-    const double xh = (double)L1 * lx2 * L2 + (double)lx * L1;
-    const double yh = (double)lx1 * L2 * lx2 + (double)NY * lx1;
-    const double rs = (double)lx1 * L2 * lx2 + (double)NY * s * C.nb;
+    const double xh = kMoved ? (double)lx * NY : (double)L1 * lx2 * L2 + (double)lx * L1;
+    const double yh = kMoved ? (double)NY * lx : (double)lx1 * L2 * lx2 + (double)NY * lx1;
+    const double rs = kMoved ? (double)NY * lx : (double)lx1 * L2 * lx2 + (double)NY * s * C.nb;
     d.cell_iters[ci] = it;
     d.cell_conv[ci] = conv ? 1 : 0;
     d.cell_bytes[ci] = bytes;
     d.cell_terms[ci] = it * (xh + yh) + xh + rs;
-    d.cell_fall[ci] = acc[20];
+    d.cell_fall[ci] = accx[12];
   }
 }
 
-size_t cell_lds_bytes(int cap, int precision) {
-  if (precision == 64) return cell_lds_layout<double>(cap, nullptr, nullptr);
-  return cell_lds_layout<float>(cap, nullptr, nullptr);
+size_t cell_lds_bytes(int cap, int precision, bool moved) {
+  if (precision == 64) return cell_lds_layout<double>(cap, moved, nullptr, nullptr);
+  return cell_lds_layout<float>(cap, moved, nullptr, nullptr);
 }
 
 hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int precision,
-                             hipStream_t st) {
+                             bool moved, hipStream_t st) {
   if (ncells <= 0) return hipSuccess;
-  const size_t lds = cell_lds_bytes(cap, precision);
+  const size_t lds = cell_lds_bytes(cap, precision, moved);
   if (precision == 64) {
-    hipLaunchKernelGGL(k_cell_solve<double>, dim3(ncells), dim3(kBlock), lds, st, d, cell_base);
+    if (moved)
+      hipLaunchKernelGGL((k_cell_solve<double, true>), dim3(ncells), dim3(kBlock), lds, st, d, cell_base);
+    else
+      hipLaunchKernelGGL((k_cell_solve<double, false>), dim3(ncells), dim3(kBlock), lds, st, d, cell_base);
   } else {
-    hipLaunchKernelGGL(k_cell_solve<float>, dim3(ncells), dim3(kBlock), lds, st, d, cell_base);
+    if (moved)
+      hipLaunchKernelGGL((k_cell_solve<float, true>), dim3(ncells), dim3(kBlock), lds, st, d, cell_base);
+    else
+      hipLaunchKernelGGL((k_cell_solve<float, false>), dim3(ncells), dim3(kBlock), lds, st, d, cell_base);
   }
   return hipGetLastError();
 }
 
 hipError_t set_cell_lds_limit(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_cell_solve<double>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_cell_solve<float>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* fns[4] = {(const void*)k_cell_solve<double, false>, (const void*)k_cell_solve<double, true>,
+                        (const void*)k_cell_solve<float, false>, (const void*)k_cell_solve<float, true>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace dduot

@@ -21,6 +21,7 @@ struct Prob {
   int margin, cap;
   int translate;
   int precision;
+  int moved;           // 1: Y points displaced (dense, non-separable cost)
   int grid_off;     // offset of this problem's grid arrays
   int basic_off, nbasic;
   int cell_off[2], ncell[2];   // composite cells of partitions A (0) and B (1)
@@ -65,6 +66,7 @@ struct Dev {
   double* cell_fall;          // pass outputs recomputed in FP64 (underflow) in the last solve
   double* ws_lnv;             // per cell: log nu on the Y-box (cap2 entries)
   double* ws_lrr;             // per cell: log(nu_{-J}/nu) on the Y-box (cap2 entries)
+  const double* ydel;         // moved Y: (y'/h - j) per grid point, 2 doubles each
   double* chunk_part;         // 2 doubles per reduction chunk
   double* theta;              // per problem
   double* hist;               // per problem ring of records

@@ -24,12 +24,14 @@ def marginals():
     return (gaussian_mixture(N, N, 3, 1e-3, 1.0, 91), gaussian_mixture(N, N, 3, 1e-3, 1.3, 92))
 
 
-def gpu_value(mu, nu, half=300):
+def gpu_value(mu, nu, half=800, ypos=False):
     h = B.dd_uot_init(cfg64(), mu, nu)
     try:
         B.dd_uot_iterate(h, half)
         s = B.dd_uot_score(h, 0)
         dmu, dnu = B.dd_uot_backward(h, 0, N, N)
+        if ypos:
+            return s, dmu, dnu, B.dd_uot_backward_ypos(h, 0, N, N)
     finally:
         B.dd_uot_destroy(h)
     return s, dmu, dnu
@@ -37,7 +39,7 @@ def gpu_value(mu, nu, half=300):
 
 def test_gradient_matches_oracle_envelope_gradient():
     mu, nu = marginals()
-    s, dmu, dnu = gpu_value(mu, nu)
+    s, dmu, dnu, dy = gpu_value(mu, nu, ypos=True)
     assert s["rel_pd_gap"] < 1e-11
     pts = uot.grid_points(N, N, 1.0 / N)
     W, a, b, pi = grad.solve_value(mu.ravel(), nu.ravel(), pts, pts, 4.0 / N ** 2, 1.0)
@@ -45,6 +47,9 @@ def test_gradient_matches_oracle_envelope_gradient():
     rmu, rnu = grad.grads_from_pair(a, b, pi, mu, nu, 4.0 / N ** 2, 1.0)
     np.testing.assert_allclose(dmu.ravel(), rmu, rtol=0, atol=1e-8 * np.abs(rmu).max())
     np.testing.assert_allclose(dnu.ravel(), rnu, rtol=0, atol=1e-8 * np.abs(rnu).max())
+    # gradient with respect to moving the grid's Y points
+    ry = grad.grad_ypos(pi, pts, pts).reshape(N, N, 2)
+    np.testing.assert_allclose(dy, ry, rtol=0, atol=1e-8 * np.abs(ry).max())
 
 
 def test_gradient_matches_central_differences():
@@ -68,7 +73,7 @@ def test_autograd_wrapper():
     mu, nu = marginals()
     tm = torch.tensor(mu, dtype=torch.float64, device="cuda", requires_grad=True)
     tn = torch.tensor(nu, dtype=torch.float64, device="cuda", requires_grad=True)
-    val = uot_value(tm, tn, cfg64(), 300)
+    val = uot_value(tm, tn, cfg64(), 800)
     val.backward()
     _, dmu, dnu = gpu_value(mu, nu)
     np.testing.assert_allclose(tm.grad.cpu().numpy(), dmu, rtol=1e-12, atol=1e-14)

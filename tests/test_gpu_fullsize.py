@@ -73,6 +73,7 @@ def test_first_half_iteration_sampled_cells(marg, oracle_problem, precision, rto
             r = dd.process_cell(p, c, st.boxes, P, opt)
             xi = r["xi"]
             e_px = np.abs(px.ravel()[xi] - r["px"]).sum() / r["px"].sum()
+            print(f"[fullsize] cell {ci}: P_X rel L1 {e_px:.2e}", flush=True)
             assert e_px < rtol, f"cell {ci}: P_X rel L1 {e_px:.2e}"
             if precision == 64:
                 e_a = np.abs(alpha.ravel()[xi] - r["alpha"]).max() / np.abs(r["alpha"]).max()
@@ -90,6 +91,7 @@ def test_first_half_iteration_sampled_cells(marg, oracle_problem, precision, rto
                     full[o1:o1 + arr.shape[0], o2:o2 + arr.shape[1]] = arr
                     got = full[box[0]:box[0] + box[2], box[1]:box[1] + box[3]]
                     e = np.abs(got - r["cand"][b]).sum() / r["cand"][b].sum()
+                    print(f"[fullsize]   basic {b}: nu rel L1 {e:.2e}", flush=True)
                     assert e < rtol, f"basic {b}: nu rel L1 {e:.2e}"
     finally:
         B.dd_uot_destroy(h)

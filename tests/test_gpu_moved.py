@@ -1,0 +1,138 @@
+"""Moved Y points (the differentiable form): y' = y + u_theta(y) with a seeded
+cubic B-spline field, cost |x - y'|^2 (not separable).  The HIP path against
+the oracle (per half-iteration, certificate, Y-position gradient), against
+central finite differences in theta, and FP32 against the oracle on sampled
+cells of the 512 x 512 workload."""
+import numpy as np
+import pytest
+
+from oracle import dd, grad, uot
+from paper_2410_08859_amd import binding as B
+from paper_2410_08859_amd.inputs import (displaced_points, displacement_basis, displacement_theta,
+                                         gaussian_mixture, workload_marginals, WORKLOADS)
+
+pytestmark = pytest.mark.gpu
+
+
+def small(n=16, seed=901):
+    mu = gaussian_mixture(n, n, 3, 1e-3, 1.0, seed)
+    nu = gaussian_mixture(n, n, 3, 1e-3, 1.3, seed + 1)
+    y = displaced_points(n, n, 1.0 / n, displacement_theta(53, 1.0 / n))
+    return mu, nu, y
+
+
+def cfg(n, s, precision=64, **kw):
+    base = dict(n1=n, n2=n, h=1.0 / n, eps=4.0 / n ** 2, lam=1.0, cell=s, precision=precision,
+                init=B.INIT_PRODUCT, lenience=0.0, box_cap=n, trunc=1e-15, box_margin=2)
+    base.update(kw)
+    return B.dd_uot_default_config(**base)
+
+
+def test_moved_fp64_follows_the_oracle():
+    n, s = 16, 2
+    mu, nu, y = small(n)
+    c = cfg(n, s, fixed_inner_iters=8)
+    p = dd.make_problem(mu, nu, c.eps, 1.0, c.h, s, ypos=y)
+    st = dd.init_product(p)
+    opt = dd.Options(fixed_iters=8, lenience=0.0, cap=n, trunc=1e-15, margin=2, translate=True)
+    h = B.dd_uot_init_moved(c, mu, nu, y)
+    try:
+        assert B.dd_uot_score(h, 0)["tracked"] == pytest.approx(dd.tracked_score(p, st), rel=1e-12)
+        for step in range(4):
+            print(f"[moved] step {step}", flush=True)
+            B.dd_uot_iterate(h, 1)
+            ost = dd.half_iteration(p, st, "A" if step % 2 == 0 else "B", opt)
+            rec = B.dd_uot_history(h, 0)[-1]
+            assert rec[0] == ost["theta"]
+            assert rec[1] == pytest.approx(ost["e_cur"], rel=1e-10)
+            assert rec[2] == pytest.approx(ost["e_greedy"], rel=1e-10)
+            px, py = B.dd_uot_marginals(h, 0, n, n)
+            np.testing.assert_allclose(px, st.px, rtol=0, atol=1e-10 * st.px.max())
+            P = dd.aggregate(p, st.boxes)
+            np.testing.assert_allclose(py, P, rtol=0, atol=1e-10 * P.max())
+        s_gpu = B.dd_uot_score(h, 0)
+        cert = dd.certificate(p, st.abar)
+        for k in ("pd", "dual", "primal"):
+            key = "pd_gap" if k == "pd" else k
+            assert s_gpu[key] == pytest.approx(cert[k], rel=1e-9), k
+        _, bh = B.dd_uot_potentials(h, 0, n, n)
+        np.testing.assert_allclose(bh, cert["beta_hat"], rtol=0,
+                                   atol=1e-9 * np.abs(cert["beta_hat"]).max())
+        # Y-position gradient of the certificate plan
+        dy = B.dd_uot_backward_ypos(h, 0, n, n)
+        xs = uot.grid_points(n, n, c.h)
+        C = dd.full_cost(p)
+        pi = uot.plan(np.ravel(st.abar), np.ravel(cert["beta_hat"]), mu, nu, C, c.eps)
+        ref = grad.grad_ypos(pi, xs, y.reshape(-1, 2)).reshape(n, n, 2)
+        np.testing.assert_allclose(dy, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+    finally:
+        B.dd_uot_destroy(h)
+
+
+def converged(mu, nu, y, half=800):
+    n = mu.shape[0]
+    c = cfg(n, 2, sinkhorn_err=1e-15, sinkhorn_max_iter=20000, trunc=0.0)
+    h = B.dd_uot_init_moved(c, mu, nu, y)
+    try:
+        B.dd_uot_iterate(h, half)
+        s = B.dd_uot_score(h, 0)
+        dy = B.dd_uot_backward_ypos(h, 0, n, n)
+    finally:
+        B.dd_uot_destroy(h)
+    return s, dy
+
+
+def test_moved_gradient_matches_oracle_and_theta_differences():
+    n = 16
+    mu, nu, _ = small(n, 911)
+    th = displacement_theta(53, 1.0 / n)
+    y = displaced_points(n, n, 1.0 / n, th)
+    s, dy = converged(mu, nu, y)
+    assert s["rel_pd_gap"] < 1e-11
+    xs = uot.grid_points(n, n, 1.0 / n)
+    W, a, b, pi = grad.solve_value(mu.ravel(), nu.ravel(), xs, y.reshape(-1, 2), 4.0 / n ** 2, 1.0)
+    assert s["dual"] == pytest.approx(W, rel=1e-10)
+    ref = grad.grad_ypos(pi, xs, y.reshape(-1, 2)).reshape(n, n, 2)
+    np.testing.assert_allclose(dy, ref, rtol=0, atol=1e-8 * np.abs(ref).max())
+    # d W / d theta through the B-spline map, against central differences
+    Bm = displacement_basis(n, th.shape[1])
+    dth = np.stack([Bm.T @ dy[..., c] @ Bm for c in range(2)])
+    rng = np.random.default_rng(54)
+    t = 1e-4
+    for _ in range(2):
+        xi = rng.normal(size=th.shape)
+        wp = converged(mu, nu, displaced_points(n, n, 1.0 / n, th + t * (1.0 / n) * xi))[0]["dual"]
+        wm = converged(mu, nu, displaced_points(n, n, 1.0 / n, th - t * (1.0 / n) * xi))[0]["dual"]
+        fd = (wp - wm) / (2 * t)
+        an = (dth * xi).sum() / n
+        assert fd == pytest.approx(an, rel=1e-6, abs=1e-12)
+
+
+def test_moved_fp32_sampled_cells_512():
+    # the differentiable workload: 512 x 512, lambda 1, eps h^2, FP32 cells
+    w = WORKLOADS["grid512"]
+    n, s = w["n"], w["cell"]
+    mu, nu = workload_marginals("grid512")
+    y = displaced_points(n, n, 1.0 / n, displacement_theta(53, 1.0 / n))
+    c = B.dd_uot_default_config(n1=n, n2=n, h=1.0 / n, eps=w["eps_h2"] / n ** 2, lam=w["lam"],
+                                cell=s, precision=32, init=B.INIT_BLOCK, sinkhorn_max_iter=100,
+                                box_cap=32, box_margin=2, getweights=B.GW_GREEDY)
+    p = dd.make_problem(mu, nu, c.eps, c.lambda_, c.h, s, ypos=y)
+    st = dd.init_block(p)
+    opt = dd.Options(err=c.sinkhorn_err, max_iter=100, trunc=c.trunc, margin=2, cap=32,
+                     getweights="greedy", translate=True)
+    print("[moved] 512^2 FP32 first half-iteration", flush=True)
+    h = B.dd_uot_init_moved(c, mu, nu, y)
+    try:
+        B.dd_uot_iterate(h, 1)
+        px, _ = B.dd_uot_marginals(h, 0, n, n)
+        P = dd.aggregate(p, st.boxes)
+        cells = dd.composite_cells(p, "A")
+        m = len(cells)
+        for ci in (0, m - 1, m // 2 + 17, 1000):
+            r = dd.process_cell(p, cells[ci], st.boxes, P, opt)
+            e = np.abs(px.ravel()[r["xi"]] - r["px"]).sum() / r["px"].sum()
+            print(f"[moved] cell {ci}: P_X rel L1 {e:.2e}", flush=True)
+            assert e < 1e-5
+    finally:
+        B.dd_uot_destroy(h)

@@ -278,3 +278,45 @@ def test_dd_with_displaced_support_converges_to_global_optimum():
     np.testing.assert_allclose(st.plan, pi, rtol=5e-6, atol=1e-15)
     cert = dd.certificate(p, st.abar)
     assert cert["rel"] < 1e-12
+
+
+def _coarse_pair(n=16, s=2):
+    pf = small_problem(n, s)
+    pc = dd.make_problem(dd.coarsen(pf.mu), dd.coarsen(pf.nu), pf.eps * 4, pf.lam, pf.h * 2, s)
+    return pc, pf
+
+
+def test_refined_product_plan_is_the_fine_product_plan():
+    # mu_c x nu_c split in proportion to the fine masses is mu_f x nu_f
+    pc, pf = _coarse_pair()
+    st = dd.refine(pc, dd.init_product(pc), pf, 0.0, 64)
+    ref = dd.init_product(pf)
+    np.testing.assert_allclose(st.px, ref.px, rtol=1e-13)
+    for (a1, a2, a), (b1, b2, b) in zip(st.boxes, ref.boxes):
+        assert (a1, a2, a.shape) == (b1, b2, b.shape)
+        np.testing.assert_allclose(a, b, rtol=1e-13)
+    assert st.force_greedy
+
+
+def test_refined_block_start_with_double_cell_is_the_fine_block_start():
+    # cell side doubles: one fine basic cell per coarse one, nu on the block
+    pf = small_problem(16, 4)
+    pc = dd.make_problem(dd.coarsen(pf.mu), dd.coarsen(pf.nu), pf.eps * 4, pf.lam, pf.h * 2, 2)
+    st = dd.refine(pc, dd.init_block(pc), pf, 0.0, 64)
+    ref = dd.init_block(pf)
+    np.testing.assert_allclose(st.px, ref.px, rtol=1e-13)
+    for (a1, a2, a), (b1, b2, b) in zip(st.boxes, ref.boxes):
+        assert (a1, a2, a.shape) == (b1, b2, b.shape)
+        np.testing.assert_allclose(a, b, rtol=1e-13)
+
+
+def test_refinement_keeps_mass_and_the_prolonged_y_marginal():
+    pc, pf = _coarse_pair()
+    stc = dd.init_block(pc)
+    dd.run(pc, stc, 3, dd.Options(cap=16, margin=2, trunc=0.0, translate=True))
+    st = dd.refine(pc, stc, pf, 0.0, 64)
+    Pc = dd.aggregate(pc, stc.boxes)
+    Pf = dd.aggregate(pf, st.boxes)
+    np.testing.assert_allclose(dd.coarsen(Pf), Pc, rtol=1e-12)
+    np.testing.assert_allclose(Pf, np.kron(Pc / pc.nu, np.ones((2, 2))) * pf.nu, rtol=1e-12)
+    assert st.px.sum() == pytest.approx(stc.px.sum(), rel=1e-13)
