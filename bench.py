@@ -7,6 +7,13 @@ score pieces, GetWeights, update), alternating A and B.  The metric counts
 grid points times inner Sinkhorn iterations: sum over solved cells of
 |X_J| * (Y-halves of that cell), divided by the wall time of the timed steps.
 
+The headline steps start from the local block start (nu_i = nu on block i);
+the same steps are also timed on the finest layer after the multiscale warm
+start of Sec. 4.4 (coarse-to-fine with eps-scaling, untimed), as in the
+paper's pipeline.  Time to a relative primal-dual gap is measured
+separately: the whole multiscale solve, FP32 and FP64, from the host
+marginals to each target.
+
 Prints one JSON line.  `--gpus` above 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
@@ -31,12 +38,62 @@ EXP_PEAK = 256 * 64 * 2.4e9 / 4.0
 HBM_PEAK = 8.0e12
 
 
+def multiscale_params(levels, final_max, target, check_every=4):
+    return B.dd_uot_default_multiscale(levels=levels, final_max_halves=final_max,
+                                       check_every=check_every, target_rel_gap=target)
+
+
+def time_to_gap(name, precision, max_inner, cap, levels, final_max, targets, stream):
+    """Wall time of the whole multiscale solve (host marginals in, certificate
+    checks included) until each relative gap first reaches each target: the
+    certificate's pd_gap/|dual| and the DD plan's (tracked - dual)/|dual|."""
+    mu, nu = workload_marginals(name)
+    cfg = workload_config(name, precision, max_inner, cap)
+    ms = multiscale_params(levels, final_max, min(targets))
+    h, tr = B.dd_uot_solve_multiscale(cfg, ms, mu, nu, stream=stream)
+    B.dd_uot_destroy(h)
+
+    def reached(col):
+        out = {}
+        for t in targets:
+            hit = np.nonzero(tr[:, col] <= t)[0]
+            out[f"{t:g}"] = None if hit.size == 0 else {"ms": float(tr[hit[0], 1]),
+                                                        "half_iters": int(tr[hit[0], 0])}
+        return out
+    return {"precision": precision, "certificate_gap": reached(2), "dd_plan_gap": reached(3),
+            "final": {"certificate_gap": float(tr[-1, 2]), "dd_plan_gap": float(tr[-1, 3]),
+                      "ms": float(tr[-1, 1]), "half_iters": int(tr[-1, 0])},
+            "schedule": f"{levels} layers, eps 2h^2 -> h^2/2 per layer (-> eps on the finest), "
+                        f"4-16 half-iterations per stage (to rel. gap 1e-3), then at most "
+                        f"{final_max} with a certificate every 4"}
+
+
+def timed_steps(h, steps, warmup):
+    """Run warmup steps, then time `steps` half-iterations (wall clock between
+    device synchronisations) and the cell-solve launches (HIP events)."""
+    import torch
+    B.dd_uot_iterate(h, warmup, stats=False)
+    torch.cuda.synchronize()
+    B.dd_uot_set_timing(h, True)
+    rec0 = len(B.dd_uot_history(h, 0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.dd_uot_iterate(h, steps, stats=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, kms, kbytes = B.dd_uot_kernel_time(h)
+    B.dd_uot_set_timing(h, False)
+    hist = B.dd_uot_history(h, 0)[rec0:]
+    return dict(dt=dt, launches=launches, kms=kms, kbytes=kbytes, hist=hist,
+                score=B.dd_uot_score(h, 0))
+
+
 def workload_config(name, precision, max_inner, cap):
     w = WORKLOADS[name]
     n = w["n"]
     return B.dd_uot_default_config(
         n1=n, n2=n, h=1.0 / n, eps=w["eps_h2"] / n ** 2, lam=w["lam"], cell=w["cell"],
-        precision=precision, init=B.INIT_BLOCK, getweights=B.GW_SWIFT,
+        precision=precision, init=B.INIT_BLOCK, getweights=B.GW_STAGGERED,
         sinkhorn_err=2e-5, sinkhorn_max_iter=max_inner, trunc=1e-15, lenience=0.005,
         box_margin=2, box_cap=cap)
 
@@ -92,25 +149,20 @@ def run(args):
     mu, nu = workload_marginals(args.workload)
     cfg = workload_config(args.workload, args.precision, args.max_inner, args.cap)
     stream = torch.cuda.current_stream(dev)
-    h = B.dd_uot_init(cfg, mu, nu, stream=stream.cuda_stream)
+    if args.start == "multiscale":
+        # untimed warm start: coarse layers and the eps stages of the finest
+        h, _ = B.dd_uot_solve_multiscale(cfg, multiscale_params(args.levels, 0, 0.0), mu, nu,
+                                         stream=stream.cuda_stream)
+    else:
+        h = B.dd_uot_init(cfg, mu, nu, stream=stream.cuda_stream)
     try:
-        B.dd_uot_iterate(h, args.warmup, stats=False)
-        torch.cuda.synchronize()
-        B.dd_uot_set_timing(h, True)
-        rec0 = len(B.dd_uot_history(h, 0))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        B.dd_uot_iterate(h, args.steps, stats=False)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        launches, kms, kbytes = B.dd_uot_kernel_time(h)
-        B.dd_uot_set_timing(h, False)
-        hist = B.dd_uot_history(h, 0)[rec0:]
-        point_iters = hist[:, 4].sum()
-        terms = hist[:, 10].sum()
-        score = B.dd_uot_score(h, 0)
+        r = timed_steps(h, args.steps, args.warmup)
     finally:
         B.dd_uot_destroy(h)
+    dt, launches, kms, kbytes, hist, score = (r["dt"], r["launches"], r["kms"], r["kbytes"],
+                                              r["hist"], r["score"])
+    point_iters = hist[:, 4].sum()
+    terms = hist[:, 10].sum()
     avg_ms = kms / max(launches, 1)
     exp_rate = terms / launches / (avg_ms * 1e-3)
     hbm_rate = kbytes / launches / (avg_ms * 1e-3)
@@ -129,7 +181,8 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": args.workload, "n": cfg.n1, "cell": cfg.cell, "lambda": cfg.lambda_,
                    "eps": cfg.eps, "precision": args.precision, "max_inner": args.max_inner,
-                   "box_cap": cfg.box_cap, "start": "block"},
+                   "box_cap": cfg.box_cap, "start": args.start,
+                   "levels": args.levels if args.start == "multiscale" else 1},
         "roofline": {"bound": "alu", "achieved": exp_rate / 1e12, "peak": EXP_PEAK / 1e12,
                      "unit": "Texp/s", "frac": exp_rate / EXP_PEAK, "traffic": None,
                      "kernel": "k_cell_solve", "avg_launch_ms": avg_ms,
@@ -140,9 +193,34 @@ def run(args):
                   "overflow_cells": float(hist[:, 7].sum()),
                   "safe_steps": int((hist[:, 0] < 1).sum()),
                   "fp64_fallbacks": float(hist[:, 11].sum())},
-        "state_after": {"rel_pd_gap": score["rel_pd_gap"], "tracked_score": score["tracked"],
-                        "half_iters": score["half_iters"]},
+        "state_after": {"certificate_gap": score["rel_pd_gap"],
+                        "dd_plan_gap": (score["tracked"] - score["dual"]) / abs(score["dual"]),
+                        "tracked_score": score["tracked"], "half_iters": score["half_iters"]},
     }
+    if args.warm and args.start != "multiscale":
+        # the same steps after the multiscale warm start (the paper's pipeline)
+        h, _ = B.dd_uot_solve_multiscale(cfg, multiscale_params(args.levels, 0, 0.0), mu, nu,
+                                         stream=stream.cuda_stream)
+        try:
+            w = timed_steps(h, args.steps, args.warmup)
+        finally:
+            B.dd_uot_destroy(h)
+        wh = w["hist"]
+        out["warm_start_steps"] = {
+            "value": float(wh[:, 4].sum() / w["dt"]), "ms_per_step": 1e3 * w["dt"] / args.steps,
+            "mean_inner_per_cell": float(wh[:, 8].sum() / max(wh[:, 3].sum(), 1)),
+            "overflow_cells": float(wh[:, 7].sum()), "unconverged_cells": float(wh[:, 6].sum()),
+            "certificate_gap": w["score"]["rel_pd_gap"],
+            "dd_plan_gap": (w["score"]["tracked"] - w["score"]["dual"]) / abs(w["score"]["dual"]),
+            "start": f"multiscale, {args.levels} layers"}
+    if args.ttg:
+        targets = (1e-2, 1e-3, 1e-4, 1e-5, 1e-6)
+        out["time_to_gap"] = [
+            time_to_gap(args.workload, 32, args.max_inner, args.cap, args.levels, args.ttg_max32,
+                        targets, stream.cuda_stream),
+            time_to_gap(args.workload, 64, args.max_inner, args.cap, args.levels, args.ttg_max64,
+                        targets, stream.cuda_stream),
+        ]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.max_inner, args.cap, args.cpu_budget)
     return out
@@ -159,6 +237,13 @@ def main():
     ap.add_argument("--cap", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--start", default="block", choices=("multiscale", "block"))
+    ap.add_argument("--warm", type=int, default=1,
+                    help="1: also time the steps after the multiscale warm start")
+    ap.add_argument("--levels", type=int, default=7)
+    ap.add_argument("--ttg", type=int, default=1, help="1: also measure time to gap (FP32, FP64)")
+    ap.add_argument("--ttg-max32", type=int, default=64)
+    ap.add_argument("--ttg-max64", type=int, default=16)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of a plain device copy run once before the solver (profiling)")
     args = ap.parse_args()

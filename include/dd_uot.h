@@ -44,7 +44,11 @@ enum {
   DDUOT_ESTATE = -5    /* call not valid in the handle's state */
 };
 
-enum { DDUOT_GW_GREEDY = 0, DDUOT_GW_SAFE = 1, DDUOT_GW_SWIFT = 2 };
+/* GetWeights (Sec. 3.4): greedy theta = 1, safe theta = 1/(cells updated),
+   swift = greedy if the tracked score rises by at most lenience*|score| else
+   safe, staggered = every partition in four batches of non-adjacent cells
+   (parity of the cell position), one swift step per batch in turn. */
+enum { DDUOT_GW_GREEDY = 0, DDUOT_GW_SAFE = 1, DDUOT_GW_SWIFT = 2, DDUOT_GW_STAGGERED = 3 };
 enum { DDUOT_INIT_BLOCK = 0, DDUOT_INIT_PRODUCT = 1 };
 
 typedef struct dduot_handle dduot_handle;
@@ -59,7 +63,8 @@ typedef struct {
                                 in FP64, FP32 exponentials of FP64 differences
                                 to a per-output shift, FP32 Newton; FP64
                                 reductions, scores and certificate */
-  int32_t getweights;        /* DDUOT_GW_* ; swift is the default */
+  int32_t getweights;        /* DDUOT_GW_* ; swift is the default; staggered must be
+                                chosen for all problems of a handle or none */
   int32_t init;              /* DDUOT_INIT_BLOCK (nu_i = nu on block i) or
                                 DDUOT_INIT_PRODUCT (pi = mu x nu, Sec. 4.2) */
   double sinkhorn_err;       /* Err: a cell stops at PD/lambda <= Err |mu_J|
@@ -149,7 +154,22 @@ int dd_uot_set_eps(dduot_handle* h, int32_t prob, double eps);
    synchronises and fills *stats for the steps of this call. */
 int dd_uot_iterate(dduot_handle* h, int32_t n_half_iters, dduot_iter_stats* stats);
 
-/* Per half-iteration record of problem `prob`, oldest first, at most `max`
+/* Autotuner: threads per cell workgroup (64, 128 or 256, at least the
+   largest composite tile's point count).  Times the cell solves of the next
+   partition on the current state once per admissible size (HIP events) and
+   keeps the fastest for later steps; the state is unchanged.  chosen
+   (nullable) receives the size, ms (nullable, 3 doubles) the times of 64,
+   128, 256 threads (-1: not admissible).  Synchronises. */
+int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms);
+
+/* enable != 0: dd_uot_iterate runs pairs of half-iterations (A then B) by
+   replaying one captured hipGraph of all their kernels (captured on first
+   use; the step's kernels read every parameter from device memory, so the
+   graph stays valid across dd_uot_set_eps).  Not used while timing is on. */
+int dd_uot_set_graph(dduot_handle* h, int32_t enable);
+
+/* Per step record of problem `prob` (one per half-iteration, four under
+   staggered GetWeights: one per batch), oldest first, at most `max`
    records of 12 doubles: theta, tracked score before, tracked score of the
    greedy candidate, cells updated, sum |X_J| * inner iterations, max inner
    iterations, unconverged cells, overflowed cells, inner iterations,
@@ -213,7 +233,8 @@ int dd_uot_kernel_time(dduot_handle* h, int64_t* launches, double* total_ms,
    of its coarse basic cell I (boxes double, then truncate at cfg->trunc and
    shrink; a box wider than box_cap keeps its central box_cap rows/columns,
    see dd_uot_refine_clipped).  cfg: the fine problem (n = 2 n_coarse,
-   cell = coarse cell or twice it, same precision); mu, nu: host fine
+   every fine basic cell inside one coarse basic cell: cell divides twice
+   the coarse cell, or is 1; same precision); mu, nu: host fine
    marginals, whose 2 x 2 sums should be the coarse ones.  The first
    half-iteration of the new handle is greedy (the tracked pieces are
    estimates until then).  `coarse` is left unchanged. */
@@ -224,29 +245,38 @@ int32_t dd_uot_refine_clipped(const dduot_handle* h);
 
 typedef struct {
   int32_t levels;            /* layers; the coarsest has n / 2^(levels-1) points per axis */
-  int32_t coarse_cell;       /* basic cell side on all but the finest layer */
+  int32_t coarse_cell;       /* basic cell side on the coarser layers (the coarsest
+                                layer uses one composite cell for the whole grid
+                                when its side is at most 16) */
   double eps_start_h2;       /* eps at the start of a layer, in units of its h^2 (paper: 2) */
   double eps_end_h2;         /* eps at the end of a coarser layer, same units (paper: 1/2);
-                                eps halves between, with halves_per_stage steps each */
-  int32_t halves_per_stage;  /* half-iterations per eps stage */
+                                eps halves in between */
+  int32_t halves_per_stage;  /* half-iterations per eps stage, at least */
+  int32_t stage_max_halves;  /* ... continued in groups of halves_per_stage until the
+                                certificate's relative gap is <= stage_gap, at most this */
+  double stage_gap;
+  int32_t coarse_max_iter;   /* cap on inner iterations per cell on the coarser layers */
   int32_t final_max_halves;  /* cap on half-iterations after the finest stage */
   int32_t check_every;       /* certificate (dd_uot_score) every this many */
   double target_rel_gap;     /* stop once the relative primal-dual gap is below */
 } dduot_multiscale;
 
-/* levels 6, coarse_cell 4, eps 2 h^2 -> h^2/2 per layer, 4 half-iterations per
-   stage, at most 200 final half-iterations, certificate every 4, target 1e-6. */
+/* levels 7, coarse_cell 4, eps 2 h^2 -> h^2/2 per layer, 4..16 half-iterations
+   per stage (stage gap 1e-3), 1000 inner iterations on coarse layers, at most
+   200 final half-iterations, certificate every 4, target 1e-6. */
 void dd_uot_default_multiscale(dduot_multiscale* m);
 
 /* Coarse-to-fine solve with eps-scaling: coarsen (mu, nu) by 2 x 2 sums to
-   `levels` layers; on the coarsest start from the product plan if it fits
-   box_cap, else the block start; on every layer run the eps stages, then
-   refine (dd_uot_refine); on the finest layer continue to cfg->eps and then
-   iterate until the certificate's relative gap is <= target_rel_gap or
-   final_max_halves are done.  trace (nullable, trace_cap triples): one
-   (total half-iterations, elapsed ms since the call, relative gap) per
-   certificate of the final stage; *trace_len gets their count.  *out
-   receives the finest handle (its state, score, backward). */
+   `levels` layers; start the coarsest from the product plan if it fits
+   box_cap (layers of side <= 64 widen box_cap to the grid), else the block
+   start; on every layer run the eps stages, then refine (dd_uot_refine); on
+   the finest layer continue to cfg->eps and then iterate until the
+   certificate's relative gap is <= target_rel_gap or final_max_halves are
+   done.  trace (nullable, trace_cap records of 4 doubles): per certificate of
+   the final stage, (total half-iterations, elapsed ms since the call,
+   relative certificate gap pd_gap/|dual|, relative gap of the DD plan
+   (tracked - dual)/|dual|); *trace_len gets their count.  *out receives the finest handle (its
+   state, score, backward). */
 int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_multiscale* ms,
                             const double* mu, const double* nu, void* hip_stream,
                             dduot_handle** out, double* trace, int32_t trace_cap,

@@ -46,7 +46,9 @@ them also fixed in the design notes):
      steps (convexity of each term).
   R9 GetWeights: greedy theta = 1; safe theta = 1/n with n the number of cells
      updated in the step; swift takes greedy iff
-     Ebar_greedy <= Ebar_cur + lenience |Ebar_cur|, else safe.
+     Ebar_greedy <= Ebar_cur + lenience |Ebar_cur|, else safe; staggered runs
+     the partition as four batches of non-adjacent cells (parity of the cell
+     position), one swift step each, in batch order.
   R10 multiscale refinement (warm start of a finer layer): see `refine`.
 """
 from __future__ import annotations
@@ -98,7 +100,7 @@ class Options:
     lenience: float = 0.0      # 0.005 in Sec. 4.4; 0 = strict
     margin: int = 2
     cap: int = 64              # maximal Y-box side
-    getweights: str = "swift"  # greedy | safe | swift
+    getweights: str = "swift"  # greedy | safe | swift | staggered
     translate: bool = False    # dual line search along (alpha + s, beta - s)
 
 
@@ -437,10 +439,23 @@ def _on_box(entry, box):
 # --------------------------------------------------------------------------
 # Algorithm 4 (parallel) and Algorithm 3 (sequential)
 # --------------------------------------------------------------------------
-def half_iteration(p: Problem, st: State, part: str, opt: Options) -> dict:
-    """One parallel DomDecIter (Algorithm 4) over partition `part`, with
-    GetWeights per reading R9.  Mutates `st`; returns the step's statistics."""
-    cells = composite_cells(p, part)
+def staggered_batches(p: Problem, part: str):
+    """The composite cells of a partition in 2^d = 4 batches by the parity of
+    their position in the partition's cell grid, so that no batch holds two
+    adjacent composite cells (Sec. 3.4 `staggered`, Sec. 4.4)."""
+    off = part == "B"
+    n2g = len(_axis_groups(p.nb2, off))
+    batches = [[], [], [], []]
+    for idx, c in enumerate(composite_cells(p, part)):
+        ga, gb = divmod(idx, n2g)
+        batches[(ga % 2) * 2 + (gb % 2)].append(c)
+    return batches
+
+
+def _dd_step(p: Problem, st: State, cells, part: str, rule: str, opt: Options,
+             force: bool) -> dict:
+    """One parallel DomDecIter (Algorithm 4) over `cells`, with GetWeights
+    `rule` (reading R9; force = greedy).  Mutates `st`."""
     P = aggregate(p, st.boxes)
     results = [process_cell(p, c, st.boxes, P, opt) for c in cells]
     upd = [(c, r) for c, r in zip(cells, results) if r is not None]
@@ -458,15 +473,14 @@ def half_iteration(p: Problem, st: State, part: str, opt: Options) -> dict:
     e_cur = float(st.hbar.sum()) + p.lam * uot.kl(P, p.nu)
     e_grd = float(htil.sum()) + p.lam * uot.kl(Pg, p.nu)
 
-    if opt.getweights == "greedy" or st.force_greedy:
+    if rule == "greedy" or force:
         theta = 1.0
-    elif opt.getweights == "safe":
+    elif rule == "safe":
         theta = 1.0 / max(n_upd, 1)
-    elif opt.getweights == "swift":
+    elif rule == "swift":
         theta = 1.0 if e_grd <= e_cur + opt.lenience * abs(e_cur) else 1.0 / max(n_upd, 1)
     else:
-        raise ValueError(opt.getweights)
-    st.force_greedy = False
+        raise ValueError(rule)
 
     # Algorithm 4: pi' = sum_J (1 - theta) pi_J + theta pi~_J
     for c, r in upd:
@@ -483,7 +497,6 @@ def half_iteration(p: Problem, st: State, part: str, opt: Options) -> dict:
             new = np.zeros((rows.size, p.n1 * p.n2))
             new[:, r["yi"]] = r["pi"]
             st.plan[rows] = (1.0 - theta) * st.plan[rows] + theta * new
-    st.k += 1
     stats = dict(part=part, theta=theta, e_cur=e_cur, e_greedy=e_grd, n_cells=len(cells),
                  n_updated=n_upd, n_overflow=len(cells) - n_upd,
                  iters=[r["iters"] for _, r in upd],
@@ -491,6 +504,24 @@ def half_iteration(p: Problem, st: State, part: str, opt: Options) -> dict:
                  point_iters=sum(r["iters"] * r["xi"].size for _, r in upd))
     st.history.append(stats)
     return stats
+
+
+def half_iteration(p: Problem, st: State, part: str, opt: Options):
+    """One half-iteration over partition `part`: a parallel DomDecIter
+    (Algorithm 4) over all its cells with GetWeights per reading R9, or, for
+    `staggered`, four of them in turn over the staggered batches, each with
+    swift.  Mutates `st`; returns the step's statistics (a list of the four
+    batch steps for `staggered`).  After an eps change or a refinement the
+    whole half-iteration is greedy."""
+    force = st.force_greedy
+    if opt.getweights == "staggered":
+        out = [_dd_step(p, st, cells, part, "swift", opt, force)
+               for cells in staggered_batches(p, part)]
+    else:
+        out = _dd_step(p, st, composite_cells(p, part), part, opt.getweights, opt, force)
+    st.force_greedy = False
+    st.k += 1
+    return out
 
 
 def half_iteration_sequential(p: Problem, st: State, part: str, opt: Options) -> dict:

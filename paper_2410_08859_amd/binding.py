@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdd_uot.so")
 
 OK, EINVAL, ENOMEM, EHIP, ESLOT, ESTATE = 0, -1, -2, -3, -4, -5
-GW_GREEDY, GW_SAFE, GW_SWIFT = 0, 1, 2
+GW_GREEDY, GW_SAFE, GW_SWIFT, GW_STAGGERED = 0, 1, 2, 3
 INIT_BLOCK, INIT_PRODUCT = 0, 1
 HIST_FIELDS = ("theta", "e_cur", "e_greedy", "n_updated", "point_iters", "max_inner",
                "n_unconverged", "n_overflow", "inner_iters", "algo_bytes", "lse_terms",
@@ -27,7 +27,7 @@ EXPORTED = (
     "dd_uot_kernel_time", "dd_uot_synchronize", "dd_uot_num_problems", "dd_uot_destroy",
     "dd_uot_last_error", "dd_uot_refine", "dd_uot_refine_clipped", "dd_uot_default_multiscale",
     "dd_uot_solve_multiscale", "dd_uot_init_moved", "dd_uot_init_batch_moved",
-    "dd_uot_backward_ypos",
+    "dd_uot_backward_ypos", "dd_uot_set_graph", "dd_uot_autotune",
 )
 
 
@@ -69,7 +69,9 @@ class dduot_multiscale(C.Structure):
     _fields_ = [
         ("levels", C.c_int32), ("coarse_cell", C.c_int32),
         ("eps_start_h2", C.c_double), ("eps_end_h2", C.c_double),
-        ("halves_per_stage", C.c_int32), ("final_max_halves", C.c_int32),
+        ("halves_per_stage", C.c_int32), ("stage_max_halves", C.c_int32),
+        ("stage_gap", C.c_double),
+        ("coarse_max_iter", C.c_int32), ("final_max_halves", C.c_int32),
         ("check_every", C.c_int32),
         ("target_rel_gap", C.c_double),
     ]
@@ -119,6 +121,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dd_uot_init_batch_moved": (C.c_int, [C.c_int32, P(dduot_config), P(dp), P(dp), P(dp),
                                               C.c_void_p, P(H)]),
         "dd_uot_backward_ypos": (C.c_int, [H, C.c_int32, C.c_double, dp]),
+        "dd_uot_set_graph": (C.c_int, [H, C.c_int32]),
+        "dd_uot_autotune": (C.c_int, [H, P(C.c_int32), dp]),
         "dd_uot_refine_clipped": (C.c_int32, [H]),
         "dd_uot_default_multiscale": (None, [P(dduot_multiscale)]),
         "dd_uot_solve_multiscale": (C.c_int, [P(dduot_config), P(dduot_multiscale), dp, dp,
@@ -283,15 +287,16 @@ def dd_uot_default_multiscale(**kw) -> dduot_multiscale:
 
 def dd_uot_solve_multiscale(cfg: dduot_config, ms: dduot_multiscale, mu, nu, stream=None,
                             trace_cap=1024):
-    """Returns (handle, trace) with trace rows (half-iterations, elapsed ms, rel gap)."""
+    """Returns (handle, trace) with trace rows (half-iterations, elapsed ms,
+    certificate rel. gap, DD-plan rel. gap)."""
     mu = _grid(mu, cfg.n1, cfg.n2)
     nu = _grid(nu, cfg.n1, cfg.n2)
     h = C.c_void_p()
-    tr = np.zeros(3 * trace_cap)
+    tr = np.zeros(4 * trace_cap)
     n = C.c_int32()
     _check(load().dd_uot_solve_multiscale(C.byref(cfg), C.byref(ms), _dptr(mu), _dptr(nu), stream,
                                           C.byref(h), _dptr(tr), trace_cap, C.byref(n)))
-    return h, tr[: 3 * n.value].reshape(-1, 3)
+    return h, tr[: 4 * n.value].reshape(-1, 4)
 
 
 def dd_uot_init_moved(cfg: dduot_config, mu, nu, ypos, stream=None):
@@ -325,3 +330,15 @@ def dd_uot_backward_ypos(h, prob, n1, n2, gout=1.0):
     out = np.zeros(2 * n1 * n2)
     _check(load().dd_uot_backward_ypos(h, prob, gout, _dptr(out)))
     return out.reshape(n1, n2, 2)
+
+
+def dd_uot_set_graph(h, enable=True):
+    _check(load().dd_uot_set_graph(h, 1 if enable else 0))
+
+
+def dd_uot_autotune(h):
+    """Returns (threads per cell chosen, [ms for 64, 128, 256 threads; -1 = not admissible])."""
+    c = C.c_int32()
+    ms = np.zeros(3)
+    _check(load().dd_uot_autotune(h, C.byref(c), _dptr(ms)))
+    return c.value, ms

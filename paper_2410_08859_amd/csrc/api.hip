@@ -13,7 +13,7 @@
 
 namespace dduot {
 hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int precision,
-                             bool moved, hipStream_t st);
+                             bool moved, int nt, hipStream_t st);
 hipError_t set_cell_lds_limit(size_t bytes);
 size_t cell_lds_bytes(int cap, int precision, bool moved);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st);
@@ -22,8 +22,12 @@ hipError_t launch_aggregate(const Box* box, const double* vals, long cap2, const
 hipError_t launch_kl_chunks(const int* cp, const int* cs, const int* cl, const Prob* probs,
                             const double* P, const double* Pg, const double* nu, double* part,
                             int nchunk, hipStream_t st);
-hipError_t launch_getweights(const Dev& d, int part, int rec, int nprob, hipStream_t st);
-hipError_t launch_mix(const Dev& d, int part, int nbasic, int cap, hipStream_t st);
+hipError_t launch_getweights(const Dev& d, int part, int blo, int bhi, int glo, int ghi, bool last,
+                             int nprob, hipStream_t st);
+hipError_t launch_aggregate_sel(const Dev& d, int part, int glo, int ghi, double* P, int nbasic,
+                                hipStream_t st);
+hipError_t launch_advance(long long* kstep, hipStream_t st);
+hipError_t launch_mix(const Dev& d, int part, int glo, int ghi, int nbasic, int cap, hipStream_t st);
 hipError_t set_mix_lds_limit(size_t bytes);
 hipError_t launch_certificate(const Prob& p, const double* alpha, const double* mu, const double* nu,
                               const double* px, const double* P, const double* ydel, double* bhat,
@@ -86,6 +90,9 @@ struct dduot_handle {
   std::vector<Prob> probs;
   std::vector<Cell> cells;
   int ncell[2] = {0, 0};
+  int boff[2][4] = {}, bn[2][4] = {};   // staggered batches: global cell ranges
+  bool staggered = false;
+  long long nrec = 0;                    // history records written (steps of batches)
   int nbasic = 0;
   long ngrid = 0;
   long maxgrid = 0;
@@ -111,6 +118,13 @@ struct dduot_handle {
   double *d_ws_lnv = nullptr, *d_ws_lrr = nullptr;
   double* d_ydel = nullptr;
   double *d_mom = nullptr, *d_dy = nullptr;   // Y-position gradient (allocated on first use)
+  long long* d_kstep = nullptr;               // device copy of k
+  // captured A+B step pair (hipGraph), replayed by dd_uot_iterate
+  bool use_graph = false;
+  int nt = 256;        // threads per cell workgroup (dd_uot_autotune)
+  int max_tile = 0;    // largest composite tile (points)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
   bool moved = false;
   int *d_chunk_prob = nullptr, *d_chunk_start = nullptr, *d_chunk_len = nullptr;
   double* d_chunk_part = nullptr;
@@ -180,7 +194,7 @@ static int validate(const dduot_config* c, const double* mu, const double* nu, i
   if (!(c->h >= 0.0) || !isfinite(c->h)) return fail(DDUOT_EINVAL, pre + "h must be >= 0");
   if (c->precision != 32 && c->precision != 64)
     return fail(DDUOT_EINVAL, pre + "precision must be 32 or 64");
-  if (c->getweights < 0 || c->getweights > 2) return fail(DDUOT_EINVAL, pre + "bad getweights");
+  if (c->getweights < 0 || c->getweights > 3) return fail(DDUOT_EINVAL, pre + "bad getweights");
   if (c->init != DDUOT_INIT_BLOCK && c->init != DDUOT_INIT_PRODUCT)
     return fail(DDUOT_EINVAL, pre + "bad init");
   if (!(c->sinkhorn_err >= 0.0)) return fail(DDUOT_EINVAL, pre + "sinkhorn_err must be >= 0");
@@ -245,6 +259,10 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
     h->cap = std::max(h->cap, cfgs[k].box_cap);
   }
   h->cap2 = (long)h->cap * h->cap;
+  h->staggered = cfgs[0].getweights == DDUOT_GW_STAGGERED;
+  for (int k = 0; k < nprob; ++k)
+    if ((cfgs[k].getweights == DDUOT_GW_STAGGERED) != h->staggered)
+      return fail(DDUOT_EINVAL, "staggered GetWeights: all problems of a handle or none");
   const size_t lds_cell = cell_lds_bytes(h->cap, h->precision, h->moved);
   const size_t lds_mix = sizeof(double) * h->cap2;
   if ((long)lds_cell > max_lds || (long)lds_mix > max_lds)
@@ -255,7 +273,9 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   // problems, basic cells, composite cells
   std::vector<int> basic_prob;
   std::vector<int2> basic_xy;
-  std::vector<Cell> cellsA, cellsB;
+  // cells by partition, staggered batch and problem, concatenated below
+  std::vector<std::vector<std::vector<Cell>>> staged[2];
+  for (int part = 0; part < 2; ++part) staged[part].assign(4, std::vector<std::vector<Cell>>(nprob));
   std::vector<int> chunk_prob, chunk_start, chunk_len;
   long goff = 0;
   for (int k = 0; k < nprob; ++k) {
@@ -286,10 +306,10 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
       }
     for (int part = 0; part < 2; ++part) {
       auto g1 = axis_groups(p.nb1, part == 1), g2 = axis_groups(p.nb2, part == 1);
-      auto& out = part == 0 ? cellsA : cellsB;
-      p.cell_off[part] = (int)out.size();   // fixed up below for B
-      for (auto& r : g1)
-        for (auto& cc : g2) {
+      for (int ri = 0; ri < (int)g1.size(); ++ri)
+        for (int ci = 0; ci < (int)g2.size(); ++ci) {
+          const auto& r = g1[ri];
+          const auto& cc = g2[ci];
           Cell C{};
           C.prob = k;
           C.nb = 0;
@@ -297,9 +317,9 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
             for (int b2 : cc) C.basic[C.nb++] = p.basic_off + b1 * p.nb2 + b2;
           C.x1 = r[0] * p.s; C.x2 = cc[0] * p.s;
           C.lx1 = (int)r.size() * p.s; C.lx2 = (int)cc.size() * p.s;
-          out.push_back(C);
+          // staggered batch: parity of the cell position (no two neighbours)
+          staged[part][(ri % 2) * 2 + (ci % 2)][k].push_back(C);
         }
-      p.ncell[part] = (int)out.size() - p.cell_off[part];
     }
     p.chunk_off = (int)chunk_prob.size();
     for (long s0 = 0; s0 < n; s0 += kChunk) {
@@ -313,11 +333,23 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
     h->maxgrid = std::max(h->maxgrid, n);
   }
   h->ngrid = goff;
-  h->ncell[0] = (int)cellsA.size();
-  h->ncell[1] = (int)cellsB.size();
-  for (auto& p : h->probs) p.cell_off[1] += h->ncell[0];
-  h->cells = cellsA;
-  h->cells.insert(h->cells.end(), cellsB.begin(), cellsB.end());
+  for (int k = 0; k < nprob; ++k) h->max_tile = std::max(h->max_tile, 4 * cfgs[k].cell * cfgs[k].cell);
+  // global order: partition, batch, problem; each (partition, batch) is one
+  // contiguous range of cells (one launch for all problems)
+  h->cells.clear();
+  for (int part = 0; part < 2; ++part) {
+    const int part_start = (int)h->cells.size();
+    for (int bt = 0; bt < 4; ++bt) {
+      h->boff[part][bt] = (int)h->cells.size();
+      for (int k = 0; k < nprob; ++k) {
+        h->probs[k].cell_off[part][bt] = (int)h->cells.size();
+        h->probs[k].ncell[part][bt] = (int)staged[part][bt][k].size();
+        h->cells.insert(h->cells.end(), staged[part][bt][k].begin(), staged[part][bt][k].end());
+      }
+      h->bn[part][bt] = (int)h->cells.size() - h->boff[part][bt];
+    }
+    h->ncell[part] = (int)h->cells.size() - part_start;
+  }
   h->nbasic = (int)basic_prob.size();
   h->nchunk = (int)chunk_prob.size();
   std::vector<int> bcell[2];
@@ -436,6 +468,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_hist, (size_t)nprob * h->hist_cap * kHistFields));
   CHK(dalloc(h, &h->d_overflow, nprob));
   CHK(dalloc(h, &h->d_force, nprob));
+  CHK(dalloc(h, &h->d_kstep, 1));
   CHK(dalloc(h, &h->d_bhat, h->ngrid));
   CHK(dalloc(h, &h->d_dmu, h->ngrid));
   CHK(dalloc(h, &h->d_dnu, h->ngrid));
@@ -478,6 +511,8 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   std::vector<int> zeros(nprob, 0);
   HIPCHK(hipMemcpyAsync(h->d_overflow, zeros.data(), sizeof(int) * nprob, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h->d_force, zeros.data(), sizeof(int) * nprob, hipMemcpyHostToDevice, st));
+  static const long long kzero = 0;
+  HIPCHK(hipMemcpyAsync(h->d_kstep, &kzero, sizeof(long long), hipMemcpyHostToDevice, st));
 
   // state slots: block start = nu on the block; product start = |mu_i| nu.
   // Staged compactly on the host, scattered into the fixed-capacity slots.
@@ -543,6 +578,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   d.ws_lnv = h->d_ws_lnv;
   d.ws_lrr = h->d_ws_lrr;
   d.ydel = h->d_ydel;
+  d.kstep = h->d_kstep;
   d.chunk_part = h->d_chunk_part;
   d.theta = h->d_theta;
   d.hist = h->d_hist;
@@ -556,6 +592,8 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
 
 static void release(dduot_handle* h) {
   if (!h) return;
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (auto& e : h->events) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -629,8 +667,9 @@ extern "C" int dd_uot_set_eps(dduot_handle* h, int32_t prob, double eps) {
   return DDUOT_OK;
 }
 
-// One half-iteration over partition `part` for all problems.
-static int half_iteration(dduot_handle* h, int part) {
+// One parallel DomDecIter (Algorithm 4) over the cells [lo, lo + n) of
+// partition `part` (all problems), GetWeights over batches [blo, bhi).
+static int dd_step(dduot_handle* h, int part, int lo, int n, int blo, int bhi) {
   hipStream_t st = h->stream;
   const Dev& d = h->d;
   HIPCHK(launch_fill(h->d_P, h->ngrid, 0.0, st));
@@ -641,19 +680,33 @@ static int half_iteration(dduot_handle* h, int part) {
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, st));
   }
-  const int base = part == 0 ? 0 : h->ncell[0];
-  HIPCHK(launch_cell_solve(d, base, h->ncell[part], h->cap, h->precision, h->moved, st));
+  HIPCHK(launch_cell_solve(d, lo, n, h->cap, h->precision, h->moved, h->nt, st));
   if (h->timing) {
     HIPCHK(hipEventRecord(e1, st));
     h->events.push_back({e0, e1});
-    h->timed_recs.push_back(h->k);
+    h->timed_recs.push_back(h->nrec);
   }
+  // greedy candidate Y-marginal: candidates of the step's basic cells, the
+  // state elsewhere
   HIPCHK(launch_fill(h->d_Pg, h->ngrid, 0.0, st));
-  HIPCHK(launch_aggregate(h->d_cbox, h->d_cand, h->cap2, h->d_basic_prob, h->d_probs, h->d_Pg, h->nbasic, st));
+  HIPCHK(launch_aggregate_sel(d, part, lo, lo + n, h->d_Pg, h->nbasic, st));
   HIPCHK(launch_kl_chunks(h->d_chunk_prob, h->d_chunk_start, h->d_chunk_len, h->d_probs, h->d_P,
                           h->d_Pg, h->d_nu, h->d_chunk_part, h->nchunk, st));
-  HIPCHK(launch_getweights(d, part, (int)(h->k % h->hist_cap), h->nprob, st));
-  HIPCHK(launch_mix(d, part, h->nbasic, h->cap, st));
+  HIPCHK(launch_getweights(d, part, blo, bhi, lo, lo + n, bhi == 4, h->nprob, st));
+  HIPCHK(launch_mix(d, part, lo, lo + n, h->nbasic, h->cap, st));
+  HIPCHK(launch_advance(h->d_kstep, st));
+  h->nrec += 1;
+  return DDUOT_OK;
+}
+
+// One half-iteration over partition `part` for all problems: one step over
+// all its cells, or (staggered) one step per batch in turn.
+static int half_iteration(dduot_handle* h, int part) {
+  if (h->staggered) {
+    for (int bt = 0; bt < 4; ++bt) CHK(dd_step(h, part, h->boff[part][bt], h->bn[part][bt], bt, bt + 1));
+  } else {
+    CHK(dd_step(h, part, h->boff[part][0], h->ncell[part], 0, 4));
+  }
   h->k += 1;
   return DDUOT_OK;
 }
@@ -671,11 +724,112 @@ static int read_records(dduot_handle* h, int prob, long long from, long long to,
   return DDUOT_OK;
 }
 
+// Capture one A half-iteration followed by one B half-iteration into a graph
+// (kernels only: fills are kernels, the record index is read on the device).
+static int capture_pair(dduot_handle* h) {
+  if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  hipStream_t keep = h->stream;
+  const long long k0 = h->k, n0 = h->nrec;
+  HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  h->stream = h->cap_stream;
+  int r = half_iteration(h, 0);
+  if (r == DDUOT_OK) r = half_iteration(h, 1);
+  h->stream = keep;
+  h->k = k0;
+  h->nrec = n0;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (r != DDUOT_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return r;
+  }
+  if (e != hipSuccess) return fail(DDUOT_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->gexec = nullptr;
+    return fail(DDUOT_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  return DDUOT_OK;
+}
+
+// Threads per cell workgroup: time the cell solve of the next partition on
+// the current state for every admissible size (at least the largest tile's
+// point count) and keep the fastest.  The timed solves write only candidate
+// buffers and the stitched potentials, which the next step rewrites with the
+// same values, so the state is unchanged.
+extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
+  if (!h) return fail(DDUOT_EINVAL, "null handle");
+  hipStream_t st = h->stream;
+  const int part = (int)(h->k % 2);
+  const int base = h->boff[part][0];
+  HIPCHK(launch_fill(h->d_P, h->ngrid, 0.0, st));
+  HIPCHK(launch_aggregate(h->d_box, h->d_vals, h->cap2, h->d_basic_prob, h->d_probs, h->d_P, h->nbasic, st));
+  const int cand[3] = {64, 128, 256};
+  double best = 1e300;
+  int pick = 256;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (int c = 0; c < 3; ++c) {
+    const int nt = cand[c];
+    if (nt < h->max_tile) {
+      if (ms) ms[c] = -1.0;
+      continue;
+    }
+    float t = 0.0f;
+    hipError_t e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = launch_cell_solve(h->d, base, h->ncell[part], h->cap, h->precision, h->moved, nt, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return fail(DDUOT_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+    }
+    if (ms) ms[c] = t;
+    if (t < best) {
+      best = t;
+      pick = nt;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->nt = pick;
+  if (h->gexec) {   // the captured step used the old size
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  if (chosen) *chosen = pick;
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_set_graph(dduot_handle* h, int32_t enable) {
+  if (!h) return fail(DDUOT_EINVAL, "null handle");
+  h->use_graph = enable != 0;
+  return DDUOT_OK;
+}
+
 extern "C" int dd_uot_iterate(dduot_handle* h, int32_t n_half_iters, dduot_iter_stats* stats) {
   if (!h) return fail(DDUOT_EINVAL, "null handle");
   if (n_half_iters < 0) return fail(DDUOT_EINVAL, "n_half_iters must be >= 0");
-  const long long k0 = h->k;
-  for (int i = 0; i < n_half_iters; ++i) CHK(half_iteration(h, (int)(h->k % 2)));
+  const long long r0 = h->nrec;
+  int i = 0;
+  if (h->use_graph && !h->timing) {
+    if (h->k % 2 == 1 && i < n_half_iters) {
+      CHK(half_iteration(h, 1));
+      ++i;
+    }
+    if (n_half_iters - i >= 2 && !h->gexec) CHK(capture_pair(h));
+    const long long per_pair = h->staggered ? 8 : 2;
+    for (; n_half_iters - i >= 2; i += 2) {
+      HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+      h->k += 2;
+      h->nrec += per_pair;
+    }
+  }
+  for (; i < n_half_iters; ++i) CHK(half_iteration(h, (int)(h->k % 2)));
   for (int p = 0; p < h->nprob; ++p) h->cert_done[p] = 0;
   if (stats) {
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -683,7 +837,7 @@ extern "C" int dd_uot_iterate(dduot_handle* h, int32_t n_half_iters, dduot_iter_
     stats->half_iters = n_half_iters;
     std::vector<double> rec;
     for (int p = 0; p < h->nprob; ++p) {
-      CHK(read_records(h, p, k0, h->k, rec));
+      CHK(read_records(h, p, r0, h->nrec, rec));
       for (size_t r = 0; r + kHistFields <= rec.size(); r += kHistFields) {
         const double* x = rec.data() + r;
         if (x[0] < 1.0) stats->n_safe += 1;
@@ -704,7 +858,7 @@ extern "C" int dd_uot_history(dduot_handle* h, int32_t prob, int32_t max, double
     return fail(DDUOT_EINVAL, "bad arguments");
   HIPCHK(hipStreamSynchronize(h->stream));
   std::vector<double> rec;
-  CHK(read_records(h, prob, 0, h->k, rec));
+  CHK(read_records(h, prob, 0, h->nrec, rec));
   const int n = (int)(rec.size() / kHistFields);
   const int m = std::min(n, (int)max);
   std::copy(rec.begin(), rec.begin() + (size_t)m * kHistFields, out);
@@ -892,8 +1046,11 @@ extern "C" int dd_uot_refine(dduot_handle* coarse, const dduot_config* cfg, cons
   const Prob& pc = coarse->probs[0];
   if (cfg->n1 != 2 * pc.n1 || cfg->n2 != 2 * pc.n2)
     return fail(DDUOT_EINVAL, "the fine grid must have twice the coarse points per axis");
-  if (cfg->cell != pc.s && cfg->cell != 2 * pc.s)
-    return fail(DDUOT_EINVAL, "the fine basic cell side must be the coarse one or twice it");
+  // every fine basic cell (cell fine points = cell/2 coarse points) must lie
+  // inside one coarse basic cell
+  if (cfg->cell > 2 * pc.s || (cfg->cell % 2 == 0 && (2 * pc.s) % cfg->cell) ||
+      (cfg->cell % 2 == 1 && cfg->cell != 1))
+    return fail(DDUOT_EINVAL, "each fine basic cell must lie inside one coarse basic cell");
   if (cfg->precision != coarse->precision)
     return fail(DDUOT_EINVAL, "coarse and fine precision differ");
   dduot_config c = *cfg;
@@ -963,11 +1120,14 @@ extern "C" int32_t dd_uot_refine_clipped(const dduot_handle* h) { return h ? h->
 
 extern "C" void dd_uot_default_multiscale(dduot_multiscale* m) {
   memset(m, 0, sizeof(*m));
-  m->levels = 6;
+  m->levels = 7;
   m->coarse_cell = 4;
   m->eps_start_h2 = 2.0;
   m->eps_end_h2 = 0.5;
   m->halves_per_stage = 4;
+  m->stage_max_halves = 16;
+  m->stage_gap = 1e-3;
+  m->coarse_max_iter = 1000;
   m->final_max_halves = 200;
   m->check_every = 4;
   m->target_rel_gap = 1e-6;
@@ -991,8 +1151,10 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
   if (L < 1 || L > 12) return fail(DDUOT_EINVAL, "levels must be in [1, 12]");
   if (!(ms->eps_start_h2 > 0.0) || !(ms->eps_end_h2 > 0.0) || ms->eps_end_h2 > ms->eps_start_h2)
     return fail(DDUOT_EINVAL, "need 0 < eps_end_h2 <= eps_start_h2");
-  if (ms->halves_per_stage < 1 || ms->final_max_halves < 0 || ms->check_every < 1)
-    return fail(DDUOT_EINVAL, "bad iteration counts");
+  if (ms->halves_per_stage < 1 || ms->final_max_halves < 0 || ms->check_every < 1 ||
+      ms->stage_max_halves < ms->halves_per_stage || ms->coarse_max_iter < 1 ||
+      ms->coarse_cell < 1 || 2 * ms->coarse_cell > kMaxTile)
+    return fail(DDUOT_EINVAL, "bad iteration counts or coarse cell");
   if (cfg->n1 % (1 << (L - 1)) || cfg->n2 % (1 << (L - 1)))
     return fail(DDUOT_EINVAL, "grid sides must be divisible by 2^(levels-1)");
   const double t0 = now_ms();
@@ -1019,11 +1181,12 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
   }
   int tl = 0;
   long long halves_before = 0;   // half-iterations of the coarser layers
-  auto record = [&](dduot_handle* h, double rel) {
+  auto record = [&](dduot_handle* h, const dduot_score& sc) {
     if (tl < trace_cap) {
-      trace[3 * tl + 0] = (double)(halves_before + h->k);
-      trace[3 * tl + 1] = now_ms() - t0;
-      trace[3 * tl + 2] = rel;
+      trace[4 * tl + 0] = (double)(halves_before + h->k);
+      trace[4 * tl + 1] = now_ms() - t0;
+      trace[4 * tl + 2] = sc.rel_pd_gap;
+      trace[4 * tl + 3] = (sc.tracked - sc.dual) / fabs(sc.dual);
       ++tl;
     }
   };
@@ -1034,7 +1197,21 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
     c.n1 = n1s[l];
     c.n2 = n2s[l];
     c.h = cfg->h * scale;
-    c.cell = l == L - 1 ? cfg->cell : std::min(cfg->cell, ms->coarse_cell);
+    const bool finest = l == L - 1;
+    if (finest) {
+      c.cell = cfg->cell;
+    } else if (l == 0 && c.n1 == c.n2 && c.n1 % 2 == 0 && c.n1 <= kMaxTile) {
+      // the coarsest layer is one composite cell: partition A solves the
+      // global problem (the role of the paper's global Sinkhorn warm start)
+      c.cell = c.n1 / 2;
+    } else {
+      c.cell = std::min(cfg->cell, ms->coarse_cell);
+    }
+    if (!finest) {
+      c.sinkhorn_max_iter = std::max(cfg->sinkhorn_max_iter, ms->coarse_max_iter);
+      // small layers keep whole-grid boxes (no overflow)
+      if (std::max(c.n1, c.n2) <= 64) c.box_cap = std::max(c.box_cap, std::max(c.n1, c.n2));
+    }
     const double h2 = c.h * c.h;
     c.eps = ms->eps_start_h2 * h2;
     dduot_handle* nh = nullptr;
@@ -1049,30 +1226,41 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
       if (r != DDUOT_OK) return r;
     }
     h = nh;
-    // eps stages of this layer: halve from eps_start down to eps_end (the
-    // finest layer continues to cfg->eps)
-    const double e_end = l == L - 1 ? cfg->eps : ms->eps_end_h2 * h2;
-    double e = c.eps;
     auto fail_out = [&](int r) {
       std::string keep = g_err;
       dd_uot_destroy(h);
       g_err = keep;
       return r;
     };
+    // eps stages of this layer: halve from eps_start down to eps_end (the
+    // finest layer continues to cfg->eps); each stage runs halves_per_stage
+    // half-iterations, then more until the certificate's relative gap is
+    // below stage_gap or stage_max_halves are done
+    const double e_end = finest ? cfg->eps : ms->eps_end_h2 * h2;
+    double e = c.eps;
     for (;;) {
-      int r = dd_uot_iterate(h, ms->halves_per_stage, nullptr);
-      if (r != DDUOT_OK) return fail_out(r);
+      int done = 0;
+      for (;;) {
+        int r = dd_uot_iterate(h, ms->halves_per_stage, nullptr);
+        if (r != DDUOT_OK) return fail_out(r);
+        done += ms->halves_per_stage;
+        if (done + ms->halves_per_stage > ms->stage_max_halves) break;
+        dduot_score sc;
+        r = dd_uot_score(h, 0, &sc);
+        if (r != DDUOT_OK) return fail_out(r);
+        if (sc.rel_pd_gap <= ms->stage_gap) break;
+      }
       if (e <= e_end * (1.0 + 1e-12)) break;
       e = std::max(e * 0.5, e_end);
-      r = dd_uot_set_eps(h, 0, e);
+      int r = dd_uot_set_eps(h, 0, e);
       if (r != DDUOT_OK) return fail_out(r);
     }
-    if (l == L - 1) {
+    if (finest) {
       // final stage: iterate, certificate every check_every half-iterations
       dduot_score sc;
       int r = dd_uot_score(h, 0, &sc);
       if (r != DDUOT_OK) return fail_out(r);
-      record(h, sc.rel_pd_gap);
+      record(h, sc);
       int done = 0;
       while (!(sc.rel_pd_gap <= ms->target_rel_gap) && done < ms->final_max_halves) {
         const int k = std::min(ms->check_every, ms->final_max_halves - done);
@@ -1081,7 +1269,7 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
         done += k;
         r = dd_uot_score(h, 0, &sc);
         if (r != DDUOT_OK) return fail_out(r);
-        record(h, sc.rel_pd_gap);
+        record(h, sc);
       }
     }
   }

@@ -31,6 +31,27 @@ __global__ __launch_bounds__(kBlock) void k_aggregate(const Box* box, const doub
   }
 }
 
+// Candidate P_Y for GetWeights: the candidate marginal of every basic cell
+// whose composite cell (in partition `part`) lies in [glo, ghi), the state
+// marginal of every other basic cell.
+__global__ __launch_bounds__(kBlock) void k_aggregate_sel(Dev d, int part, int glo, int ghi,
+                                                          double* P) {
+  const int b = blockIdx.x;
+  const int J = d.basic_cell[part][b];
+  const bool in = J >= glo && J < ghi;
+  const Box bx = in ? d.cbox[b] : d.box[b];
+  if (bx.l1 <= 0 || bx.l2 <= 0) return;
+  const Prob& p = d.probs[d.basic_prob[b]];
+  const long n = (long)bx.l1 * bx.l2;
+  const double* v = (in ? d.cand : d.vals) + b * d.cap2;
+  double* out = P + p.grid_off;
+  for (long o = threadIdx.x; o < n; o += kBlock) {
+    const int j1 = (int)(o / bx.l2), j2 = (int)(o - (long)j1 * bx.l2);
+    const double x = v[o];
+    if (x != 0.0) unsafeAtomicAdd(out + (long)(bx.o1 + j1) * p.n2 + (bx.o2 + j2), x);
+  }
+}
+
 __device__ __forceinline__ double kl_term(double p, double q) {
   return p > 0.0 ? p * (log(p) - log(q)) - p + q : q;
 }
@@ -83,33 +104,41 @@ __global__ __launch_bounds__(kBlock) void k_kl_chunks(const int* chunk_prob, con
 // E_cur = sum Hbar + lam KL(P|nu), E_greedy = sum Htil + lam KL(Pg|nu);
 // greedy theta = 1, safe theta = 1/n (n = cells updated), swift = greedy iff
 // E_greedy <= E_cur + lenience |E_cur|.  One workgroup per problem.
-__global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int rec) {
+__global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int blo, int bhi, int glo,
+                                                       int ghi, int last) {
+  const long long rec = d.kstep[0];
   __shared__ double red[4 * 10];
   const int pi = blockIdx.x;
   const Prob p = d.probs[pi];
   double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  // [0] sum hbar, [1] sum htil, [2] cells updated, [3] point iters, [4] unconverged,
-  // [5] overflow, [6] inner iters, [7] bytes, [8] log-sum-exp terms
+  // [0] sum hbar, [1] sum of the candidate pieces (htil for the step's basic
+  // cells, hbar elsewhere), [2] cells updated, [3] point iters, [4] unconverged,
+  // [5] overflow, [6] inner iters, [7] bytes, [8] log-sum-exp terms, [9] exact
+  // recomputations
   for (int b = threadIdx.x; b < p.nbasic; b += kBlock) {
-    acc[0] += d.hbar[p.basic_off + b];
-    acc[1] += d.htil[p.basic_off + b];
+    const int gb = p.basic_off + b;
+    const int J = d.basic_cell[part][gb];
+    acc[0] += d.hbar[gb];
+    acc[1] += (J >= glo && J < ghi) ? d.htil[gb] : d.hbar[gb];
   }
   int maxit = 0;
-  const int c0 = p.cell_off[part], nc = p.ncell[part];
-  for (int c = threadIdx.x; c < nc; c += kBlock) {
-    const int it = d.cell_iters[c0 + c];
-    const Cell C = d.cells[c0 + c];
-    if (it >= 0) {
-      acc[2] += 1.0;
-      acc[3] += (double)it * C.lx1 * C.lx2;
-      acc[4] += d.cell_conv[c0 + c] ? 0.0 : 1.0;
-      acc[6] += it;
-      acc[7] += d.cell_bytes[c0 + c];
-      acc[8] += d.cell_terms[c0 + c];
-      acc[9] += d.cell_fall[c0 + c];
-      maxit = max(maxit, it);
-    } else {
-      acc[5] += 1.0;
+  for (int bt = blo; bt < bhi; ++bt) {
+    const int c0 = p.cell_off[part][bt], nc = p.ncell[part][bt];
+    for (int c = threadIdx.x; c < nc; c += kBlock) {
+      const int it = d.cell_iters[c0 + c];
+      const Cell C = d.cells[c0 + c];
+      if (it >= 0) {
+        acc[2] += 1.0;
+        acc[3] += (double)it * C.lx1 * C.lx2;
+        acc[4] += d.cell_conv[c0 + c] ? 0.0 : 1.0;
+        acc[6] += it;
+        acc[7] += d.cell_bytes[c0 + c];
+        acc[8] += d.cell_terms[c0 + c];
+        acc[9] += d.cell_fall[c0 + c];
+        maxit = max(maxit, it);
+      } else {
+        acc[5] += 1.0;
+      }
     }
   }
   block_sum_aux<10>(acc, red);
@@ -131,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int rec)
     if (d.force_greedy[pi] || p.getweights == 0) th = 1.0;
     else if (p.getweights == 1) th = 1.0 / n;
     else th = (egr <= ecur + p.lenience * fabs(ecur)) ? 1.0 : 1.0 / n;
-    d.force_greedy[pi] = 0;
+    if (last) d.force_greedy[pi] = 0;   // a forced greedy half-iteration covers every batch
     d.theta[pi] = th;
     double* r = d.hist + ((long)pi * d.hist_cap + (rec % d.hist_cap)) * kHistFields;
     r[0] = th;
@@ -152,14 +181,14 @@ __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int rec)
 // Algorithm 4 update: nu_i <- (1 - theta) nu_i + theta nu~_i on the cell box,
 // truncation below `trunc`, shrink to the bbox of the nonzeros; the tracked
 // piece and the X-marginal are mixed with the same weight.
-__global__ __launch_bounds__(kBlock) void k_mix(Dev d, int part) {
+__global__ __launch_bounds__(kBlock) void k_mix(Dev d, int part, int glo, int ghi) {
   extern __shared__ __align__(16) double vbuf[];
   __shared__ int ired[4 * 4];
   const int b = blockIdx.x;
   const int pi = d.basic_prob[b];
   const Prob& p = d.probs[pi];
   const int J = d.basic_cell[part][b];
-  if (d.cell_iters[J] < 0) return;
+  if (J < glo || J >= ghi || d.cell_iters[J] < 0) return;   // not in this step, or overflowed
   const double th = d.theta[pi];
   const Box cb = d.cbox[b];
   const Box ob = d.box[b];
@@ -326,11 +355,29 @@ hipError_t launch_scatter_slots(const double* src, const long* off, double* vals
   return hipGetLastError();
 }
 
+// The half-iteration counter lives on the device, so a captured step graph
+// writes every replay's history record to its own slot.
+__global__ void k_advance(long long* kstep) {
+  if (threadIdx.x == 0) kstep[0] += 1;
+}
+
+hipError_t launch_advance(long long* kstep, hipStream_t st) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, kstep);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int blocks = (int)min((n + 255) / 256, (long)4096);
   hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_aggregate_sel(const Dev& d, int part, int glo, int ghi, double* P, int nbasic,
+                                hipStream_t st) {
+  if (nbasic <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_aggregate_sel, dim3(nbasic), dim3(kBlock), 0, st, d, part, glo, ghi, P);
   return hipGetLastError();
 }
 
@@ -350,15 +397,17 @@ hipError_t launch_kl_chunks(const int* cp, const int* cs, const int* cl, const P
   return hipGetLastError();
 }
 
-hipError_t launch_getweights(const Dev& d, int part, int rec, int nprob, hipStream_t st) {
-  hipLaunchKernelGGL(k_getweights, dim3(nprob), dim3(kBlock), 0, st, d, part, rec);
+hipError_t launch_getweights(const Dev& d, int part, int blo, int bhi, int glo, int ghi, bool last,
+                             int nprob, hipStream_t st) {
+  hipLaunchKernelGGL(k_getweights, dim3(nprob), dim3(kBlock), 0, st, d, part, blo, bhi, glo, ghi,
+                     last ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_mix(const Dev& d, int part, int nbasic, int cap, hipStream_t st) {
+hipError_t launch_mix(const Dev& d, int part, int glo, int ghi, int nbasic, int cap, hipStream_t st) {
   if (nbasic <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mix, dim3(nbasic), dim3(kBlock), sizeof(double) * (size_t)cap * cap, st, d,
-                     part);
+                     part, glo, ghi);
   return hipGetLastError();
 }
 

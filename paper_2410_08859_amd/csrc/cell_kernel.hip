@@ -61,7 +61,7 @@ struct M<double> {
 };
 
 // Sum N doubles over the workgroup in a fixed order (deterministic).
-template <int N>
+template <int NT, int N>
 __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -80,7 +80,7 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     double s = 0.0;
-    for (int ww = 0; ww < kBlock / 64; ++ww) s += red[ww * N + k];
+    for (int ww = 0; ww < NT / 64; ++ww) s += red[ww * N + k];
     v[k] = s;
   }
   __syncthreads();
@@ -88,11 +88,11 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
 
 // out[r] = max_c a[r*rs + c*cs] for r < rows, c < cols: G consecutive lanes
 // share a row and combine by butterfly shuffles (G divides 64).
-template <int G>
+template <int NT, int G>
 __device__ __forceinline__ void seg_max(const double* a, int rows, int cols, int rs, int cs,
                                         double* out) {
   const int g = threadIdx.x % G;
-  for (int r0 = 0; r0 < rows; r0 += kBlock / G) {
+  for (int r0 = 0; r0 < rows; r0 += NT / G) {
     const int r = r0 + threadIdx.x / G;
     double m = -INFINITY;
     if (r < rows)
@@ -118,7 +118,7 @@ __device__ __forceinline__ double newton_v(double a, double v0, double K, R tol,
   if (!(a > -INFINITY)) return 0.0;
   const R aR = R(a), KR = R(K);
   R v = R(v0);
-  R prev = R(INFINITY);
+  R gprev = R(INFINITY);
   for (int it = 0; it < maxit; ++it) {
     R la, sig;
     if (v >= aR) {
@@ -130,13 +130,18 @@ __device__ __forceinline__ double newton_v(double a, double v0, double K, R tol,
       la = aR + M<R>::lg1p(e);
       sig = e / (R(1) + e);
     }
-    const R dv = (v + KR * la) / (R(1) + KR * sig);
+    const R g = v + KR * la;
+    // Right of the root (G > 0) the Newton iterates of a convex increasing G
+    // decrease monotonically and so does G; a residual that stops decreasing
+    // is the rounding floor of K logaddexp, inside which steps only move v
+    // around.  (Step lengths need not shrink: they grow where G' drops.)
+    if (g > R(0)) {
+      if (!(g < gprev)) break;
+      gprev = g;
+    }
+    const R dv = g / (R(1) + KR * sig);
     v -= dv;
-    // converged, or at the rounding floor of K logaddexp (the step stopped
-    // shrinking): further steps only move v inside that floor
-    const R adv = fabs(dv);
-    if (!(adv > tol * (R(1) + fabs(v))) || !(adv < prev)) break;
-    prev = adv;
+    if (!(fabs(dv) > tol * (R(1) + fabs(v)))) break;
   }
   return (double)v;
 }
@@ -244,12 +249,12 @@ __host__ __device__ inline size_t cell_lds_layout(int cmax, bool moved, CellLds<
   const size_t n2 = (size_t)cmax * cmax, nt = (size_t)cmax * kMaxTile;
   size_t o_bd = take(8 * n2), o_zp = take(8 * n2), o_Tt = take(8 * nt), o_Ud = take(8 * nt);
   size_t o_Mr = take(8 * cmax), o_MU = take(8 * cmax), o_Mc = take(8 * kMaxTile);
-  size_t o_adr = take(8 * kBlock), o_Ma = take(8 * kMaxTile), o_red = take(8 * 4 * 16);
+  size_t o_adr = take(8 * kMaxTile * kMaxTile), o_Ma = take(8 * kMaxTile), o_red = take(8 * 4 * 16);
   // FP32 kernels keep log nu and log r in LDS (FP64 kernels use the global
   // per-cell workspace, whose full precision the FP64 parity needs)
   const size_t o_lnv = sizeof(R) == 4 ? take(4 * n2) : 0, o_lr = sizeof(R) == 4 ? take(4 * n2) : 0;
   const size_t o_d1 = moved ? take(sizeof(R) * n2) : 0, o_d2 = moved ? take(sizeof(R) * n2) : 0;
-  const size_t o_mx = moved ? take(8 * 3 * kBlock) : 0;
+  const size_t o_mx = moved ? take(8 * 3 * kMaxTile * kMaxTile) : 0;
   if (L) {
     L->bd = (double*)(base + o_bd);
     L->zp = (double*)(base + o_zp);
@@ -363,8 +368,10 @@ __device__ __forceinline__ double dense_y_lse(const double* adr, const double* M
   return m + (double)M<R>::lg(acc);
 }
 
-template <typename R, bool kMoved>
-__global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
+// NT threads per cell (64, 128 or 256; at least the tile's point count,
+// since thread t owns tile point t).
+template <typename R, bool kMoved, int NT>
+__global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int t = threadIdx.x;
   const int ci = cell_base + blockIdx.x;
@@ -396,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
       const int b = C.basic[k];
       const Box bx = d.box[b];
       const long n = (long)bx.l1 * bx.l2;
-      for (long o = t; o < n; o += kBlock) d.cand[b * cap2 + o] = d.vals[b * cap2 + o];
+      for (long o = t; o < n; o += NT) d.cand[b * cap2 + o] = d.vals[b * cap2 + o];
       if (t == 0) {
         d.cbox[b] = bx;
         d.htil[b] = d.hbar[b];
@@ -445,7 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
 
   // ---- Y box inputs: nu_{-J}, r, log nu, warm start -------------------------
   double acc0[3] = {mux, 0.0, 0.0};
-  for (int o = t; o < NY; o += kBlock) {
+  for (int o = t; o < NY; o += NT) {
     const int j1 = o / L2, j2 = o - j1 * L2;
     const int y1 = o1 + j1, y2 = o2 + j2;
     const long g = (long)y1 * P.n2 + y2;
@@ -477,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
       S.dl2[o] = R(d.ydel[2 * (P.grid_off + g) + 1]);
     }
   }
-  block_sum<3>(acc0, red);
+  block_sum<NT, 3>(acc0, red);
   const double muJ = acc0[0];
   const double Rmass = acc0[1];    // |nu_{-J}| on the box
   const double B0mass = acc0[2];   // sum of e^{-beta0/lam} nu on the box
@@ -491,14 +498,14 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
     if constexpr (kMoved) {
       // dense: tile point xi summed over the box by np threads, each over a
       // contiguous part of the box; partial sums, shifts and flags meet in mx
-      const int np = max(1, kBlock / lx);
+      const int np = max(1, NT / lx);
       const int xi = t % lx, part = t / lx;
       const bool act = part < np;
       const int ja = (int)((long)NY * part / np), jb = (int)((long)NY * (part + 1) / np);
       const double c1 = D1 + xi / lx2, c2 = D2 + xi % lx2;
       double* pt = S.mx;                  // [np * lx] partial sums / maxima
-      double* sh = S.mx + kBlock;         // [lx] shift, then result
-      double* need = S.mx + 2 * kBlock;   // [lx] exact recomputation flag
+      double* sh = S.mx + kMaxTile * kMaxTile;        // [lx] shift, then result
+      double* need = S.mx + 2 * kMaxTile * kMaxTile;  // [lx] exact recomputation flag
       if (t < lx) sh[t] = sprev;
       __syncthreads();
       if (have_x) {
@@ -547,15 +554,15 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
       __syncthreads();
       return sv;
     } else {
-      seg_max<8>(S.bd, L1, L2, L2, 1, S.Mr);
+      seg_max<NT, 8>(S.bd, L1, L2, L2, 1, S.Mr);
       __syncthreads();
-      for (int o = t; o < L1 * lx2; o += kBlock) {
+      for (int o = t; o < L1 * lx2; o += NT) {
         const int j1 = o / lx2, i2 = o - j1 * lx2;
         S.Tt[o] = lse_pass<R>(S.bd + j1 * L2, 1, 0, L2, (double)(D2 + i2), ch, have_x, S.Tt[o],
                               S.Mr[j1], nfall);
       }
       __syncthreads();
-      seg_max<16>(S.Tt, lx2, L1, 1, lx2, S.Mc);
+      seg_max<NT, 16>(S.Tt, lx2, L1, 1, lx2, S.Mc);
       __syncthreads();
       double sv = 0.0;
       if (t < lx)
@@ -583,18 +590,18 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
   auto y_prepare = [&]() {
     if (t < lx) S.adr[t] = aeps + lmux;
     __syncthreads();
-    seg_max<16>(S.adr, lx1, lx2, lx2, 1, S.Ma);
+    seg_max<NT, 16>(S.adr, lx1, lx2, lx2, 1, S.Ma);
     __syncthreads();
   };
   // Y pass 1 over tile columns [ib, ie): Uo(i1, j2) = LSE_i2 [a - ch (i2 - (j2 - D2))^2]
   auto y_pass1 = [&](double* Uo, int ib, int ie, bool have, double extra) {
-    for (int o = t; o < lx1 * L2; o += kBlock) {
+    for (int o = t; o < lx1 * L2; o += NT) {
       const int i1 = o / L2, j2 = o - i1 * L2;
       Uo[o] = lse_pass<R>(S.adr + i1 * lx2, 1, ib, ie, (double)(j2 - D2), ch, have, Uo[o] + extra,
                           S.Ma[i1], nfall);
     }
     __syncthreads();
-    seg_max<8>(Uo, L2, lx1, 1, L2, S.MU);
+    seg_max<NT, 8>(Uo, L2, lx1, 1, L2, S.MU);
     __syncthreads();
   };
 
@@ -610,19 +617,19 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
       // direction, so R-level relative accuracy of w suffices.
       double ab[1] = {0.0};
       if (t < lx) ab[0] = mux * exp(-aeps / K);
-      block_sum<1>(ab, red);
+      block_sum<NT, 1>(ab, red);
       const double Bsum = it == 1 ? B0mass : pxsum + Rmass;
       const double w = (Rmass + sqrt(Rmass * Rmass + 4.0 * ab[0] * Bsum)) / (2.0 * Bsum);
       const double sh = K * log(w);   // s/eps
       aeps += sh;
       ushift += sh;
-      for (int o = t; o < NY; o += kBlock) S.bd[o] -= sh;
+      for (int o = t; o < NY; o += NT) S.bd[o] -= sh;
       __syncthreads();
     }
     // ---- Y-half: z by two passes, Newton per point --------------------------
     y_prepare();
     if constexpr (!kMoved) y_pass1(S.Ud, 0, lx2, have_y, ushift);
-    for (int o = t; o < NY; o += kBlock) {
+    for (int o = t; o < NY; o += NT) {
       const int j1 = o / L2, j2 = o - j1 * L2;
       double z;
       if constexpr (kMoved)
@@ -660,7 +667,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
       term = pxv * (lpv + aol) - pxv + mux * exp(-aol);
     }
     double pdv[2] = {term, pxv};
-    block_sum<2>(pdv, red);
+    block_sum<NT, 2>(pdv, red);
     conv = pdv[0] <= tol;
     pxsum = pdv[1];
     const bool done = P.fixed_iters > 0 ? (it >= P.fixed_iters) : (conv || it >= P.max_iter);
@@ -686,7 +693,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
   for (int c = 0; c < nc; ++c) {
     double* Uo = c == 0 ? S.Ud : S.Tt;
     if constexpr (!kMoved) y_pass1(Uo, c * s, (c + 1) * s, false, 0.0);
-    for (int o = t; o < NY; o += kBlock) {
+    for (int o = t; o < NY; o += NT) {
       const int j1 = o / L2, j2 = o - j1 * L2;
       const double beta =
           eps * (S.bd[o] - (sizeof(R) == 4 ? (double)S.lnvf[o] : wlnv[o]));
@@ -712,7 +719,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
     }
     __syncthreads();
   }
-  block_sum<8>(accy, red);
+  block_sum<NT, 8>(accy, red);
   // X sums per basic cell k: <alpha, px>, KL terms, |mu_k|; then the count of
   // exact recomputations
   double accx[13];
@@ -733,7 +740,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_solve(Dev d, int cell_base) {
     d.abar[P.grid_off + gx] = alpha;
   }
   accx[12] = nfall;
-  block_sum<13>(accx, red);
+  block_sum<NT, 13>(accx, red);
   if (t == 0) {
     double bytes = 8.0 * (2.0 * NY + 3.0 * lx + (double)C.nb * NY);
     for (int k = 0; k < C.nb; ++k) {
@@ -764,32 +771,47 @@ size_t cell_lds_bytes(int cap, int precision, bool moved) {
   return cell_lds_layout<float>(cap, moved, nullptr, nullptr);
 }
 
+template <typename R, bool kMoved>
+static void launch_nt(const Dev& d, int cell_base, int ncells, size_t lds, int nt, hipStream_t st) {
+  if (nt == 64)
+    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 64>), dim3(ncells), dim3(64), lds, st, d, cell_base);
+  else if (nt == 128)
+    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 128>), dim3(ncells), dim3(128), lds, st, d, cell_base);
+  else
+    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 256>), dim3(ncells), dim3(256), lds, st, d, cell_base);
+}
+
 hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int precision,
-                             bool moved, hipStream_t st) {
+                             bool moved, int nt, hipStream_t st) {
   if (ncells <= 0) return hipSuccess;
   const size_t lds = cell_lds_bytes(cap, precision, moved);
   if (precision == 64) {
-    if (moved)
-      hipLaunchKernelGGL((k_cell_solve<double, true>), dim3(ncells), dim3(kBlock), lds, st, d, cell_base);
-    else
-      hipLaunchKernelGGL((k_cell_solve<double, false>), dim3(ncells), dim3(kBlock), lds, st, d, cell_base);
+    if (moved) launch_nt<double, true>(d, cell_base, ncells, lds, nt, st);
+    else launch_nt<double, false>(d, cell_base, ncells, lds, nt, st);
   } else {
-    if (moved)
-      hipLaunchKernelGGL((k_cell_solve<float, true>), dim3(ncells), dim3(kBlock), lds, st, d, cell_base);
-    else
-      hipLaunchKernelGGL((k_cell_solve<float, false>), dim3(ncells), dim3(kBlock), lds, st, d, cell_base);
+    if (moved) launch_nt<float, true>(d, cell_base, ncells, lds, nt, st);
+    else launch_nt<float, false>(d, cell_base, ncells, lds, nt, st);
   }
   return hipGetLastError();
 }
 
-hipError_t set_cell_lds_limit(size_t bytes) {
-  const void* fns[4] = {(const void*)k_cell_solve<double, false>, (const void*)k_cell_solve<double, true>,
-                        (const void*)k_cell_solve<float, false>, (const void*)k_cell_solve<float, true>};
+template <typename R, bool kMoved>
+static hipError_t set_lds_nt(size_t bytes) {
+  const void* fns[3] = {(const void*)k_cell_solve<R, kMoved, 64>, (const void*)k_cell_solve<R, kMoved, 128>,
+                        (const void*)k_cell_solve<R, kMoved, 256>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t set_cell_lds_limit(size_t bytes) {
+  hipError_t e = set_lds_nt<double, false>(bytes);
+  if (e == hipSuccess) e = set_lds_nt<double, true>(bytes);
+  if (e == hipSuccess) e = set_lds_nt<float, false>(bytes);
+  if (e == hipSuccess) e = set_lds_nt<float, true>(bytes);
+  return e;
 }
 
 }  // namespace dduot

@@ -24,7 +24,8 @@ struct Prob {
   int moved;           // 1: Y points displaced (dense, non-separable cost)
   int grid_off;     // offset of this problem's grid arrays
   int basic_off, nbasic;
-  int cell_off[2], ncell[2];   // composite cells of partitions A (0) and B (1)
+  int cell_off[2][4], ncell[2][4];   // composite cells of partition A (0) / B (1)
+                                     // in its four staggered batches
   int chunk_off, nchunk;       // reduction chunks over the grid
   double mass_mu, mass_nu;
 };
@@ -67,6 +68,7 @@ struct Dev {
   double* ws_lnv;             // per cell: log nu on the Y-box (cap2 entries)
   double* ws_lrr;             // per cell: log(nu_{-J}/nu) on the Y-box (cap2 entries)
   const double* ydel;         // moved Y: (y'/h - j) per grid point, 2 doubles each
+  long long* kstep;           // half-iterations done (history record index)
   double* chunk_part;         // 2 doubles per reduction chunk
   double* theta;              // per problem
   double* hist;               // per problem ring of records

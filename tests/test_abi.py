@@ -29,16 +29,20 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_the_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dd_uot.h"\n'
-                   'int main(){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dduot_config),'
+                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dduot_config),'
                    'sizeof(dduot_iter_stats), sizeof(dduot_score), offsetof(dduot_config, box_cap),'
-                   'offsetof(dduot_score, overflow), offsetof(dduot_iter_stats, n_cells));return 0;}\n')
+                   'offsetof(dduot_score, overflow), offsetof(dduot_iter_stats, n_cells),'
+                   'sizeof(dduot_multiscale), offsetof(dduot_multiscale, stage_gap),'
+                   'offsetof(dduot_multiscale, target_rel_gap));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     got = [int(v) for v in out]
     want = [ctypes.sizeof(binding.dduot_config), ctypes.sizeof(binding.dduot_iter_stats),
             ctypes.sizeof(binding.dduot_score), binding.dduot_config.box_cap.offset,
-            binding.dduot_score.overflow.offset, binding.dduot_iter_stats.n_cells.offset]
+            binding.dduot_score.overflow.offset, binding.dduot_iter_stats.n_cells.offset,
+            ctypes.sizeof(binding.dduot_multiscale), binding.dduot_multiscale.stage_gap.offset,
+            binding.dduot_multiscale.target_rel_gap.offset]
     assert got == want
 
 

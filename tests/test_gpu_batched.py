@@ -103,3 +103,60 @@ def test_batched_workload_64_problems_runs():
             assert abs(s["mass_x"] - s["mass_y"]) <= 1e-5 * s["mass_x"]
     finally:
         B.dd_uot_destroy(h)
+
+
+def test_graph_replays_match_eager_steps():
+    # hipGraph of an A+B pair replayed between eager work (scores, odd
+    # counts, an eps change); every replay must match the eager handle
+    cfgs = make_cfgs(64)
+    data = [problem_data(k, c.n1) for k, c in enumerate(cfgs)]
+    he = B.dd_uot_init_batch(cfgs, [d[0] for d in data], [d[1] for d in data])
+    hg = B.dd_uot_init_batch(cfgs, [d[0] for d in data], [d[1] for d in data])
+    B.dd_uot_set_graph(hg, True)
+    try:
+        for chunk in (2, 3, 4, 1, 2):
+            print(f"[graph] chunk {chunk}", flush=True)
+            B.dd_uot_iterate(he, chunk)
+            B.dd_uot_iterate(hg, chunk)
+            if chunk == 4:
+                for h in (he, hg):
+                    B.dd_uot_set_eps(h, 1, 0.8 * cfgs[1].eps)
+            for k, c in enumerate(cfgs):
+                n = c.n1
+                se, sg = B.dd_uot_score(he, k), B.dd_uot_score(hg, k)
+                assert sg["half_iters"] == se["half_iters"]
+                assert sg["tracked"] == pytest.approx(se["tracked"], rel=1e-12)
+                for a, b in zip(B.dd_uot_marginals(hg, k, n, n), B.dd_uot_marginals(he, k, n, n)):
+                    np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * b.max())
+                np.testing.assert_allclose(B.dd_uot_history(hg, k), B.dd_uot_history(he, k),
+                                           rtol=1e-12, atol=0)
+    finally:
+        B.dd_uot_destroy(he)
+        B.dd_uot_destroy(hg)
+
+
+def test_autotuned_threads_per_cell_keep_the_trajectory():
+    # the autotuner picks 64, 128 or 256 threads per cell for tiles of at
+    # most 64 points; any choice must follow the same trajectory
+    cfgs = make_cfgs(64)
+    data = [problem_data(k, c.n1) for k, c in enumerate(cfgs)]
+    ha = B.dd_uot_init_batch(cfgs, [d[0] for d in data], [d[1] for d in data])
+    hb = B.dd_uot_init_batch(cfgs, [d[0] for d in data], [d[1] for d in data])
+    try:
+        B.dd_uot_iterate(ha, 1)
+        B.dd_uot_iterate(hb, 1)
+        nt, ms = B.dd_uot_autotune(ha)
+        print(f"[autotune] chose {nt} threads, ms {ms}", flush=True)
+        assert nt in (64, 128, 256) and ms[[64, 128, 256].index(nt)] >= 0
+        assert np.all(ms >= 0)   # every size is admissible for tiles of <= 64 points
+        B.dd_uot_iterate(ha, 4)
+        B.dd_uot_iterate(hb, 4)
+        for k, c in enumerate(cfgs):
+            n = c.n1
+            for a, b in zip(B.dd_uot_marginals(ha, k, n, n), B.dd_uot_marginals(hb, k, n, n)):
+                np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * b.max())
+            np.testing.assert_allclose(B.dd_uot_history(ha, k)[:, :3], B.dd_uot_history(hb, k)[:, :3],
+                                       rtol=1e-12)
+    finally:
+        B.dd_uot_destroy(ha)
+        B.dd_uot_destroy(hb)

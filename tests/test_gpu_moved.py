@@ -136,3 +136,33 @@ def test_moved_fp32_sampled_cells_512():
             assert e < 1e-5
     finally:
         B.dd_uot_destroy(h)
+
+
+def test_autograd_wrapper_with_theta():
+    torch = pytest.importorskip("torch")
+    from paper_2410_08859_amd.autograd import uot_value
+    n = 16
+    mu, nu, _ = small(n, 921)
+    th = displacement_theta(53, 1.0 / n)
+    c = cfg(n, 2, sinkhorn_err=1e-15, sinkhorn_max_iter=20000, trunc=0.0)
+    tm = torch.tensor(mu, dtype=torch.float64, device="cuda", requires_grad=True)
+    tn = torch.tensor(nu, dtype=torch.float64, device="cuda", requires_grad=True)
+    tt = torch.tensor(th, dtype=torch.float64, device="cuda", requires_grad=True)
+    val = uot_value(tm, tn, c, 400, theta=tt)
+    val.backward()
+    y = displaced_points(n, n, 1.0 / n, th)
+    h = B.dd_uot_init_moved(c, mu, nu, y)
+    try:
+        B.dd_uot_iterate(h, 400)
+        s = B.dd_uot_score(h, 0)
+        dmu, dnu = B.dd_uot_backward(h, 0, n, n)
+        dy = B.dd_uot_backward_ypos(h, 0, n, n)
+    finally:
+        B.dd_uot_destroy(h)
+    # two separate solves (order-dependent FP64 atomics): agreement to 1e-6
+    assert val.item() == pytest.approx(s["dual"], rel=1e-10)
+    np.testing.assert_allclose(tm.grad.cpu().numpy(), dmu, rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(tn.grad.cpu().numpy(), dnu, rtol=1e-6, atol=1e-12)
+    Bm = displacement_basis(n, th.shape[1])
+    dth = np.stack([Bm.T @ dy[..., k] @ Bm for k in range(2)])
+    np.testing.assert_allclose(tt.grad.cpu().numpy(), dth, rtol=1e-6, atol=1e-12 * np.abs(dth).max())

@@ -60,23 +60,81 @@ def test_refine_matches_oracle(sc, sf):
         B.dd_uot_destroy(hf)
 
 
-def test_multiscale_driver_reduces_the_gap():
-    n = 128
+def oracle_multiscale(mu, nu, c, ms):
+    """The driver's schedule written out with the oracle's pieces (coarsen,
+    refine, DD half-iterations, eps stages, certificate-controlled stages)."""
+    L = ms.levels
+    mus, nus = [mu], [nu]
+    for _ in range(L - 1):
+        mus.insert(0, dd.coarsen(mus[0]))
+        nus.insert(0, dd.coarsen(nus[0]))
+    p = st = None
+    trace = []
+    halves = 0
+    for l in range(L):
+        n = mus[l].shape[0]
+        h = c.h * 2 ** (L - 1 - l)
+        fin = l == L - 1
+        s = c.cell if fin else (n // 2 if (l == 0 and n <= 16) else min(c.cell, ms.coarse_cell))
+        cap = c.box_cap if (fin or n > 64) else max(c.box_cap, n)
+        opt = dd.Options(err=c.sinkhorn_err, max_iter=c.sinkhorn_max_iter if fin else
+                         max(c.sinkhorn_max_iter, ms.coarse_max_iter), trunc=c.trunc,
+                         lenience=c.lenience, margin=c.box_margin, cap=cap,
+                         getweights="swift", translate=True)
+        pn = dd.make_problem(mus[l], nus[l], ms.eps_start_h2 * h * h, c.lambda_, h, s)
+        if l == 0:
+            st = dd.init_product(pn) if cap >= n else dd.init_block(pn)
+        else:
+            halves += st.k if hasattr(st, "k") else 0
+            st = dd.refine(p, st, pn, c.trunc, cap)
+        p = pn
+        e_end = c.eps if fin else ms.eps_end_h2 * h * h
+        e = p.eps
+        while True:
+            done = 0
+            while True:
+                dd.run(p, st, ms.halves_per_stage, opt)
+                done += ms.halves_per_stage
+                if done + ms.halves_per_stage > ms.stage_max_halves:
+                    break
+                if dd.certificate(p, st.abar)["rel"] <= ms.stage_gap:
+                    break
+            if e <= e_end * (1 + 1e-12):
+                break
+            e = max(e * 0.5, e_end)
+            dd.set_eps(p, st, e)
+        if fin:
+            trace.append(dd.certificate(p, st.abar)["rel"])
+            done = 0
+            while trace[-1] > ms.target_rel_gap and done < ms.final_max_halves:
+                k = min(ms.check_every, ms.final_max_halves - done)
+                dd.run(p, st, k, opt)
+                done += k
+                trace.append(dd.certificate(p, st.abar)["rel"])
+    return p, st, trace
+
+
+def test_multiscale_driver_follows_the_oracle():
+    n = 32
     mu = gaussian_mixture(n, n, 3, 1e-3, 1.0, 811)
     nu = gaussian_mixture(n, n, 3, 1e-3, 1.3, 812)
     c = B.dd_uot_default_config(n1=n, n2=n, h=1.0 / n, eps=1.0 / n ** 2, lam=1.0, cell=4,
-                                precision=64, box_cap=48, sinkhorn_max_iter=500)
-    ms = B.dd_uot_default_multiscale(levels=3, final_max_halves=24, check_every=4,
-                                     target_rel_gap=1e-9)
-    print("[multiscale] driver 32 -> 128", flush=True)
+                                precision=64, box_cap=32, sinkhorn_max_iter=200, lenience=0.0)
+    ms = B.dd_uot_default_multiscale(levels=2, final_max_halves=8, check_every=4,
+                                     target_rel_gap=1e-12, stage_max_halves=8, coarse_max_iter=400)
+    print("[multiscale] driver 16 -> 32 against the oracle", flush=True)
     h, tr = B.dd_uot_solve_multiscale(c, ms, mu, nu)
     try:
-        assert tr.shape[0] >= 2
-        print(tr, flush=True)
+        p, st, otr = oracle_multiscale(mu, nu, c, ms)
+        print(tr, otr, flush=True)
+        assert tr.shape[0] == len(otr)
         assert np.all(np.diff(tr[:, 1]) > 0)
-        assert tr[-1, 2] < tr[0, 2]
+        np.testing.assert_allclose(tr[:, 2], otr, rtol=1e-6)
+        px, py = B.dd_uot_marginals(h, 0, n, n)
+        np.testing.assert_allclose(px, st.px, rtol=0, atol=1e-9 * st.px.max())
+        P = dd.aggregate(p, st.boxes)
+        np.testing.assert_allclose(py, P, rtol=0, atol=1e-9 * P.max())
         s = B.dd_uot_score(h, 0)
         assert s["rel_pd_gap"] == pytest.approx(tr[-1, 2], rel=1e-12)
-        assert abs(s["mass_x"] - s["mass_y"]) <= 1e-9 * s["mass_x"]
     finally:
         B.dd_uot_destroy(h)

@@ -320,3 +320,35 @@ def test_refinement_keeps_mass_and_the_prolonged_y_marginal():
     np.testing.assert_allclose(dd.coarsen(Pf), Pc, rtol=1e-12)
     np.testing.assert_allclose(Pf, np.kron(Pc / pc.nu, np.ones((2, 2))) * pf.nu, rtol=1e-12)
     assert st.px.sum() == pytest.approx(stc.px.sum(), rel=1e-13)
+
+
+@pytest.mark.parametrize("part", ["A", "B"])
+def test_staggered_batches_partition_the_cells_without_neighbours(part):
+    p = small_problem(24, 2)   # 12 basic cells per axis: B has border singletons
+    batches = dd.staggered_batches(p, part)
+    cells = dd.composite_cells(p, part)
+    got = sorted(tuple(c["basic"]) for b in batches for c in b)
+    assert got == sorted(tuple(c["basic"]) for c in cells)
+    for b in batches:
+        for i, c in enumerate(b):
+            for d in b[i + 1:]:
+                (a1, a2, l1, l2), (b1, b2, m1, m2) = c["rect"], d["rect"]
+                # rectangles of one batch do not touch (not even at a corner)
+                assert a1 + l1 < b1 or b1 + m1 < a1 or a2 + l2 < b2 or b2 + m2 < a2
+
+
+def test_staggered_scores_decrease_and_reach_the_optimum():
+    p = small_problem(8, 2)
+    pi, sol, C = global_optimum(p)
+    st = dd.init_product(p, dense_plan=True)
+    opt = dd.Options(cap=8, trunc=0.0, getweights="staggered", err=1e-15, max_iter=20000,
+                     lenience=0.0)
+    prev = dd.tracked_score(p, st)
+    for _ in range(120):
+        out = dd.half_iteration(p, st, "A" if st.k % 2 == 0 else "B", opt)
+        assert len(out) == 4
+        cur = dd.tracked_score(p, st)
+        assert cur <= prev + 1e-12 * abs(prev)
+        prev = cur
+    np.testing.assert_allclose(st.plan, pi, rtol=5e-6, atol=1e-15)
+    assert dd.certificate(p, st.abar)["rel"] < 1e-12
