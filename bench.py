@@ -43,12 +43,12 @@ def multiscale_params(levels, final_max, target, check_every=4):
                                        check_every=check_every, target_rel_gap=target)
 
 
-def time_to_gap(name, precision, max_inner, cap, levels, final_max, targets, stream):
+def time_to_gap(name, precision, max_inner, cap, levels, final_max, targets, stream, err):
     """Wall time of the whole multiscale solve (host marginals in, certificate
     checks included) until each relative gap first reaches each target: the
     certificate's pd_gap/|dual| and the DD plan's (tracked - dual)/|dual|."""
     mu, nu = workload_marginals(name)
-    cfg = workload_config(name, precision, max_inner, cap)
+    cfg = workload_config(name, precision, max_inner, cap, err)
     ms = multiscale_params(levels, final_max, min(targets))
     h, tr = B.dd_uot_solve_multiscale(cfg, ms, mu, nu, stream=stream)
     B.dd_uot_destroy(h)
@@ -60,12 +60,13 @@ def time_to_gap(name, precision, max_inner, cap, levels, final_max, targets, str
             out[f"{t:g}"] = None if hit.size == 0 else {"ms": float(tr[hit[0], 1]),
                                                         "half_iters": int(tr[hit[0], 0])}
         return out
-    return {"precision": precision, "certificate_gap": reached(2), "dd_plan_gap": reached(3),
+    return {"precision": precision, "dd_plan_gap": reached(3), "certificate_gap": reached(2),
             "final": {"certificate_gap": float(tr[-1, 2]), "dd_plan_gap": float(tr[-1, 3]),
                       "ms": float(tr[-1, 1]), "half_iters": int(tr[-1, 0])},
             "schedule": f"{levels} layers, eps 2h^2 -> h^2/2 per layer (-> eps on the finest), "
                         f"4-16 half-iterations per stage (to rel. gap 1e-3), then at most "
-                        f"{final_max} with a certificate every 4"}
+                        f"{final_max} with a certificate every 4; staggered GetWeights, "
+                        f"cell Err {err:g}, at most {max_inner} inner iterations"}
 
 
 def timed_steps(h, steps, warmup):
@@ -88,13 +89,13 @@ def timed_steps(h, steps, warmup):
                 score=B.dd_uot_score(h, 0))
 
 
-def workload_config(name, precision, max_inner, cap):
+def workload_config(name, precision, max_inner, cap, err=2e-5):
     w = WORKLOADS[name]
     n = w["n"]
     return B.dd_uot_default_config(
         n1=n, n2=n, h=1.0 / n, eps=w["eps_h2"] / n ** 2, lam=w["lam"], cell=w["cell"],
         precision=precision, init=B.INIT_BLOCK, getweights=B.GW_STAGGERED,
-        sinkhorn_err=2e-5, sinkhorn_max_iter=max_inner, trunc=1e-15, lenience=0.005,
+        sinkhorn_err=err, sinkhorn_max_iter=max_inner, trunc=1e-15, lenience=0.005,
         box_margin=2, box_cap=cap)
 
 
@@ -199,7 +200,9 @@ def run(args):
     }
     if args.warm and args.start != "multiscale":
         # the same steps after the multiscale warm start (the paper's pipeline)
-        h, _ = B.dd_uot_solve_multiscale(cfg, multiscale_params(args.levels, 0, 0.0), mu, nu,
+        wcfg = workload_config(args.workload, args.precision, args.ms_max_inner, args.cap,
+                               args.ms_err)
+        h, _ = B.dd_uot_solve_multiscale(wcfg, multiscale_params(args.levels, 0, 0.0), mu, nu,
                                          stream=stream.cuda_stream)
         try:
             w = timed_steps(h, args.steps, args.warmup)
@@ -212,14 +215,15 @@ def run(args):
             "overflow_cells": float(wh[:, 7].sum()), "unconverged_cells": float(wh[:, 6].sum()),
             "certificate_gap": w["score"]["rel_pd_gap"],
             "dd_plan_gap": (w["score"]["tracked"] - w["score"]["dual"]) / abs(w["score"]["dual"]),
-            "start": f"multiscale, {args.levels} layers"}
+            "start": f"multiscale, {args.levels} layers", "cell_err": args.ms_err,
+            "max_inner": args.ms_max_inner}
     if args.ttg:
         targets = (1e-2, 1e-3, 1e-4, 1e-5, 1e-6)
         out["time_to_gap"] = [
-            time_to_gap(args.workload, 32, args.max_inner, args.cap, args.levels, args.ttg_max32,
-                        targets, stream.cuda_stream),
-            time_to_gap(args.workload, 64, args.max_inner, args.cap, args.levels, args.ttg_max64,
-                        targets, stream.cuda_stream),
+            time_to_gap(args.workload, 32, args.ms_max_inner, args.cap, args.levels,
+                        args.ttg_max32, targets, stream.cuda_stream, args.ms_err),
+            time_to_gap(args.workload, 64, args.ms_max_inner, args.cap, args.levels,
+                        args.ttg_max64, targets, stream.cuda_stream, args.ms_err),
         ]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.max_inner, args.cap, args.cpu_budget)
@@ -242,6 +246,9 @@ def main():
                     help="1: also time the steps after the multiscale warm start")
     ap.add_argument("--levels", type=int, default=7)
     ap.add_argument("--ttg", type=int, default=1, help="1: also measure time to gap (FP32, FP64)")
+    ap.add_argument("--ms-err", type=float, default=2e-6,
+                    help="cell tolerance Err of the multiscale runs")
+    ap.add_argument("--ms-max-inner", type=int, default=1000)
     ap.add_argument("--ttg-max32", type=int, default=64)
     ap.add_argument("--ttg-max64", type=int, default=16)
     ap.add_argument("--copy-probe", type=int, default=0,

@@ -457,9 +457,11 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_terms, h->cells.size()));
   CHK(dalloc(h, &h->d_fall, h->cells.size()));
   // per-cell FP64 workspace of log nu and log r (FP32 kernels keep them in LDS)
-  const size_t ws = h->precision == 64 ? h->cells.size() * (size_t)h->cap2 : 1;
-  CHK(dalloc(h, &h->d_ws_lnv, ws));
-  CHK(dalloc(h, &h->d_ws_lrr, ws));
+  // per-cell workspace: FP64 kernels keep log nu and log r there (FP64);
+  // FP32 kernels keep log r there (FP32, cap2 floats per cell)
+  const size_t ncap = h->cells.size() * (size_t)h->cap2;
+  CHK(dalloc(h, &h->d_ws_lnv, h->precision == 64 ? ncap : 1));
+  CHK(dalloc(h, &h->d_ws_lrr, h->precision == 64 ? ncap : (ncap + 1) / 2));
   CHK(dalloc(h, &h->d_chunk_prob, h->nchunk));
   CHK(dalloc(h, &h->d_chunk_start, h->nchunk));
   CHK(dalloc(h, &h->d_chunk_len, h->nchunk));

@@ -30,9 +30,10 @@
 // when it is not representable (first iteration, very large change) the
 // output is recomputed exactly by a max pass and a sum pass.
 // The Newton solve works in R on the log cell share relative to the FP64
-// reference z/(1+K) (the root when nu_{-J} = 0).  In FP32 kernels log nu and
-// log r live in LDS as FP32 (a relative perturbation of nu below 1e-6); FP64
-// kernels read them from a per-cell FP64 workspace.
+// reference z/(1+K) (the root when nu_{-J} = 0).  FP32 kernels keep log nu in
+// LDS as FP32 (a relative perturbation of nu below 1e-6) and log r in a
+// per-cell FP32 workspace in global memory; FP64 kernels keep both in a
+// per-cell FP64 workspace.
 #include "dd_types.h"
 
 #include <float.h>
@@ -49,7 +50,13 @@ struct M<float> {
   static __device__ __forceinline__ float ex2s(float x) { return __builtin_amdgcn_exp2f(x); }
   static __device__ __forceinline__ float ex(float x) { return __expf(x); }
   static __device__ __forceinline__ float lg(float x) { return __logf(x); }
-  static __device__ __forceinline__ float lg1p(float x) { return log1pf(x); }
+  // log(1 + x) for x in [0, 1]: the series below 1e-4 (error < x^3/3), the
+  // hardware logarithm above (absolute error ~1e-7, the level of the FP32
+  // rounding of the Newton variables anyway)
+  static __device__ __forceinline__ float lg1p(float x) {
+    return x < 1e-4f ? x * (1.0f - 0.5f * x) : __logf(1.0f + x);
+  }
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 };
 template <>
 struct M<double> {
@@ -58,6 +65,7 @@ struct M<double> {
   static __device__ __forceinline__ double ex(double x) { return exp(x); }
   static __device__ __forceinline__ double lg(double x) { return log(x); }
   static __device__ __forceinline__ double lg1p(double x) { return log1p(x); }
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 };
 
 // Sum N doubles over the workgroup in a fixed order (deterministic).
@@ -124,11 +132,11 @@ __device__ __forceinline__ double newton_v(double a, double v0, double K, R tol,
     if (v >= aR) {
       const R e = M<R>::ex(aR - v);
       la = v + M<R>::lg1p(e);
-      sig = R(1) / (R(1) + e);
+      sig = M<R>::rcp(R(1) + e);
     } else {
       const R e = M<R>::ex(v - aR);
       la = aR + M<R>::lg1p(e);
-      sig = e / (R(1) + e);
+      sig = e * M<R>::rcp(R(1) + e);
     }
     const R g = v + KR * la;
     // Right of the root (G > 0) the Newton iterates of a convex increasing G
@@ -139,7 +147,7 @@ __device__ __forceinline__ double newton_v(double a, double v0, double K, R tol,
       if (!(g < gprev)) break;
       gprev = g;
     }
-    const R dv = g / (R(1) + KR * sig);
+    const R dv = g * M<R>::rcp(R(1) + KR * sig);
     v -= dv;
     if (!(fabs(dv) > tol * (R(1) + fabs(v)))) break;
   }
@@ -152,7 +160,8 @@ __device__ __forceinline__ double newton_v(double a, double v0, double K, R tol,
 // in nfall.
 template <typename R>
 __device__ __forceinline__ double lse_pass(const double* base, int stride, int k0, int k1, double c,
-                                           double ch, bool have_shift, double shift, double bmax,
+                                           double ch, float ichf, const R* qc, int qlim,
+                                           bool have_shift, double shift, double bmax,
                                            double& nfall) {
   // Terms more than W below the shift are skipped; an output is accepted when
   // its shifted sum stays above e^-22, so every skipped term is below e^-(W-22)
@@ -163,33 +172,43 @@ __device__ __forceinline__ double lse_pass(const double* base, int stride, int k
   for (int attempt = 0; have_shift && attempt < 2; ++attempt) {
     int a = k0, b = k1;
     if (ch > 0.0) {
-      const double r2 = (bmax - shift + W) / ch;
-      if (r2 < 0.0) {
+      // window in FP32 (1/ch precomputed), widened by 1e-3 of a point
+      const float r2 = (float)(bmax - shift + W) * ichf;
+      if (r2 < 0.0f) {
         a = b = k0;   // every term is below e^-W of the shift: recompute
       } else {
-        const double rr = sqrt(r2);
-        a = max(k0, (int)ceil(c - rr));
-        b = min(k1, (int)floor(c + rr) + 1);
+        const float rr = fminf(__fsqrt_rn(r2), 1e6f) + 1e-3f, cf = (float)c;
+        a = max(k0, (int)ceilf(cf - rr));
+        b = min(k1, (int)floorf(cf + rr) + 1);
       }
     }
     // Terms are evaluated as 2^(sc (base_k - shift) - sc ch d^2) in FP32 (sc =
-    // log2 e, one v_exp_f32 each) and as exp() in FP64; four terms per trip
-    // with their LDS reads issued together.
+    // log2 e, one v_exp_f32 each) and as exp() in FP64, the cost read from
+    // the table qc[d] = -sc ch d^2 (d = k - c is an integer); four terms per
+    // trip with their LDS reads issued together.
     const R sc = M<R>::kScale;
-    const R chs = R(ch) * sc;
     R acc0 = R(0), acc1 = R(0);
-    R dk = R(a) - R(c);   // integer-valued: exact
-    const double* p = base + (long)a * stride;
-    int k = a;
-    for (; k + 4 <= b; k += 4, p += 4 * stride, dk += R(4)) {
-      const double v0 = p[0], v1 = p[stride], v2 = p[2 * stride], v3 = p[3 * stride];
-      const R d1 = dk + R(1), d2 = dk + R(2), d3 = dk + R(3);
-      acc0 += M<R>::ex2s(R(v0 - shift) * sc - chs * dk * dk);
-      acc1 += M<R>::ex2s(R(v1 - shift) * sc - chs * d1 * d1);
-      acc0 += M<R>::ex2s(R(v2 - shift) * sc - chs * d2 * d2);
-      acc1 += M<R>::ex2s(R(v3 - shift) * sc - chs * d3 * d3);
+    const int ci = (int)c;
+    if (a - ci >= -qlim && b - 1 - ci <= qlim) {
+      const R* q = qc + (a - ci);
+      const double* p = base + (long)a * stride;
+      int k = a;
+      for (; k + 4 <= b; k += 4, p += 4 * stride, q += 4) {
+        const double v0 = p[0], v1 = p[stride], v2 = p[2 * stride], v3 = p[3 * stride];
+        acc0 += M<R>::ex2s(R(v0 - shift) * sc + q[0]);
+        acc1 += M<R>::ex2s(R(v1 - shift) * sc + q[1]);
+        acc0 += M<R>::ex2s(R(v2 - shift) * sc + q[2]);
+        acc1 += M<R>::ex2s(R(v3 - shift) * sc + q[3]);
+      }
+      for (; k < b; ++k, p += stride, ++q) acc0 += M<R>::ex2s(R(p[0] - shift) * sc + q[0]);
+    } else {
+      // offsets beyond the table (a Y-box far from its tile): costs computed
+      const R chs = R(ch) * sc;
+      R dk = R(a - ci);
+      const double* p = base + (long)a * stride;
+      for (int k = a; k < b; ++k, p += stride, dk += R(1))
+        acc0 += M<R>::ex2s(R(p[0] - shift) * sc - chs * dk * dk);
     }
-    for (; k < b; ++k, p += stride, dk += R(1)) acc0 += M<R>::ex2s(R(p[0] - shift) * sc - chs * dk * dk);
     const R acc = acc0 + acc1;
     if (acc > R(2.8e-10) && acc < R(1.1e26)) return shift + (double)M<R>::lg(acc);   // e^-22 .. e^60
     if (!(acc > R(0)) || !(acc < R(INFINITY))) break;
@@ -206,9 +225,9 @@ __device__ __forceinline__ double lse_pass(const double* base, int stride, int k
   if (!(m > -INFINITY)) return m;
   int a = k0, b = k1;
   if (ch > 0.0) {
-    const double rr = sqrt((bmax - m + W) / ch);
-    a = max(k0, (int)ceil(c - rr));
-    b = min(k1, (int)floor(c + rr) + 1);
+    const float rr = fminf(__fsqrt_rn((float)(bmax - m + W) * ichf), 1e6f) + 1e-3f, cf = (float)c;
+    a = max(k0, (int)ceilf(cf - rr));
+    b = min(k1, (int)floorf(cf + rr) + 1);
   }
   R acc = R(0);
   for (int k = a; k < b; ++k) {
@@ -218,10 +237,63 @@ __device__ __forceinline__ double lse_pass(const double* base, int stride, int k
   return m + (double)M<R>::lg(acc);
 }
 
+// One pass output over a short range (the tile's extent, at most 16 terms):
+// every term is summed, so no window is needed, and a shifted sum anywhere in
+// [e^-80, e^80] (FP32; e^-700 .. e^700 in FP64) is accurate to R rounding.
+// Otherwise one retry with the corrected shift, then the exact two passes.
+template <typename R>
+__device__ __forceinline__ double lse_full(const double* base, int stride, int k0, int k1, double c,
+                                           double ch, const R* qc, int qlim, bool have_shift,
+                                           double shift, double& nfall) {
+  constexpr R lo = sizeof(R) == 8 ? R(1e-304) : R(1.8e-35);
+  constexpr R hi = sizeof(R) == 8 ? R(1e304) : R(5.5e34);
+  const R sc = M<R>::kScale;
+  const int ci = (int)c;
+  const bool tab = k0 - ci >= -qlim && k1 - 1 - ci <= qlim;
+  for (int attempt = 0; have_shift && attempt < 2; ++attempt) {
+    R acc0 = R(0), acc1 = R(0);
+    const double* p = base + (long)k0 * stride;
+    int k = k0;
+    if (tab) {
+      const R* q = qc + (k0 - ci);
+      for (; k + 4 <= k1; k += 4, p += 4 * stride, q += 4) {
+        const double v0 = p[0], v1 = p[stride], v2 = p[2 * stride], v3 = p[3 * stride];
+        acc0 += M<R>::ex2s(R(v0 - shift) * sc + q[0]);
+        acc1 += M<R>::ex2s(R(v1 - shift) * sc + q[1]);
+        acc0 += M<R>::ex2s(R(v2 - shift) * sc + q[2]);
+        acc1 += M<R>::ex2s(R(v3 - shift) * sc + q[3]);
+      }
+      for (; k < k1; ++k, p += stride, ++q) acc0 += M<R>::ex2s(R(p[0] - shift) * sc + q[0]);
+    } else {
+      const R chs = R(ch) * sc;
+      R dk = R(k0 - ci);
+      for (; k < k1; ++k, p += stride, dk += R(1))
+        acc0 += M<R>::ex2s(R(p[0] - shift) * sc - chs * dk * dk);
+    }
+    const R acc = acc0 + acc1;
+    if (acc > lo && acc < hi) return shift + (double)M<R>::lg(acc);
+    if (!(acc > R(0)) || !(acc < R(INFINITY))) break;
+    shift += (double)M<R>::lg(acc);
+  }
+  nfall += 1.0;
+  double m = -INFINITY;
+  for (int k = k0; k < k1; ++k) {
+    const double d = k - c;
+    m = fmax(m, base[k * stride] - ch * d * d);
+  }
+  if (!(m > -INFINITY)) return m;
+  R acc = R(0);
+  for (int k = k0; k < k1; ++k) {
+    const double d = k - c;
+    acc += M<R>::ex(R(base[k * stride] - ch * d * d - m));
+  }
+  return m + (double)M<R>::lg(acc);
+}
+
 template <typename R>
 struct CellLds {
   double* bd;    // b(y) = beta/eps + log nu                      [cmax^2]
-  double* zp;    // z(y) of the last Y-half                       [cmax^2]
+  R* zp;         // z(y) of the last Y-half (a shift estimate)    [cmax^2]
   double* Tt;    // X pass 1 output / re-split half 1             [16*cmax]
   double* Ud;    // Y pass 1 output                               [16*cmax]
   double* Mr;    // row maxima of b                               [cmax]
@@ -231,10 +303,11 @@ struct CellLds {
   double* Ma;    // row maxima of adr                             [16]
   double* red;   // reductions                                    [4*16]
   float* lnvf;   // FP32 kernels: log nu on the box                [cmax^2]
-  float* lrf;    // FP32 kernels: log r on the box                 [cmax^2]
+
   R* dl1;        // moved Y: displacement (pixels) on the box      [cmax^2]
   R* dl2;
   double* mx;    // moved Y: partial sums, shifts, flags           [3*256]
+  R* qtab;       // -sc ch d^2 for d = -cmax .. cmax (pass costs) [2*cmax+1]
 };
 
 template <typename R>
@@ -247,17 +320,18 @@ __host__ __device__ inline size_t cell_lds_layout(int cmax, bool moved, CellLds<
     return o;
   };
   const size_t n2 = (size_t)cmax * cmax, nt = (size_t)cmax * kMaxTile;
-  size_t o_bd = take(8 * n2), o_zp = take(8 * n2), o_Tt = take(8 * nt), o_Ud = take(8 * nt);
+  size_t o_bd = take(8 * n2), o_zp = take(sizeof(R) * n2), o_Tt = take(8 * nt), o_Ud = take(8 * nt);
   size_t o_Mr = take(8 * cmax), o_MU = take(8 * cmax), o_Mc = take(8 * kMaxTile);
   size_t o_adr = take(8 * kMaxTile * kMaxTile), o_Ma = take(8 * kMaxTile), o_red = take(8 * 4 * 16);
   // FP32 kernels keep log nu and log r in LDS (FP64 kernels use the global
   // per-cell workspace, whose full precision the FP64 parity needs)
-  const size_t o_lnv = sizeof(R) == 4 ? take(4 * n2) : 0, o_lr = sizeof(R) == 4 ? take(4 * n2) : 0;
+  const size_t o_lnv = sizeof(R) == 4 ? take(4 * n2) : 0;
   const size_t o_d1 = moved ? take(sizeof(R) * n2) : 0, o_d2 = moved ? take(sizeof(R) * n2) : 0;
   const size_t o_mx = moved ? take(8 * 3 * kMaxTile * kMaxTile) : 0;
+  const size_t o_q = take(sizeof(R) * (2 * (size_t)cmax + 1));
   if (L) {
     L->bd = (double*)(base + o_bd);
-    L->zp = (double*)(base + o_zp);
+    L->zp = (R*)(base + o_zp);
     L->Tt = (double*)(base + o_Tt);
     L->Ud = (double*)(base + o_Ud);
     L->Mr = (double*)(base + o_Mr);
@@ -267,10 +341,10 @@ __host__ __device__ inline size_t cell_lds_layout(int cmax, bool moved, CellLds<
     L->Ma = (double*)(base + o_Ma);
     L->red = (double*)(base + o_red);
     L->lnvf = sizeof(R) == 4 ? (float*)(base + o_lnv) : nullptr;
-    L->lrf = sizeof(R) == 4 ? (float*)(base + o_lr) : nullptr;
     L->dl1 = moved ? (R*)(base + o_d1) : nullptr;
     L->dl2 = moved ? (R*)(base + o_d2) : nullptr;
     L->mx = moved ? (double*)(base + o_mx) : nullptr;
+    L->qtab = (R*)(base + o_q);
   }
   return off;
 }
@@ -434,12 +508,20 @@ __global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
   double* red = S.red;
 
   const double eps = P.eps, lam = P.lam, kap = P.kappa, K = P.K, ch = P.ch;
+  const float ichf = ch > 0.0 ? (float)(1.0 / ch) : 0.0f;   // window: 1/ch (unused for ch = 0)
+  // cost table of the separable passes, centred: qc[d] = -sc ch d^2, |d| <= cap
+  const R* qc = S.qtab + cap;
+  for (int i = t; i <= 2 * cap; i += NT) {
+    const double dd = (double)(i - cap);
+    S.qtab[i] = R(-(double)M<R>::kScale * ch * dd * dd);
+  }
   const int D1 = C.x1 - o1, D2 = C.x2 - o2;      // tile origin in box coordinates
   const double* nu = d.nu + P.grid_off;
   const double* mu = d.mu + P.grid_off;
   const double* Pst = d.P + P.grid_off;
   double* wlnv = d.ws_lnv + (long)ci * cap2;
   double* wlrr = d.ws_lrr + (long)ci * cap2;
+  float* wlrf = reinterpret_cast<float*>(d.ws_lrr) + (long)ci * cap2;   // FP32 kernels
 
   // ---- X tile inputs (thread t owns tile point t) --------------------------
   const int ti1 = t < lx ? t / lx2 : 0, ti2 = t < lx ? t - ti1 * lx2 : 0;
@@ -471,7 +553,7 @@ __global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
     const double lr = r > 0.0 ? log(r) : -INFINITY;
     if constexpr (sizeof(R) == 4) {
       S.lnvf[o] = (float)lnv;
-      S.lrf[o] = (float)lr;
+      wlrf[o] = (float)lr;
       lnv = (double)(float)lnv;   // b carries the same rounded log nu
     } else {
       wlrr[o] = lr;
@@ -494,6 +576,7 @@ __global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
   // ---- X-half: S(i) = LSE_j [b(j) - ch |j - (D + i)|^2], in place over Tt ----
   // Returns S for the thread's point; sprev is that point's previous S.
   bool have_x = false;
+  double xext = 0.0;   // expected move of the X-half outputs since the last X-half
   auto x_half = [&](double sprev) -> double {
     if constexpr (kMoved) {
       // dense: tile point xi summed over the box by np threads, each over a
@@ -506,7 +589,8 @@ __global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
       double* pt = S.mx;                  // [np * lx] partial sums / maxima
       double* sh = S.mx + kMaxTile * kMaxTile;        // [lx] shift, then result
       double* need = S.mx + 2 * kMaxTile * kMaxTile;  // [lx] exact recomputation flag
-      if (t < lx) sh[t] = sprev;
+      const double sprev_x = sprev + xext;
+      if (t < lx) sh[t] = sprev_x;
       __syncthreads();
       if (have_x) {
         if (act)
@@ -518,7 +602,7 @@ __global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
           for (int q = 0; q < np; ++q) a += pt[q * lx + t];
           const bool ok = a > 2.8e-10 && a < 1.1e26;
           need[t] = ok ? 0.0 : 1.0;
-          if (ok) sh[t] = sprev + log(a);
+          if (ok) sh[t] = sprev_x + log(a);
         }
       } else if (t < lx) {
         need[t] = 1.0;
@@ -551,6 +635,7 @@ __global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
       __syncthreads();
       const double sv = t < lx ? sh[t] : 0.0;
       have_x = true;
+      xext = 0.0;
       __syncthreads();
       return sv;
     } else {
@@ -558,7 +643,8 @@ __global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
       __syncthreads();
       for (int o = t; o < L1 * lx2; o += NT) {
         const int j1 = o / lx2, i2 = o - j1 * lx2;
-        S.Tt[o] = lse_pass<R>(S.bd + j1 * L2, 1, 0, L2, (double)(D2 + i2), ch, have_x, S.Tt[o],
+        S.Tt[o] = lse_pass<R>(S.bd + j1 * L2, 1, 0, L2, (double)(D2 + i2), ch, ichf, qc, cap, have_x,
+                              S.Tt[o] + xext,
                               S.Mr[j1], nfall);
       }
       __syncthreads();
@@ -566,9 +652,11 @@ __global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
       __syncthreads();
       double sv = 0.0;
       if (t < lx)
-        sv = lse_pass<R>(S.Tt + ti2, lx2, 0, L1, (double)(D1 + ti1), ch, have_x, sprev, S.Mc[ti2],
+        sv = lse_pass<R>(S.Tt + ti2, lx2, 0, L1, (double)(D1 + ti1), ch, ichf, qc, cap, have_x, sprev + xext,
+                         S.Mc[ti2],
                          nfall);
       have_x = true;
+      xext = 0.0;
       __syncthreads();
       return sv;
     }
@@ -585,23 +673,24 @@ __global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
   bool conv = false;
   bool have_y = false;
   double ushift = 0.0;   // shift applied to alpha since the last Y-half (eps units)
+  double Anext = 0.0;    // translation: sum of e^{-alpha/lam} mu for the current alpha
 
   // ---- Y-half pieces -------------------------------------------------------
   auto y_prepare = [&]() {
     if (t < lx) S.adr[t] = aeps + lmux;
     __syncthreads();
-    seg_max<NT, 16>(S.adr, lx1, lx2, lx2, 1, S.Ma);
-    __syncthreads();
+    if constexpr (kMoved) {   // row maxima prune the dense sums
+      seg_max<NT, 16>(S.adr, lx1, lx2, lx2, 1, S.Ma);
+      __syncthreads();
+    }
   };
   // Y pass 1 over tile columns [ib, ie): Uo(i1, j2) = LSE_i2 [a - ch (i2 - (j2 - D2))^2]
   auto y_pass1 = [&](double* Uo, int ib, int ie, bool have, double extra) {
     for (int o = t; o < lx1 * L2; o += NT) {
       const int i1 = o / L2, j2 = o - i1 * L2;
-      Uo[o] = lse_pass<R>(S.adr + i1 * lx2, 1, ib, ie, (double)(j2 - D2), ch, have, Uo[o] + extra,
-                          S.Ma[i1], nfall);
+      Uo[o] = lse_full<R>(S.adr + i1 * lx2, 1, ib, ie, (double)(j2 - D2), ch, qc, cap, have,
+                          Uo[o] + extra, nfall);
     }
-    __syncthreads();
-    seg_max<NT, 8>(Uo, L2, lx1, 1, L2, S.MU);
     __syncthreads();
   };
 
@@ -615,14 +704,20 @@ __global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
       // B = |P_Y pi| of the state before the first Y-half, where
       // e^{-beta0/lam} nu = P_Y pi).  The plan is invariant along this
       // direction, so R-level relative accuracy of w suffices.
-      double ab[1] = {0.0};
-      if (t < lx) ab[0] = mux * exp(-aeps / K);
-      block_sum<NT, 1>(ab, red);
+      // (A of the next alpha is summed with the PD terms of the previous
+      // iteration, saving a reduction)
+      if (it == 1) {
+        double ab[1] = {0.0};
+        if (t < lx) ab[0] = mux * exp(-aeps / K);
+        block_sum<NT, 1>(ab, red);
+        Anext = ab[0];
+      }
       const double Bsum = it == 1 ? B0mass : pxsum + Rmass;
-      const double w = (Rmass + sqrt(Rmass * Rmass + 4.0 * ab[0] * Bsum)) / (2.0 * Bsum);
+      const double w = (Rmass + sqrt(Rmass * Rmass + 4.0 * Anext * Bsum)) / (2.0 * Bsum);
       const double sh = K * log(w);   // s/eps
       aeps += sh;
       ushift += sh;
+      xext -= sh;   // b = beta/eps + log nu moves by about -s/eps through the Y-half
       for (int o = t; o < NY; o += NT) S.bd[o] -= sh;
       __syncthreads();
     }
@@ -636,13 +731,13 @@ __global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
         z = dense_y_lse<R>(S.adr, S.Ma, lx1, lx2, (double)D1, (double)D2, j1 + (double)S.dl1[o],
                            j2 + (double)S.dl2[o], ch, have_y, S.zp[o] + ushift, nfall);
       else
-        z = lse_pass<R>(S.Ud + j2, L2, 0, lx1, (double)(j1 - D1), ch, have_y, S.zp[o] + ushift,
-                        S.MU[j2], nfall);
-      S.zp[o] = z;
+        z = lse_full<R>(S.Ud + j2, L2, 0, lx1, (double)(j1 - D1), ch, qc, cap, have_y,
+                        S.zp[o] + ushift, nfall);
+      S.zp[o] = R(z);
       double lnv, lrr;
       if constexpr (sizeof(R) == 4) {
         lnv = (double)S.lnvf[o];
-        lrr = (double)S.lrf[o];
+        lrr = (double)wlrf[o];
       } else {
         lnv = wlnv[o];
         lrr = wlrr[o];
@@ -666,10 +761,13 @@ __global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
       pxv = mux * exp(lpv);
       term = pxv * (lpv + aol) - pxv + mux * exp(-aol);
     }
-    double pdv[2] = {term, pxv};
-    block_sum<NT, 2>(pdv, red);
+    // A = sum e^{-alpha/lam} mu of the next iteration's alpha, for its
+    // translation step
+    double pdv[3] = {term, pxv, (P.translate && t < lx) ? mux * exp(kap * Sn / K) : 0.0};
+    block_sum<NT, 3>(pdv, red);
     conv = pdv[0] <= tol;
     pxsum = pdv[1];
+    Anext = pdv[2];
     const bool done = P.fixed_iters > 0 ? (it >= P.fixed_iters) : (conv || it >= P.max_iter);
     if (done) break;
     Sx = Sn;
@@ -708,8 +806,8 @@ __global__ __launch_bounds__(NT) void k_cell_solve(Dev d, int cell_base) {
                                      sizeof(R) == 8 ? 60.0 : 40.0);
           zk = a > R(0) ? S.zp[o] + (double)M<R>::lg(a) : -INFINITY;
         } else {
-          zk = lse_pass<R>(Uo + j2, L2, kr[k] * s, (kr[k] + 1) * s, (double)(j1 - D1), ch, true,
-                           S.zp[o], S.MU[j2], nfall);
+          zk = lse_full<R>(Uo + j2, L2, kr[k] * s, (kr[k] + 1) * s, (double)(j1 - D1), ch, qc, cap,
+                           true, S.zp[o], nfall);
         }
         const double nt = exp(S.bd[o] + zk);   // nu e^{beta/eps} e^{z_k}
         accy[k] += beta * nt;
