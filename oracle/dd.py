@@ -50,6 +50,11 @@ them also fixed in the design notes):
      the partition as four batches of non-adjacent cells (parity of the cell
      position), one swift step each, in batch order.
   R10 multiscale refinement (warm start of a finer layer): see `refine`.
+  R11 global Sinkhorn warm start: the coarse layers are solved by the global
+     Sinkhorn iteration (uot.sinkhorn) and the first DD layer starts from the
+     plan those potentials define: see `interpolate_potential` and
+     `init_from_duals`; later DD layers may be refined the same way from the
+     stitched alpha and the certificate's beta (`refine_duals`).
 """
 from __future__ import annotations
 
@@ -620,6 +625,117 @@ def refine(pc: Problem, stc: State, pf: Problem, trunc: float, cap: int) -> Stat
     px = np.kron(stc.px / pc.mu, ones) * pf.mu
     abar = np.kron(stc.abar, ones)
     return State(boxes, px, hbar, abar, force_greedy=True)
+
+
+def interpolate_potential(a_c, n1f: int, n2f: int) -> np.ndarray:
+    """Potential of the finer layer from the coarse one (reading R11).
+
+    Coarse point I stands for the fine block {2I, 2I + 1}: its potential is
+    taken at the block centre, fine index 2I + 1/2.  Each axis is linear
+    between the two nearest coarse points, continued linearly past the first
+    and last centres (one coarse point: constant).  Potentials are in cost
+    units, so a layer whose eps equals the coarse one's keeps their meaning."""
+    a_c = np.asarray(a_c, dtype=np.float64)
+
+    def along(a, axis, nf):
+        nc = a.shape[axis]
+        if nc == 1:
+            return np.repeat(a, nf, axis=axis)
+        u = (np.arange(nf) - 0.5) / 2.0
+        k = np.clip(np.floor(u).astype(int), 0, nc - 2)
+        t = u - k
+        lo = np.take(a, k, axis=axis)
+        hi = np.take(a, k + 1, axis=axis)
+        shape = [1] * a.ndim
+        shape[axis] = nf
+        t = t.reshape(shape)
+        return (1.0 - t) * lo + t * hi
+
+    return along(along(a_c, 0, n1f), 1, n2f)
+
+
+def init_from_duals(p: Problem, alpha, beta, trunc: float, cap: int | None = None,
+                    windows=None) -> State:
+    """DD state of the plan pi = exp((alpha + beta - c)/eps) mu x nu (the
+    diagonal-scaling form of Sec. 4.1) split by basic cells (reading R11):
+    nu_i(y) = sum_{x in X_i} pi(x, y), restricted to the basic cell's scan
+    window (default: the whole grid), entries below `trunc` dropped, box =
+    bbox of the rest, a box wider than `cap` keeps its central `cap` rows /
+    columns.  The cell plan is pi on X_i x (kept points of the box); P_X pi
+    and the tracked pieces Hbar_i (cell_piece) are those of the cell plans.
+    The first half-iteration from this state is greedy.  Dense: small grids."""
+    C = full_cost(p)
+    a = np.ravel(alpha).astype(np.float64)
+    b = np.ravel(beta).astype(np.float64)
+    pi = uot.plan(a, b, p.mu, p.nu, C, p.eps)
+    nbasic = p.nb1 * p.nb2
+    nu_tot = p.nu.sum()
+    boxes, hbar = [], np.zeros(nbasic)
+    px = np.zeros_like(p.mu)
+    for bi in range(nbasic):
+        rect = basic_rect(p, bi)
+        idx = rect_index(rect, p.n2)
+        rows = pi[idx]
+        nb = rows.sum(0).reshape(p.n1, p.n2)
+        inwin = np.zeros((p.n1, p.n2), dtype=bool)
+        w1, w2, wl1, wl2 = (0, 0, p.n1, p.n2) if windows is None else windows[bi]
+        inwin[w1:w1 + wl1, w2:w2 + wl2] = True
+        keep = inwin & (nb >= trunc) & (nb > 0)
+        mu_x = p.mu.ravel()[idx]
+        if not keep.any():
+            boxes.append((rect[0], rect[1], np.zeros((0, 0))))
+            hbar[bi] = cell_piece(np.zeros((idx.size, 0)), mu_x, np.zeros(0), nu_tot,
+                                  np.zeros((idx.size, 0)), p.eps, p.lam)
+            continue
+        r1, r2 = np.nonzero(keep)
+        o1, o2 = r1.min(), r2.min()
+        l1, l2 = r1.max() + 1 - o1, r2.max() + 1 - o2
+        if cap is not None and l1 > cap:
+            o1, l1 = o1 + (l1 - cap) // 2, cap
+        if cap is not None and l2 > cap:
+            o2, l2 = o2 + (l2 - cap) // 2, cap
+        yrect = (o1, o2, l1, l2)
+        kb = keep[o1:o1 + l1, o2:o2 + l2]
+        yidx = rect_index(yrect, p.n2)
+        pi_box = rows[:, yidx] * kb.ravel()[None, :]
+        boxes.append((o1, o2, np.where(kb, nb[o1:o1 + l1, o2:o2 + l2], 0.0)))
+        px.ravel()[idx] = pi_box.sum(1)
+        hbar[bi] = cell_piece(pi_box, mu_x, p.nu.ravel()[yidx], nu_tot,
+                              rect_cost(p, rect, yrect), p.eps, p.lam)
+    return State(boxes, px, hbar, np.asarray(alpha, dtype=np.float64).reshape(p.mu.shape).copy(),
+                 force_greedy=True)
+
+
+def refine_windows(pc: Problem, stc: State, pf: Problem, margin: int):
+    """Scan window of each fine basic cell for `refine_duals`: the box of its
+    coarse basic cell, doubled, dilated by `margin` fine points and clipped
+    to the grid (the whole grid for an empty coarse box)."""
+    out = []
+    for b in range(pf.nb1 * pf.nb2):
+        rect = basic_rect(pf, b)
+        I = ((rect[0] // 2) // pc.s1) * pc.nb2 + (rect[1] // 2) // pc.s2
+        o1, o2, arr = stc.boxes[I]
+        if arr.size == 0:
+            out.append((0, 0, pf.n1, pf.n2))
+            continue
+        a1, a2 = max(2 * o1 - margin, 0), max(2 * o2 - margin, 0)
+        e1 = min(2 * (o1 + arr.shape[0]) + margin, pf.n1)
+        e2 = min(2 * (o2 + arr.shape[1]) + margin, pf.n2)
+        out.append((a1, a2, e1 - a1, e2 - a2))
+    return out
+
+
+def refine_duals(pc: Problem, stc: State, pf: Problem, trunc: float, cap: int,
+                 margin: int) -> State:
+    """Finer-layer warm start from a coarse DD state through its potentials
+    (reading R11): the stitched alpha and the certificate's beta_hat, each
+    interpolated, define the fine plan, which `init_from_duals` splits by
+    basic cells inside `refine_windows`.  Needs pf.eps == pc.eps (the paper's
+    layer schedule ends a layer at the next one's starting eps)."""
+    cert = certificate(pc, stc.abar)
+    af = interpolate_potential(stc.abar, pf.n1, pf.n2)
+    bf = interpolate_potential(cert["beta_hat"], pf.n1, pf.n2)
+    return init_from_duals(pf, af, bf, trunc, cap, refine_windows(pc, stc, pf, margin))
 
 
 # --------------------------------------------------------------------------

@@ -352,3 +352,115 @@ def test_staggered_scores_decrease_and_reach_the_optimum():
         prev = cur
     np.testing.assert_allclose(st.plan, pi, rtol=5e-6, atol=1e-15)
     assert dd.certificate(p, st.abar)["rel"] < 1e-12
+
+
+# ---- global Sinkhorn warm start and potential-based refinement (R11) --------
+def test_interpolated_potential_is_exact_for_affine_potentials():
+    # a coarse potential sampled at the block centres 2I + 1/2 of an affine
+    # function gives that affine function at every fine point, also past the
+    # first and last centres (linear continuation)
+    nc1, nc2 = 5, 7
+    I1, I2 = np.meshgrid(np.arange(nc1), np.arange(nc2), indexing="ij")
+    f = lambda u, v: 0.3 - 1.7 * u + 0.45 * v
+    ac = f(2 * I1 + 0.5, 2 * I2 + 0.5)
+    af = dd.interpolate_potential(ac, 2 * nc1, 2 * nc2)
+    i1, i2 = np.meshgrid(np.arange(2 * nc1), np.arange(2 * nc2), indexing="ij")
+    np.testing.assert_allclose(af, f(i1, i2), rtol=0, atol=1e-13)
+    # a single coarse point: constant
+    np.testing.assert_array_equal(dd.interpolate_potential(np.full((1, 3), 2.5), 2, 6), 2.5)
+
+
+def test_interpolated_potential_keeps_the_coarse_values_between_centres():
+    # midway between two centres the value is their mean; a nonlinear coarse
+    # potential is reproduced at the centres' neighbours with weights 3/4, 1/4
+    rng = np.random.default_rng(5)
+    ac = rng.normal(size=(4, 4))
+    af = dd.interpolate_potential(ac, 8, 8)
+    # fine index 2I + 1 lies 1/4 of the way from centre I to centre I + 1
+    np.testing.assert_allclose(af[3, 5], (0.75 * (0.75 * ac[1, 2] + 0.25 * ac[1, 3]) +
+                                          0.25 * (0.75 * ac[2, 2] + 0.25 * ac[2, 3])), rtol=1e-14)
+
+
+def test_state_from_optimal_potentials_has_the_optimal_score():
+    # the plan of the optimal pair split by basic cells: the tracked score is
+    # the exact primal of that plan, which equals the optimal dual value
+    # (strong duality, Sec. 2.2), and the marginals are the plan's
+    p = small_problem(8, 2)
+    pi, sol, C = global_optimum(p)
+    st = dd.init_from_duals(p, sol["alpha"].reshape(8, 8), sol["beta"].reshape(8, 8), 0.0)
+    assert st.force_greedy
+    E = uot.primal(pi, p.mu, p.nu, C, p.eps, p.lam)
+    D = uot.dual(sol["alpha"], sol["beta"], p.mu, p.nu, C, p.eps, p.lam)
+    assert dd.tracked_score(p, st) == pytest.approx(E, rel=1e-12)
+    assert dd.tracked_score(p, st) == pytest.approx(D, rel=1e-9)
+    np.testing.assert_allclose(st.px, pi.sum(1).reshape(8, 8), rtol=1e-12)
+    np.testing.assert_allclose(dd.aggregate(p, st.boxes), pi.sum(0).reshape(8, 8), rtol=1e-12)
+
+
+def test_state_from_potentials_truncates_and_boxes_tightly():
+    p = small_problem(16, 4, eps_h2=1.0)
+    pi, sol, C = global_optimum(p)
+    a, b = sol["alpha"].reshape(16, 16), sol["beta"].reshape(16, 16)
+    trunc = 1e-9
+    st = dd.init_from_duals(p, a, b, trunc, cap=10)
+    for bi, (o1, o2, arr) in enumerate(st.boxes):
+        full = pi[dd.rect_index(dd.basic_rect(p, bi), p.n2)].sum(0).reshape(16, 16)
+        kept = arr > 0
+        assert arr.shape[0] <= 10 and arr.shape[1] <= 10
+        assert np.all(arr[kept] >= trunc)
+        np.testing.assert_allclose(arr[kept], full[o1:o1 + arr.shape[0], o2:o2 + arr.shape[1]][kept],
+                                   rtol=1e-13)
+        big = full >= trunc
+        r1, r2 = np.nonzero(big)
+        if r1.max() + 1 - r1.min() <= 10 and r2.max() + 1 - r2.min() <= 10:
+            # unclipped: the box is the bbox of the entries >= trunc
+            assert (o1, o2, arr.shape) == (r1.min(), r2.min(),
+                                           (r1.max() + 1 - r1.min(), r2.max() + 1 - r2.min()))
+        else:
+            # clipped: the central cap rows / columns of that bbox
+            assert arr.shape[0] == 10 or arr.shape[1] == 10
+    # px is the X-marginal of the kept cell plans: at most the full row sums
+    assert np.all(st.px <= pi.sum(1).reshape(16, 16) * (1 + 1e-13))
+
+
+def test_optimal_state_is_a_fixed_point_of_a_dd_half_iteration():
+    # optimal plan split by cells (Sec. 3: pi^dagger is a fixed point of
+    # DomDecIter): a greedy half-iteration from it keeps it
+    p = small_problem(8, 2)
+    pi, sol, C = global_optimum(p)
+    st = dd.init_from_duals(p, sol["alpha"].reshape(8, 8), sol["beta"].reshape(8, 8), 0.0)
+    ref = [arr.copy() for _, _, arr in st.boxes]
+    opt = dd.Options(cap=8, trunc=0.0, getweights="greedy", err=1e-14, max_iter=5000)
+    out = dd.half_iteration(p, st, "B", opt)
+    assert out["theta"] == 1.0
+    P = dd.aggregate(p, st.boxes)
+    np.testing.assert_allclose(P, pi.sum(0).reshape(8, 8), rtol=1e-6)
+    for (o1, o2, arr), r in zip(st.boxes, ref):
+        assert np.abs(arr).sum() == pytest.approx(r.sum(), rel=1e-6)
+
+
+def test_refine_duals_windows_cover_the_doubled_coarse_boxes():
+    pc, pf = _coarse_pair()
+    pf.eps = pc.eps
+    stc = dd.init_block(pc)
+    dd.run(pc, stc, 4, dd.Options(cap=16, margin=2, trunc=1e-15, translate=True))
+    wins = dd.refine_windows(pc, stc, pf, 3)
+    for b, (w1, w2, l1, l2) in enumerate(wins):
+        rect = dd.basic_rect(pf, b)
+        I = ((rect[0] // 2) // pc.s1) * pc.nb2 + (rect[1] // 2) // pc.s2
+        o1, o2, arr = stc.boxes[I]
+        assert w1 == max(2 * o1 - 3, 0) and w2 == max(2 * o2 - 3, 0)
+        assert w1 + l1 == min(2 * (o1 + arr.shape[0]) + 3, pf.n1)
+        assert w2 + l2 == min(2 * (o2 + arr.shape[1]) + 3, pf.n2)
+    st = dd.refine_duals(pc, stc, pf, 1e-15, 64, 3)
+    for (o1, o2, arr), (w1, w2, l1, l2) in zip(st.boxes, wins):
+        if arr.size:
+            assert w1 <= o1 and o1 + arr.shape[0] <= w1 + l1
+            assert w2 <= o2 and o2 + arr.shape[1] <= w2 + l2
+    # whole-grid windows: the plain instantiation from the interpolated pair
+    big = dd.refine_duals(pc, stc, pf, 1e-15, 64, 10 ** 6)
+    cert = dd.certificate(pc, stc.abar)
+    ref = dd.init_from_duals(pf, dd.interpolate_potential(stc.abar, pf.n1, pf.n2),
+                             dd.interpolate_potential(cert["beta_hat"], pf.n1, pf.n2), 1e-15, 64)
+    np.testing.assert_allclose(big.px, ref.px, rtol=1e-14)
+    np.testing.assert_allclose(big.hbar, ref.hbar, rtol=1e-12)
