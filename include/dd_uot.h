@@ -240,8 +240,46 @@ int dd_uot_kernel_time(dduot_handle* h, int64_t* launches, double* total_ms,
    estimates until then).  `coarse` is left unchanged. */
 int dd_uot_refine(dduot_handle* coarse, const dduot_config* cfg, const double* mu,
                   const double* nu, void* hip_stream, dduot_handle** out);
-/* Basic boxes clipped by the refinement that created h (0 otherwise). */
+/* Basic boxes clipped by the refinement or potential start that created h
+   (0 otherwise). */
 int32_t dd_uot_refine_clipped(const dduot_handle* h);
+
+/* Linear interpolation of a potential (cost units) to the grid with twice the
+   points per axis: coarse point I stands for the fine points {2I, 2I+1} and
+   its value is placed at the fine position 2I + 1/2; each axis is linear
+   between the two nearest such positions and continued linearly beyond the
+   first and last (a single coarse point: constant).  Exact for affine
+   potentials.  coarse: host, n1c*n2c doubles; fine: host, 4*n1c*n2c. */
+int dd_uot_interpolate_potential(const double* coarse, int32_t n1c, int32_t n2c, double* fine,
+                                 void* hip_stream);
+
+/* Global unbalanced Sinkhorn on the grid of cfg (Definition sinkhorn, the
+   closed-form updates eq. sinkhorn-iters-ot with nu_- = 0), FP64, separable
+   log-sum-exp: alpha = X-update(beta) from the warm beta; then per iteration
+   the Y-update, the gap pd = KL(P_X pi | e^{-alpha/lambda} mu) of the pair
+   (alpha, beta) (eq. PD-gap-KL divided by lambda), stop if pd <= tol, else the
+   X-update.  On return beta is the last Y-update; alpha is the potential it
+   was computed from when the tolerance stopped the loop, else the X-update
+   of beta (max_iter reached).  Uses n1, n2, h, lambda, eps of cfg.
+   mu, nu: host, n1*n2, finite and > 0; alpha (out), beta (in: warm start,
+   out): host, n1*n2; iters, pd (nullable): iterations done, last gap.
+   Allocates and frees its own device buffers; synchronises. */
+int dd_uot_global_sinkhorn(const dduot_config* cfg, const double* mu, const double* nu,
+                           double* alpha, double* beta, int32_t max_iter, double tol,
+                           void* hip_stream, int32_t* iters, double* pd);
+
+/* New single-problem handle whose state is the plan of the potentials
+   (alpha, beta) (cost units), pi = exp((alpha + beta - c)/eps) mu x nu
+   (Sec. 4.1), split by basic cells (Sec. 5.1 Sinkhorn warm start):
+   nu_i(y) = sum_{x in X_i} pi(x, y) over the whole grid, entries below trunc
+   dropped, box = bbox of the rest (a box wider than box_cap keeps its
+   central box_cap rows / columns, counted by dd_uot_refine_clipped); P_X pi
+   and the tracked pieces are those of the kept cell plans, alpha is the
+   stitched potential.  The first half-iteration is greedy.  alpha, beta:
+   host, n1*n2, finite.  Needs cell * n2 <= 8192 (LDS of the scan). */
+int dd_uot_init_duals(const dduot_config* cfg, const double* mu, const double* nu,
+                      const double* alpha, const double* beta, void* hip_stream,
+                      dduot_handle** out);
 
 typedef struct {
   int32_t levels;            /* layers; the coarsest has n / 2^(levels-1) points per axis */
@@ -259,18 +297,36 @@ typedef struct {
   int32_t final_max_halves;  /* cap on half-iterations after the finest stage */
   int32_t check_every;       /* certificate (dd_uot_score) every this many */
   double target_rel_gap;     /* stop once the relative primal-dual gap is below */
+  int32_t dd_from;           /* side of the first layer solved by DD; the coarser layers
+                                run the global Sinkhorn (dd_uot_global_sinkhorn), the plan
+                                of the last one's potentials is split by basic cells
+                                (dd_uot_init_duals) and refined to the first DD layer
+                                (Sec. 5.1 "Sinkhorn warm start": DD from 256^2 on).  The
+                                finest layer is always DD.  0: every layer is DD, the
+                                coarsest one started from the product or block plan */
+  int32_t global_max_iter;   /* global Sinkhorn iterations per eps stage, at most */
+  double global_tol;         /* a global eps stage ends once
+                                KL(P_X pi | e^{-alpha/lambda} mu) <= global_tol |mu|
+                                (Sec. 5.1: a quarter of the DD tolerance) */
 } dduot_multiscale;
 
 /* levels 7, coarse_cell 4, eps 2 h^2 -> h^2/2 per layer, 4..16 half-iterations
    per stage (stage gap 1e-3), 1000 inner iterations on coarse layers, at most
-   200 final half-iterations, certificate every 4, target 1e-6. */
+   200 final half-iterations, certificate every 4, target 1e-6; global Sinkhorn
+   below 256 points per axis, at most 2000 iterations per eps stage, tolerance
+   5e-6 (a quarter of Err = 2e-5). */
 void dd_uot_default_multiscale(dduot_multiscale* m);
 
 /* Coarse-to-fine solve with eps-scaling: coarsen (mu, nu) by 2 x 2 sums to
-   `levels` layers; start the coarsest from the product plan if it fits
-   box_cap (layers of side <= 64 widen box_cap to the grid), else the block
-   start; on every layer run the eps stages, then refine (dd_uot_refine); on
-   the finest layer continue to cfg->eps and then iterate until the
+   `levels` layers; the layers coarser than dd_from run the global Sinkhorn
+   through their eps stages (beta carried to the next layer by
+   dd_uot_interpolate_potential as its warm start), and the plan of the last
+   one's potentials, split by basic cells of side min(cell, coarse_cell)
+   (dd_uot_init_duals), is refined to the first DD layer; with dd_from = 0
+   the coarsest layer starts from the product plan if it fits box_cap
+   (layers of side <= 64 widen box_cap to the grid), else the block start.
+   On every DD layer run the eps stages, then refine (dd_uot_refine); on the
+   finest layer continue to cfg->eps and then iterate until the
    certificate's relative gap is <= target_rel_gap or final_max_halves are
    done.  trace (nullable, trace_cap records of 4 doubles): per certificate of
    the final stage, (total half-iterations, elapsed ms since the call,

@@ -51,10 +51,10 @@ them also fixed in the design notes):
      position), one swift step each, in batch order.
   R10 multiscale refinement (warm start of a finer layer): see `refine`.
   R11 global Sinkhorn warm start: the coarse layers are solved by the global
-     Sinkhorn iteration (uot.sinkhorn) and the first DD layer starts from the
-     plan those potentials define: see `interpolate_potential` and
-     `init_from_duals`; later DD layers may be refined the same way from the
-     stitched alpha and the certificate's beta (`refine_duals`).
+     Sinkhorn iteration (uot.sinkhorn), each warm-started from the previous
+     layer's beta (`interpolate_potential`); the plan of the last global
+     layer's potentials is split by basic cells (`init_from_duals`) and
+     refined to the first DD layer by `refine` (R10).
 """
 from __future__ import annotations
 
@@ -704,38 +704,6 @@ def init_from_duals(p: Problem, alpha, beta, trunc: float, cap: int | None = Non
                               rect_cost(p, rect, yrect), p.eps, p.lam)
     return State(boxes, px, hbar, np.asarray(alpha, dtype=np.float64).reshape(p.mu.shape).copy(),
                  force_greedy=True)
-
-
-def refine_windows(pc: Problem, stc: State, pf: Problem, margin: int):
-    """Scan window of each fine basic cell for `refine_duals`: the box of its
-    coarse basic cell, doubled, dilated by `margin` fine points and clipped
-    to the grid (the whole grid for an empty coarse box)."""
-    out = []
-    for b in range(pf.nb1 * pf.nb2):
-        rect = basic_rect(pf, b)
-        I = ((rect[0] // 2) // pc.s1) * pc.nb2 + (rect[1] // 2) // pc.s2
-        o1, o2, arr = stc.boxes[I]
-        if arr.size == 0:
-            out.append((0, 0, pf.n1, pf.n2))
-            continue
-        a1, a2 = max(2 * o1 - margin, 0), max(2 * o2 - margin, 0)
-        e1 = min(2 * (o1 + arr.shape[0]) + margin, pf.n1)
-        e2 = min(2 * (o2 + arr.shape[1]) + margin, pf.n2)
-        out.append((a1, a2, e1 - a1, e2 - a2))
-    return out
-
-
-def refine_duals(pc: Problem, stc: State, pf: Problem, trunc: float, cap: int,
-                 margin: int) -> State:
-    """Finer-layer warm start from a coarse DD state through its potentials
-    (reading R11): the stitched alpha and the certificate's beta_hat, each
-    interpolated, define the fine plan, which `init_from_duals` splits by
-    basic cells inside `refine_windows`.  Needs pf.eps == pc.eps (the paper's
-    layer schedule ends a layer at the next one's starting eps)."""
-    cert = certificate(pc, stc.abar)
-    af = interpolate_potential(stc.abar, pf.n1, pf.n2)
-    bf = interpolate_potential(cert["beta_hat"], pf.n1, pf.n2)
-    return init_from_duals(pf, af, bf, trunc, cap, refine_windows(pc, stc, pf, margin))
 
 
 # --------------------------------------------------------------------------

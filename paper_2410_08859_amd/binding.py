@@ -28,6 +28,7 @@ EXPORTED = (
     "dd_uot_last_error", "dd_uot_refine", "dd_uot_refine_clipped", "dd_uot_default_multiscale",
     "dd_uot_solve_multiscale", "dd_uot_init_moved", "dd_uot_init_batch_moved",
     "dd_uot_backward_ypos", "dd_uot_set_graph", "dd_uot_autotune",
+    "dd_uot_interpolate_potential", "dd_uot_global_sinkhorn", "dd_uot_init_duals",
 )
 
 
@@ -74,6 +75,8 @@ class dduot_multiscale(C.Structure):
         ("coarse_max_iter", C.c_int32), ("final_max_halves", C.c_int32),
         ("check_every", C.c_int32),
         ("target_rel_gap", C.c_double),
+        ("dd_from", C.c_int32), ("global_max_iter", C.c_int32),
+        ("global_tol", C.c_double),
     ]
 
 
@@ -127,6 +130,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dd_uot_default_multiscale": (None, [P(dduot_multiscale)]),
         "dd_uot_solve_multiscale": (C.c_int, [P(dduot_config), P(dduot_multiscale), dp, dp,
                                               C.c_void_p, P(H), dp, C.c_int32, P(C.c_int32)]),
+        "dd_uot_interpolate_potential": (C.c_int, [dp, C.c_int32, C.c_int32, dp, C.c_void_p]),
+        "dd_uot_global_sinkhorn": (C.c_int, [P(dduot_config), dp, dp, dp, dp, C.c_int32, C.c_double,
+                                             C.c_void_p, P(C.c_int32), dp]),
+        "dd_uot_init_duals": (C.c_int, [P(dduot_config), dp, dp, dp, dp, C.c_void_p, P(H)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -275,6 +282,43 @@ def dd_uot_refine(coarse, cfg: dduot_config, mu, nu, stream=None):
 
 def dd_uot_refine_clipped(h):
     return load().dd_uot_refine_clipped(h)
+
+
+def dd_uot_interpolate_potential(coarse, stream=None):
+    """(n1c, n2c) potential -> (2 n1c, 2 n2c) on the device kernel."""
+    a = np.ascontiguousarray(coarse, dtype=np.float64)
+    if a.ndim != 2:
+        raise ValueError("coarse potential must be 2-D")
+    out = np.empty((2 * a.shape[0], 2 * a.shape[1]))
+    _check(load().dd_uot_interpolate_potential(_dptr(a), a.shape[0], a.shape[1], _dptr(out), stream))
+    return out
+
+
+def dd_uot_global_sinkhorn(cfg: dduot_config, mu, nu, beta0=None, max_iter=1000, tol=0.0,
+                           stream=None):
+    """Returns dict(alpha, beta, iters, pd) (grids of the config's shape)."""
+    mu = _grid(mu, cfg.n1, cfg.n2)
+    nu = _grid(nu, cfg.n1, cfg.n2)
+    beta = np.zeros((cfg.n1, cfg.n2)) if beta0 is None else \
+        np.array(beta0, dtype=np.float64).reshape(cfg.n1, cfg.n2)
+    alpha = np.empty((cfg.n1, cfg.n2))
+    it = C.c_int32()
+    pd = C.c_double()
+    _check(load().dd_uot_global_sinkhorn(C.byref(cfg), _dptr(mu), _dptr(nu), _dptr(alpha),
+                                         _dptr(beta), int(max_iter), float(tol), stream,
+                                         C.byref(it), C.byref(pd)))
+    return dict(alpha=alpha, beta=beta, iters=it.value, pd=pd.value)
+
+
+def dd_uot_init_duals(cfg: dduot_config, mu, nu, alpha, beta, stream=None):
+    mu = _grid(mu, cfg.n1, cfg.n2)
+    nu = _grid(nu, cfg.n1, cfg.n2)
+    a = _grid(alpha, cfg.n1, cfg.n2)
+    b = _grid(beta, cfg.n1, cfg.n2)
+    h = C.c_void_p()
+    _check(load().dd_uot_init_duals(C.byref(cfg), _dptr(mu), _dptr(nu), _dptr(a), _dptr(b), stream,
+                                    C.byref(h)))
+    return h
 
 
 def dd_uot_default_multiscale(**kw) -> dduot_multiscale:

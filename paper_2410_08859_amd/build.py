@@ -11,7 +11,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["cell_kernel.hip", "aux_kernels.hip", "dense_lse.hip", "multiscale.hip", "api.hip"]
+SOURCES = ["cell_kernel.hip", "aux_kernels.hip", "dense_lse.hip", "multiscale.hip", "warmstart.hip",
+           "api.hip"]
 LIB = os.path.join(HERE, "libdd_uot.so")
 
 FLAGS = [

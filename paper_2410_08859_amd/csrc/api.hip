@@ -60,6 +60,14 @@ struct RefineArgs {
 };
 hipError_t launch_refine(const RefineArgs& A, int fnbasic, const double* px_c, const double* abar_c,
                          double* px_f, double* abar_f, int fn1, hipStream_t st);
+hipError_t launch_interp(const double* ac, int n1c, int n2c, double* af, hipStream_t st);
+size_t from_duals_lds(int s, int gcols, int cap);
+hipError_t launch_from_duals(const DualsArgs& A, int nbasic, hipStream_t st);
+hipError_t gs_x_update(const Prob& p, const double* beta, const double* nu, double* alpha,
+                       double* scratch, hipStream_t st);
+hipError_t gs_iteration(const Prob& p, const double* alpha, const double* mu, const double* nu,
+                        double* beta, double* scratch, double* part, int nblk, hipStream_t st);
+hipError_t gs_alpha_from_s(const Prob& p, const double* scratch, double* alpha, hipStream_t st);
 }  // namespace dduot
 
 using namespace dduot;
@@ -1120,6 +1128,207 @@ extern "C" int dd_uot_refine(dduot_handle* coarse, const dduot_config* cfg, cons
 
 extern "C" int32_t dd_uot_refine_clipped(const dduot_handle* h) { return h ? h->clipped : 0; }
 
+// ---- global Sinkhorn warm start (Sec. 5.1) and potential-based refinement ----
+static const int kGsBlocks = 256;
+
+static Prob grid_prob(const dduot_config* c) {
+  Prob p{};
+  p.n1 = c->n1; p.n2 = c->n2; p.s = c->cell;
+  p.h = c->h; p.eps = c->eps; p.lam = c->lambda;
+  p.kappa = c->lambda / (c->lambda + c->eps);
+  p.K = c->lambda / c->eps;
+  p.ch = c->h * c->h / c->eps;
+  return p;
+}
+
+// Global Sinkhorn on device grids, the iteration of the oracle's uot.sinkhorn:
+// alpha = X-update(beta); then per iteration the Y-update, the gap
+// KL(P_X pi | e^{-alpha/lam} mu) of the pair (alpha, beta), stop if <= tol,
+// else the X-update.  scratch: 5 grids; part: kGsBlocks doubles.
+static int gs_solve(const Prob& p, const double* mu, const double* nu, double* alpha, double* beta,
+                    double* scratch, double* part, int max_iter, double tol, hipStream_t st,
+                    int* iters, double* pd_out) {
+  HIPCHK(set_rows_lds_limit(std::max<size_t>(sizeof(double) * std::max(p.n1, p.n2), 1024)));
+  HIPCHK(gs_x_update(p, beta, nu, alpha, scratch, st));
+  std::vector<double> hp(kGsBlocks);
+  double pd = INFINITY;
+  int it = 0;
+  for (it = 1; it <= max_iter; ++it) {
+    HIPCHK(gs_iteration(p, alpha, mu, nu, beta, scratch, part, kGsBlocks, st));
+    HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * kGsBlocks, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    pd = 0.0;
+    for (double v : hp) pd += v;
+    if (pd <= tol) break;
+    HIPCHK(gs_alpha_from_s(p, scratch, alpha, st));
+  }
+  if (iters) *iters = std::min(it, max_iter);
+  if (pd_out) *pd_out = pd;
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_global_sinkhorn(const dduot_config* cfg, const double* mu, const double* nu,
+                                      double* alpha, double* beta, int32_t max_iter, double tol,
+                                      void* hip_stream, int32_t* iters, double* pd) {
+  if (!cfg || !mu || !nu || !alpha || !beta) return fail(DDUOT_EINVAL, "null argument");
+  if (cfg->n1 <= 0 || cfg->n2 <= 0) return fail(DDUOT_EINVAL, "grid sides must be positive");
+  if (!(cfg->lambda > 0.0) || !isfinite(cfg->lambda) || !(cfg->eps > 0.0) || !isfinite(cfg->eps) ||
+      !(cfg->h >= 0.0) || !isfinite(cfg->h))
+    return fail(DDUOT_EINVAL, "lambda, eps must be > 0 and h >= 0");
+  if (max_iter < 1) return fail(DDUOT_EINVAL, "max_iter must be >= 1");
+  if (!(tol >= 0.0)) return fail(DDUOT_EINVAL, "tol must be >= 0");
+  const long n = (long)cfg->n1 * cfg->n2;
+  for (long i = 0; i < n; ++i)
+    if (!(mu[i] > 0.0) || !isfinite(mu[i]) || !(nu[i] > 0.0) || !isfinite(nu[i]) || !isfinite(beta[i]))
+      return fail(DDUOT_EINVAL, "masses must be finite and > 0, beta finite");
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::vector<void*> mem;
+  auto grab = [&](double** p, long count) -> int {
+    HIPCHK(hipMalloc((void**)p, sizeof(double) * count));
+    mem.push_back(*p);
+    return DDUOT_OK;
+  };
+  auto body = [&]() -> int {
+    double *d_mu, *d_nu, *d_a, *d_b, *d_s, *d_part;
+    CHK(grab(&d_mu, n));
+    CHK(grab(&d_nu, n));
+    CHK(grab(&d_a, n));
+    CHK(grab(&d_b, n));
+    CHK(grab(&d_s, 5 * n));
+    CHK(grab(&d_part, kGsBlocks));
+    HIPCHK(hipMemcpyAsync(d_mu, mu, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_nu, nu, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_b, beta, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    const Prob p = grid_prob(cfg);
+    CHK(gs_solve(p, d_mu, d_nu, d_a, d_b, d_s, d_part, max_iter, tol, st, iters, pd));
+    HIPCHK(hipMemcpyAsync(alpha, d_a, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(beta, d_b, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return DDUOT_OK;
+  };
+  const int r = body();
+  for (void* p : mem) (void)hipFree(p);
+  return r;
+}
+
+extern "C" int dd_uot_interpolate_potential(const double* coarse, int32_t n1c, int32_t n2c,
+                                            double* fine, void* hip_stream) {
+  if (!coarse || !fine || n1c <= 0 || n2c <= 0) return fail(DDUOT_EINVAL, "bad arguments");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const long nc = (long)n1c * n2c;
+  double *dc = nullptr, *df = nullptr;
+  auto body = [&]() -> int {
+    HIPCHK(hipMalloc((void**)&dc, sizeof(double) * nc));
+    HIPCHK(hipMalloc((void**)&df, sizeof(double) * 4 * nc));
+    HIPCHK(hipMemcpyAsync(dc, coarse, sizeof(double) * nc, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_interp(dc, n1c, n2c, df, st));
+    HIPCHK(hipMemcpyAsync(fine, df, sizeof(double) * 4 * nc, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return DDUOT_OK;
+  };
+  const int r = body();
+  if (dc) (void)hipFree(dc);
+  if (df) (void)hipFree(df);
+  return r;
+}
+
+// State of the single problem of h from device potentials (cost units) with
+// per-basic-cell scan windows; the next half-iteration is greedy.
+static int state_from_duals(dduot_handle* h, const double* d_alpha, const double* d_beta,
+                            const std::vector<Box>& win) {
+  const Prob& p = h->probs[0];
+  hipStream_t st = h->stream;
+  int gcols = 1;
+  for (const Box& b : win) gcols = std::max(gcols, b.l2);
+  int dev = 0, max_lds = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if ((long)from_duals_lds(p.s, gcols, h->cap) + 4096 > max_lds)
+    return fail(DDUOT_EINVAL, "scan window too wide for the LDS of one workgroup");
+  Box* d_win = nullptr;
+  int* d_nclip = nullptr;
+  CHK(dalloc(h, &d_win, win.size()));
+  CHK(dalloc(h, &d_nclip, 1));
+  HIPCHK(hipMemcpyAsync(d_win, win.data(), sizeof(Box) * win.size(), hipMemcpyHostToDevice, st));
+  static const int zero = 0, one = 1;
+  HIPCHK(hipMemcpyAsync(d_nclip, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+  DualsArgs A{};
+  A.alpha = d_alpha;
+  A.beta = d_beta;
+  A.mu = h->d_mu;
+  A.nu = h->d_nu;
+  A.bxy = h->d_basic_xy;
+  A.win = d_win;
+  A.n1 = p.n1;
+  A.n2 = p.n2;
+  A.s = p.s;
+  A.cap = h->cap;
+  A.gcols = gcols;
+  A.cap2 = h->cap2;
+  A.eps = p.eps;
+  A.lam = p.lam;
+  A.ch = p.ch;
+  A.trunc = p.trunc;
+  A.mass_nu = p.mass_nu;
+  A.box = h->d_box;
+  A.vals = h->d_vals;
+  A.px = h->d_px;
+  A.hbar = h->d_hbar;
+  A.nclip = d_nclip;
+  HIPCHK(launch_from_duals(A, p.nbasic, st));
+  HIPCHK(hipMemcpyAsync(h->d_abar, d_alpha, sizeof(double) * p.n1 * p.n2, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_force, &one, sizeof(int), hipMemcpyHostToDevice, st));
+  int nclip = 0;
+  HIPCHK(hipMemcpyAsync(&nclip, d_nclip, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  h->clipped = nclip;
+  return DDUOT_OK;
+}
+
+// New single-problem handle with a placeholder state (block start).
+static int placeholder_handle(const dduot_config* cfg, const double* mu, const double* nu,
+                              void* hip_stream, dduot_handle** out) {
+  dduot_config c = *cfg;
+  c.init = DDUOT_INIT_BLOCK;
+  return dd_uot_init(&c, mu, nu, hip_stream, out);
+}
+
+static void destroy_keep_error(dduot_handle* h) {
+  std::string keep = g_err;
+  dd_uot_destroy(h);
+  g_err = keep;
+}
+
+extern "C" int dd_uot_init_duals(const dduot_config* cfg, const double* mu, const double* nu,
+                                 const double* alpha, const double* beta, void* hip_stream,
+                                 dduot_handle** out) {
+  if (!out) return fail(DDUOT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!alpha || !beta) return fail(DDUOT_EINVAL, "null potential");
+  if (!cfg) return fail(DDUOT_EINVAL, "null config");
+  const long n = (long)cfg->n1 * cfg->n2;
+  for (long i = 0; i < n; ++i)
+    if (!isfinite(alpha[i]) || !isfinite(beta[i])) return fail(DDUOT_EINVAL, "potentials must be finite");
+  dduot_handle* h = nullptr;
+  CHK(placeholder_handle(cfg, mu, nu, hip_stream, &h));
+  double *da = nullptr, *db = nullptr;
+  auto body = [&]() -> int {
+    CHK(dalloc(h, &da, n));
+    CHK(dalloc(h, &db, n));
+    HIPCHK(hipMemcpyAsync(da, alpha, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(db, beta, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+    std::vector<Box> win(h->probs[0].nbasic, Box{0, 0, cfg->n1, cfg->n2});
+    return state_from_duals(h, da, db, win);
+  };
+  const int r = body();
+  if (r != DDUOT_OK) {
+    destroy_keep_error(h);
+    return r;
+  }
+  *out = h;
+  return DDUOT_OK;
+}
+
 extern "C" void dd_uot_default_multiscale(dduot_multiscale* m) {
   memset(m, 0, sizeof(*m));
   m->levels = 7;
@@ -1133,6 +1342,9 @@ extern "C" void dd_uot_default_multiscale(dduot_multiscale* m) {
   m->final_max_halves = 200;
   m->check_every = 4;
   m->target_rel_gap = 1e-6;
+  m->dd_from = 256;
+  m->global_max_iter = 2000;
+  m->global_tol = 5e-6;
 }
 
 static double now_ms() {
@@ -1157,6 +1369,8 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
       ms->stage_max_halves < ms->halves_per_stage || ms->coarse_max_iter < 1 ||
       ms->coarse_cell < 1 || 2 * ms->coarse_cell > kMaxTile)
     return fail(DDUOT_EINVAL, "bad iteration counts or coarse cell");
+  if (ms->dd_from < 0 || ms->global_max_iter < 1 || !(ms->global_tol >= 0.0))
+    return fail(DDUOT_EINVAL, "bad global Sinkhorn settings");
   if (cfg->n1 % (1 << (L - 1)) || cfg->n2 % (1 << (L - 1)))
     return fail(DDUOT_EINVAL, "grid sides must be divisible by 2^(levels-1)");
   const double t0 = now_ms();
@@ -1192,8 +1406,88 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
       ++tl;
     }
   };
+  // layers coarser than dd_from (never the finest) run the global Sinkhorn
+  // (Sec. 5.1 "Sinkhorn warm start"); the plan of the last one's potentials,
+  // split by basic cells, is refined to the first DD layer
+  int first_dd = 0;
+  if (ms->dd_from > 0)
+    while (first_dd < L - 1 && std::max(n1s[first_dd], n2s[first_dd]) < ms->dd_from) ++first_dd;
+  struct DevBufs {
+    std::vector<void*> p;
+    ~DevBufs() {
+      for (void* q : p) (void)hipFree(q);
+    }
+  } gbufs;
+  auto galloc = [&](double** p, long count) -> int {
+    HIPCHK(hipMalloc((void**)p, sizeof(double) * count));
+    gbufs.p.push_back(*p);
+    return DDUOT_OK;
+  };
+  double *g_a = nullptr, *g_b = nullptr, *g_fb = nullptr;
+  if (first_dd > 0) {
+    hipStream_t st = (hipStream_t)hip_stream;
+    const long nmax = (long)n1s[first_dd - 1] * n2s[first_dd - 1];
+    double *g_mu, *g_nu, *g_s, *g_part;
+    CHK(galloc(&g_a, nmax));
+    CHK(galloc(&g_b, nmax));
+    CHK(galloc(&g_mu, nmax));
+    CHK(galloc(&g_nu, nmax));
+    CHK(galloc(&g_s, 5 * nmax));
+    CHK(galloc(&g_part, kGsBlocks));
+    CHK(galloc(&g_fb, nmax));
+    double mass = 0.0;
+    for (double v : mus[0]) mass += v;
+    for (int l = 0; l < first_dd; ++l) {
+      dduot_config c = *cfg;
+      c.n1 = n1s[l];
+      c.n2 = n2s[l];
+      c.h = cfg->h * (double)(1 << (L - 1 - l));
+      const long n = (long)c.n1 * c.n2;
+      HIPCHK(hipMemcpyAsync(g_mu, mus[l].data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(g_nu, nus[l].data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+      if (l == 0) {
+        HIPCHK(launch_fill(g_b, n, 0.0, st));
+      } else {
+        // beta of the coarser layer, interpolated (alpha follows from it)
+        HIPCHK(launch_interp(g_b, n1s[l - 1], n2s[l - 1], g_fb, st));
+        HIPCHK(hipMemcpyAsync(g_b, g_fb, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      }
+      const double h2 = c.h * c.h;
+      double e = ms->eps_start_h2 * h2;
+      const double e_end = ms->eps_end_h2 * h2;
+      for (;;) {
+        c.eps = e;
+        const Prob p = grid_prob(&c);
+        int it = 0;
+        double pd = 0.0;
+        CHK(gs_solve(p, g_mu, g_nu, g_a, g_b, g_s, g_part, ms->global_max_iter, ms->global_tol * mass,
+                     st, &it, &pd));
+        if (e <= e_end * (1.0 + 1e-12)) break;
+        e = std::max(e * 0.5, e_end);
+      }
+    }
+  }
   dduot_handle* h = nullptr;
-  for (int l = 0; l < L; ++l) {
+  if (first_dd > 0) {
+    // DD state of the last global layer: its own potentials' plan split by
+    // basic cells; the next layer refines it like any DD layer
+    const int l = first_dd - 1;
+    dduot_config c = *cfg;
+    c.n1 = n1s[l];
+    c.n2 = n2s[l];
+    c.h = cfg->h * (double)(1 << (L - 1 - l));
+    c.cell = std::min(cfg->cell, ms->coarse_cell);
+    if (std::max(c.n1, c.n2) <= 64) c.box_cap = std::max(c.box_cap, std::max(c.n1, c.n2));
+    c.eps = ms->eps_end_h2 * c.h * c.h;
+    CHK(placeholder_handle(&c, mus[l].data(), nus[l].data(), hip_stream, &h));
+    std::vector<Box> win(h->probs[0].nbasic, Box{0, 0, c.n1, c.n2});
+    const int r = state_from_duals(h, g_a, g_b, win);
+    if (r != DDUOT_OK) {
+      destroy_keep_error(h);
+      return r;
+    }
+  }
+  for (int l = first_dd; l < L; ++l) {
     const double scale = (double)(1 << (L - 1 - l));
     dduot_config c = *cfg;
     c.n1 = n1s[l];
@@ -1223,7 +1517,7 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
     } else {
       const int r = dd_uot_refine(h, &c, mus[l].data(), nus[l].data(), hip_stream, &nh);
       halves_before += h->k;
-      dd_uot_destroy(h);
+      destroy_keep_error(h);
       h = nullptr;
       if (r != DDUOT_OK) return r;
     }

@@ -458,6 +458,78 @@ hipError_t launch_certificate(const Prob& p, const double* alpha, const double* 
   return hipGetLastError();
 }
 
+// ---- global Sinkhorn (Definition sinkhorn; eq. sinkhorn-iters-ot) ---------
+// One iteration on one problem's grid, all in FP64 with the separable
+// log-sum-exp of the certificate:
+//   beta  = -eps kappa LSE_x [alpha/eps + log mu - ch |x - y|^2]   (Y-update)
+//   S     =            LSE_y [beta/eps + log nu - ch |x - y|^2]
+//   PD/lam terms of the pair (alpha, beta): log P_X pi = alpha/eps + log mu + S,
+//   then (when continuing) alpha = -eps kappa S                      (X-update)
+__global__ void k_gs_alpha(const double* S, double* alpha, long n, double f) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    alpha[i] = f * S[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_gs_pd(const double* alpha, const double* S,
+                                                  const double* mu, long n, double eps, double lam,
+                                                  double* part) {
+  __shared__ double red[4];
+  double acc[1] = {0.0};
+  for (long i = blockIdx.x * (long)kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+    const double a = alpha[i], m = mu[i];
+    const double lp = a / eps + S[i];
+    const double pxh = m * exp(lp);
+    const double aol = a / lam;
+    acc[0] += pxh * (lp + aol) - pxh + m * exp(-aol);
+  }
+  block_sum_aux<1>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+// alpha = -eps kappa LSE_y [beta/eps + log nu - c/eps] (scratch: 3 grids)
+hipError_t gs_x_update(const Prob& p, const double* beta, const double* nu, double* alpha,
+                       double* scratch, hipStream_t st) {
+  const long n = (long)p.n1 * p.n2;
+  double* b = scratch;
+  double* S = scratch + n;
+  double* tmp = scratch + 2 * n;
+  const int eb = (int)min((n + 255) / 256, (long)4096);
+  hipLaunchKernelGGL(k_prep_alpha, dim3(eb), dim3(256), 0, st, beta, nu, b, n, 1.0 / p.eps);
+  hipError_t e = gauss_lse2d(b, S, tmp, p.n1, p.n2, p.ch, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gs_alpha, dim3(eb), dim3(256), 0, st, S, alpha, n, -p.eps * p.kappa);
+  return hipGetLastError();
+}
+
+// Y-update, then S and the PD partial sums (nblk doubles) of the pair
+// (alpha, beta).  scratch: 5 grids; S stays in scratch + n.
+hipError_t gs_iteration(const Prob& p, const double* alpha, const double* mu, const double* nu,
+                        double* beta, double* scratch, double* part, int nblk, hipStream_t st) {
+  const long n = (long)p.n1 * p.n2;
+  double* b = scratch;
+  double* S = scratch + n;
+  double* tmp = scratch + 2 * n;
+  double* a = scratch + 3 * n;
+  double* z = scratch + 4 * n;
+  const int eb = (int)min((n + 255) / 256, (long)4096);
+  hipLaunchKernelGGL(k_prep_alpha, dim3(eb), dim3(256), 0, st, alpha, mu, a, n, 1.0 / p.eps);
+  hipError_t e = gauss_lse2d(a, z, tmp, p.n1, p.n2, p.ch, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prep_beta, dim3(eb), dim3(256), 0, st, z, nu, beta, b, n, p.eps, p.kappa);
+  e = gauss_lse2d(b, S, tmp, p.n1, p.n2, p.ch, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gs_pd, dim3(nblk), dim3(kBlock), 0, st, alpha, S, mu, n, p.eps, p.lam, part);
+  return hipGetLastError();
+}
+
+// alpha = -eps kappa S with S from the last gs_iteration
+hipError_t gs_alpha_from_s(const Prob& p, const double* scratch, double* alpha, hipStream_t st) {
+  const long n = (long)p.n1 * p.n2;
+  const int eb = (int)min((n + 255) / 256, (long)4096);
+  hipLaunchKernelGGL(k_gs_alpha, dim3(eb), dim3(256), 0, st, scratch + n, alpha, n, -p.eps * p.kappa);
+  return hipGetLastError();
+}
+
 // dW/dy' = sum_x pi_hat(x, y) 2 (y' - x) = 2 h P_Y pi_hat(y) (y'/h - E[x | y]) with
 // the conditional mean E[x | y] (pixel units) from the moments of the Y-update sum.
 __global__ void k_grad_ypos(const double* mom, const double* z, const double* bhat, const double* nu,

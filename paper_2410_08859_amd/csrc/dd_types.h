@@ -78,4 +78,23 @@ struct Dev {
   long cap2;                  // doubles per slot
 };
 
+// Basic-cell state from a pair of global potentials (warmstart.hip).
+struct DualsArgs {
+  const double* alpha;   // grid, cost units
+  const double* beta;
+  const double* mu;
+  const double* nu;
+  const int2* bxy;       // X origin of each basic cell
+  const Box* win;        // Y scan window of each basic cell
+  int n1, n2, s, cap;
+  int gcols;             // largest window width (LDS rows of G)
+  long cap2;
+  double eps, lam, ch, trunc, mass_nu;
+  Box* box;
+  double* vals;
+  double* px;
+  double* hbar;
+  int* nclip;
+};
+
 }  // namespace dduot

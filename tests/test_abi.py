@@ -33,7 +33,10 @@ def test_struct_layouts_match_the_header(tmp_path):
                    'sizeof(dduot_iter_stats), sizeof(dduot_score), offsetof(dduot_config, box_cap),'
                    'offsetof(dduot_score, overflow), offsetof(dduot_iter_stats, n_cells),'
                    'sizeof(dduot_multiscale), offsetof(dduot_multiscale, stage_gap),'
-                   'offsetof(dduot_multiscale, target_rel_gap));return 0;}\n')
+                   'offsetof(dduot_multiscale, target_rel_gap));'
+                   'printf("%zu %zu ", offsetof(dduot_multiscale, dd_from), '
+                   'offsetof(dduot_multiscale, global_tol));'
+                   'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
@@ -42,7 +45,8 @@ def test_struct_layouts_match_the_header(tmp_path):
             ctypes.sizeof(binding.dduot_score), binding.dduot_config.box_cap.offset,
             binding.dduot_score.overflow.offset, binding.dduot_iter_stats.n_cells.offset,
             ctypes.sizeof(binding.dduot_multiscale), binding.dduot_multiscale.stage_gap.offset,
-            binding.dduot_multiscale.target_rel_gap.offset]
+            binding.dduot_multiscale.target_rel_gap.offset,
+            binding.dduot_multiscale.dd_from.offset, binding.dduot_multiscale.global_tol.offset]
     assert got == want
 
 

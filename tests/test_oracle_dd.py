@@ -437,30 +437,3 @@ def test_optimal_state_is_a_fixed_point_of_a_dd_half_iteration():
     np.testing.assert_allclose(P, pi.sum(0).reshape(8, 8), rtol=1e-6)
     for (o1, o2, arr), r in zip(st.boxes, ref):
         assert np.abs(arr).sum() == pytest.approx(r.sum(), rel=1e-6)
-
-
-def test_refine_duals_windows_cover_the_doubled_coarse_boxes():
-    pc, pf = _coarse_pair()
-    pf.eps = pc.eps
-    stc = dd.init_block(pc)
-    dd.run(pc, stc, 4, dd.Options(cap=16, margin=2, trunc=1e-15, translate=True))
-    wins = dd.refine_windows(pc, stc, pf, 3)
-    for b, (w1, w2, l1, l2) in enumerate(wins):
-        rect = dd.basic_rect(pf, b)
-        I = ((rect[0] // 2) // pc.s1) * pc.nb2 + (rect[1] // 2) // pc.s2
-        o1, o2, arr = stc.boxes[I]
-        assert w1 == max(2 * o1 - 3, 0) and w2 == max(2 * o2 - 3, 0)
-        assert w1 + l1 == min(2 * (o1 + arr.shape[0]) + 3, pf.n1)
-        assert w2 + l2 == min(2 * (o2 + arr.shape[1]) + 3, pf.n2)
-    st = dd.refine_duals(pc, stc, pf, 1e-15, 64, 3)
-    for (o1, o2, arr), (w1, w2, l1, l2) in zip(st.boxes, wins):
-        if arr.size:
-            assert w1 <= o1 and o1 + arr.shape[0] <= w1 + l1
-            assert w2 <= o2 and o2 + arr.shape[1] <= w2 + l2
-    # whole-grid windows: the plain instantiation from the interpolated pair
-    big = dd.refine_duals(pc, stc, pf, 1e-15, 64, 10 ** 6)
-    cert = dd.certificate(pc, stc.abar)
-    ref = dd.init_from_duals(pf, dd.interpolate_potential(stc.abar, pf.n1, pf.n2),
-                             dd.interpolate_potential(cert["beta_hat"], pf.n1, pf.n2), 1e-15, 64)
-    np.testing.assert_allclose(big.px, ref.px, rtol=1e-14)
-    np.testing.assert_allclose(big.hbar, ref.hbar, rtol=1e-12)
