@@ -82,6 +82,13 @@ typedef struct {
                                 form, removes the slowly contracting constant
                                 mode; not in the paper); 0: the paper's plain
                                 Sinkhorn iteration */
+  int32_t fast_cap;          /* cell solves run in two launches when fast_cap <
+                                box_cap: the cells whose Y-box side exceeds
+                                fast_cap first, with the LDS layout of box_cap,
+                                then the others with the smaller layout of
+                                fast_cap (more workgroups per CU); the results
+                                do not depend on it.  0: the largest side whose
+                                layout lets three workgroups share a CU */
 } dduot_config;
 
 /* Per call of dd_uot_iterate, summed over all problems of the handle. */
@@ -308,13 +315,17 @@ typedef struct {
   double global_tol;         /* a global eps stage ends once
                                 KL(P_X pi | e^{-alpha/lambda} mu) <= global_tol |mu|
                                 (Sec. 5.1: a quarter of the DD tolerance) */
+  int32_t coarse_box_cap;    /* DD layers other than the finest use
+                                max(cfg->box_cap, coarse_box_cap) (<= 128) */
+  double coarse_lenience;    /* ... and this GetWeights lenience */
 } dduot_multiscale;
 
 /* levels 7, coarse_cell 4, eps 2 h^2 -> h^2/2 per layer, 4..16 half-iterations
    per stage (stage gap 1e-3), 1000 inner iterations on coarse layers, at most
    200 final half-iterations, certificate every 4, target 1e-6; global Sinkhorn
    below 256 points per axis, at most 2000 iterations per eps stage, tolerance
-   5e-6 (a quarter of Err = 2e-5). */
+   5e-6 (a quarter of Err = 2e-5); coarser DD layers with box cap 80 and
+   strict GetWeights (lenience 0). */
 void dd_uot_default_multiscale(dduot_multiscale* m);
 
 /* Coarse-to-fine solve with eps-scaling: coarsen (mu, nu) by 2 x 2 sums to
@@ -340,6 +351,9 @@ int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_multiscale* ms,
 
 int dd_uot_synchronize(dduot_handle* h);
 int32_t dd_uot_num_problems(const dduot_handle* h);
+/* Y-box sides of the two cell-solve launches of h (see fast_cap): the fast
+   tier's and the slot capacity; equal when one launch does every cell. */
+int dd_uot_launch_caps(const dduot_handle* h, int32_t* fast_cap, int32_t* box_cap);
 void dd_uot_destroy(dduot_handle* h);
 const char* dd_uot_last_error(void);
 

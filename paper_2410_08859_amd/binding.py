@@ -29,6 +29,7 @@ EXPORTED = (
     "dd_uot_solve_multiscale", "dd_uot_init_moved", "dd_uot_init_batch_moved",
     "dd_uot_backward_ypos", "dd_uot_set_graph", "dd_uot_autotune",
     "dd_uot_interpolate_potential", "dd_uot_global_sinkhorn", "dd_uot_init_duals",
+    "dd_uot_launch_caps",
 )
 
 
@@ -43,7 +44,7 @@ class dduot_config(C.Structure):
         ("sinkhorn_max_iter", C.c_int32), ("fixed_inner_iters", C.c_int32),
         ("trunc", C.c_double), ("lenience", C.c_double),
         ("box_margin", C.c_int32), ("box_cap", C.c_int32),
-        ("translate", C.c_int32),
+        ("translate", C.c_int32), ("fast_cap", C.c_int32),
     ]
 
 
@@ -77,6 +78,7 @@ class dduot_multiscale(C.Structure):
         ("target_rel_gap", C.c_double),
         ("dd_from", C.c_int32), ("global_max_iter", C.c_int32),
         ("global_tol", C.c_double),
+        ("coarse_box_cap", C.c_int32), ("coarse_lenience", C.c_double),
     ]
 
 
@@ -134,6 +136,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dd_uot_global_sinkhorn": (C.c_int, [P(dduot_config), dp, dp, dp, dp, C.c_int32, C.c_double,
                                              C.c_void_p, P(C.c_int32), dp]),
         "dd_uot_init_duals": (C.c_int, [P(dduot_config), dp, dp, dp, dp, C.c_void_p, P(H)]),
+        "dd_uot_launch_caps": (C.c_int, [H, P(C.c_int32), P(C.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -319,6 +322,13 @@ def dd_uot_init_duals(cfg: dduot_config, mu, nu, alpha, beta, stream=None):
     _check(load().dd_uot_init_duals(C.byref(cfg), _dptr(mu), _dptr(nu), _dptr(a), _dptr(b), stream,
                                     C.byref(h)))
     return h
+
+
+def dd_uot_launch_caps(h):
+    """(fast tier box side, slot box side) of the cell-solve launches."""
+    a, b = C.c_int32(), C.c_int32()
+    _check(load().dd_uot_launch_caps(h, C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 def dd_uot_default_multiscale(**kw) -> dduot_multiscale:

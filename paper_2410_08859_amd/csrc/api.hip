@@ -12,10 +12,10 @@
 #include <vector>
 
 namespace dduot {
-hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int precision,
-                             bool moved, int nt, hipStream_t st);
+hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int tcap,
+                             int precision, bool moved, int nt, hipStream_t st);
 hipError_t set_cell_lds_limit(size_t bytes);
-size_t cell_lds_bytes(int cap, int precision, bool moved);
+size_t cell_lds_bytes(int lcap, int cap, int precision, bool moved);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st);
 hipError_t launch_aggregate(const Box* box, const double* vals, long cap2, const int* basic_prob,
                             const Prob* probs, double* P, int nbasic, hipStream_t st);
@@ -93,6 +93,7 @@ struct dduot_handle {
   int nprob = 0;
   int precision = 32;
   int cap = 0;
+  int tcap = 0;        // fast launch tier: cells whose Y-box side fits tcap
   long cap2 = 0;
   hipStream_t stream = nullptr;
   std::vector<Prob> probs;
@@ -214,6 +215,7 @@ static int validate(const dduot_config* c, const double* mu, const double* nu, i
   if (c->translate != 0 && c->translate != 1) return fail(DDUOT_EINVAL, pre + "translate must be 0 or 1");
   if (c->box_cap < 2 * c->cell || c->box_cap > 128)
     return fail(DDUOT_EINVAL, pre + "box_cap must be in [2*cell, 128]");
+  if (c->fast_cap < 0 || c->fast_cap > 128) return fail(DDUOT_EINVAL, pre + "fast_cap must be in [0, 128]");
   if (c->init == DDUOT_INIT_PRODUCT && (c->box_cap < c->n1 || c->box_cap < c->n2))
     return fail(DDUOT_EINVAL, pre + "product start needs box_cap >= grid side");
   const long n = (long)c->n1 * c->n2;
@@ -271,10 +273,25 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   for (int k = 0; k < nprob; ++k)
     if ((cfgs[k].getweights == DDUOT_GW_STAGGERED) != h->staggered)
       return fail(DDUOT_EINVAL, "staggered GetWeights: all problems of a handle or none");
-  const size_t lds_cell = cell_lds_bytes(h->cap, h->precision, h->moved);
+  const size_t lds_cell = cell_lds_bytes(h->cap, h->cap, h->precision, h->moved);
   const size_t lds_mix = sizeof(double) * h->cap2;
   if ((long)lds_cell > max_lds || (long)lds_mix > max_lds)
     return fail(DDUOT_EINVAL, "box_cap too large for the LDS of one workgroup");
+  // fast tier: by default the largest box side whose cell LDS lets three
+  // workgroups share a CU; cells with larger boxes run in a second launch
+  int lds_cu = 0;
+  if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+          hipSuccess ||
+      lds_cu <= 0)
+    lds_cu = max_lds;
+  int fc = cfgs[0].fast_cap;
+  if (fc <= 0)
+    for (int c = h->cap; c >= 1; --c)
+      if (3 * cell_lds_bytes(c, h->cap, h->precision, h->moved) <= (size_t)lds_cu) {
+        fc = c;
+        break;
+      }
+  h->tcap = (fc <= 0 || fc >= h->cap) ? h->cap : fc;
   HIPCHK(set_cell_lds_limit(lds_cell));
   HIPCHK(set_mix_lds_limit(lds_mix));
 
@@ -654,6 +671,12 @@ extern "C" void dd_uot_destroy(dduot_handle* h) {
 }
 
 extern "C" int32_t dd_uot_num_problems(const dduot_handle* h) { return h ? h->nprob : 0; }
+extern "C" int dd_uot_launch_caps(const dduot_handle* h, int32_t* fast_cap, int32_t* box_cap) {
+  if (!h) return fail(DDUOT_EINVAL, "null handle");
+  if (fast_cap) *fast_cap = h->tcap;
+  if (box_cap) *box_cap = h->cap;
+  return DDUOT_OK;
+}
 
 extern "C" int dd_uot_synchronize(dduot_handle* h) {
   if (!h) return fail(DDUOT_EINVAL, "null handle");
@@ -690,7 +713,7 @@ static int dd_step(dduot_handle* h, int part, int lo, int n, int blo, int bhi) {
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, st));
   }
-  HIPCHK(launch_cell_solve(d, lo, n, h->cap, h->precision, h->moved, h->nt, st));
+  HIPCHK(launch_cell_solve(d, lo, n, h->cap, h->tcap, h->precision, h->moved, h->nt, st));
   if (h->timing) {
     HIPCHK(hipEventRecord(e1, st));
     h->events.push_back({e0, e1});
@@ -789,7 +812,7 @@ extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
     }
     float t = 0.0f;
     hipError_t e = hipEventRecord(e0, st);
-    if (e == hipSuccess) e = launch_cell_solve(h->d, base, h->ncell[part], h->cap, h->precision, h->moved, nt, st);
+    if (e == hipSuccess) e = launch_cell_solve(h->d, base, h->ncell[part], h->cap, h->tcap, h->precision, h->moved, nt, st);
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
@@ -1345,6 +1368,8 @@ extern "C" void dd_uot_default_multiscale(dduot_multiscale* m) {
   m->dd_from = 256;
   m->global_max_iter = 2000;
   m->global_tol = 5e-6;
+  m->coarse_box_cap = 80;
+  m->coarse_lenience = 0.0;
 }
 
 static double now_ms() {
@@ -1371,6 +1396,8 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
     return fail(DDUOT_EINVAL, "bad iteration counts or coarse cell");
   if (ms->dd_from < 0 || ms->global_max_iter < 1 || !(ms->global_tol >= 0.0))
     return fail(DDUOT_EINVAL, "bad global Sinkhorn settings");
+  if (ms->coarse_box_cap < 0 || ms->coarse_box_cap > 128 || !(ms->coarse_lenience >= 0.0))
+    return fail(DDUOT_EINVAL, "coarse_box_cap must be in [0, 128], coarse_lenience >= 0");
   if (cfg->n1 % (1 << (L - 1)) || cfg->n2 % (1 << (L - 1)))
     return fail(DDUOT_EINVAL, "grid sides must be divisible by 2^(levels-1)");
   const double t0 = now_ms();
@@ -1477,6 +1504,8 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
     c.n2 = n2s[l];
     c.h = cfg->h * (double)(1 << (L - 1 - l));
     c.cell = std::min(cfg->cell, ms->coarse_cell);
+    c.box_cap = std::max(c.box_cap, ms->coarse_box_cap);
+    c.lenience = ms->coarse_lenience;
     if (std::max(c.n1, c.n2) <= 64) c.box_cap = std::max(c.box_cap, std::max(c.n1, c.n2));
     c.eps = ms->eps_end_h2 * c.h * c.h;
     CHK(placeholder_handle(&c, mus[l].data(), nus[l].data(), hip_stream, &h));
@@ -1505,6 +1534,8 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
     }
     if (!finest) {
       c.sinkhorn_max_iter = std::max(cfg->sinkhorn_max_iter, ms->coarse_max_iter);
+      c.box_cap = std::max(c.box_cap, ms->coarse_box_cap);
+      c.lenience = ms->coarse_lenience;
       // small layers keep whole-grid boxes (no overflow)
       if (std::max(c.n1, c.n2) <= 64) c.box_cap = std::max(c.box_cap, std::max(c.n1, c.n2));
     }

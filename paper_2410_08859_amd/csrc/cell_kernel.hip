@@ -310,8 +310,10 @@ struct CellLds {
   R* qtab;       // -sc ch d^2 for d = -cmax .. cmax (pass costs) [2*cmax+1]
 };
 
+// cmax: largest box side of the launch; qmax: the handle's box cap, which
+// sizes the cost table (so every launch reads the same table entries).
 template <typename R>
-__host__ __device__ inline size_t cell_lds_layout(int cmax, bool moved, CellLds<R>* L,
+__host__ __device__ inline size_t cell_lds_layout(int cmax, int qmax, bool moved, CellLds<R>* L,
                                                   unsigned char* base) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -328,7 +330,7 @@ __host__ __device__ inline size_t cell_lds_layout(int cmax, bool moved, CellLds<
   const size_t o_lnv = sizeof(R) == 4 ? take(4 * n2) : 0;
   const size_t o_d1 = moved ? take(sizeof(R) * n2) : 0, o_d2 = moved ? take(sizeof(R) * n2) : 0;
   const size_t o_mx = moved ? take(8 * 3 * kMaxTile * kMaxTile) : 0;
-  const size_t o_q = take(sizeof(R) * (2 * (size_t)cmax + 1));
+  const size_t o_q = take(sizeof(R) * (2 * (size_t)qmax + 1));
   if (L) {
     L->bd = (double*)(base + o_bd);
     L->zp = (R*)(base + o_zp);
@@ -443,13 +445,19 @@ __device__ __forceinline__ double dense_y_lse(const double* adr, const double* M
 }
 
 // NT threads per cell (64, 128 or 256; at least the tile's point count,
-// since thread t owns tile point t).  The FP32 separable kernel asks for three
+// since thread t owns tile point t).  Launch tiers (same arithmetic, the Y-box
+// always follows the handle's cap): tier 0 solves every cell of the range
+// with the LDS layout of the cap; tier 1 only the cells whose box fits tcap,
+// with the smaller layout of tcap; tier 2 the others (and the overflowing
+// cells) with the layout of the cap.  The FP32 separable kernel asks for three
 // waves per SIMD (its LDS at box cap 48 allows three workgroups per CU; the
 // register limit costs a few spills outside the hot loops, and the extra
 // wave hides more latency: measured 7 % faster at 1024^2).
 template <typename R, bool kMoved, int NT>
 __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cell_solve(Dev d,
-                                                                                       int cell_base) {
+                                                                                       int cell_base,
+                                                                                       int tcap,
+                                                                                       int tier) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int t = threadIdx.x;
   const int ci = cell_base + blockIdx.x;
@@ -476,6 +484,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
   const int lx1 = C.lx1, lx2 = C.lx2, lx = lx1 * lx2;
   const int s = P.s;
   if (U1 > cap || U2 > cap) {
+    if (tier == 1) return;
     // overflow: keep the old state of every basic cell of J
     for (int k = 0; k < C.nb; ++k) {
       const int b = C.basic[k];
@@ -506,9 +515,11 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
   const int o1 = max(lo1 - m1, 0), o2 = max(lo2 - m2, 0);
   const int L1 = min(hi1 + m1, P.n1) - o1, L2 = min(hi2 + m2, P.n2) - o2;
   const int NY = L1 * L2;
+  const bool fits = L1 <= tcap && L2 <= tcap;
+  if ((tier == 1 && !fits) || (tier == 2 && fits)) return;
 
   CellLds<R> S;
-  cell_lds_layout<R>(cap, kMoved, &S, smem_raw);
+  cell_lds_layout<R>(tier == 1 ? tcap : cap, cap, kMoved, &S, smem_raw);
   double* red = S.red;
 
   const double eps = P.eps, lam = P.lam, kap = P.kappa, K = P.K, ch = P.ch;
@@ -868,31 +879,49 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
   }
 }
 
-size_t cell_lds_bytes(int cap, int precision, bool moved) {
-  if (precision == 64) return cell_lds_layout<double>(cap, moved, nullptr, nullptr);
-  return cell_lds_layout<float>(cap, moved, nullptr, nullptr);
+size_t cell_lds_bytes(int lcap, int cap, int precision, bool moved) {
+  if (precision == 64) return cell_lds_layout<double>(lcap, cap, moved, nullptr, nullptr);
+  return cell_lds_layout<float>(lcap, cap, moved, nullptr, nullptr);
 }
 
 template <typename R, bool kMoved>
-static void launch_nt(const Dev& d, int cell_base, int ncells, size_t lds, int nt, hipStream_t st) {
+static void launch_nt(const Dev& d, int cell_base, int ncells, size_t lds, int nt, int tcap, int tier,
+                      hipStream_t st) {
   if (nt == 64)
-    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 64>), dim3(ncells), dim3(64), lds, st, d, cell_base);
+    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 64>), dim3(ncells), dim3(64), lds, st, d, cell_base,
+                       tcap, tier);
   else if (nt == 128)
-    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 128>), dim3(ncells), dim3(128), lds, st, d, cell_base);
+    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 128>), dim3(ncells), dim3(128), lds, st, d, cell_base,
+                       tcap, tier);
   else
-    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 256>), dim3(ncells), dim3(256), lds, st, d, cell_base);
+    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 256>), dim3(ncells), dim3(256), lds, st, d, cell_base,
+                       tcap, tier);
 }
 
-hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int precision,
-                             bool moved, int nt, hipStream_t st) {
-  if (ncells <= 0) return hipSuccess;
-  const size_t lds = cell_lds_bytes(cap, precision, moved);
+static void launch_tier(const Dev& d, int cell_base, int ncells, int lcap, int cap, int precision,
+                        bool moved, int nt, int tcap, int tier, hipStream_t st) {
+  const size_t lds = cell_lds_bytes(lcap, cap, precision, moved);
   if (precision == 64) {
-    if (moved) launch_nt<double, true>(d, cell_base, ncells, lds, nt, st);
-    else launch_nt<double, false>(d, cell_base, ncells, lds, nt, st);
+    if (moved) launch_nt<double, true>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+    else launch_nt<double, false>(d, cell_base, ncells, lds, nt, tcap, tier, st);
   } else {
-    if (moved) launch_nt<float, true>(d, cell_base, ncells, lds, nt, st);
-    else launch_nt<float, false>(d, cell_base, ncells, lds, nt, st);
+    if (moved) launch_nt<float, true>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+    else launch_nt<float, false>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+  }
+}
+
+// tcap < cap: two launches, the cells whose box exceeds tcap first (larger
+// LDS layout, fewer workgroups per CU), then the others.
+hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int tcap,
+                             int precision, bool moved, int nt, hipStream_t st) {
+  if (ncells <= 0) return hipSuccess;
+  if (tcap >= cap) {
+    launch_tier(d, cell_base, ncells, cap, cap, precision, moved, nt, cap, 0, st);
+  } else {
+    launch_tier(d, cell_base, ncells, cap, cap, precision, moved, nt, tcap, 2, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    launch_tier(d, cell_base, ncells, tcap, cap, precision, moved, nt, tcap, 1, st);
   }
   return hipGetLastError();
 }

@@ -34,8 +34,8 @@ def test_struct_layouts_match_the_header(tmp_path):
                    'offsetof(dduot_score, overflow), offsetof(dduot_iter_stats, n_cells),'
                    'sizeof(dduot_multiscale), offsetof(dduot_multiscale, stage_gap),'
                    'offsetof(dduot_multiscale, target_rel_gap));'
-                   'printf("%zu %zu ", offsetof(dduot_multiscale, dd_from), '
-                   'offsetof(dduot_multiscale, global_tol));'
+                   'printf("%zu %zu %zu ", offsetof(dduot_multiscale, dd_from), '
+                   'offsetof(dduot_multiscale, global_tol), offsetof(dduot_multiscale, coarse_lenience));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
@@ -46,7 +46,8 @@ def test_struct_layouts_match_the_header(tmp_path):
             binding.dduot_score.overflow.offset, binding.dduot_iter_stats.n_cells.offset,
             ctypes.sizeof(binding.dduot_multiscale), binding.dduot_multiscale.stage_gap.offset,
             binding.dduot_multiscale.target_rel_gap.offset,
-            binding.dduot_multiscale.dd_from.offset, binding.dduot_multiscale.global_tol.offset]
+            binding.dduot_multiscale.dd_from.offset, binding.dduot_multiscale.global_tol.offset,
+            binding.dduot_multiscale.coarse_lenience.offset]
     assert got == want
 
 

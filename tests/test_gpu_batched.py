@@ -160,3 +160,42 @@ def test_autotuned_threads_per_cell_keep_the_trajectory():
     finally:
         B.dd_uot_destroy(ha)
         B.dd_uot_destroy(hb)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_two_launch_tiers_keep_the_trajectory(precision):
+    # cells whose Y-box exceeds fast_cap run in a second launch with the
+    # larger LDS layout; the arithmetic is the same, so the trajectory is too
+    cfgs = make_cfgs(precision)
+    tiered = []
+    for c in make_cfgs(precision):
+        c.fast_cap = 12
+        tiered.append(c)
+    data = [problem_data(k, c.n1) for k, c in enumerate(cfgs)]
+    ha = B.dd_uot_init_batch(cfgs, [d[0] for d in data], [d[1] for d in data])
+    hb = B.dd_uot_init_batch(tiered, [d[0] for d in data], [d[1] for d in data])
+    try:
+        print(f"[tiers] FP{precision} caps {B.dd_uot_launch_caps(ha)} vs {B.dd_uot_launch_caps(hb)}",
+              flush=True)
+        assert B.dd_uot_launch_caps(hb) == (12, 32)
+        fa, ca = B.dd_uot_launch_caps(ha)
+        assert ca == 32 and 1 <= fa <= 32
+        B.dd_uot_iterate(ha, 6)
+        B.dd_uot_iterate(hb, 6)
+        # FP64: equal to rounding; FP32: the FP64 atomics of the aggregation
+        # change the last bit of P_Y from run to run, which FP32 amplifies
+        tol = 1e-12 if precision == 64 else 1e-5
+        wide = 0
+        for k, c in enumerate(cfgs):
+            n = c.n1
+            for a, b in zip(B.dd_uot_marginals(ha, k, n, n), B.dd_uot_marginals(hb, k, n, n)):
+                np.testing.assert_allclose(a, b, rtol=0, atol=tol * b.max())
+            np.testing.assert_allclose(B.dd_uot_history(ha, k)[:, :3], B.dd_uot_history(hb, k)[:, :3],
+                                       rtol=tol, atol=0)
+            for b in range(0, (n // c.cell) ** 2):
+                o1, o2, arr = B.dd_uot_basic_marginal(hb, k, b)
+                wide += int(max(arr.shape, default=0) > 12)
+        assert wide > 0   # the second tier had cells to solve
+    finally:
+        B.dd_uot_destroy(ha)
+        B.dd_uot_destroy(hb)

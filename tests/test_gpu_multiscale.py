@@ -76,11 +76,11 @@ def oracle_multiscale(mu, nu, c, ms):
         h = c.h * 2 ** (L - 1 - l)
         fin = l == L - 1
         s = c.cell if fin else (n // 2 if (l == 0 and n <= 16) else min(c.cell, ms.coarse_cell))
-        cap = c.box_cap if (fin or n > 64) else max(c.box_cap, n)
+        cap = c.box_cap if fin else max(c.box_cap, ms.coarse_box_cap, n if n <= 64 else 0)
         opt = dd.Options(err=c.sinkhorn_err, max_iter=c.sinkhorn_max_iter if fin else
                          max(c.sinkhorn_max_iter, ms.coarse_max_iter), trunc=c.trunc,
-                         lenience=c.lenience, margin=c.box_margin, cap=cap,
-                         getweights="swift", translate=True)
+                         lenience=c.lenience if fin else ms.coarse_lenience,
+                         margin=c.box_margin, cap=cap, getweights="swift", translate=True)
         pn = dd.make_problem(mus[l], nus[l], ms.eps_start_h2 * h * h, c.lambda_, h, s)
         if l == 0:
             st = dd.init_product(pn) if cap >= n else dd.init_block(pn)
@@ -121,7 +121,8 @@ def test_multiscale_driver_follows_the_oracle():
     c = B.dd_uot_default_config(n1=n, n2=n, h=1.0 / n, eps=1.0 / n ** 2, lam=1.0, cell=4,
                                 precision=64, box_cap=32, sinkhorn_max_iter=200, lenience=0.0)
     ms = B.dd_uot_default_multiscale(levels=2, final_max_halves=8, check_every=4,
-                                     target_rel_gap=1e-12, stage_max_halves=8, coarse_max_iter=400)
+                                     target_rel_gap=1e-12, stage_max_halves=8, coarse_max_iter=400,
+                                     dd_from=0, coarse_lenience=0.005)
     print("[multiscale] driver 16 -> 32 against the oracle", flush=True)
     h, tr = B.dd_uot_solve_multiscale(c, ms, mu, nu)
     try:

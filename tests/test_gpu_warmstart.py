@@ -135,7 +135,7 @@ def oracle_multiscale_global(mu, nu, c, ms):
                 break
             e = max(e * 0.5, e_end)
         if l == first - 1:
-            cap = c.box_cap if n > 64 else max(c.box_cap, n)
+            cap = max(c.box_cap, ms.coarse_box_cap, n if n <= 64 else 0)
             p = dd.make_problem(mus[l], nus[l], e, c.lambda_, h, min(c.cell, ms.coarse_cell))
             st = dd.init_from_duals(p, alpha.reshape(n, n), beta.reshape(n, n), c.trunc, cap)
     trace = []
@@ -144,11 +144,11 @@ def oracle_multiscale_global(mu, nu, c, ms):
         h = c.h * 2 ** (L - 1 - l)
         fin = l == L - 1
         s = c.cell if fin else min(c.cell, ms.coarse_cell)
-        cap = c.box_cap if (fin or n > 64) else max(c.box_cap, n)
+        cap = c.box_cap if fin else max(c.box_cap, ms.coarse_box_cap, n if n <= 64 else 0)
         opt = dd.Options(err=c.sinkhorn_err, max_iter=c.sinkhorn_max_iter if fin else
                          max(c.sinkhorn_max_iter, ms.coarse_max_iter), trunc=c.trunc,
-                         lenience=c.lenience, margin=c.box_margin, cap=cap,
-                         getweights="swift", translate=True)
+                         lenience=c.lenience if fin else ms.coarse_lenience,
+                         margin=c.box_margin, cap=cap, getweights="swift", translate=True)
         pn = dd.make_problem(mus[l], nus[l], ms.eps_start_h2 * h * h, c.lambda_, h, s)
         st = dd.refine(p, st, pn, c.trunc, cap)
         p = pn
