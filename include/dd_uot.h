@@ -277,7 +277,7 @@ int dd_uot_global_sinkhorn(const dduot_config* cfg, const double* mu, const doub
 
 /* New single-problem handle whose state is the plan of the potentials
    (alpha, beta) (cost units), pi = exp((alpha + beta - c)/eps) mu x nu
-   (Sec. 4.1), split by basic cells (Sec. 5.1 Sinkhorn warm start):
+   (Sec. 4.1), split by basic cells (Sec. 4.4 Sinkhorn warm start):
    nu_i(y) = sum_{x in X_i} pi(x, y) over the whole grid, entries below trunc
    dropped, box = bbox of the rest (a box wider than box_cap keeps its
    central box_cap rows / columns, counted by dd_uot_refine_clipped); P_X pi
@@ -308,13 +308,13 @@ typedef struct {
                                 run the global Sinkhorn (dd_uot_global_sinkhorn), the plan
                                 of the last one's potentials is split by basic cells
                                 (dd_uot_init_duals) and refined to the first DD layer
-                                (Sec. 5.1 "Sinkhorn warm start": DD from 256^2 on).  The
+                                (Sec. 4.4 "Sinkhorn warm start": DD from 256^2 on).  The
                                 finest layer is always DD.  0: every layer is DD, the
                                 coarsest one started from the product or block plan */
   int32_t global_max_iter;   /* global Sinkhorn iterations per eps stage, at most */
   double global_tol;         /* a global eps stage ends once
                                 KL(P_X pi | e^{-alpha/lambda} mu) <= global_tol |mu|
-                                (Sec. 5.1: a quarter of the DD tolerance) */
+                                (Sec. 4.4: a quarter of the DD tolerance) */
   int32_t coarse_box_cap;    /* DD layers other than the finest use
                                 max(cfg->box_cap, coarse_box_cap) (<= 128) */
   double coarse_lenience;    /* ... and this GetWeights lenience */

@@ -1151,7 +1151,7 @@ extern "C" int dd_uot_refine(dduot_handle* coarse, const dduot_config* cfg, cons
 
 extern "C" int32_t dd_uot_refine_clipped(const dduot_handle* h) { return h ? h->clipped : 0; }
 
-// ---- global Sinkhorn warm start (Sec. 5.1) and potential-based refinement ----
+// ---- global Sinkhorn warm start (Sec. 4.4) and potential-based refinement ----
 static const int kGsBlocks = 256;
 
 static Prob grid_prob(const dduot_config* c) {
@@ -1434,7 +1434,7 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
     }
   };
   // layers coarser than dd_from (never the finest) run the global Sinkhorn
-  // (Sec. 5.1 "Sinkhorn warm start"); the plan of the last one's potentials,
+  // (Sec. 4.4 "Sinkhorn warm start"); the plan of the last one's potentials,
   // split by basic cells, is refined to the first DD layer
   int first_dd = 0;
   if (ms->dd_from > 0)

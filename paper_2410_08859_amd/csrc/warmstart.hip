@@ -1,5 +1,5 @@
 // Warm start of a domain-decomposition layer from global dual potentials
-// (Sec. 5.1 "Sinkhorn warm start" with the multiscale layers of Sec. 4.4).
+// (Sec. 4.4 "Sinkhorn warm start" with the multiscale layers of Sec. 4.4).
 //
 // The coarse layers are solved by the global Sinkhorn iteration; their
 // potentials (alpha, beta), in cost units, are carried to the next layer by
