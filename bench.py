@@ -33,7 +33,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 from paper_2410_08859_amd import binding as B  # noqa: E402
-from paper_2410_08859_amd.inputs import WORKLOADS, workload_marginals  # noqa: E402
+from paper_2410_08859_amd.inputs import (WORKLOADS, batched_problems,  # noqa: E402
+                                         displaced_points, displacement_theta,
+                                         workload_marginals)
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 9.83e13 FP32 lane-ops/s;
 # v_exp_f32 runs at a quarter of that rate.
@@ -168,6 +170,97 @@ def cpu_baseline(name, max_inner, cap, budget_s=15.0):
                       f"({n}x{n}, FP64 dense numpy, Err 2e-5, max {max_inner} inner iterations)"}
 
 
+def timed_iterate(h, steps, warmup):
+    """(wall seconds, grid-pts*iters) of `steps` half-iterations after `warmup`."""
+    import torch
+    B.dd_uot_iterate(h, warmup, stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = B.dd_uot_iterate(h, steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, float(st["point_iters"])
+
+
+def batched_form(steps, warmup):
+    """The batched workload (64 problems, sides 64..512, lambda log-uniform in
+    [0.1, 10], eps = h^2, FP32, cells 4x4, box cap 48): one handle whose
+    launches cover every problem's cells, A+B pairs replayed from a hipGraph,
+    threads per cell autotuned; against the same problems stepped one handle
+    at a time (eager, 256 threads per cell)."""
+    probs = batched_problems(64)
+    cfgs = [B.dd_uot_default_config(n1=q["n"], n2=q["n"], h=1.0 / q["n"], eps=1.0 / q["n"] ** 2,
+                                    lam=q["lam"], cell=4, precision=32, sinkhorn_max_iter=100,
+                                    box_cap=48, getweights=B.GW_STAGGERED) for q in probs]
+    h = B.dd_uot_init_batch(cfgs, [q["mu"] for q in probs], [q["nu"] for q in probs])
+    try:
+        nt, _ = B.dd_uot_autotune(h)
+        B.dd_uot_set_graph(h, True)
+        dt, pts = timed_iterate(h, steps, warmup)
+    finally:
+        B.dd_uot_destroy(h)
+    dts, ptss = 0.0, 0.0
+    for c, q in zip(cfgs, probs):
+        hs = B.dd_uot_init(c, q["mu"], q["nu"])
+        try:
+            d, p = timed_iterate(hs, steps, warmup)
+        finally:
+            B.dd_uot_destroy(hs)
+        dts += d
+        ptss += p
+    progress(f"batched form: {pts / dt:.3g} vs one by one {ptss / dts:.3g} grid-pts*iters/s")
+    return {"problems": len(probs), "grid_points": int(sum(q["n"] ** 2 for q in probs)),
+            "steps": steps, "threads_per_cell": nt, "value": pts / dt, "ms_per_step": 1e3 * dt / steps,
+            "one_by_one": {"value": ptss / dts, "ms_per_step": 1e3 * dts / steps},
+            "unit": "grid-pts*iters/s", "speedup": (pts / dt) / (ptss / dts)}
+
+
+def differentiable_form(halves):
+    """The differentiable workload (512^2, Y points displaced by the seeded
+    8x8 cubic B-spline field of amplitude 2h, lambda 1, eps = h^2, cells 4x4,
+    box cap 32): forward half-iterations, then the certificate and the
+    gradients d/dmu, d/dnu (dd_uot_backward) and d/dy' (dd_uot_backward_ypos),
+    in FP32 and FP64; the gradient difference between the two is reported
+    relative to the FP64 gradient."""
+    import torch
+    w = WORKLOADS["grid512"]
+    n = w["n"]
+    mu, nu = workload_marginals("grid512")
+    y = displaced_points(n, n, 1.0 / n, displacement_theta(53, 1.0 / n))
+    out, grads = {}, {}
+    for prec in (32, 64):
+        c = B.dd_uot_default_config(n1=n, n2=n, h=1.0 / n, eps=w["eps_h2"] / n ** 2, lam=w["lam"],
+                                    cell=w["cell"], precision=prec, init=B.INIT_BLOCK,
+                                    sinkhorn_max_iter=100, box_cap=32,
+                                    getweights=B.GW_STAGGERED)
+        h = B.dd_uot_init_moved(c, mu, nu, y)
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = B.dd_uot_iterate(h, halves)
+            torch.cuda.synchronize()
+            tf = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            s = B.dd_uot_score(h, 0)
+            dmu, dnu = B.dd_uot_backward(h, 0, n, n)
+            dy = B.dd_uot_backward_ypos(h, 0, n, n)
+            tb = time.perf_counter() - t0
+        finally:
+            B.dd_uot_destroy(h)
+        grads[prec] = (dmu, dnu, dy)
+        out[f"fp{prec}"] = {"forward_ms": 1e3 * tf, "forward_value": st["point_iters"] / tf,
+                            "backward_ms": 1e3 * tb, "certificate_gap": s["rel_pd_gap"],
+                            "dd_plan_gap": (s["tracked"] - s["dual"]) / abs(s["dual"])}
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    out["grad_fp32_vs_fp64"] = {"dmu": rel(grads[32][0], grads[64][0]),
+                                "dnu": rel(grads[32][1], grads[64][1]),
+                                "dypos": rel(grads[32][2], grads[64][2])}
+    out["half_iters"] = halves
+    out["unit"] = "grid-pts*iters/s"
+    progress(f"differentiable form: forward FP32 {out['fp32']['forward_ms']:.0f} ms, backward "
+             f"{out['fp32']['backward_ms']:.0f} ms")
+    return out
+
+
 def copy_probe(mib):
     """One plain device copy of `mib` MiB (a reference dispatch of known HBM
     traffic for the profiler's FETCH_SIZE / WRITE_SIZE counters)."""
@@ -267,6 +360,9 @@ def run(args):
                         args.ttg_max32 if prec == 32 else args.ttg_max64, targets,
                         stream.cuda_stream, args.ms_err)
             for name in args.ttg_workloads.split(",") for prec in (32, 64)]
+    if args.forms:
+        out["batched_form"] = batched_form(args.steps, args.warmup)
+        out["differentiable_form"] = differentiable_form(args.steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.max_inner, args.cap, args.cpu_budget)
         progress("CPU oracle sample timed")
@@ -289,6 +385,8 @@ def main():
                     help="1: also time the steps after the multiscale warm start")
     ap.add_argument("--levels", type=int, default=7)
     ap.add_argument("--ttg", type=int, default=1, help="1: also measure time to gap (FP32, FP64)")
+    ap.add_argument("--forms", type=int, default=1,
+                    help="1: also time the batched and the differentiable workloads")
     ap.add_argument("--ms-err", type=float, default=2e-5,
                     help="cell tolerance Err of the multiscale runs")
     ap.add_argument("--ms-max-inner", type=int, default=1000)

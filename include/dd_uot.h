@@ -125,7 +125,9 @@ typedef struct {
 void dd_uot_default_config(dduot_config* cfg);
 
 /* Create a solver for one problem.  mu, nu: host, n1*n2 each, every entry
-   finite and > 0 (Assumption full support, Sec. 3.2) else DDUOT_EINVAL.
+   finite and > 0 (Assumption full support, Sec. 3.2), each total below 1024
+   (the aggregation of the basic-cell marginals sums in fixed point, so its
+   results do not depend on the order of the adds), else DDUOT_EINVAL.
    hip_stream: a hipStream_t or NULL.  The start plan is cfg->init. */
 int dd_uot_init(const dduot_config* cfg, const double* mu, const double* nu,
                 void* hip_stream, dduot_handle** out);

@@ -18,14 +18,15 @@ hipError_t set_cell_lds_limit(size_t bytes);
 size_t cell_lds_bytes(int lcap, int cap, int precision, bool moved);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st);
 hipError_t launch_aggregate(const Box* box, const double* vals, long cap2, const int* basic_prob,
-                            const Prob* probs, double* P, int nbasic, hipStream_t st);
+                            const Prob* probs, unsigned long long* acc, double* P, int nbasic,
+                            long ngrid, hipStream_t st);
 hipError_t launch_kl_chunks(const int* cp, const int* cs, const int* cl, const Prob* probs,
                             const double* P, const double* Pg, const double* nu, double* part,
                             int nchunk, hipStream_t st);
 hipError_t launch_getweights(const Dev& d, int part, int blo, int bhi, int glo, int ghi, bool last,
                              int nprob, hipStream_t st);
 hipError_t launch_aggregate_sel(const Dev& d, int part, int glo, int ghi, double* P, int nbasic,
-                                hipStream_t st);
+                                long ngrid, hipStream_t st);
 hipError_t launch_advance(long long* kstep, hipStream_t st);
 hipError_t launch_mix(const Dev& d, int part, int glo, int ghi, int nbasic, int cap, hipStream_t st);
 hipError_t set_mix_lds_limit(size_t bytes);
@@ -116,6 +117,7 @@ struct dduot_handle {
   int* d_basic_prob = nullptr;
   int2* d_basic_xy = nullptr;
   int* d_basic_cell[2] = {nullptr, nullptr};
+  unsigned long long* d_fx = nullptr;   // fixed-point sums of the aggregation
   double *d_mu = nullptr, *d_nu = nullptr, *d_P = nullptr, *d_Pg = nullptr, *d_px = nullptr,
          *d_pxc = nullptr, *d_abar = nullptr;
   Box *d_box = nullptr, *d_cbox = nullptr;
@@ -219,10 +221,16 @@ static int validate(const dduot_config* c, const double* mu, const double* nu, i
   if (c->init == DDUOT_INIT_PRODUCT && (c->box_cap < c->n1 || c->box_cap < c->n2))
     return fail(DDUOT_EINVAL, pre + "product start needs box_cap >= grid side");
   const long n = (long)c->n1 * c->n2;
+  double sm = 0.0, sn = 0.0;
   for (long i = 0; i < n; ++i) {
     if (!(mu[i] > 0.0) || !isfinite(mu[i]) || !(nu[i] > 0.0) || !isfinite(nu[i]))
       return fail(DDUOT_EINVAL, pre + "masses must be finite and > 0 (full support)");
+    sm += mu[i];
+    sn += nu[i];
   }
+  // the fixed-point aggregation holds point sums below 2^13
+  if (!(sm < 1024.0) || !(sn < 1024.0))
+    return fail(DDUOT_EINVAL, pre + "total masses must be below 1024 (rescale the problem)");
   return DDUOT_OK;
 }
 
@@ -467,6 +475,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_nu, h->ngrid));
   CHK(dalloc(h, &h->d_P, h->ngrid));
   CHK(dalloc(h, &h->d_Pg, h->ngrid));
+  CHK(dalloc(h, &h->d_fx, 2 * (size_t)h->ngrid));
   CHK(dalloc(h, &h->d_px, h->ngrid));
   CHK(dalloc(h, &h->d_pxc, h->ngrid));
   CHK(dalloc(h, &h->d_abar, h->ngrid));
@@ -588,6 +597,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   d.nu = h->d_nu;
   d.P = h->d_P;
   d.Pg = h->d_Pg;
+  d.fxacc = h->d_fx;
   d.px = h->d_px;
   d.pxc = h->d_pxc;
   d.abar = h->d_abar;
@@ -705,8 +715,8 @@ extern "C" int dd_uot_set_eps(dduot_handle* h, int32_t prob, double eps) {
 static int dd_step(dduot_handle* h, int part, int lo, int n, int blo, int bhi) {
   hipStream_t st = h->stream;
   const Dev& d = h->d;
-  HIPCHK(launch_fill(h->d_P, h->ngrid, 0.0, st));
-  HIPCHK(launch_aggregate(h->d_box, h->d_vals, h->cap2, h->d_basic_prob, h->d_probs, h->d_P, h->nbasic, st));
+  HIPCHK(launch_aggregate(h->d_box, h->d_vals, h->cap2, h->d_basic_prob, h->d_probs, h->d_fx, h->d_P,
+                          h->nbasic, h->ngrid, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->timing) {
     HIPCHK(hipEventCreate(&e0));
@@ -721,8 +731,7 @@ static int dd_step(dduot_handle* h, int part, int lo, int n, int blo, int bhi) {
   }
   // greedy candidate Y-marginal: candidates of the step's basic cells, the
   // state elsewhere
-  HIPCHK(launch_fill(h->d_Pg, h->ngrid, 0.0, st));
-  HIPCHK(launch_aggregate_sel(d, part, lo, lo + n, h->d_Pg, h->nbasic, st));
+  HIPCHK(launch_aggregate_sel(d, part, lo, lo + n, h->d_Pg, h->nbasic, h->ngrid, st));
   HIPCHK(launch_kl_chunks(h->d_chunk_prob, h->d_chunk_start, h->d_chunk_len, h->d_probs, h->d_P,
                           h->d_Pg, h->d_nu, h->d_chunk_part, h->nchunk, st));
   HIPCHK(launch_getweights(d, part, blo, bhi, lo, lo + n, bhi == 4, h->nprob, st));
@@ -796,8 +805,8 @@ extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
   hipStream_t st = h->stream;
   const int part = (int)(h->k % 2);
   const int base = h->boff[part][0];
-  HIPCHK(launch_fill(h->d_P, h->ngrid, 0.0, st));
-  HIPCHK(launch_aggregate(h->d_box, h->d_vals, h->cap2, h->d_basic_prob, h->d_probs, h->d_P, h->nbasic, st));
+  HIPCHK(launch_aggregate(h->d_box, h->d_vals, h->cap2, h->d_basic_prob, h->d_probs, h->d_fx, h->d_P,
+                          h->nbasic, h->ngrid, st));
   const int cand[3] = {64, 128, 256};
   double best = 1e300;
   int pick = 256;
@@ -900,8 +909,8 @@ extern "C" int dd_uot_history(dduot_handle* h, int32_t prob, int32_t max, double
 
 // Re-aggregate the current state into d_P (the state Y-marginal).
 static int refresh_state_marginal(dduot_handle* h) {
-  HIPCHK(launch_fill(h->d_P, h->ngrid, 0.0, h->stream));
-  HIPCHK(launch_aggregate(h->d_box, h->d_vals, h->cap2, h->d_basic_prob, h->d_probs, h->d_P, h->nbasic,
+  HIPCHK(launch_aggregate(h->d_box, h->d_vals, h->cap2, h->d_basic_prob, h->d_probs, h->d_fx, h->d_P,
+                          h->nbasic, h->ngrid,
                           h->stream));
   return DDUOT_OK;
 }

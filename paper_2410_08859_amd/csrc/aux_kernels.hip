@@ -13,29 +13,50 @@ __global__ void k_fill(double* p, long n, double v) {
     p[i] = v;
 }
 
+// Deterministic sums for the aggregation: a value v is added as the
+// fixed-point pair (floor(v 2^50), round(frac(v 2^50) 2^50)) to two 64-bit
+// integer sums per grid point, so the result (exact to 2^-100 absolute) does
+// not depend on the order of the atomic adds.  The pair holds any point sum
+// below 2^13 (masses are limited to 2^10) and 2^13 terms.
+__device__ __forceinline__ void fx_add(unsigned long long* acc, double v) {
+  const double s = v * 0x1p50;
+  const double fh = floor(s);
+  atomicAdd(acc, (unsigned long long)(long long)fh);
+  atomicAdd(acc + 1, (unsigned long long)(long long)rint((s - fh) * 0x1p50));
+}
+
+__global__ void k_fx_zero(unsigned long long* acc, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    acc[i] = 0ull;
+}
+
+__global__ void k_fx_finish(const unsigned long long* acc, double* P, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    P[i] = (double)(long long)acc[2 * i] * 0x1p-50 + (double)(long long)acc[2 * i + 1] * 0x1p-100;
+}
+
 // P_Y pi = sum_i nu_i (Sec. 4.1): one workgroup per basic cell scatters its box.
 __global__ __launch_bounds__(kBlock) void k_aggregate(const Box* box, const double* vals, long cap2,
                                                       const int* basic_prob, const Prob* probs,
-                                                      double* P) {
+                                                      unsigned long long* acc) {
   const int b = blockIdx.x;
   const Box bx = box[b];
   if (bx.l1 <= 0 || bx.l2 <= 0) return;
   const Prob& p = probs[basic_prob[b]];
   const long n = (long)bx.l1 * bx.l2;
   const double* v = vals + b * cap2;
-  double* out = P + p.grid_off;
+  unsigned long long* out = acc + 2 * (long)p.grid_off;
   for (long o = threadIdx.x; o < n; o += kBlock) {
     const int j1 = (int)(o / bx.l2), j2 = (int)(o - (long)j1 * bx.l2);
     const double x = v[o];
-    if (x != 0.0) unsafeAtomicAdd(out + (long)(bx.o1 + j1) * p.n2 + (bx.o2 + j2), x);
+    if (x != 0.0) fx_add(out + 2 * ((long)(bx.o1 + j1) * p.n2 + (bx.o2 + j2)), x);
   }
 }
 
 // Candidate P_Y for GetWeights: the candidate marginal of every basic cell
 // whose composite cell (in partition `part`) lies in [glo, ghi), the state
 // marginal of every other basic cell.
-__global__ __launch_bounds__(kBlock) void k_aggregate_sel(Dev d, int part, int glo, int ghi,
-                                                          double* P) {
+__global__ __launch_bounds__(kBlock) void k_aggregate_sel(Dev d, int part, int glo, int ghi) {
   const int b = blockIdx.x;
   const int J = d.basic_cell[part][b];
   const bool in = J >= glo && J < ghi;
@@ -44,11 +65,11 @@ __global__ __launch_bounds__(kBlock) void k_aggregate_sel(Dev d, int part, int g
   const Prob& p = d.probs[d.basic_prob[b]];
   const long n = (long)bx.l1 * bx.l2;
   const double* v = (in ? d.cand : d.vals) + b * d.cap2;
-  double* out = P + p.grid_off;
+  unsigned long long* out = d.fxacc + 2 * (long)p.grid_off;
   for (long o = threadIdx.x; o < n; o += kBlock) {
     const int j1 = (int)(o / bx.l2), j2 = (int)(o - (long)j1 * bx.l2);
     const double x = v[o];
-    if (x != 0.0) unsafeAtomicAdd(out + (long)(bx.o1 + j1) * p.n2 + (bx.o2 + j2), x);
+    if (x != 0.0) fx_add(out + 2 * ((long)(bx.o1 + j1) * p.n2 + (bx.o2 + j2)), x);
   }
 }
 
@@ -374,18 +395,29 @@ hipError_t launch_fill(double* p, long n, double v, hipStream_t st) {
   return hipGetLastError();
 }
 
+static int grid_blocks(long n) { return (int)min((n + 255) / 256, (long)8192); }
+
+// P over all problems' grids (ngrid points) from the candidate marginals of
+// the cells in [glo, ghi) and the state marginals of every other cell.
 hipError_t launch_aggregate_sel(const Dev& d, int part, int glo, int ghi, double* P, int nbasic,
-                                hipStream_t st) {
-  if (nbasic <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_aggregate_sel, dim3(nbasic), dim3(kBlock), 0, st, d, part, glo, ghi, P);
+                                long ngrid, hipStream_t st) {
+  hipLaunchKernelGGL(k_fx_zero, dim3(grid_blocks(2 * ngrid)), dim3(256), 0, st, d.fxacc, 2 * ngrid);
+  if (nbasic > 0)
+    hipLaunchKernelGGL(k_aggregate_sel, dim3(nbasic), dim3(kBlock), 0, st, d, part, glo, ghi);
+  hipLaunchKernelGGL(k_fx_finish, dim3(grid_blocks(ngrid)), dim3(256), 0, st, d.fxacc, P, ngrid);
   return hipGetLastError();
 }
 
+// P = sum of the state marginals over all problems' grids (ngrid points);
+// acc: 2 * ngrid integers of workspace.
 hipError_t launch_aggregate(const Box* box, const double* vals, long cap2, const int* basic_prob,
-                            const Prob* probs, double* P, int nbasic, hipStream_t st) {
-  if (nbasic <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_aggregate, dim3(nbasic), dim3(kBlock), 0, st, box, vals, cap2, basic_prob,
-                     probs, P);
+                            const Prob* probs, unsigned long long* acc, double* P, int nbasic,
+                            long ngrid, hipStream_t st) {
+  hipLaunchKernelGGL(k_fx_zero, dim3(grid_blocks(2 * ngrid)), dim3(256), 0, st, acc, 2 * ngrid);
+  if (nbasic > 0)
+    hipLaunchKernelGGL(k_aggregate, dim3(nbasic), dim3(kBlock), 0, st, box, vals, cap2, basic_prob,
+                       probs, acc);
+  hipLaunchKernelGGL(k_fx_finish, dim3(grid_blocks(ngrid)), dim3(256), 0, st, acc, P, ngrid);
   return hipGetLastError();
 }
 

@@ -50,6 +50,7 @@ struct Dev {
   const double* mu;           // grids
   const double* nu;
   double* P;                  // aggregated Y-marginal of the state
+  unsigned long long* fxacc;  // 2 per grid point: fixed-point sums of the aggregation
   double* Pg;                 // aggregated Y-marginal of the greedy candidate
   double* px;                 // X-marginal of the state plan
   double* pxc;                // X-marginal of the candidate cell plans

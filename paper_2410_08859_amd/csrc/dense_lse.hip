@@ -13,9 +13,9 @@
 // the bounding box of their positions, so ub_k = vmax_k - ch dist^2(p, box_k)
 // bounds every term of block k.  Per output: the block of largest bound is
 // summed exactly first, giving a lower bound L of the result; then every
-// block with ub_k >= L - T is summed, T = 37 + log(256 * blocks), so the
-// skipped blocks hold less than e^-37 of the result together (below FP64
-// rounding).  One workgroup covers a 16 x 16 block of outputs; a block is
+// block with ub_k >= L - T is summed (relative to a running maximum of its
+// terms), T = 37 + log(256 * blocks), so the skipped blocks hold less than
+// e^-37 of the result together (below FP64 rounding).  One workgroup covers a 16 x 16 block of outputs; a block is
 // staged in LDS when any output of the workgroup needs it.
 #include "dd_types.h"
 
@@ -126,9 +126,12 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const double* v, const dou
       L = mx + log(s0);
     }
   }
-  // 3. every block that can matter, staged in LDS
+  // 3. every block that can matter, staged in LDS.  The terms are summed
+  // relative to a running maximum m (starting at L): a block's actual terms
+  // may lie far below its bound, so another block's terms can exceed L by
+  // more than exp's range.
   const double T = 37.0 + log(256.0 * nbk);
-  double s0 = 0, s1 = 0, s2 = 0;
+  double s0 = 0, s1 = 0, s2 = 0, m = L;
   for (int k = 0; k < nbk; ++k) {
     if (threadIdx.x < 5) sinf[threadIdx.x] = info[5 * (long)k + threadIdx.x];
     __syncthreads();
@@ -151,7 +154,15 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const double* v, const dou
       if (need) {
         for (int a = 0; a < kB * kB; ++a) {
           const double e1 = p1 - sq1[a], e2 = p2 - sq2[a];
-          const double e = exp(sv[a] - ch * (e1 * e1 + e2 * e2) - L);
+          const double t = sv[a] - ch * (e1 * e1 + e2 * e2);
+          if (t > m) {
+            const double r = exp(m - t);
+            s0 *= r;
+            s1 *= r;
+            s2 *= r;
+            m = t;
+          }
+          const double e = exp(t - m);
           s0 += e;
           s1 += e * sq1[a];
           s2 += e * sq2[a];
@@ -161,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_lse(const double* v, const dou
     __syncthreads();
   }
   if (act) {
-    out[go] = L > -INFINITY ? L + log(s0) : -INFINITY;
+    out[go] = L > -INFINITY ? m + log(s0) : -INFINITY;
     if (mom) {
       mom[2 * go] = s0 > 0.0 ? s1 / s0 : 0.0;
       mom[2 * go + 1] = s0 > 0.0 ? s2 / s0 : 0.0;

@@ -74,12 +74,12 @@ def test_batched_matches_single_handles_fp32():
             n = cfgs[k].n1
             pb = B.dd_uot_marginals(hb, k, n, n)
             ps = B.dd_uot_marginals(hs, 0, n, n)
-            # FP64 atomics in the aggregation make the last bit of P_Y depend on
-            # the order of the adds, which FP32 arithmetic amplifies to ~1e-7 per step
+            # the same arithmetic per cell and a deterministic (fixed-point)
+            # aggregation: the batched handle reproduces each single handle
             for a, b in zip(pb, ps):
-                np.testing.assert_allclose(a, b, rtol=0, atol=1e-5 * b.max())
+                np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * b.max())
             np.testing.assert_allclose(B.dd_uot_history(hb, k)[:, :3], B.dd_uot_history(hs, 0)[:, :3],
-                                       rtol=1e-5)
+                                       rtol=1e-12)
     finally:
         B.dd_uot_destroy(hb)
         for hs in singles:
@@ -182,9 +182,8 @@ def test_two_launch_tiers_keep_the_trajectory(precision):
         assert ca == 32 and 1 <= fa <= 32
         B.dd_uot_iterate(ha, 6)
         B.dd_uot_iterate(hb, 6)
-        # FP64: equal to rounding; FP32: the FP64 atomics of the aggregation
-        # change the last bit of P_Y from run to run, which FP32 amplifies
-        tol = 1e-12 if precision == 64 else 1e-5
+        # the same arithmetic in both handles (fixed-point aggregation)
+        tol = 1e-12
         wide = 0
         for k, c in enumerate(cfgs):
             n = c.n1

@@ -159,10 +159,43 @@ def test_autograd_wrapper_with_theta():
         dy = B.dd_uot_backward_ypos(h, 0, n, n)
     finally:
         B.dd_uot_destroy(h)
-    # two separate solves (order-dependent FP64 atomics): agreement to 1e-6
-    assert val.item() == pytest.approx(s["dual"], rel=1e-10)
-    np.testing.assert_allclose(tm.grad.cpu().numpy(), dmu, rtol=1e-6, atol=1e-12)
-    np.testing.assert_allclose(tn.grad.cpu().numpy(), dnu, rtol=1e-6, atol=1e-12)
+    # two separate solves of one problem (deterministic aggregation): equal
+    assert val.item() == pytest.approx(s["dual"], rel=1e-12)
+    np.testing.assert_allclose(tm.grad.cpu().numpy(), dmu, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(tn.grad.cpu().numpy(), dnu, rtol=1e-12, atol=0)
     Bm = displacement_basis(n, th.shape[1])
     dth = np.stack([Bm.T @ dy[..., k] @ Bm for k in range(2)])
-    np.testing.assert_allclose(tt.grad.cpu().numpy(), dth, rtol=1e-6, atol=1e-12 * np.abs(dth).max())
+    np.testing.assert_allclose(tt.grad.cpu().numpy(), dth, rtol=1e-12, atol=1e-14 * np.abs(dth).max())
+
+
+def test_moved_certificate_far_from_the_optimum_matches_the_oracle():
+    # block start, one half-iteration at eps = h^2 on 64 x 64: the potentials
+    # vary by hundreds of eps across a 16 x 16 block, so blocks whose bound
+    # is not the largest hold terms far above the first block's sum (the
+    # pruned dense sums must rescale instead of overflowing)
+    n = 64
+    w = WORKLOADS["grid512"]
+    mu, nu = workload_marginals("grid512", n)
+    y = displaced_points(n, n, 1.0 / n, displacement_theta(53, 1.0 / n))
+    c = cfg(n, 4, eps=w["eps_h2"] / n ** 2, init=B.INIT_BLOCK, box_cap=32, sinkhorn_max_iter=100,
+            getweights=B.GW_STAGGERED)
+    print("[moved] certificate 64^2 after one half-iteration", flush=True)
+    h = B.dd_uot_init_moved(c, mu, nu, y)
+    try:
+        B.dd_uot_iterate(h, 1)
+        s = B.dd_uot_score(h, 0)
+        a, bh = B.dd_uot_potentials(h, 0, n, n)
+        p = dd.make_problem(mu, nu, c.eps, c.lambda_, c.h, 4, ypos=y)
+        ref = dd.certificate(p, a)
+        np.testing.assert_allclose(bh, ref["beta_hat"], rtol=0, atol=1e-12 * np.abs(ref["beta_hat"]).max())
+        assert np.isfinite(s["dual"]) and np.isfinite(s["pd_gap"])
+        assert s["dual"] == pytest.approx(ref["dual"], rel=1e-9)
+        assert s["pd_gap"] == pytest.approx(ref["pd"], rel=1e-9)
+        dy = B.dd_uot_backward_ypos(h, 0, n, n)
+        pi = uot.plan(a, ref["beta_hat"], mu, nu, dd.full_cost(p), c.eps)
+        ys = y.reshape(-1, 2)
+        xs = uot.grid_points(n, n, c.h)
+        want = grad.grad_ypos(pi, xs, ys).reshape(n, n, 2)
+        np.testing.assert_allclose(dy, want, rtol=0, atol=1e-8 * np.abs(want).max())
+    finally:
+        B.dd_uot_destroy(h)
