@@ -50,6 +50,7 @@ them also fixed in the design notes):
      the partition as four batches of non-adjacent cells (parity of the cell
      position), one swift step each, in batch order.
   R10 multiscale refinement (warm start of a finer layer): see `refine`.
+  R12 GetWeights `line` on the tracked score: see `line_weight`.
   R11 global Sinkhorn warm start: the coarse layers are solved by the global
      Sinkhorn iteration (uot.sinkhorn), each warm-started from the previous
      layer's beta (`interpolate_potential`); the plan of the last global
@@ -105,7 +106,7 @@ class Options:
     lenience: float = 0.0      # 0.005 in Sec. 4.4; 0 = strict
     margin: int = 2
     cap: int = 64              # maximal Y-box side
-    getweights: str = "swift"  # greedy | safe | swift | staggered
+    getweights: str = "swift"  # greedy | safe | swift | staggered | line
     translate: bool = False    # dual line search along (alpha + s, beta - s)
 
 
@@ -457,6 +458,32 @@ def staggered_batches(p: Problem, part: str):
     return batches
 
 
+def line_weight(p: Problem, P, Pg, dH: float, n_upd: int) -> float:
+    """GetWeights `line` (Proposition converging-getweights) on the tracked
+    score (reading R12): one weight z for every updated cell, minimising
+        f(z) = sum Hbar + z dH + lam KL((1 - z) P + z Pg | nu)
+    over [1/n, 1] (the mixed pieces are linear in z, the KL term convex).
+    The minimiser is an endpoint or the root of
+        f'(z) = dH + lam sum (Pg - P) log(P_z / nu),
+    found by bracketed root finding."""
+    from scipy.optimize import brentq
+    lo = 1.0 / max(n_upd, 1)
+    D = (Pg - P).ravel()
+    m = D != 0.0
+    D, P0, nu = D[m], P.ravel()[m], p.nu.ravel()[m]
+
+    def fprime(z):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t = D * (np.log(P0 + z * D) - np.log(nu))
+        return dH + p.lam * float(np.sum(t))
+
+    if lo >= 1.0 or fprime(lo) >= 0.0:
+        return lo
+    if fprime(1.0) <= 0.0:
+        return 1.0
+    return float(brentq(fprime, lo, 1.0, xtol=1e-16, rtol=1e-15, maxiter=500))
+
+
 def _dd_step(p: Problem, st: State, cells, part: str, rule: str, opt: Options,
              force: bool) -> dict:
     """One parallel DomDecIter (Algorithm 4) over `cells`, with GetWeights
@@ -484,6 +511,8 @@ def _dd_step(p: Problem, st: State, cells, part: str, rule: str, opt: Options,
         theta = 1.0 / max(n_upd, 1)
     elif rule == "swift":
         theta = 1.0 if e_grd <= e_cur + opt.lenience * abs(e_cur) else 1.0 / max(n_upd, 1)
+    elif rule == "line":
+        theta = line_weight(p, P, Pg, float(htil.sum() - st.hbar.sum()), n_upd)
     else:
         raise ValueError(rule)
 

@@ -119,7 +119,7 @@ def test_global_optimum_is_a_fixed_point_of_the_cell_step():
     np.testing.assert_allclose(st.px, pi.sum(1).reshape(p.mu.shape), rtol=1e-6)
 
 
-@pytest.mark.parametrize("gw", ["swift", "safe"])
+@pytest.mark.parametrize("gw", ["swift", "safe", "line"])
 def test_monotone_scores(gw):
     # Safe decrement proof (Sec. 3.4): with safe weights the exact score of the
     # mixed plan never rises.  The tracked score Ebar (reading R8) bounds E from
@@ -437,3 +437,56 @@ def test_optimal_state_is_a_fixed_point_of_a_dd_half_iteration():
     np.testing.assert_allclose(P, pi.sum(0).reshape(8, 8), rtol=1e-6)
     for (o1, o2, arr), r in zip(st.boxes, ref):
         assert np.abs(arr).sum() == pytest.approx(r.sum(), rel=1e-6)
+
+
+def _mixed_tracked(p, st, cells, res, theta, P, Pg):
+    """Tracked score of the mixture with weight theta (untruncated): the
+    pieces and the aggregated Y-marginal are linear in theta."""
+    hb = st.hbar.copy()
+    for c, r in zip(cells, res):
+        if r is None:
+            continue
+        for b in c["basic"]:
+            hb[b] = (1 - theta) * st.hbar[b] + theta * r["pieces"][b]
+    return float(hb.sum()) + p.lam * uot.kl((1 - theta) * P + theta * Pg, p.nu)
+
+
+def test_line_weight_minimises_the_tracked_score_of_the_mixture():
+    # GetWeights line (Proposition converging-getweights, reading R12): the
+    # weight is the minimiser over [1/n, 1] of the mixture's tracked score, so
+    # it does at least as well as both swift candidates and as any nearby
+    # weight (checked by evaluating the score itself, not its derivative)
+    p = small_problem(16, 2, eps_h2=2.0)
+    st = dd.init_product(p)
+    opt = dd.Options(cap=16, trunc=0.0, err=1e-12, max_iter=3000, margin=2)
+    dd.run(p, st, 1, dd.Options(cap=16, trunc=0.0, err=1e-12, max_iter=3000, margin=2,
+                                getweights="greedy"))
+    found_interior = False
+    for part in ("B", "A", "B"):
+        cells = dd.composite_cells(p, part)
+        P = dd.aggregate(p, st.boxes)
+        res = [dd.process_cell(p, c, st.boxes, P, opt) for c in cells]
+        cand = list(st.boxes)
+        for c, r in zip(cells, res):
+            if r is None:
+                continue
+            for b in c["basic"]:
+                cand[b] = dd.truncate_to_box(r["box"][0], r["box"][1], r["cand"][b], 0.0)
+        Pg = dd.aggregate(p, cand)
+        n = sum(r is not None for r in res)
+        dH = sum(r["pieces"][b] - st.hbar[b] for c, r in zip(cells, res) if r is not None
+                 for b in c["basic"])
+        z = dd.line_weight(p, P, Pg, dH, n)
+        assert 1.0 / n <= z <= 1.0
+        f = lambda th: _mixed_tracked(p, st, cells, res, th, P, Pg)
+        fz = f(z)
+        assert fz <= f(1.0 / n) + 1e-13 * abs(fz) and fz <= f(1.0) + 1e-13 * abs(fz)
+        if 1.0 / n < z < 1.0:
+            found_interior = True
+            for dz in (1e-3, 1e-5):
+                assert fz <= f(min(z + dz, 1.0)) + 1e-13 * abs(fz)
+                assert fz <= f(max(z - dz, 1.0 / n)) + 1e-13 * abs(fz)
+        dd.half_iteration(p, st, part, dd.Options(cap=16, trunc=0.0, err=1e-12, max_iter=3000,
+                                                   margin=2, getweights="line"))
+        assert st.history[-1]["theta"] == pytest.approx(z, rel=1e-12)
+    assert found_interior
