@@ -47,8 +47,17 @@ enum {
 /* GetWeights (Sec. 3.4): greedy theta = 1, safe theta = 1/(cells updated),
    swift = greedy if the tracked score rises by at most lenience*|score| else
    safe, staggered = every partition in four batches of non-adjacent cells
-   (parity of the cell position), one swift step per batch in turn. */
-enum { DDUOT_GW_GREEDY = 0, DDUOT_GW_SAFE = 1, DDUOT_GW_SWIFT = 2, DDUOT_GW_STAGGERED = 3 };
+   (parity of the cell position), one swift step per batch in turn, line =
+   the one weight in [1/(cells updated), 1] for every cell that minimises
+   the tracked score of the mixture (Proposition converging-getweights,
+   item line; the pieces are linear in the weight and the KL term convex). */
+enum {
+  DDUOT_GW_GREEDY = 0,
+  DDUOT_GW_SAFE = 1,
+  DDUOT_GW_SWIFT = 2,
+  DDUOT_GW_STAGGERED = 3,
+  DDUOT_GW_LINE = 4
+};
 enum { DDUOT_INIT_BLOCK = 0, DDUOT_INIT_PRODUCT = 1 };
 
 typedef struct dduot_handle dduot_handle;

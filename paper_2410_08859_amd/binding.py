@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdd_uot.so")
 
 OK, EINVAL, ENOMEM, EHIP, ESLOT, ESTATE = 0, -1, -2, -3, -4, -5
-GW_GREEDY, GW_SAFE, GW_SWIFT, GW_STAGGERED = 0, 1, 2, 3
+GW_GREEDY, GW_SAFE, GW_SWIFT, GW_STAGGERED, GW_LINE = 0, 1, 2, 3, 4
 INIT_BLOCK, INIT_PRODUCT = 0, 1
 HIST_FIELDS = ("theta", "e_cur", "e_greedy", "n_updated", "point_iters", "max_inner",
                "n_unconverged", "n_overflow", "inner_iters", "algo_bytes", "lse_terms",

@@ -205,7 +205,7 @@ static int validate(const dduot_config* c, const double* mu, const double* nu, i
   if (!(c->h >= 0.0) || !isfinite(c->h)) return fail(DDUOT_EINVAL, pre + "h must be >= 0");
   if (c->precision != 32 && c->precision != 64)
     return fail(DDUOT_EINVAL, pre + "precision must be 32 or 64");
-  if (c->getweights < 0 || c->getweights > 3) return fail(DDUOT_EINVAL, pre + "bad getweights");
+  if (c->getweights < 0 || c->getweights > 4) return fail(DDUOT_EINVAL, pre + "bad getweights");
   if (c->init != DDUOT_INIT_BLOCK && c->init != DDUOT_INIT_PRODUCT)
     return fail(DDUOT_EINVAL, pre + "bad init");
   if (!(c->sinkhorn_err >= 0.0)) return fail(DDUOT_EINVAL, pre + "sinkhorn_err must be >= 0");

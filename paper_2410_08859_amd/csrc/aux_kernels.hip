@@ -124,7 +124,13 @@ __global__ __launch_bounds__(kBlock) void k_kl_chunks(const int* chunk_prob, con
 // GetWeights (Proposition converging-getweights) with tracked scores:
 // E_cur = sum Hbar + lam KL(P|nu), E_greedy = sum Htil + lam KL(Pg|nu);
 // greedy theta = 1, safe theta = 1/n (n = cells updated), swift = greedy iff
-// E_greedy <= E_cur + lenience |E_cur|.  One workgroup per problem.
+// E_greedy <= E_cur + lenience |E_cur|; line = the minimiser over [1/n, 1] of
+// f(z) = E_cur + z dH + lam (KL(P_z|nu) - KL(P|nu)), P_z = (1 - z) P + z Pg,
+// dH = sum (Htil - Hbar): an endpoint or the root of
+// f'(z) = dH + lam sum (Pg - P) log(P_z / nu), by Newton steps on f' (f'' =
+// lam sum (Pg - P)^2 / P_z > 0) kept inside a bisection bracket, every sum a
+// reduction of the workgroup over the problem's grid.  One workgroup per
+// problem.
 __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int blo, int bhi, int glo,
                                                        int ghi, int last) {
   const long long rec = d.kstep[0];
@@ -167,6 +173,54 @@ __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int blo,
   for (int o = 32; o > 0; o >>= 1) maxit = max(maxit, __shfl_down(maxit, o, 64));
   if ((threadIdx.x & 63) == 0) mred[threadIdx.x >> 6] = maxit;
   __syncthreads();
+  const double n = acc[2] > 0.0 ? acc[2] : 1.0;
+  double zline = 1.0;
+  if (p.getweights == 4 && !d.force_greedy[pi]) {
+    // line: every thread runs the same root search on workgroup-wide sums
+    const double* P = d.P + p.grid_off;
+    const double* Pg = d.Pg + p.grid_off;
+    const double* nu = d.nu + p.grid_off;
+    const long ng = (long)p.n1 * p.n2;
+    const double dH = acc[1] - acc[0];
+    __shared__ double lred[4 * 2];
+    auto deriv = [&](double z, double& f1, double& f2) {
+      double s[2] = {0.0, 0.0};
+      for (long g = threadIdx.x; g < ng; g += kBlock) {
+        const double P0 = P[g], D = Pg[g] - P0;
+        if (D == 0.0) continue;
+        const double Pz = P0 + z * D;
+        s[0] += D * (log(Pz) - log(nu[g]));
+        s[1] += D * D / Pz;
+      }
+      block_sum_aux<2>(s, lred);
+      f1 = dH + p.lam * s[0];
+      f2 = p.lam * s[1];
+    };
+    const double lo = 1.0 / n;
+    double f1, f2;
+    deriv(lo, f1, f2);
+    if (lo >= 1.0 || f1 >= 0.0) {
+      zline = lo;
+    } else {
+      deriv(1.0, f1, f2);
+      if (f1 <= 0.0) {
+        zline = 1.0;
+      } else {
+        double a = lo, b = 1.0, z = 0.5 * (lo + 1.0);
+        for (int k = 0; k < 200; ++k) {
+          deriv(z, f1, f2);
+          if (f1 == 0.0) break;
+          if (f1 < 0.0) a = z; else b = z;
+          double zn = (f2 > 0.0) ? z - f1 / f2 : 0.5 * (a + b);
+          if (!(zn > a && zn < b)) zn = 0.5 * (a + b);
+          const bool stop = fabs(zn - z) <= 1e-15 * z || b - a <= 1e-15 * b;
+          z = zn;
+          if (stop) break;
+        }
+        zline = z;
+      }
+    }
+  }
   if (threadIdx.x == 0) {
     maxit = max(max(mred[0], mred[1]), max(mred[2], mred[3]));
     double kp = 0.0, kg = 0.0;
@@ -176,10 +230,10 @@ __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int blo,
     }
     const double ecur = acc[0] + p.lam * kp;
     const double egr = acc[1] + p.lam * kg;
-    const double n = acc[2] > 0.0 ? acc[2] : 1.0;
     double th;
     if (d.force_greedy[pi] || p.getweights == 0) th = 1.0;
     else if (p.getweights == 1) th = 1.0 / n;
+    else if (p.getweights == 4) th = zline;
     else th = (egr <= ecur + p.lenience * fabs(ecur)) ? 1.0 : 1.0 / n;
     if (last) d.force_greedy[pi] = 0;   // a forced greedy half-iteration covers every batch
     d.theta[pi] = th;
