@@ -92,7 +92,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not built; run paper_2410_08859_amd/build.py "
-                           "(or __graft_entry__.build())")
+                           "first")
     # One HIP runtime per process: when PyTorch is installed its runtime
     # (same soname) is loaded first, so the library and torch share it.
     try:
