@@ -51,6 +51,7 @@ them also fixed in the design notes):
      position), one swift step each, in batch order.
   R10 multiscale refinement (warm start of a finer layer): see `refine`.
   R12 GetWeights `line` on the tracked score: see `line_weight`.
+  R13 balancing step: see `balance_cell`.
   R11 global Sinkhorn warm start: the coarse layers are solved by the global
      Sinkhorn iteration (uot.sinkhorn), each warm-started from the previous
      layer's beta (`interpolate_potential`); the plan of the last global
@@ -108,6 +109,7 @@ class Options:
     cap: int = 64              # maximal Y-box side
     getweights: str = "swift"  # greedy | safe | swift | staggered | line
     translate: bool = False    # dual line search along (alpha + s, beta - s)
+    balance: bool = False      # balancing step of Sec. 4.1 (reading R13)
 
 
 def make_problem(mu, nu, eps, lam, h, s1, s2=None, ypos=None) -> Problem:
@@ -388,6 +390,45 @@ def cell_inputs(p: Problem, cell, box, boxes, P):
     return r.ravel(), beta0.ravel()
 
 
+def balance_cell(p: Problem, cell, sol, pi, mu_x, nu_y, C, rows_of):
+    """Balancing step (Sec. 4.1 "Balancing", reading R13).  One more X-half
+    of the final beta gives mubar = e^{-alpha'/lam} mu; basic cell i should
+    carry m_i = mubar(X_i) |nu_J| / mubar(X_J).  Mass moves horizontally
+    (same y) inside the cell: every donor (|nu_i| > m_i) keeps the fraction
+    m_i / |nu_i| of its plan, the removed profile R(y) = sum of the donors'
+    (1 - m_i/|nu_i|) nu_i(y) goes to the receivers in proportion to their
+    deficits, and a receiver spreads what it gets at y over its rows like
+    its own plan column, i.e. with the cell kernel e^{(alpha(x) - c)/eps}
+    mu(x) restricted to X_j and normalised.  nu_J stays unchanged."""
+    a2 = uot.x_update(sol["beta"], nu_y, C, p.eps, p.lam)
+    mubar = np.exp(-a2 / p.lam) * mu_x
+    basics = cell["basic"]
+    M = {b: pi[rows_of[b]].sum() for b in basics}
+    tot = sum(M.values())
+    mtot = mubar.sum()
+    if not (tot > 0.0 and mtot > 0.0):
+        return pi
+    m = {b: mubar[rows_of[b]].sum() * tot / mtot for b in basics}
+    e = {b: M[b] - m[b] for b in basics}
+    E = sum(v for v in e.values() if v > 0.0)
+    if not (E > 0.0):
+        return pi
+    pi = pi.copy()
+    R = np.zeros(pi.shape[1])
+    for b in basics:
+        if e[b] > 0.0:
+            R += (e[b] / M[b]) * pi[rows_of[b]].sum(0)
+            pi[rows_of[b]] *= m[b] / M[b]
+    for b in basics:
+        if e[b] < 0.0:
+            rows = rows_of[b]
+            lk = (sol["alpha"][rows][:, None] - C[rows]) / p.eps + np.log(mu_x[rows])[:, None]
+            lk -= lk.max(0)[None, :]
+            k = np.exp(lk)
+            pi[rows] += (-e[b] / E) * R[None, :] * k / k.sum(0)[None, :]
+    return pi
+
+
 def process_cell(p: Problem, cell, boxes, P, opt: Options):
     """Solve one composite cell and re-split its plan into basic cells.
 
@@ -409,9 +450,11 @@ def process_cell(p: Problem, cell, boxes, P, opt: Options):
     pi = uot.plan(sol["alpha"], sol["beta"], mu_x, nu_y, C, p.eps)
     nu_tot = p.nu.sum()
     cand, pieces = {}, {}
+    rows_of = {b: np.isin(xi, rect_index(basic_rect(p, b), p.n2)) for b in cell["basic"]}
+    if opt.balance and len(cell["basic"]) > 1:
+        pi = balance_cell(p, cell, sol, pi, mu_x, nu_y, C, rows_of)
     for b in cell["basic"]:
-        brect = basic_rect(p, b)
-        rows = np.isin(xi, rect_index(brect, p.n2))
+        rows = rows_of[b]
         pib = pi[rows]
         nut = pib.sum(0).reshape(box[2], box[3])
         pieces[b] = cell_piece(pib, mu_x[rows], nu_y, nu_tot, C[rows], p.eps, p.lam)

@@ -490,3 +490,45 @@ def test_line_weight_minimises_the_tracked_score_of_the_mixture():
                                                    margin=2, getweights="line"))
         assert st.history[-1]["theta"] == pytest.approx(z, rel=1e-12)
     assert found_interior
+
+
+def test_balancing_moves_mass_horizontally_to_the_targets():
+    # Sec. 4.1 "Balancing" (reading R13): nu_J is kept pointwise, every basic
+    # cell ends with m_i = mubar(X_i) |nu_J| / mubar(X_J), where mubar is the
+    # X-marginal after one more X-half, and a receiver's column at y is its
+    # kernel column e^{(alpha - c)/eps} mu restricted to its rows, rescaled
+    p = small_problem(16, 2, eps_h2=1.0)
+    st = dd.init_block(p)
+    P = dd.aggregate(p, st.boxes)
+    # a solve stopped early leaves P_X away from mubar, so there is mass to move
+    opt = dd.Options(cap=16, trunc=0.0, err=1e-10, max_iter=3, margin=2, translate=True)
+    cell = dd.composite_cells(p, "A")[5]
+    plain = dd.process_cell(p, cell, st.boxes, P, opt)
+    opt.balance = True
+    bal = dd.process_cell(p, cell, st.boxes, P, opt)
+    basics = cell["basic"]
+    tot = sum(plain["cand"][b].sum() for b in basics)
+    np.testing.assert_allclose(sum(bal["cand"][b] for b in basics),
+                               sum(plain["cand"][b] for b in basics), rtol=1e-12, atol=1e-300)
+    C = dd.rect_cost(p, cell["rect"], plain["box"])
+    mu_x = p.mu.ravel()[plain["xi"]]
+    nu_y = p.nu.ravel()[plain["yi"]]
+    a2 = uot.x_update(plain["beta"], nu_y, C, p.eps, p.lam)
+    mubar = np.exp(-a2 / p.lam) * mu_x
+    moved = False
+    for b in basics:
+        rows = np.isin(plain["xi"], dd.rect_index(dd.basic_rect(p, b), p.n2))
+        target = mubar[rows].sum() * tot / mubar.sum()
+        assert bal["cand"][b].sum() == pytest.approx(target, rel=1e-11)
+        moved |= abs(plain["cand"][b].sum() - target) > 1e-6 * target
+        gain = (bal["pi"][rows] - plain["pi"][rows]).sum(0)
+        if np.all(gain >= 0) and gain.sum() > 0:
+            # receiver: the added mass follows the kernel column of its rows
+            lk = (plain["alpha"][rows][:, None] - C[rows]) / p.eps + np.log(mu_x[rows])[:, None]
+            k = np.exp(lk - lk.max(0)[None, :])
+            np.testing.assert_allclose(bal["pi"][rows] - plain["pi"][rows],
+                                       gain[None, :] * k / k.sum(0)[None, :], rtol=1e-9,
+                                       atol=1e-14 * plain["pi"][rows].max())
+        # P_X and the pieces follow the balanced plan
+        np.testing.assert_allclose(bal["px"][rows], bal["pi"][rows].sum(1), rtol=1e-12)
+    assert moved
