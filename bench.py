@@ -43,6 +43,8 @@ EXP_PEAK = 256 * 64 * 2.4e9 / 4.0
 HBM_PEAK = 8.0e12
 
 
+GW_NAMES = {B.GW_GREEDY: "greedy", B.GW_SAFE: "safe", B.GW_SWIFT: "swift",
+            B.GW_STAGGERED: "staggered", B.GW_LINE: "line"}
 PROFILE = os.path.join(ROOT, "profiles", "k_cell_solve_grid1024_fp32_block.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2410_08859_amd", "csrc", "cell_kernel.hip")
 PROFILED = dict(workload="grid1024", precision=32, cap=48, start="block", steps=4, warmup=1,
@@ -69,7 +71,7 @@ def multiscale_params(levels, final_max, target, check_every=4):
                                        check_every=check_every, target_rel_gap=target)
 
 
-def time_to_gap(name, precision, max_inner, cap, final_max, targets, stream, err):
+def time_to_gap(name, precision, max_inner, cap, final_max, targets, stream, err, getweights):
     # strict GetWeights on every layer: with the paper's lenience the tracked
     # score drifts up by up to 0.5 % per step and the gap stalls far higher
     """Wall time of the whole multiscale solve (host marginals in, certificate
@@ -79,6 +81,7 @@ def time_to_gap(name, precision, max_inner, cap, final_max, targets, stream, err
     mu, nu = workload_marginals(name)
     cfg = workload_config(name, precision, max_inner, cap, err)
     cfg.lenience = 0.0
+    cfg.getweights = getweights
     levels = int(round(np.log2(cfg.n1 / 16))) + 1
     ms = multiscale_params(levels, final_max, min(targets))
     h, tr = B.dd_uot_solve_multiscale(cfg, ms, mu, nu, stream=stream)
@@ -93,7 +96,8 @@ def time_to_gap(name, precision, max_inner, cap, final_max, targets, stream, err
             out[f"{t:g}"] = None if hit.size == 0 else {"ms": float(tr[hit[0], 1]),
                                                         "half_iters": int(tr[hit[0], 0])}
         return out
-    return {"workload": name, "precision": precision, "dd_plan_gap": reached(3),
+    return {"workload": name, "precision": precision, "getweights": GW_NAMES[getweights],
+            "dd_plan_gap": reached(3),
             "certificate_gap": reached(2),
             "final": {"certificate_gap": float(tr[-1, 2]), "dd_plan_gap": float(tr[-1, 3]),
                       "ms": float(tr[-1, 1]), "half_iters": int(tr[-1, 0])},
@@ -102,7 +106,7 @@ def time_to_gap(name, precision, max_inner, cap, final_max, targets, stream, err
                         f"finest), DD 4-16 half-iterations per stage (to rel. gap 1e-3), coarser DD "
                         f"layers box cap {ms.coarse_box_cap} and lenience {ms.coarse_lenience:g}, "
                         f"then at most {final_max} half-iterations with a certificate every 4; "
-                        f"staggered GetWeights with lenience 0, box cap {cap}, cell Err {err:g}, "
+                        f"GetWeights {GW_NAMES[getweights]} (lenience 0), box cap {cap}, cell Err {err:g}, "
                         f"at most {max_inner} inner iterations"}
 
 
@@ -358,7 +362,8 @@ def run(args):
         out["time_to_gap"] = [
             time_to_gap(name, prec, args.ms_max_inner, args.ttg_cap,
                         args.ttg_max32 if prec == 32 else args.ttg_max64, targets,
-                        stream.cuda_stream, args.ms_err)
+                        stream.cuda_stream, args.ms_err,
+                        {v: k for k, v in GW_NAMES.items()}[args.ttg_getweights])
             for name in args.ttg_workloads.split(",") for prec in (32, 64)]
     if args.forms:
         out["batched_form"] = batched_form(args.steps, args.warmup)
@@ -392,6 +397,8 @@ def main():
     ap.add_argument("--ms-max-inner", type=int, default=1000)
     ap.add_argument("--ttg-workloads", default="grid256")
     ap.add_argument("--ttg-cap", type=int, default=80)
+    ap.add_argument("--ttg-getweights", default="line", choices=("swift", "staggered", "line"),
+                    help="GetWeights of the time-to-gap runs (line: the fastest decrement)")
     ap.add_argument("--ttg-max32", type=int, default=64)
     ap.add_argument("--ttg-max64", type=int, default=64)
     ap.add_argument("--copy-probe", type=int, default=0,
