@@ -8,7 +8,8 @@ grid points times inner Sinkhorn iterations: sum over solved cells of
 |X_J| * (Y-halves of that cell), divided by the wall time of the timed steps.
 
 The headline steps start from the local block start (nu_i = nu on block i),
-where every cell's Y-box fits the slot and every cell is solved.  With
+where every cell's Y-box fits the slot and every cell is solved; GetWeights
+`line` (one launch over every cell of the partition per step).  With
 --warm 1 the same steps are also timed on the finest layer after the
 multiscale warm start (untimed).  Time to a relative primal-dual gap is
 measured separately (--ttg): the whole multiscale solve, FP32 and FP64, from
@@ -48,7 +49,7 @@ GW_NAMES = {B.GW_GREEDY: "greedy", B.GW_SAFE: "safe", B.GW_SWIFT: "swift",
 PROFILE = os.path.join(ROOT, "profiles", "k_cell_solve_grid1024_fp32_block.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2410_08859_amd", "csrc", "cell_kernel.hip")
 PROFILED = dict(workload="grid1024", precision=32, cap=48, start="block", steps=4, warmup=1,
-                max_inner=100)
+                max_inner=100, getweights="line")
 
 
 def profiled_traffic(args):
@@ -135,12 +136,13 @@ def timed_steps(h, steps, warmup):
                 score=B.dd_uot_score(h, 0))
 
 
-def workload_config(name, precision, max_inner, cap, err=2e-5):
+def workload_config(name, precision, max_inner, cap, err=2e-5, getweights=None):
     w = WORKLOADS[name]
     n = w["n"]
     return B.dd_uot_default_config(
         n1=n, n2=n, h=1.0 / n, eps=w["eps_h2"] / n ** 2, lam=w["lam"], cell=w["cell"],
-        precision=precision, init=B.INIT_BLOCK, getweights=B.GW_STAGGERED,
+        precision=precision, init=B.INIT_BLOCK,
+        getweights=B.GW_LINE if getweights is None else getweights,
         sinkhorn_err=err, sinkhorn_max_iter=max_inner, trunc=1e-15, lenience=0.005,
         box_margin=2, box_cap=cap)
 
@@ -285,7 +287,8 @@ def run(args):
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
     mu, nu = workload_marginals(args.workload)
-    cfg = workload_config(args.workload, args.precision, args.max_inner, args.cap)
+    gw = {v: k for k, v in GW_NAMES.items()}[args.getweights]
+    cfg = workload_config(args.workload, args.precision, args.max_inner, args.cap, getweights=gw)
     stream = torch.cuda.current_stream(dev)
     if args.start == "multiscale":
         # untimed warm start: coarse layers and the eps stages of the finest
@@ -320,7 +323,7 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": args.workload, "n": cfg.n1, "cell": cfg.cell, "lambda": cfg.lambda_,
                    "eps": cfg.eps, "precision": args.precision, "max_inner": args.max_inner,
-                   "box_cap": cfg.box_cap, "start": args.start,
+                   "box_cap": cfg.box_cap, "start": args.start, "getweights": args.getweights,
                    "levels": args.levels if args.start == "multiscale" else 1},
         "roofline": {"bound": "alu", "achieved": exp_rate / 1e12, "peak": EXP_PEAK / 1e12,
                      "unit": "Texp/s", "frac": exp_rate / EXP_PEAK,
@@ -340,7 +343,7 @@ def run(args):
     if args.warm and args.start != "multiscale":
         # the same steps after the multiscale warm start (the paper's pipeline)
         wcfg = workload_config(args.workload, args.precision, args.ms_max_inner, args.cap,
-                               args.ms_err)
+                               args.ms_err, gw)
         h, _ = B.dd_uot_solve_multiscale(wcfg, multiscale_params(args.levels, 0, 0.0), mu, nu,
                                          stream=stream.cuda_stream)
         try:
@@ -382,6 +385,8 @@ def main():
     ap.add_argument("--workload", default="grid1024", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
     ap.add_argument("--max-inner", type=int, default=100)
+    ap.add_argument("--getweights", default="line", choices=("swift", "staggered", "line"),
+                    help="GetWeights of the timed steps")
     ap.add_argument("--cap", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)

@@ -28,6 +28,9 @@ hipError_t launch_getweights(const Dev& d, int part, int blo, int bhi, int glo, 
 hipError_t launch_aggregate_sel(const Dev& d, int part, int glo, int ghi, double* P, int nbasic,
                                 long ngrid, hipStream_t st);
 hipError_t launch_advance(long long* kstep, hipStream_t st);
+hipError_t launch_line_search(const Dev& d, const int* chunk_prob, const int* chunk_start,
+                              const int* chunk_len, int nchunk, int nprob, int rounds,
+                              hipStream_t st);
 hipError_t launch_mix(const Dev& d, int part, int glo, int ghi, int nbasic, int cap, hipStream_t st);
 hipError_t set_mix_lds_limit(size_t bytes);
 hipError_t launch_certificate(const Prob& p, const double* alpha, const double* mu, const double* nu,
@@ -88,6 +91,7 @@ static int fail(int code, const std::string& msg) {
   } while (0)
 
 static const int kChunk = 16384;
+static const int kLineRounds = 40;   // GetWeights line: f' evaluations per step, at most
 static const int kCertBlocks = 1024;
 
 struct dduot_handle {
@@ -102,6 +106,7 @@ struct dduot_handle {
   int ncell[2] = {0, 0};
   int boff[2][4] = {}, bn[2][4] = {};   // staggered batches: global cell ranges
   bool staggered = false;
+  bool any_line = false;                 // some problem uses GetWeights line
   long long nrec = 0;                    // history records written (steps of batches)
   int nbasic = 0;
   long ngrid = 0;
@@ -140,6 +145,7 @@ struct dduot_handle {
   int *d_chunk_prob = nullptr, *d_chunk_start = nullptr, *d_chunk_len = nullptr;
   double* d_chunk_part = nullptr;
   double *d_theta = nullptr, *d_hist = nullptr;
+  double *d_line = nullptr, *d_line_part = nullptr;   // GetWeights line search state
   int *d_overflow = nullptr, *d_force = nullptr;
   double *d_bhat = nullptr, *d_dmu = nullptr, *d_dnu = nullptr, *d_scratch = nullptr,
          *d_cpart = nullptr;
@@ -278,6 +284,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   }
   h->cap2 = (long)h->cap * h->cap;
   h->staggered = cfgs[0].getweights == DDUOT_GW_STAGGERED;
+  for (int k = 0; k < nprob; ++k) h->any_line |= cfgs[k].getweights == DDUOT_GW_LINE;
   for (int k = 0; k < nprob; ++k)
     if ((cfgs[k].getweights == DDUOT_GW_STAGGERED) != h->staggered)
       return fail(DDUOT_EINVAL, "staggered GetWeights: all problems of a handle or none");
@@ -500,7 +507,9 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_chunk_start, h->nchunk));
   CHK(dalloc(h, &h->d_chunk_len, h->nchunk));
   CHK(dalloc(h, &h->d_chunk_part, 2 * (size_t)h->nchunk));
+  CHK(dalloc(h, &h->d_line_part, 2 * (size_t)h->nchunk));
   CHK(dalloc(h, &h->d_theta, nprob));
+  CHK(dalloc(h, &h->d_line, 8 * (size_t)nprob));
   CHK(dalloc(h, &h->d_hist, (size_t)nprob * h->hist_cap * kHistFields));
   CHK(dalloc(h, &h->d_overflow, nprob));
   CHK(dalloc(h, &h->d_force, nprob));
@@ -618,6 +627,8 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   d.kstep = h->d_kstep;
   d.chunk_part = h->d_chunk_part;
   d.theta = h->d_theta;
+  d.line = h->d_line;
+  d.line_part = h->d_line_part;
   d.hist = h->d_hist;
   d.overflow_any = h->d_overflow;
   d.force_greedy = h->d_force;
@@ -735,6 +746,9 @@ static int dd_step(dduot_handle* h, int part, int lo, int n, int blo, int bhi) {
   HIPCHK(launch_kl_chunks(h->d_chunk_prob, h->d_chunk_start, h->d_chunk_len, h->d_probs, h->d_P,
                           h->d_Pg, h->d_nu, h->d_chunk_part, h->nchunk, st));
   HIPCHK(launch_getweights(d, part, blo, bhi, lo, lo + n, bhi == 4, h->nprob, st));
+  if (h->any_line)
+    HIPCHK(launch_line_search(d, h->d_chunk_prob, h->d_chunk_start, h->d_chunk_len, h->nchunk,
+                              h->nprob, kLineRounds, st));
   HIPCHK(launch_mix(d, part, lo, lo + n, h->nbasic, h->cap, st));
   HIPCHK(launch_advance(h->d_kstep, st));
   h->nrec += 1;

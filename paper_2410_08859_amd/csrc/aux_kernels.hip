@@ -124,13 +124,8 @@ __global__ __launch_bounds__(kBlock) void k_kl_chunks(const int* chunk_prob, con
 // GetWeights (Proposition converging-getweights) with tracked scores:
 // E_cur = sum Hbar + lam KL(P|nu), E_greedy = sum Htil + lam KL(Pg|nu);
 // greedy theta = 1, safe theta = 1/n (n = cells updated), swift = greedy iff
-// E_greedy <= E_cur + lenience |E_cur|; line = the minimiser over [1/n, 1] of
-// f(z) = E_cur + z dH + lam (KL(P_z|nu) - KL(P|nu)), P_z = (1 - z) P + z Pg,
-// dH = sum (Htil - Hbar): an endpoint or the root of
-// f'(z) = dH + lam sum (Pg - P) log(P_z / nu), by Newton steps on f' (f'' =
-// lam sum (Pg - P)^2 / P_z > 0) kept inside a bisection bracket, every sum a
-// reduction of the workgroup over the problem's grid.  One workgroup per
-// problem.
+// E_greedy <= E_cur + lenience |E_cur|; line: set up the search of
+// k_line_partials / k_line_update / k_line_finish.  One workgroup per problem.
 __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int blo, int bhi, int glo,
                                                        int ghi, int last) {
   const long long rec = d.kstep[0];
@@ -174,53 +169,6 @@ __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int blo,
   if ((threadIdx.x & 63) == 0) mred[threadIdx.x >> 6] = maxit;
   __syncthreads();
   const double n = acc[2] > 0.0 ? acc[2] : 1.0;
-  double zline = 1.0;
-  if (p.getweights == 4 && !d.force_greedy[pi]) {
-    // line: every thread runs the same root search on workgroup-wide sums
-    const double* P = d.P + p.grid_off;
-    const double* Pg = d.Pg + p.grid_off;
-    const double* nu = d.nu + p.grid_off;
-    const long ng = (long)p.n1 * p.n2;
-    const double dH = acc[1] - acc[0];
-    __shared__ double lred[4 * 2];
-    auto deriv = [&](double z, double& f1, double& f2) {
-      double s[2] = {0.0, 0.0};
-      for (long g = threadIdx.x; g < ng; g += kBlock) {
-        const double P0 = P[g], D = Pg[g] - P0;
-        if (D == 0.0) continue;
-        const double Pz = P0 + z * D;
-        s[0] += D * (log(Pz) - log(nu[g]));
-        s[1] += D * D / Pz;
-      }
-      block_sum_aux<2>(s, lred);
-      f1 = dH + p.lam * s[0];
-      f2 = p.lam * s[1];
-    };
-    const double lo = 1.0 / n;
-    double f1, f2;
-    deriv(lo, f1, f2);
-    if (lo >= 1.0 || f1 >= 0.0) {
-      zline = lo;
-    } else {
-      deriv(1.0, f1, f2);
-      if (f1 <= 0.0) {
-        zline = 1.0;
-      } else {
-        double a = lo, b = 1.0, z = 0.5 * (lo + 1.0);
-        for (int k = 0; k < 200; ++k) {
-          deriv(z, f1, f2);
-          if (f1 == 0.0) break;
-          if (f1 < 0.0) a = z; else b = z;
-          double zn = (f2 > 0.0) ? z - f1 / f2 : 0.5 * (a + b);
-          if (!(zn > a && zn < b)) zn = 0.5 * (a + b);
-          const bool stop = fabs(zn - z) <= 1e-15 * z || b - a <= 1e-15 * b;
-          z = zn;
-          if (stop) break;
-        }
-        zline = z;
-      }
-    }
-  }
   if (threadIdx.x == 0) {
     maxit = max(max(mred[0], mred[1]), max(mred[2], mred[3]));
     double kp = 0.0, kg = 0.0;
@@ -233,8 +181,19 @@ __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int blo,
     double th;
     if (d.force_greedy[pi] || p.getweights == 0) th = 1.0;
     else if (p.getweights == 1) th = 1.0 / n;
-    else if (p.getweights == 4) th = zline;
+    else if (p.getweights == 4) th = 1.0 / n;   // provisional: the line search sets it
     else th = (egr <= ecur + p.lenience * fabs(ecur)) ? 1.0 : 1.0 / n;
+    // line search state (k_line_*): phase 0 evaluates f' at 1/n, 1 at 1, 2 inside
+    // the bracket, 3 = done
+    double* ls = d.line + 8 * pi;
+    const bool line = p.getweights == 4 && !d.force_greedy[pi];
+    ls[0] = 1.0 / n;
+    ls[1] = 1.0 / n;
+    ls[2] = 1.0;
+    ls[3] = 1.0 / n;
+    ls[4] = acc[1] - acc[0];
+    ls[5] = line ? 0.0 : 3.0;
+    ls[6] = line ? 1.0 : 0.0;
     if (last) d.force_greedy[pi] = 0;   // a forced greedy half-iteration covers every batch
     d.theta[pi] = th;
     double* r = d.hist + ((long)pi * d.hist_cap + (rec % d.hist_cap)) * kHistFields;
@@ -251,6 +210,110 @@ __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int blo,
     r[10] = acc[8];
     r[11] = acc[9];
   }
+}
+
+// GetWeights line: the minimiser over [1/n, 1] of the tracked score of the
+// mixture, f(z) = E_cur + z dH + lam (KL(P_z|nu) - KL(P|nu)), P_z = (1 - z) P
+// + z Pg, dH = sum (Htil - Hbar): an endpoint or the root of
+// f'(z) = dH + lam sum (Pg - P) log(P_z / nu), found by Newton steps on f'
+// (f'' = lam sum (Pg - P)^2 / P_z > 0) kept inside a bisection bracket.
+// Every round sums over all reduction chunks of the grid (one workgroup per
+// chunk, fixed order), then advances each problem's search by one step.
+__global__ __launch_bounds__(kBlock) void k_line_partials(Dev d, const int* chunk_prob,
+                                                          const int* chunk_start,
+                                                          const int* chunk_len) {
+  __shared__ double red[4 * 2];
+  const int c = blockIdx.x;
+  const int pi = chunk_prob[c];
+  const double* ls = d.line + 8 * pi;
+  if (ls[5] == 3.0) return;   // uniform across the workgroup
+  const Prob& p = d.probs[pi];
+  const double z = ls[3];
+  const long base = p.grid_off + chunk_start[c];
+  double s[2] = {0.0, 0.0};
+  for (int o = threadIdx.x; o < chunk_len[c]; o += kBlock) {
+    const double P0 = d.P[base + o], D = d.Pg[base + o] - P0;
+    if (D == 0.0) continue;
+    const double Pz = P0 + z * D;
+    s[0] += D * (log(Pz) - log(d.nu[base + o]));
+    s[1] += D * D / Pz;
+  }
+  block_sum_aux<2>(s, red);
+  if (threadIdx.x == 0) {
+    d.line_part[2 * c] = s[0];
+    d.line_part[2 * c + 1] = s[1];
+  }
+}
+
+__global__ void k_line_update(Dev d) {
+  if (threadIdx.x != 0) return;
+  const int pi = blockIdx.x;
+  double* ls = d.line + 8 * pi;
+  if (ls[5] == 3.0) return;
+  const Prob& p = d.probs[pi];
+  double s0 = 0.0, s1 = 0.0;
+  for (int c = 0; c < p.nchunk; ++c) {
+    s0 += d.line_part[2 * (p.chunk_off + c)];
+    s1 += d.line_part[2 * (p.chunk_off + c) + 1];
+  }
+  const double f1 = ls[4] + p.lam * s0, f2 = p.lam * s1;
+  const double lo = ls[0];
+  if (ls[5] == 0.0) {   // f' at 1/n
+    if (lo >= 1.0 || f1 >= 0.0) {
+      ls[3] = lo;
+      ls[5] = 3.0;
+    } else {
+      ls[3] = 1.0;
+      ls[5] = 1.0;
+    }
+  } else if (ls[5] == 1.0) {   // f' at 1
+    if (f1 <= 0.0) {
+      ls[3] = 1.0;
+      ls[5] = 3.0;
+    } else {
+      ls[1] = lo;
+      ls[2] = 1.0;
+      ls[3] = 0.5 * (lo + 1.0);
+      ls[5] = 2.0;
+    }
+  } else {   // inside the bracket
+    const double z = ls[3];
+    if (f1 == 0.0) {
+      ls[5] = 3.0;
+      return;
+    }
+    double a = ls[1], b = ls[2];
+    if (f1 < 0.0) a = z; else b = z;
+    double zn = f2 > 0.0 ? z - f1 / f2 : 0.5 * (a + b);
+    if (!(zn > a && zn < b)) zn = 0.5 * (a + b);
+    const bool stop = fabs(zn - z) <= 1e-15 * z || b - a <= 1e-15 * b;
+    ls[1] = a;
+    ls[2] = b;
+    ls[3] = zn;
+    if (stop) ls[5] = 3.0;
+  }
+}
+
+__global__ void k_line_finish(Dev d) {
+  if (threadIdx.x != 0) return;
+  const int pi = blockIdx.x;
+  if (d.line[8 * pi + 6] != 1.0) return;   // not searched in this step
+  const double th = d.line[8 * pi + 3];
+  d.theta[pi] = th;
+  const long long rec = d.kstep[0];
+  d.hist[((long)pi * d.hist_cap + (rec % d.hist_cap)) * kHistFields] = th;
+}
+
+hipError_t launch_line_search(const Dev& d, const int* chunk_prob, const int* chunk_start,
+                              const int* chunk_len, int nchunk, int nprob, int rounds,
+                              hipStream_t st) {
+  for (int r = 0; r < rounds; ++r) {
+    hipLaunchKernelGGL(k_line_partials, dim3(nchunk), dim3(kBlock), 0, st, d, chunk_prob,
+                       chunk_start, chunk_len);
+    hipLaunchKernelGGL(k_line_update, dim3(nprob), dim3(64), 0, st, d);
+  }
+  hipLaunchKernelGGL(k_line_finish, dim3(nprob), dim3(64), 0, st, d);
+  return hipGetLastError();
 }
 
 // Algorithm 4 update: nu_i <- (1 - theta) nu_i + theta nu~_i on the cell box,

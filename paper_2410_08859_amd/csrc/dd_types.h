@@ -72,6 +72,8 @@ struct Dev {
   long long* kstep;           // half-iterations done (history record index)
   double* chunk_part;         // 2 doubles per reduction chunk
   double* theta;              // per problem
+  double* line;               // per problem, GetWeights line search: lo, a, b, z, dH, phase, active, -
+  double* line_part;          // 2 doubles per reduction chunk (line search sums)
   double* hist;               // per problem ring of records
   int* overflow_any;          // per problem
   int* force_greedy;          // per problem: next GetWeights takes theta = 1
