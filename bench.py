@@ -73,14 +73,14 @@ def multiscale_params(levels, final_max, target, check_every=4):
 
 
 def time_to_gap(name, precision, max_inner, cap, final_max, targets, stream, err, getweights):
-    # strict GetWeights on every layer: with the paper's lenience the tracked
-    # score drifts up by up to 0.5 % per step and the gap stalls far higher
     """Wall time of the whole multiscale solve (host marginals in, certificate
     checks included) until each relative gap first reaches each target: the
     certificate's pd_gap/|dual| and the DD plan's (tracked - dual)/|dual|.
     Layers from 16 x 16 up; global Sinkhorn below 256 x 256."""
     mu, nu = workload_marginals(name)
     cfg = workload_config(name, precision, max_inner, cap, err)
+    # strict GetWeights on every layer: with the paper's lenience the tracked
+    # score drifts up by up to 0.5 % per step and the gap stalls far higher
     cfg.lenience = 0.0
     cfg.getweights = getweights
     levels = int(round(np.log2(cfg.n1 / 16))) + 1
@@ -410,8 +410,8 @@ def main():
                     help="MiB of a plain device copy run once before the solver (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver "
+              "runs on a single device)", file=sys.stderr)
         sys.exit(2)
     print(json.dumps(run(args)), flush=True)
 
