@@ -98,6 +98,14 @@ typedef struct {
                                 fast_cap (more workgroups per CU); the results
                                 do not depend on it.  0: the largest side whose
                                 layout lets three workgroups share a CU */
+  int32_t balance;           /* 1: balancing step (Sec. 4.1 "Balancing") after
+                                every cell solve: the mass of the cell plan is
+                                moved along X between its basic cells, in
+                                proportion to mubar = e^{-alpha'/lambda} mu
+                                (alpha' the X-half of the final beta), before
+                                the re-split; 0 (default): no balancing.
+                                Regular Y points only (DDUOT_EINVAL with moved
+                                Y points) */
 } dduot_config;
 
 /* Per call of dd_uot_iterate, summed over all problems of the handle. */
@@ -130,7 +138,7 @@ typedef struct {
 
 /* Fill *cfg with the paper's defaults (Err 2e-5, trunc 1e-15, lenience 0.005,
    swift, FP32, block start, margin 2, cap 64, max 1000 inner iterations,
-   translation step on). */
+   translation step on, no balancing). */
 void dd_uot_default_config(dduot_config* cfg);
 
 /* Create a solver for one problem.  mu, nu: host, n1*n2 each, every entry

@@ -45,6 +45,7 @@ class dduot_config(C.Structure):
         ("trunc", C.c_double), ("lenience", C.c_double),
         ("box_margin", C.c_int32), ("box_cap", C.c_int32),
         ("translate", C.c_int32), ("fast_cap", C.c_int32),
+        ("balance", C.c_int32),
     ]
 
 

@@ -13,7 +13,7 @@
 
 namespace dduot {
 hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int tcap,
-                             int precision, bool moved, int nt, hipStream_t st);
+                             int precision, bool moved, bool balance, int nt, hipStream_t st);
 hipError_t set_cell_lds_limit(size_t bytes);
 size_t cell_lds_bytes(int lcap, int cap, int precision, bool moved);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st);
@@ -142,6 +142,7 @@ struct dduot_handle {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool moved = false;
+  bool balance = false;   // some problem takes the balancing step
   int *d_chunk_prob = nullptr, *d_chunk_start = nullptr, *d_chunk_len = nullptr;
   double* d_chunk_part = nullptr;
   double *d_theta = nullptr, *d_hist = nullptr;
@@ -221,6 +222,7 @@ static int validate(const dduot_config* c, const double* mu, const double* nu, i
   if (!(c->lenience >= 0.0)) return fail(DDUOT_EINVAL, pre + "lenience must be >= 0");
   if (c->box_margin < 0) return fail(DDUOT_EINVAL, pre + "box_margin must be >= 0");
   if (c->translate != 0 && c->translate != 1) return fail(DDUOT_EINVAL, pre + "translate must be 0 or 1");
+  if (c->balance != 0 && c->balance != 1) return fail(DDUOT_EINVAL, pre + "balance must be 0 or 1");
   if (c->box_cap < 2 * c->cell || c->box_cap > 128)
     return fail(DDUOT_EINVAL, pre + "box_cap must be in [2*cell, 128]");
   if (c->fast_cap < 0 || c->fast_cap > 128) return fail(DDUOT_EINVAL, pre + "fast_cap must be in [0, 128]");
@@ -266,6 +268,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
     if (mk != h->moved) return fail(DDUOT_EINVAL, "moved Y points: give them for all problems or none");
     if (!mk) continue;
     if (!(cfgs[k].h > 0.0)) return fail(DDUOT_EINVAL, "moved Y points need h > 0");
+    if (cfgs[k].balance) return fail(DDUOT_EINVAL, "the balancing step needs regular Y points");
     const long n = 2L * cfgs[k].n1 * cfgs[k].n2;
     for (long i = 0; i < n; ++i)
       if (!isfinite(yps[k][i])) return fail(DDUOT_EINVAL, "moved Y points must be finite");
@@ -331,6 +334,8 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
     p.getweights = c.getweights; p.fixed_iters = c.fixed_inner_iters; p.max_iter = c.sinkhorn_max_iter;
     p.margin = c.box_margin; p.cap = c.box_cap; p.precision = c.precision;
     p.translate = c.translate;
+    p.balance = c.balance;
+    if (c.balance) h->balance = true;
     p.moved = h->moved ? 1 : 0;
     p.grid_off = (int)goff;
     p.basic_off = (int)basic_prob.size();
@@ -497,7 +502,6 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_bytes, h->cells.size()));
   CHK(dalloc(h, &h->d_terms, h->cells.size()));
   CHK(dalloc(h, &h->d_fall, h->cells.size()));
-  // per-cell FP64 workspace of log nu and log r (FP32 kernels keep them in LDS)
   // per-cell workspace: FP64 kernels keep log nu and log r there (FP64);
   // FP32 kernels keep log r there (FP32, cap2 floats per cell)
   const size_t ncap = h->cells.size() * (size_t)h->cap2;
@@ -734,7 +738,7 @@ static int dd_step(dduot_handle* h, int part, int lo, int n, int blo, int bhi) {
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, st));
   }
-  HIPCHK(launch_cell_solve(d, lo, n, h->cap, h->tcap, h->precision, h->moved, h->nt, st));
+  HIPCHK(launch_cell_solve(d, lo, n, h->cap, h->tcap, h->precision, h->moved, h->balance, h->nt, st));
   if (h->timing) {
     HIPCHK(hipEventRecord(e1, st));
     h->events.push_back({e0, e1});
@@ -835,7 +839,7 @@ extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
     }
     float t = 0.0f;
     hipError_t e = hipEventRecord(e0, st);
-    if (e == hipSuccess) e = launch_cell_solve(h->d, base, h->ncell[part], h->cap, h->tcap, h->precision, h->moved, nt, st);
+    if (e == hipSuccess) e = launch_cell_solve(h->d, base, h->ncell[part], h->cap, h->tcap, h->precision, h->moved, h->balance, nt, st);
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);

@@ -453,7 +453,174 @@ __device__ __forceinline__ double dense_y_lse(const double* adr, const double* M
 // waves per SIMD (its LDS at box cap 48 allows three workgroups per CU; the
 // register limit costs a few spills outside the hot loops, and the extra
 // wave hides more latency: measured 7 % faster at 1024^2).
-template <typename R, bool kMoved, int NT>
+// Balancing step of Sec. 4.1 ("Balancing") for one composite cell J, after
+// its solve and before the re-split marginals are truncated.  On entry
+// d.cand holds log nu_k(y) = log nu + beta/eps + z_k(y) of every basic cell k
+// of J on the Y-box (untruncated), pxb the thread's P_X pi, lmb = -alpha'/lam
+// at the thread's point with alpha' the X-half of the final beta.  Basic cell
+// k should carry m_k = mubar(X_k) |pi| / |mubar| of the mass, mubar =
+// e^{-alpha'/lam} mu.  Mass moves along X only (every y keeps its total): a
+// donor (|pi_k| > m_k) keeps the fraction m_k / |pi_k| of its plan; what the
+// donors give up, R(y), goes to the receivers in proportion to their
+// deficits, spread over X_k at every y like the cell kernel
+// k(x, y) = e^{(alpha(x) - c(x, y))/eps} mu(x) normalised on X_k.  The
+// balanced plan on X_k is again k(x, y) g_k(y), so its piece keeps the closed
+// form with eps log(g_k/nu) = eps (log nu'_k - z_k - log nu) in place of
+// beta.  A receiver's P_X needs sum_y R(y) e^{-z_k(y)} k(x, y), one more
+// separable pass (FP64, exact maximum then sum) over the rows of X_k.  On
+// exit d.cand holds the balanced, truncated marginals; accy the Y sums
+// (<eps log(g_k/nu), nu'_k>, |nu'_k|), pxb and lpb the balanced P_X and
+// log(P_X/mu) of the thread's point.  wlR: per-cell workspace for log R.
+template <typename R, int NT>
+__device__ void balance_cell(const Dev& d, const Cell& C, const Prob& P, const CellLds<R>& S,
+                             int ti1, int ti2, int lx, int L1, int L2, int NY, int D1, int D2,
+                             int nc, const int* kr, const int* kc, double mux, double lmb,
+                             const double* wlnv, R* wlR, double (&accy)[8], double& pxb,
+                             double& lpb) {
+  const int t = threadIdx.x;
+  const long cap2 = d.cap2;
+  const int nb = C.nb, s = P.s;
+  const double eps = P.eps, ch = P.ch;
+  const int kt = t < lx ? (ti1 / s) * nc + (ti2 / s) : -1;   // basic cell of the thread's point
+  double ms[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) ms[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (q != kt) continue;
+    ms[q] = pxb;
+    ms[4 + q] = mux * exp(lmb);
+  }
+  block_sum<NT, 8>(ms, S.red);
+  double tot = 0.0, mtot = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    tot += ms[k];
+    mtot += ms[4 + k];
+  }
+  // per basic cell: role (1 donor, -1 receiver, 0 neither), donor factor
+  // m/M and share e/M of its plan given away, receiver share -e/E
+  int role[4] = {0, 0, 0, 0};
+  double fac[4] = {1.0, 1.0, 1.0, 1.0}, give[4] = {0.0, 0.0, 0.0, 0.0},
+         rcv[4] = {0.0, 0.0, 0.0, 0.0};
+  if (tot > 0.0 && mtot > 0.0) {
+    double ex[4] = {0.0, 0.0, 0.0, 0.0}, mk[4] = {0.0, 0.0, 0.0, 0.0}, E = 0.0;
+    for (int k = 0; k < nb; ++k) {
+      mk[k] = ms[4 + k] * tot / mtot;
+      ex[k] = ms[k] - mk[k];
+      if (ex[k] > 0.0) E += ex[k];
+    }
+    if (E > 0.0) {
+      for (int k = 0; k < nb; ++k) {
+        if (ex[k] > 0.0) {
+          role[k] = 1;
+          fac[k] = mk[k] / ms[k];
+          give[k] = ex[k] / ms[k];
+        } else if (ex[k] < 0.0) {
+          role[k] = -1;
+          rcv[k] = -ex[k] / E;
+        }
+      }
+    }
+  }
+  bool anyr = false;
+  for (int k = 0; k < nb; ++k) anyr = anyr || role[k] < 0;
+  auto removed = [&](int o) {   // R(y) at box point o
+    double r = 0.0;
+    for (int k = 0; k < nb; ++k)
+      if (role[k] > 0) r += give[k] * exp(d.cand[(long)C.basic[k] * cap2 + o]);
+    return r;
+  };
+  if (anyr) {
+    for (int o = t; o < NY; o += NT) {
+      const double r = removed(o);
+      wlR[o] = r > 0.0 ? R(log(r)) : R(-INFINITY);
+    }
+    __syncthreads();
+    const double pxold = pxb;
+    double add = 0.0;
+    for (int k = 0; k < nb; ++k) {
+      if (role[k] >= 0) continue;
+      const double* lk = d.cand + (long)C.basic[k] * cap2;
+      // pass 1 over y2 for the columns of X_k: T(j1, i) =
+      // LSE_j2 [log R - z_k - ch (D2 + kc s + i - j2)^2]
+      for (int o = t; o < L1 * s; o += NT) {
+        const int j1 = o / s, il = o - j1 * s;
+        const double c2 = (double)(D2 + kc[k] * s + il);
+        const int row = j1 * L2;
+        double m = -INFINITY;
+        for (int j2 = 0; j2 < L2; ++j2) {
+          const double dd = c2 - j2;
+          m = fmax(m, (double)wlR[row + j2] - lk[row + j2] + S.bd[row + j2] - ch * dd * dd);
+        }
+        double v = -INFINITY;
+        if (m > -INFINITY) {
+          double a = 0.0;
+          for (int j2 = 0; j2 < L2; ++j2) {
+            const double dd = c2 - j2;
+            a += exp((double)wlR[row + j2] - lk[row + j2] + S.bd[row + j2] - ch * dd * dd - m);
+          }
+          v = m + log(a);
+        }
+        S.Tt[o] = v;
+      }
+      __syncthreads();
+      // pass 2 over y1 for the points of X_k
+      if (kt == k) {
+        const int il = ti2 - kc[k] * s;
+        const double c1 = (double)(D1 + ti1);
+        double m = -INFINITY;
+        for (int j1 = 0; j1 < L1; ++j1) {
+          const double dd = c1 - j1;
+          m = fmax(m, S.Tt[j1 * s + il] - ch * dd * dd);
+        }
+        if (m > -INFINITY) {
+          double a = 0.0;
+          for (int j1 = 0; j1 < L1; ++j1) {
+            const double dd = c1 - j1;
+            a += exp(S.Tt[j1 * s + il] - ch * dd * dd - m);
+          }
+          add = rcv[k] * exp(S.adr[t] + m + log(a));
+        }
+      }
+      __syncthreads();
+    }
+    if (kt >= 0 && role[kt] < 0) pxb = pxold + add;
+  }
+  if (kt >= 0 && role[kt] > 0) pxb *= fac[kt];
+  if (kt >= 0 && role[kt] != 0) lpb = pxb > 0.0 ? log(pxb / mux) : -INFINITY;
+  // balanced marginals, their Y sums, truncation
+  for (int o = t; o < NY; o += NT) {
+    double lnv;
+    if constexpr (sizeof(R) == 4)
+      lnv = (double)S.lnvf[o];
+    else
+      lnv = wlnv[o];
+    const double bo = S.bd[o];
+    const double r = anyr ? removed(o) : 0.0;
+    for (int k = 0; k < nb; ++k) {
+      double* ck = d.cand + (long)C.basic[k] * cap2;
+      const double lnk = ck[o];
+      double lv = lnk;
+      if (role[k] > 0) {
+        lv = lnk + log(fac[k]);
+      } else if (role[k] < 0) {
+        const double nv = exp(lnk) + rcv[k] * r;
+        lv = nv > 0.0 ? log(nv) : -INFINITY;
+      }
+      const double nt = exp(lv);
+      if (nt > 0.0) {
+        accy[k] += eps * (lv - lnk + bo - lnv) * nt;
+        accy[4 + k] += nt;
+      }
+      ck[o] = nt < P.trunc ? 0.0 : nt;
+    }
+  }
+  __syncthreads();
+}
+
+// kBal: the variant with the balancing step (separable cost only); the
+// plain variant keeps its own register allocation.
+template <typename R, bool kMoved, int NT, bool kBal = false>
 __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cell_solve(Dev d,
                                                                                        int cell_base,
                                                                                        int tcap,
@@ -684,6 +851,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
   const R newton_tol = sizeof(R) == 8 ? R(1e-14) : R(1e-6);
   const int newton_max = sizeof(R) == 8 ? 100 : 60;
   double pxv = 0.0, lpv = 0.0;
+  double Sfin = 0.0;   // X-half output of the final beta (balancing)
   int it = 0;
   bool conv = false;
   bool have_y = false;
@@ -769,6 +937,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
 
     // ---- next X-half (gives P_X of the pair for the stopping rule) ----------
     const double Sn = x_half(Sx);
+    Sfin = Sn;
     double term = 0.0;
     if (t < lx) {
       lpv = aeps + Sn;               // log(P_X / mu)
@@ -799,6 +968,9 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
     kr[k] = (bx.x - C.x1) / s;
     kc[k] = (bx.y - C.x2) / s;
   }
+  // balancing (Sec. 4.1): the loop below then stores log nu_k untruncated
+  // and the balanced marginals replace them afterwards
+  const bool bal = kBal && !kMoved && P.balance && C.nb > 1;
   // Y sums per basic cell k: <beta, nu_k>, |nu_k|
   double accy[8];
 #pragma unroll
@@ -824,6 +996,10 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
           zk = lse_full<R>(Uo + j2, L2, kr[k] * s, (kr[k] + 1) * s, (double)(j1 - D1), ch, qc, cap,
                            true, S.zp[o], nfall);
         }
+        if (bal) {
+          d.cand[(long)C.basic[k] * cap2 + o] = S.bd[o] + zk;
+          continue;
+        }
         const double nt = exp(S.bd[o] + zk);   // nu e^{beta/eps} e^{z_k}
         accy[k] += beta * nt;
         accy[4 + k] += nt;
@@ -831,6 +1007,14 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
       }
     }
     __syncthreads();
+  }
+  double pxb = pxv, lpb = lpv;   // P_X of the (balanced) plan at the thread's point
+  if constexpr (kBal && !kMoved) {
+    if (bal) {
+      R* wlR = sizeof(R) == 4 ? reinterpret_cast<R*>(wlrf) : reinterpret_cast<R*>(wlrr);
+      balance_cell<R, NT>(d, C, P, S, ti1, ti2, lx, L1, L2, NY, D1, D2, nc, kr, kc, mux,
+                          kap * Sfin / K, wlnv, wlR, accy, pxb, lpb);
+    }
   }
   block_sum<NT, 8>(accy, red);
   // X sums per basic cell k: <alpha, px>, KL terms, |mu_k|; then the count of
@@ -841,15 +1025,15 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
   if (t < lx) {
     const int k = (ti1 / s) * nc + (ti2 / s);
     const double alpha = eps * aeps;
-    const double e = exp(lpv);
+    const double e = exp(lpb);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (q != k) continue;
-      accx[q] = alpha * pxv;
-      accx[4 + q] = mux * (e * lpv - e + 1.0);
+      accx[q] = alpha * pxb;
+      accx[4 + q] = pxb > 0.0 ? mux * (e * lpb - e + 1.0) : mux;
       accx[8 + q] = mux;
     }
-    d.pxc[P.grid_off + gx] = pxv;
+    d.pxc[P.grid_off + gx] = pxb;
     d.abar[P.grid_off + gx] = alpha;
   }
   accx[12] = nfall;
@@ -884,52 +1068,57 @@ size_t cell_lds_bytes(int lcap, int cap, int precision, bool moved) {
   return cell_lds_layout<float>(lcap, cap, moved, nullptr, nullptr);
 }
 
-template <typename R, bool kMoved>
+template <typename R, bool kMoved, bool kBal>
 static void launch_nt(const Dev& d, int cell_base, int ncells, size_t lds, int nt, int tcap, int tier,
                       hipStream_t st) {
   if (nt == 64)
-    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 64>), dim3(ncells), dim3(64), lds, st, d, cell_base,
-                       tcap, tier);
+    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 64, kBal>), dim3(ncells), dim3(64), lds, st, d,
+                       cell_base, tcap, tier);
   else if (nt == 128)
-    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 128>), dim3(ncells), dim3(128), lds, st, d, cell_base,
-                       tcap, tier);
+    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 128, kBal>), dim3(ncells), dim3(128), lds, st, d,
+                       cell_base, tcap, tier);
   else
-    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 256>), dim3(ncells), dim3(256), lds, st, d, cell_base,
-                       tcap, tier);
+    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 256, kBal>), dim3(ncells), dim3(256), lds, st, d,
+                       cell_base, tcap, tier);
 }
 
+// balance: some problem of the handle takes the balancing step (the host
+// rejects it with moved Y points)
 static void launch_tier(const Dev& d, int cell_base, int ncells, int lcap, int cap, int precision,
-                        bool moved, int nt, int tcap, int tier, hipStream_t st) {
+                        bool moved, bool balance, int nt, int tcap, int tier, hipStream_t st) {
   const size_t lds = cell_lds_bytes(lcap, cap, precision, moved);
   if (precision == 64) {
-    if (moved) launch_nt<double, true>(d, cell_base, ncells, lds, nt, tcap, tier, st);
-    else launch_nt<double, false>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+    if (moved) launch_nt<double, true, false>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+    else if (balance) launch_nt<double, false, true>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+    else launch_nt<double, false, false>(d, cell_base, ncells, lds, nt, tcap, tier, st);
   } else {
-    if (moved) launch_nt<float, true>(d, cell_base, ncells, lds, nt, tcap, tier, st);
-    else launch_nt<float, false>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+    if (moved) launch_nt<float, true, false>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+    else if (balance) launch_nt<float, false, true>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+    else launch_nt<float, false, false>(d, cell_base, ncells, lds, nt, tcap, tier, st);
   }
 }
 
 // tcap < cap: two launches, the cells whose box exceeds tcap first (larger
 // LDS layout, fewer workgroups per CU), then the others.
 hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int tcap,
-                             int precision, bool moved, int nt, hipStream_t st) {
+                             int precision, bool moved, bool balance, int nt, hipStream_t st) {
   if (ncells <= 0) return hipSuccess;
   if (tcap >= cap) {
-    launch_tier(d, cell_base, ncells, cap, cap, precision, moved, nt, cap, 0, st);
+    launch_tier(d, cell_base, ncells, cap, cap, precision, moved, balance, nt, cap, 0, st);
   } else {
-    launch_tier(d, cell_base, ncells, cap, cap, precision, moved, nt, tcap, 2, st);
+    launch_tier(d, cell_base, ncells, cap, cap, precision, moved, balance, nt, tcap, 2, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    launch_tier(d, cell_base, ncells, tcap, cap, precision, moved, nt, tcap, 1, st);
+    launch_tier(d, cell_base, ncells, tcap, cap, precision, moved, balance, nt, tcap, 1, st);
   }
   return hipGetLastError();
 }
 
-template <typename R, bool kMoved>
+template <typename R, bool kMoved, bool kBal = false>
 static hipError_t set_lds_nt(size_t bytes) {
-  const void* fns[3] = {(const void*)k_cell_solve<R, kMoved, 64>, (const void*)k_cell_solve<R, kMoved, 128>,
-                        (const void*)k_cell_solve<R, kMoved, 256>};
+  const void* fns[3] = {(const void*)k_cell_solve<R, kMoved, 64, kBal>,
+                        (const void*)k_cell_solve<R, kMoved, 128, kBal>,
+                        (const void*)k_cell_solve<R, kMoved, 256, kBal>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
@@ -942,6 +1131,8 @@ hipError_t set_cell_lds_limit(size_t bytes) {
   if (e == hipSuccess) e = set_lds_nt<double, true>(bytes);
   if (e == hipSuccess) e = set_lds_nt<float, false>(bytes);
   if (e == hipSuccess) e = set_lds_nt<float, true>(bytes);
+  if (e == hipSuccess) e = set_lds_nt<double, false, true>(bytes);
+  if (e == hipSuccess) e = set_lds_nt<float, false, true>(bytes);
   return e;
 }
 

@@ -20,6 +20,7 @@ struct Prob {
   int getweights, fixed_iters, max_iter;
   int margin, cap;
   int translate;
+  int balance;         // 1: balancing step after every cell solve (Sec. 4.1)
   int precision;
   int moved;           // 1: Y points displaced (dense, non-separable cost)
   int grid_off;     // offset of this problem's grid arrays

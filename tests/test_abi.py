@@ -59,7 +59,8 @@ def test_default_config_values():
 
 @pytest.mark.parametrize("field,value", [("n1", 30), ("cell", 0), ("cell", 9), ("eps", 0.0),
                                          ("lambda_", -1.0), ("precision", 16), ("box_cap", 4),
-                                         ("getweights", 7), ("getweights", 5), ("translate", 2)])
+                                         ("getweights", 7), ("getweights", 5), ("translate", 2),
+                                         ("balance", 2)])
 def test_invalid_configs_are_rejected_before_any_device_work(field, value):
     import numpy as np
     cfg = binding.dd_uot_default_config(n1=32, n2=32, h=1 / 32, eps=1 / 1024)
@@ -83,3 +84,14 @@ def test_nonpositive_mass_is_rejected():
     nu[7] = np.nan
     with pytest.raises(binding.DDUOTError):
         binding.dd_uot_init(cfg, mu, nu)
+
+
+def test_balancing_with_moved_points_is_rejected():
+    import numpy as np
+    cfg = binding.dd_uot_default_config(n1=16, n2=16, h=1 / 16, eps=1 / 256, balance=1)
+    mu = np.full(256, 1.0 / 256)
+    y = np.stack(np.meshgrid(np.arange(16), np.arange(16), indexing="ij"), -1) / 16.0
+    with pytest.raises(binding.DDUOTError) as e:
+        binding.dd_uot_init_moved(cfg, mu, mu.copy(), y)
+    assert e.value.code == binding.EINVAL
+    assert "balancing" in str(e.value)

@@ -24,7 +24,7 @@ def oracle_options(cfg):
     return dd.Options(err=cfg.sinkhorn_err, max_iter=cfg.sinkhorn_max_iter,
                       fixed_iters=cfg.fixed_inner_iters, trunc=cfg.trunc, lenience=cfg.lenience,
                       margin=cfg.box_margin, cap=cfg.box_cap, getweights=GW[cfg.getweights],
-                      translate=bool(cfg.translate))
+                      translate=bool(cfg.translate), balance=bool(cfg.balance))
 
 
 def oracle_start(p, cfg):
@@ -137,6 +137,33 @@ def test_fp64_other_getweights(grid32, gw):
         print(f"[parity] line weights {thetas}", flush=True)
         assert np.any((thetas > 1.0 / 16) & (thetas < 1.0))   # an interior minimiser
     B.dd_uot_destroy(h)
+
+
+@pytest.mark.parametrize("precision,lam,init", [(64, 10.0, B.INIT_BLOCK), (64, 1.0, B.INIT_PRODUCT),
+                                                 (32, 10.0, B.INIT_BLOCK)])
+def test_balancing_follows_the_oracle(grid32, precision, lam, init):
+    # balancing step (Sec. 4.1): mass moved along X between the basic cells
+    # of every composite cell, in proportion to e^{-alpha'/lambda} mu
+    mu, nu = grid32
+    n = 32
+    kw = dict(precision=precision, init=init, fixed_inner_iters=20, lenience=0.0, box_cap=32,
+              box_margin=2)
+    cfg = config(n, 4, 4.0 / n ** 2, lam, 1.0 / n, balance=1, **kw)
+    rtol = 1e-10 if precision == 64 else 1e-5
+    h, p, st = run_pair(mu, nu, cfg, 6, rtol=rtol)
+    h0 = B.dd_uot_init(config(n, 4, 4.0 / n ** 2, lam, 1.0 / n, **kw), mu, nu)
+    try:
+        if precision == 64:
+            compare_boxes(h, p, st, 1e-10)
+        B.dd_uot_iterate(h0, 6)
+        px, _ = B.dd_uot_marginals(h, 0, n, n)
+        px0, _ = B.dd_uot_marginals(h0, 0, n, n)
+        moved = l1_rel(px0, px)
+        print(f"[parity] balancing changed P_X by {moved:.2e} (L1, relative)", flush=True)
+        assert moved > 1e-4   # the step is not vacuous on this problem
+    finally:
+        B.dd_uot_destroy(h)
+        B.dd_uot_destroy(h0)
 
 
 def test_fp32_matches_fp64_oracle(grid32):
