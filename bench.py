@@ -111,6 +111,48 @@ def time_to_gap(name, precision, max_inner, cap, final_max, targets, stream, err
                         f"at most {max_inner} inner iterations"}
 
 
+def plateau_study(name, lams, targets, max_iter, stream):
+    """Global UOT Sinkhorn (no decomposition) at eps = (8h)^2 from beta = 0:
+    iterations and wall time until KL(P_X pi | e^{-alpha/lambda} mu) / |mu|
+    first reaches each target, and that error at fixed iteration counts, for
+    each lambda (the convergence-plateau study of Sec. 4.4).  The run is cut
+    into calls that stop at the next target or the next milestone, each
+    continuing from the previous beta (the same iteration run without a
+    stop)."""
+    mu, nu = workload_marginals(name)
+    n = mu.shape[0]
+    mass = float(mu.sum())
+    miles = [m for m in (10, 30, 100, 300, 1000, 3000, 10000, 30000) if m < max_iter] + [max_iter]
+    rows = []
+    for lam in lams:
+        cfg = B.dd_uot_default_config(n1=n, n2=n, h=1.0 / n, eps=64.0 / n ** 2, lam=lam, cell=4,
+                                      precision=64)
+        beta = np.zeros((n, n))
+        done, ti, mi, kl = 0, 0, 0, None
+        hits = {f"{t:g}": None for t in targets}
+        trace = []
+        t0 = time.perf_counter()
+        while done < max_iter and ti < len(targets):
+            tol = targets[ti] * mass
+            r = B.dd_uot_global_sinkhorn(cfg, mu, nu, beta, max_iter=miles[mi] - done, tol=tol,
+                                         stream=stream)
+            done += r["iters"]
+            beta = r["beta"]
+            kl = r["pd"] / mass
+            ms = 1e3 * (time.perf_counter() - t0)
+            while ti < len(targets) and r["pd"] <= targets[ti] * mass:
+                hits[f"{targets[ti]:g}"] = {"iters": done, "ms": ms}
+                ti += 1
+            if done >= miles[mi]:
+                trace.append([done, kl])
+                mi += 1
+        rows.append({"lambda": lam, "to_tolerance": hits, "iters_run": done, "final_kl_rel": kl,
+                     "kl_rel_at_iters": trace})
+        progress(f"plateau study lambda={lam:g}: {done} iterations, KL/|mu| {kl:.3g}")
+    return {"workload": name, "eps": "(8h)^2", "criterion": "KL(P_X pi | e^{-alpha/lambda} mu)/|mu|",
+            "max_iter": max_iter, "rows": rows}
+
+
 def progress(msg):
     """One line on stderr per finished phase (the JSON result goes to stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -368,6 +410,10 @@ def run(args):
                         stream.cuda_stream, args.ms_err,
                         {v: k for k, v in GW_NAMES.items()}[args.ttg_getweights])
             for name in args.ttg_workloads.split(",") for prec in (32, 64)]
+    if args.plateau:
+        out["plateau_study"] = plateau_study("grid256", (0.01, 0.1, 1.0, 10.0, 100.0, 1000.0),
+                                             (1e-2, 1e-3, 1e-4, 1e-5, 1e-6), args.plateau_max,
+                                             stream.cuda_stream)
     if args.forms:
         out["batched_form"] = batched_form(args.steps, args.warmup)
         out["differentiable_form"] = differentiable_form(args.steps)
@@ -406,6 +452,10 @@ def main():
                     help="GetWeights of the time-to-gap runs (line: the fastest decrement)")
     ap.add_argument("--ttg-max32", type=int, default=64)
     ap.add_argument("--ttg-max64", type=int, default=64)
+    ap.add_argument("--plateau", type=int, default=1,
+                    help="1: also run the global-Sinkhorn convergence study over lambda")
+    ap.add_argument("--plateau-max", type=int, default=10000,
+                    help="iteration cap per lambda of the plateau study")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of a plain device copy run once before the solver (profiling)")
     args = ap.parse_args()
