@@ -24,17 +24,21 @@ def problem_data(k, n):
     return mu, nu
 
 
-def make_cfgs(precision, fixed=8):
+def make_cfgs(precision, fixed=8, balance=(0, 0, 0, 0)):
     cfgs = []
-    for (n, s, lam, e, init) in SPECS:
+    for (n, s, lam, e, init), bal in zip(SPECS, balance):
         cfgs.append(B.dd_uot_default_config(
             n1=n, n2=n, h=1.0 / n, eps=e / n ** 2, lam=lam, cell=s, precision=precision,
-            init=init, fixed_inner_iters=fixed, lenience=0.0, box_cap=32, getweights=B.GW_SWIFT))
+            init=init, fixed_inner_iters=fixed, lenience=0.0, box_cap=32, getweights=B.GW_SWIFT,
+            balance=bal))
     return cfgs
 
 
-def test_batched_fp64_follows_each_oracle():
-    cfgs = make_cfgs(64)
+@pytest.mark.parametrize("balance", [(0, 0, 0, 0), (1, 0, 1, 1)])
+def test_batched_fp64_follows_each_oracle(balance):
+    # balance: per problem; a handle mixing both runs the balancing kernel
+    # variant, which leaves the problems without it untouched
+    cfgs = make_cfgs(64, balance=balance)
     data = [problem_data(k, c.n1) for k, c in enumerate(cfgs)]
     h = B.dd_uot_init_batch(cfgs, [d[0] for d in data], [d[1] for d in data])
     try:
@@ -44,12 +48,13 @@ def test_batched_fp64_follows_each_oracle():
             p = dd.make_problem(data[k][0], data[k][1], c.eps, c.lambda_, c.h, c.cell)
             probs.append(p)
             states.append(dd.init_product(p))
-        opt = dd.Options(fixed_iters=8, lenience=0.0, cap=32, trunc=1e-15, margin=2, translate=True)
+        opts = [dd.Options(fixed_iters=8, lenience=0.0, cap=32, trunc=1e-15, margin=2, translate=True,
+                           balance=bool(b)) for b in balance]
         for step in range(4):
             print(f"[batched] step {step}", flush=True)
             B.dd_uot_iterate(h, 1)
             for k, (p, st) in enumerate(zip(probs, states)):
-                ost = dd.half_iteration(p, st, "A" if step % 2 == 0 else "B", opt)
+                ost = dd.half_iteration(p, st, "A" if step % 2 == 0 else "B", opts[k])
                 rec = B.dd_uot_history(h, k)[-1]
                 assert rec[0] == ost["theta"]
                 assert rec[1] == pytest.approx(ost["e_cur"], rel=1e-10)
@@ -135,10 +140,11 @@ def test_graph_replays_match_eager_steps():
         B.dd_uot_destroy(hg)
 
 
-def test_autotuned_threads_per_cell_keep_the_trajectory():
+@pytest.mark.parametrize("balance", [0, 1])
+def test_autotuned_threads_per_cell_keep_the_trajectory(balance):
     # the autotuner picks 64, 128 or 256 threads per cell for tiles of at
     # most 64 points; any choice must follow the same trajectory
-    cfgs = make_cfgs(64)
+    cfgs = make_cfgs(64, balance=(balance,) * 4)
     data = [problem_data(k, c.n1) for k, c in enumerate(cfgs)]
     ha = B.dd_uot_init_batch(cfgs, [d[0] for d in data], [d[1] for d in data])
     hb = B.dd_uot_init_batch(cfgs, [d[0] for d in data], [d[1] for d in data])
@@ -162,13 +168,13 @@ def test_autotuned_threads_per_cell_keep_the_trajectory():
         B.dd_uot_destroy(hb)
 
 
-@pytest.mark.parametrize("precision", [64, 32])
-def test_two_launch_tiers_keep_the_trajectory(precision):
+@pytest.mark.parametrize("precision,balance", [(64, 0), (32, 0), (64, 1)])
+def test_two_launch_tiers_keep_the_trajectory(precision, balance):
     # cells whose Y-box exceeds fast_cap run in a second launch with the
     # larger LDS layout; the arithmetic is the same, so the trajectory is too
-    cfgs = make_cfgs(precision)
+    cfgs = make_cfgs(precision, balance=(balance,) * 4)
     tiered = []
-    for c in make_cfgs(precision):
+    for c in make_cfgs(precision, balance=(balance,) * 4):
         c.fast_cap = 12
         tiered.append(c)
     data = [problem_data(k, c.n1) for k, c in enumerate(cfgs)]

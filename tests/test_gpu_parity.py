@@ -218,14 +218,16 @@ def test_box_overflow_is_reported_and_keeps_state(grid32):
         B.dd_uot_destroy(h)
 
 
-def test_fp64_staggered_batches(grid32):
+@pytest.mark.parametrize("balance", [0, 1])
+def test_fp64_staggered_batches(grid32, balance):
     # staggered GetWeights: four batch steps per half-iteration, each with its
-    # own record, theta and scores
+    # own record, theta and scores (with balancing: the paper's production
+    # setting)
     mu, nu = grid32
     n = 32
     cfg = config(n, 4, 4.0 / n ** 2, 1.0, 1.0 / n, precision=64, init=B.INIT_BLOCK,
                  fixed_inner_iters=20, lenience=0.0, box_cap=32, box_margin=2,
-                 getweights=B.GW_STAGGERED)
+                 getweights=B.GW_STAGGERED, balance=balance)
     p = dd.make_problem(mu, nu, cfg.eps, cfg.lambda_, cfg.h, cfg.cell)
     st = dd.init_block(p)
     opt = oracle_options(cfg)
