@@ -9,7 +9,7 @@ import pytest
 
 from oracle import dd
 from paper_2410_08859_amd import binding as B
-from paper_2410_08859_amd.inputs import workload_marginals
+from paper_2410_08859_amd.inputs import gaussian_mixture, workload_marginals
 
 pytestmark = pytest.mark.gpu
 
@@ -44,13 +44,13 @@ def l1_rel(a, b):
 
 
 def run_pair(mu, nu, cfg, n_half, check_every=True, rtol=1e-10, theta_rtol=1e-15):
-    n = cfg.n1
+    n, n2 = cfg.n1, cfg.n2
     p = dd.make_problem(mu, nu, cfg.eps, cfg.lambda_, cfg.h, cfg.cell)
     st = oracle_start(p, cfg)
     opt = oracle_options(cfg)
     h = B.dd_uot_init(cfg, mu, nu)
     try:
-        print(f"[parity] n={n} s={cfg.cell} prec={cfg.precision} init={cfg.init} "
+        print(f"[parity] n={n}x{n2} s={cfg.cell} h={cfg.h:g} prec={cfg.precision} init={cfg.init} "
               f"fixed={cfg.fixed_inner_iters} gw={cfg.getweights}", flush=True)
         for k in range(n_half):
             ost = dd.half_iteration(p, st, "A" if k % 2 == 0 else "B", opt)
@@ -64,12 +64,12 @@ def run_pair(mu, nu, cfg, n_half, check_every=True, rtol=1e-10, theta_rtol=1e-15
             rel_close(rec[2], ost["e_greedy"], rtol, f"greedy score at step {k}")
             if cfg.precision == 64:
                 assert int(rec[4]) == ost["point_iters"], f"inner iterations at step {k}"
-            px, py = B.dd_uot_marginals(h, 0, n, n)
+            px, py = B.dd_uot_marginals(h, 0, n, n2)
             P = dd.aggregate(p, st.boxes)
             if cfg.precision == 64:
                 rel_close(px, st.px, rtol, f"P_X at step {k}")
                 rel_close(py, P, rtol, f"P_Y at step {k}")
-                a, _ = B.dd_uot_potentials(h, 0, n, n, beta=False)
+                a, _ = B.dd_uot_potentials(h, 0, n, n2, beta=False)
                 rel_close(a, st.abar, rtol, f"alpha_bar at step {k}")
             else:
                 assert l1_rel(px, st.px) < rtol, f"P_X at step {k}: {l1_rel(px, st.px):.2e}"
@@ -164,6 +164,56 @@ def test_balancing_follows_the_oracle(grid32, precision, lam, init):
     finally:
         B.dd_uot_destroy(h)
         B.dd_uot_destroy(h0)
+
+
+@pytest.mark.parametrize("n1,n2,s,h", [(24, 40, 2, 1 / 32), (16, 16, 1, 1 / 16), (16, 16, 2, 0.0)])
+def test_fp64_grid_shapes_and_vanishing_cost(n1, n2, s, h):
+    # a rectangular grid (its own B offsets on each axis), one-point basic
+    # cells (2 x 2 tiles), and h = 0 (the cost vanishes, no windows)
+    mu = gaussian_mixture(n1, n2, 3, 1e-3, 1.0, 1001)
+    nu = gaussian_mixture(n1, n2, 3, 1e-3, 1.3, 1002)
+    cfg = B.dd_uot_default_config(n1=n1, n2=n2, h=h, eps=4.0 / 32 ** 2, lam=1.0, cell=s,
+                                  precision=64, init=B.INIT_BLOCK, fixed_inner_iters=20,
+                                  lenience=0.0, box_cap=32 if n1 != 16 else 16, box_margin=2)
+    h_, p, st = run_pair(mu, nu, cfg, 4)
+    try:
+        compare_boxes(h_, p, st, 1e-10)
+    finally:
+        B.dd_uot_destroy(h_)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_largest_box_cap_fits_and_keeps_the_trajectory(precision):
+    # the largest box side whose cell layout fits the LDS of one workgroup:
+    # one more is rejected before any launch; at the largest, a trajectory
+    # whose boxes stay small is that of a small cap
+    n = 64
+    mu = gaussian_mixture(n, n, 3, 1e-3, 1.0, 1011)
+    nu = gaussian_mixture(n, n, 3, 1e-3, 1.3, 1012)
+    kw = dict(precision=precision, init=B.INIT_BLOCK, fixed_inner_iters=10, lenience=0.0,
+              box_margin=2)
+    big = None
+    for cap in range(128, 31, -1):
+        try:
+            big = B.dd_uot_init(config(n, 4, 2.0 / n ** 2, 1.0, 1.0 / n, box_cap=cap, **kw), mu, nu)
+            break
+        except B.DDUOTError as e:
+            assert e.code == B.EINVAL and "LDS" in str(e)
+    assert big is not None and cap < 128
+    print(f"[parity] FP{precision}: largest box cap {cap}, launch caps {B.dd_uot_launch_caps(big)}",
+          flush=True)
+    small = B.dd_uot_init(config(n, 4, 2.0 / n ** 2, 1.0, 1.0 / n, box_cap=64, **kw), mu, nu)
+    try:
+        B.dd_uot_iterate(big, 3)
+        B.dd_uot_iterate(small, 3)
+        assert B.dd_uot_score(small, 0)["overflow"] == 0 and B.dd_uot_score(big, 0)["overflow"] == 0
+        for a, b in zip(B.dd_uot_marginals(big, 0, n, n), B.dd_uot_marginals(small, 0, n, n)):
+            np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * b.max())
+        np.testing.assert_allclose(B.dd_uot_history(big, 0)[:, :3], B.dd_uot_history(small, 0)[:, :3],
+                                   rtol=1e-12, atol=0)
+    finally:
+        B.dd_uot_destroy(big)
+        B.dd_uot_destroy(small)
 
 
 def test_fp32_matches_fp64_oracle(grid32):
