@@ -149,7 +149,10 @@ __device__ __forceinline__ double newton_v(double a, double v0, double K, R tol,
     }
     const R dv = g * M<R>::rcp(R(1) + KR * sig);
     v -= dv;
-    if (!(fabs(dv) > tol * (R(1) + fabs(v)))) break;
+    // Near the root the error after a step is at most (G''/2G') dv^2, and
+    // G''/G' = K sig (1 - sig) / (1 + K sig) <= 1: stop once dv^2/2 is below
+    // the tolerance (the step just taken then meets it).
+    if (!(R(0.5) * dv * dv > tol * (R(1) + fabs(v)))) break;
   }
   return (double)v;
 }
