@@ -128,16 +128,15 @@ __device__ __forceinline__ double newton_v(double a, double v0, double K, R tol,
   R v = R(v0);
   R gprev = R(INFINITY);
   for (int it = 0; it < maxit; ++it) {
-    R la, sig;
-    if (v >= aR) {
-      const R e = M<R>::ex(aR - v);
-      la = v + M<R>::lg1p(e);
-      sig = M<R>::rcp(R(1) + e);
-    } else {
-      const R e = M<R>::ex(v - aR);
-      la = aR + M<R>::lg1p(e);
-      sig = e * M<R>::rcp(R(1) + e);
-    }
+    // logaddexp(a, v) = max(a, v) + log1p(e), e = e^{-|a - v|}, without a
+    // branch (lanes on both sides of a would run both); the share
+    // sig = e^v / (e^a + e^v) is 1/(1 + e) right of a and e/(1 + e) left of
+    // it, and G' (1 + e) = 1 + e + K (1 or e): one reciprocal per step
+    const bool right = v >= aR;
+    const R e = M<R>::ex(-fabs(aR - v));
+    const R la = (right ? v : aR) + M<R>::lg1p(e);
+    const R e1 = R(1) + e;
+    const R den = e1 + KR * (right ? R(1) : e);
     const R g = v + KR * la;
     // Right of the root (G > 0) the Newton iterates of a convex increasing G
     // decrease monotonically and so does G; a residual that stops decreasing
@@ -147,7 +146,7 @@ __device__ __forceinline__ double newton_v(double a, double v0, double K, R tol,
       if (!(g < gprev)) break;
       gprev = g;
     }
-    const R dv = g * M<R>::rcp(R(1) + KR * sig);
+    const R dv = g * e1 * M<R>::rcp(den);
     v -= dv;
     // Near the root the error after a step is at most (G''/2G') dv^2, and
     // G''/G' = K sig (1 - sig) / (1 + K sig) <= 1: stop once dv^2/2 is below
@@ -851,7 +850,8 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
   double aeps = -kap * Sx;   // alpha/eps of the thread's point
 
   const double tol = P.err * muJ;
-  const R newton_tol = sizeof(R) == 8 ? R(1e-14) : R(1e-6);
+  // Newton stops when its error bound reaches the rounding of v (R epsilon)
+  const R newton_tol = sizeof(R) == 8 ? R(1.1e-16) : R(6e-8);
   const int newton_max = sizeof(R) == 8 ? 100 : 60;
   double pxv = 0.0, lpv = 0.0;
   double Sfin = 0.0;   // X-half output of the final beta (balancing)
