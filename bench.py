@@ -382,6 +382,23 @@ def run(args):
                         "dd_plan_gap": (score["tracked"] - score["dual"]) / abs(score["dual"]),
                         "tracked_score": score["tracked"], "half_iters": score["half_iters"]},
     }
+    if args.other_precision and args.start == "block":
+        # the same workload and steps in the other cell precision (FP32 vs FP64)
+        prec = 64 if args.precision == 32 else 32
+        c2 = workload_config(args.workload, prec, args.max_inner, args.cap, getweights=gw)
+        h = B.dd_uot_init(c2, mu, nu, stream=stream.cuda_stream)
+        try:
+            o = timed_steps(h, args.steps, args.warmup)
+        finally:
+            B.dd_uot_destroy(h)
+        oh = o["hist"]
+        out["other_precision"] = {
+            "precision": prec, "value": float(oh[:, 4].sum() / o["dt"]),
+            "ms_per_step": 1e3 * o["dt"] / args.steps,
+            "avg_launch_ms": o["kms"] / max(o["launches"], 1),
+            "mean_inner_per_cell": float(oh[:, 8].sum() / max(oh[:, 3].sum(), 1)),
+            "unit": "grid-pts\u00b7iters/s"}
+        progress(f"FP{prec} steps: {1e3 * o['dt'] / args.steps:.2f} ms per step")
     if args.warm and args.start != "multiscale":
         # the same steps after the multiscale warm start (the paper's pipeline)
         wcfg = workload_config(args.workload, args.precision, args.ms_max_inner, args.cap,
@@ -452,6 +469,8 @@ def main():
                     help="GetWeights of the time-to-gap runs (line: the fastest decrement)")
     ap.add_argument("--ttg-max32", type=int, default=64)
     ap.add_argument("--ttg-max64", type=int, default=64)
+    ap.add_argument("--other-precision", type=int, default=1,
+                    help="1: also time the same steps in the other cell precision")
     ap.add_argument("--plateau", type=int, default=1,
                     help="1: also run the global-Sinkhorn convergence study over lambda")
     ap.add_argument("--plateau-max", type=int, default=10000,
