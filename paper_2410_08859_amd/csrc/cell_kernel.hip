@@ -850,6 +850,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
   double aeps = -kap * Sx;   // alpha/eps of the thread's point
 
   const double tol = P.err * muJ;
+  const double iK1 = 1.0 / (K + 1.0);   // q_ref = z / (1 + K), one divide per cell
   // Newton stops when its error bound reaches the rounding of v (R epsilon)
   const R newton_tol = sizeof(R) == 8 ? R(1.1e-16) : R(6e-8);
   const int newton_max = sizeof(R) == 8 ? 100 : 60;
@@ -928,7 +929,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
         lnv = wlnv[o];
         lrr = wlrr[o];
       }
-      const double qref = z / (K + 1.0);
+      const double qref = z * iK1;
       // warm start: the previous beta/eps = bd - log nu, i.e. v0 = bd - lnv + K qref
       const double v0 = S.bd[o] - lnv + K * qref;
       const double v = newton_v<R>(lrr - qref, v0, K, newton_tol, newton_max);
