@@ -49,12 +49,17 @@ struct M<float> {
   static constexpr float kScale = 1.4426950408889634f;   // log2(e): exp(x) = 2^(x log2 e)
   static __device__ __forceinline__ float ex2s(float x) { return __builtin_amdgcn_exp2f(x); }
   static __device__ __forceinline__ float ex(float x) { return __expf(x); }
-  static __device__ __forceinline__ float lg(float x) { return __logf(x); }
+  // hardware log2 times ln 2: the arguments are normal floats (shifted sums
+  // accepted in [1.8e-35, 5.5e34], exact sums >= 1, 1 + x in [1, 2]); a
+  // subnormal retry sum gives -inf, which sends that output to the exact path
+  static __device__ __forceinline__ float lg(float x) {
+    return __builtin_amdgcn_logf(x) * 0.69314718055994531f;
+  }
   // log(1 + x) for x in [0, 1]: the series below 1e-4 (error < x^3/3), the
   // hardware logarithm above (absolute error ~1e-7, the level of the FP32
   // rounding of the Newton variables anyway)
   static __device__ __forceinline__ float lg1p(float x) {
-    return x < 1e-4f ? x * (1.0f - 0.5f * x) : __logf(1.0f + x);
+    return x < 1e-4f ? x * (1.0f - 0.5f * x) : lg(1.0f + x);
   }
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 };
