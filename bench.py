@@ -16,7 +16,7 @@ measured separately (--ttg): the whole multiscale solve, FP32 and FP64, from
 the host marginals to each target.
 
 Prints one JSON line on stdout, progress lines on stderr.  `--gpus` above 1
-is refused: this build runs on one GPU.
+is refused: the solver runs on a single device.
 """
 from __future__ import annotations
 
