@@ -11,8 +11,9 @@
  * composite cell of a partition is solved at once by the unbalanced Sinkhorn
  * iteration of Sec. 4.1 (X-update eq. sinkhorn-X-iteration, Y-update
  * eq. proxdiv-problem by Newton, stopping rule eq. PD-gap-KL), the basic-cell
- * Y-marginals are stored on bounding boxes truncated at `trunc` (Sec. 4.4),
- * and the step weights come from GetWeights (Proposition converging-getweights).
+ * Y-marginals are stored on bounding boxes truncated at `trunc` (Sec. 4.4) in
+ * device pools that grow with the boxes (no box size limit), and the step
+ * weights come from GetWeights (Proposition converging-getweights).
  *
  * Conventions for every function:
  *  - return 0 (DDUOT_OK) or a negative DDUOT_E* code; no C++ exception
@@ -40,7 +41,9 @@ enum {
                           (full-support assumption, Sec. 3.2), eps/lambda <= 0 */
   DDUOT_ENOMEM = -2,   /* device allocation failed */
   DDUOT_EHIP = -3,     /* HIP runtime error (text kept in dd_uot_last_error) */
-  DDUOT_ESLOT = -4,    /* a cell's Y-box exceeded box_cap (reported, not fatal) */
+  DDUOT_ESLOT = -4,    /* a step found a device pool too small: the cells that
+                          did not fit kept their state (the pools grow before the
+                          next step; reported, not fatal) */
   DDUOT_ESTATE = -5    /* call not valid in the handle's state */
 };
 
@@ -84,16 +87,22 @@ typedef struct {
   double lenience;           /* swift accepts greedy if the tracked score rises
                                 by at most lenience*|score| (Sec. 4.4: 0.005) */
   int32_t box_margin;        /* Y-box of a cell = bbox of its basic boxes
-                                dilated by this margin, clipped to the grid */
-  int32_t box_cap;           /* maximal Y-box side (device slot capacity) */
+                                dilated by this margin, clipped to the grid
+                                (any size) */
+  int32_t box_cap;           /* box side of the larger in-LDS cell layout
+                                (at most what one workgroup's LDS holds);
+                                cells with wider boxes keep their arrays in
+                                a per-cell global workspace.  A performance
+                                setting: the results do not depend on it */
   int32_t translate;         /* 1: before every Y-half, maximise the cell dual
                                 exactly along (alpha + s, beta - s) (closed
                                 form, removes the slowly contracting constant
                                 mode; not in the paper); 0: the paper's plain
                                 Sinkhorn iteration */
-  int32_t fast_cap;          /* cell solves run in two launches when fast_cap <
-                                box_cap: the cells whose Y-box side exceeds
-                                fast_cap first, with the LDS layout of box_cap,
+  int32_t fast_cap;          /* cell solves run in up to three launches: the
+                                cells wider than box_cap (workspace layout),
+                                then, when fast_cap < box_cap, those wider
+                                than fast_cap with the LDS layout of box_cap,
                                 then the others with the smaller layout of
                                 fast_cap (more workgroups per CU); the results
                                 do not depend on it.  0: the largest side whose
@@ -117,7 +126,8 @@ typedef struct {
   int64_t point_iters;       /* sum over solved cells of |X_J| * Y-halves */
   int32_t max_inner;         /* largest Y-half count of one cell */
   int32_t n_unconverged;     /* cells that hit the iteration cap */
-  int32_t n_overflow;        /* cells skipped because the Y-box exceeded box_cap */
+  int32_t n_overflow;        /* cells not solved because a pool was too small
+                                (then the call returns DDUOT_ESLOT) */
   int32_t n_cells;           /* cells solved (all half-iterations) */
 } dduot_iter_stats;
 
@@ -133,11 +143,11 @@ typedef struct {
   double l1_err_y;           /* || P_Y pi - e^{-beta_hat/lambda} nu ||_1 (state plan) */
   double mass_x, mass_y;     /* |P_X pi|, |P_Y pi| of the state plan */
   int64_t half_iters;        /* half-iterations done so far */
-  int32_t overflow;          /* nonzero if any cell ever overflowed */
+  int32_t overflow;          /* nonzero if any step ever found a pool too small */
 } dduot_score;
 
 /* Fill *cfg with the paper's defaults (Err 2e-5, trunc 1e-15, lenience 0.005,
-   swift, FP32, block start, margin 2, cap 64, max 1000 inner iterations,
+   swift, FP32, block start, margin 2, box_cap 64, max 1000 inner iterations,
    translation step on, no balancing). */
 void dd_uot_default_config(dduot_config* cfg);
 
@@ -176,8 +186,13 @@ int dd_uot_set_eps(dduot_handle* h, int32_t prob, double eps);
 
 /* Run n_half_iters parallel DomDecIter steps (Algorithm 4), alternating
    partitions A and B (Algorithm 2; the first step after init uses A).
-   stats == NULL: asynchronous on the handle's stream.  Otherwise the call
-   synchronises and fills *stats for the steps of this call. */
+   stats == NULL: asynchronous on the handle's stream, except that every
+   fourth half-iteration the call waits for the queued steps to read the pool
+   sizes they needed and grows the pools (state, candidates, cell workspace)
+   to twice any need above half a pool.  Otherwise the call synchronises and
+   fills *stats for the steps of this call.  DDUOT_ESLOT: some earlier step
+   found a pool too small (its cells that did not fit kept their state); the
+   pools have been grown and the call can be repeated. */
 int dd_uot_iterate(dduot_handle* h, int32_t n_half_iters, dduot_iter_stats* stats);
 
 /* Autotuner: threads per cell workgroup (64, 128 or 256, at least the
@@ -198,7 +213,7 @@ int dd_uot_set_graph(dduot_handle* h, int32_t enable);
    staggered GetWeights: one per batch), oldest first, at most `max`
    records of 12 doubles: theta, tracked score before, tracked score of the
    greedy candidate, cells updated, sum |X_J| * inner iterations, max inner
-   iterations, unconverged cells, overflowed cells, inner iterations,
+   iterations, unconverged cells, cells not solved (pool too small), inner iterations,
    algorithmic bytes of the cell solves, log-sum-exp terms of the cell solves,
    pass outputs recomputed in FP64 after an underflow.
    Returns the number of records written (>= 0) or an error code.
@@ -217,7 +232,8 @@ int dd_uot_marginals(dduot_handle* h, int32_t prob, double* px, double* py);
 
 /* Stored Y-marginal nu_i of basic cell `basic` (row-major ids over the
    (n1/cell) x (n2/cell) blocks).  box[4] receives (o1, o2, L1, L2); values
-   receives L1*L2 doubles if L1*L2 <= cap, else DDUOT_EINVAL.  Synchronises. */
+   receives L1*L2 doubles if L1*L2 <= cap, else DDUOT_EINVAL (values == NULL:
+   only the box).  Synchronises. */
 int dd_uot_basic_marginal(dduot_handle* h, int32_t prob, int32_t basic, int32_t box[4],
                           double* values, int64_t cap);
 
@@ -257,8 +273,7 @@ int dd_uot_kernel_time(dduot_handle* h, int64_t* launches, double* total_ms,
    is split in proportion to the fine masses inside its 2 x 2 points, a fine
    basic cell takes the share |mu(X_i)| / |mu(X_I)| of the refined Y-marginal
    of its coarse basic cell I (boxes double, then truncate at cfg->trunc and
-   shrink; a box wider than box_cap keeps its central box_cap rows/columns,
-   see dd_uot_refine_clipped).  cfg: the fine problem (n = 2 n_coarse,
+   shrink).  cfg: the fine problem (n = 2 n_coarse,
    every fine basic cell inside one coarse basic cell: cell divides twice
    the coarse cell, or is 1; same precision); mu, nu: host fine
    marginals, whose 2 x 2 sums should be the coarse ones.  The first
@@ -266,9 +281,6 @@ int dd_uot_kernel_time(dduot_handle* h, int64_t* launches, double* total_ms,
    estimates until then).  `coarse` is left unchanged. */
 int dd_uot_refine(dduot_handle* coarse, const dduot_config* cfg, const double* mu,
                   const double* nu, void* hip_stream, dduot_handle** out);
-/* Basic boxes clipped by the refinement or potential start that created h
-   (0 otherwise). */
-int32_t dd_uot_refine_clipped(const dduot_handle* h);
 
 /* Linear interpolation of a potential (cost units) to the grid with twice the
    points per axis: coarse point I stands for the fine points {2I, 2I+1} and
@@ -298,11 +310,11 @@ int dd_uot_global_sinkhorn(const dduot_config* cfg, const double* mu, const doub
    (alpha, beta) (cost units), pi = exp((alpha + beta - c)/eps) mu x nu
    (Sec. 4.1), split by basic cells (Sec. 4.4 Sinkhorn warm start):
    nu_i(y) = sum_{x in X_i} pi(x, y) over the whole grid, entries below trunc
-   dropped, box = bbox of the rest (a box wider than box_cap keeps its
-   central box_cap rows / columns, counted by dd_uot_refine_clipped); P_X pi
+   dropped, box = bbox of the rest; P_X pi
    and the tracked pieces are those of the kept cell plans, alpha is the
    stitched potential.  The first half-iteration is greedy.  alpha, beta:
-   host, n1*n2, finite.  Needs cell * n2 <= 8192 (LDS of the scan). */
+   host, n1*n2, finite.  Needs cell * (n1 + n2) doubles to fit the LDS of
+   one workgroup (the scan). */
 int dd_uot_init_duals(const dduot_config* cfg, const double* mu, const double* nu,
                       const double* alpha, const double* beta, void* hip_stream,
                       dduot_handle** out);
@@ -334,8 +346,8 @@ typedef struct {
   double global_tol;         /* a global eps stage ends once
                                 KL(P_X pi | e^{-alpha/lambda} mu) <= global_tol |mu|
                                 (Sec. 4.4: a quarter of the DD tolerance) */
-  int32_t coarse_box_cap;    /* DD layers other than the finest use
-                                max(cfg->box_cap, coarse_box_cap) (<= 128) */
+  int32_t coarse_box_cap;    /* DD layers other than the finest use the in-LDS
+                                layout max(cfg->box_cap, coarse_box_cap) (<= 128) */
   double coarse_lenience;    /* ... and this GetWeights lenience */
 } dduot_multiscale;
 
@@ -353,8 +365,9 @@ void dd_uot_default_multiscale(dduot_multiscale* m);
    dd_uot_interpolate_potential as its warm start), and the plan of the last
    one's potentials, split by basic cells of side min(cell, coarse_cell)
    (dd_uot_init_duals), is refined to the first DD layer; with dd_from = 0
-   the coarsest layer starts from the product plan if it fits box_cap
-   (layers of side <= 64 widen box_cap to the grid), else the block start.
+   the coarsest layer starts from the product plan if its side is at most
+   64 or box_cap (layers of side <= 64 widen box_cap to the grid), else the
+   block start.
    On every DD layer run the eps stages, then refine (dd_uot_refine); on the
    finest layer continue to cfg->eps and then iterate until the
    certificate's relative gap is <= target_rel_gap or final_max_halves are
@@ -370,8 +383,9 @@ int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_multiscale* ms,
 
 int dd_uot_synchronize(dduot_handle* h);
 int32_t dd_uot_num_problems(const dduot_handle* h);
-/* Y-box sides of the two cell-solve launches of h (see fast_cap): the fast
-   tier's and the slot capacity; equal when one launch does every cell. */
+/* Box sides of the in-LDS cell layouts of h (see fast_cap and box_cap): the
+   fast tier's and the larger one; equal when one in-LDS launch does every
+   cell that fits. */
 int dd_uot_launch_caps(const dduot_handle* h, int32_t* fast_cap, int32_t* box_cap);
 void dd_uot_destroy(dduot_handle* h);
 const char* dd_uot_last_error(void);

@@ -20,11 +20,10 @@ them also fixed in the design notes):
   R3 state: the basic-cell Y-marginals nu_i stored on bounding boxes, plus the
      X-marginal P_X pi, plus per basic cell a tracked score Hbar_i and the
      last cell potential alpha (stitched).
-  R4 cell Y-box: bbox of the union of the basic boxes of J, dilated by a
-     margin m = min(M, (cap - U) // 2) per axis (U = union extent), clipped to
-     the grid.  A union wider than cap makes the cell overflow: it is skipped
-     (its basic cells keep their old state).  An all-empty union uses the X
-     rectangle of J instead.
+  R4 cell Y-box: bbox of the union of the basic boxes of J, dilated by the
+     margin M per axis, clipped to the grid; boxes of any size (Sec. 4.1 keeps
+     nu_{-J} on the support of nu_J, whatever its extent).  An all-empty union
+     uses the X rectangle of J instead.
   R5 warm start: beta^0 = -lam log(P_Y pi / nu) on the box (0 where P_Y pi = 0),
      i.e. the Y optimality condition eq. (optimality-conditions-KL) evaluated
      for the current plan.
@@ -106,7 +105,6 @@ class Options:
     trunc: float = 1e-15       # Sec. 4.4
     lenience: float = 0.0      # 0.005 in Sec. 4.4; 0 = strict
     margin: int = 2
-    cap: int = 64              # maximal Y-box side
     getweights: str = "swift"  # greedy | safe | swift | staggered | line
     translate: bool = False    # dual line search along (alpha + s, beta - s)
     balance: bool = False      # balancing step of Sec. 4.1 (reading R13)
@@ -304,8 +302,7 @@ def exact_score(p: Problem, st: State) -> float:
 # one cell
 # --------------------------------------------------------------------------
 def cell_box(p: Problem, cell, boxes, opt: Options):
-    """Y-box of composite cell J (reading R4).  Returns (o1, o2, L1, L2) or None
-    on overflow."""
+    """Y-box of composite cell J (reading R4): (o1, o2, L1, L2)."""
     rect = cell["rect"]
     los, his = [], []
     for b in cell["basic"]:
@@ -321,11 +318,7 @@ def cell_box(p: Problem, cell, boxes, opt: Options):
         hi = [rect[0] + rect[2], rect[1] + rect[3]]
     out = []
     for ax, n in ((0, p.n1), (1, p.n2)):
-        U = hi[ax] - lo[ax]
-        if U > opt.cap:
-            return None
-        m = min(opt.margin, (opt.cap - U) // 2)
-        out.append((max(lo[ax] - m, 0), min(hi[ax] + m, n)))
+        out.append((max(lo[ax] - opt.margin, 0), min(hi[ax] + opt.margin, n)))
     return (out[0][0], out[1][0], out[0][1] - out[0][0], out[1][1] - out[1][0])
 
 
@@ -432,12 +425,10 @@ def balance_cell(p: Problem, cell, sol, pi, mu_x, nu_y, C, rows_of):
 def process_cell(p: Problem, cell, boxes, P, opt: Options):
     """Solve one composite cell and re-split its plan into basic cells.
 
-    Returns None on overflow, else dict with the box, the cell potentials, the
-    candidate basic marginals (untruncated and truncated), their pieces
-    H_i (definition cell_piece), P_X of the cell plan, iteration count."""
+    Returns a dict with the box, the cell potentials, the candidate basic
+    marginals (untruncated), their pieces H_i (definition cell_piece), P_X of
+    the cell plan, iteration count."""
     box = cell_box(p, cell, boxes, opt)
-    if box is None:
-        return None
     rect = cell["rect"]
     xi = rect_index(rect, p.n2)
     yi = rect_index(box, p.n2)
@@ -532,8 +523,7 @@ def _dd_step(p: Problem, st: State, cells, part: str, rule: str, opt: Options,
     """One parallel DomDecIter (Algorithm 4) over `cells`, with GetWeights
     `rule` (reading R9; force = greedy).  Mutates `st`."""
     P = aggregate(p, st.boxes)
-    results = [process_cell(p, c, st.boxes, P, opt) for c in cells]
-    upd = [(c, r) for c, r in zip(cells, results) if r is not None]
+    upd = [(c, process_cell(p, c, st.boxes, P, opt)) for c in cells]
     n_upd = len(upd)
 
     # candidate state for the greedy choice
@@ -575,7 +565,7 @@ def _dd_step(p: Problem, st: State, cells, part: str, rule: str, opt: Options,
             new[:, r["yi"]] = r["pi"]
             st.plan[rows] = (1.0 - theta) * st.plan[rows] + theta * new
     stats = dict(part=part, theta=theta, e_cur=e_cur, e_greedy=e_grd, n_cells=len(cells),
-                 n_updated=n_upd, n_overflow=len(cells) - n_upd,
+                 n_updated=n_upd,
                  iters=[r["iters"] for _, r in upd],
                  n_unconverged=sum(1 for _, r in upd if not r["converged"]),
                  point_iters=sum(r["iters"] * r["xi"].size for _, r in upd))
@@ -609,8 +599,6 @@ def half_iteration_sequential(p: Problem, st: State, part: str, opt: Options) ->
     for c in cells:
         P = aggregate(p, st.boxes)
         r = process_cell(p, c, st.boxes, P, opt)
-        if r is None:
-            continue
         iters.append(r["iters"])
         o1, o2 = r["box"][0], r["box"][1]
         for b in c["basic"]:
@@ -656,7 +644,7 @@ def coarsen(a):
     return a.reshape(n1 // 2, 2, n2 // 2, 2).sum(axis=(1, 3))
 
 
-def refine(pc: Problem, stc: State, pf: Problem, trunc: float, cap: int) -> State:
+def refine(pc: Problem, stc: State, pf: Problem, trunc: float) -> State:
     """Warm start of the finer layer from a coarse DD state.
 
     Reading R10: the coarse plan is carried to the fine grid by splitting each
@@ -664,9 +652,8 @@ def refine(pc: Problem, stc: State, pf: Problem, trunc: float, cap: int) -> Stat
     X and Y; the state keeps only basic-cell Y-marginals, so a fine basic
     cell i inside the coarse basic cell I takes the share |mu_f(X_i)| /
     |mu_c(X_I)| of the refined marginal of I.  Boxes double, then entries
-    below `trunc` are dropped and the box shrinks (R7); a box wider than
-    `cap` keeps its central `cap` rows / columns.  The tracked pieces are
-    scaled alike (estimates: the next step is forced greedy)."""
+    below `trunc` are dropped and the box shrinks (R7).  The tracked pieces
+    are scaled alike (estimates: the next step is forced greedy)."""
     ones = np.ones((2, 2))
     nbasic = pf.nb1 * pf.nb2
     boxes, hbar = [], np.zeros(nbasic)
@@ -686,14 +673,7 @@ def refine(pc: Problem, stc: State, pf: Problem, trunc: float, cap: int) -> Stat
         l1, l2 = arr.shape
         fine = np.kron(arr / pc.nu[o1:o1 + l1, o2:o2 + l2], ones) * \
             pf.nu[2 * o1:2 * (o1 + l1), 2 * o2:2 * (o2 + l2)] * f
-        t1, t2, tarr = truncate_to_box(2 * o1, 2 * o2, fine, trunc)
-        if tarr.shape[0] > cap:
-            k = (tarr.shape[0] - cap) // 2
-            t1, tarr = t1 + k, tarr[k:k + cap]
-        if tarr.shape[1] > cap:
-            k = (tarr.shape[1] - cap) // 2
-            t2, tarr = t2 + k, tarr[:, k:k + cap]
-        boxes.append((t1, t2, tarr.copy()))
+        boxes.append(truncate_to_box(2 * o1, 2 * o2, fine, trunc))
     px = np.kron(stc.px / pc.mu, ones) * pf.mu
     abar = np.kron(stc.abar, ones)
     return State(boxes, px, hbar, abar, force_greedy=True)
@@ -726,14 +706,12 @@ def interpolate_potential(a_c, n1f: int, n2f: int) -> np.ndarray:
     return along(along(a_c, 0, n1f), 1, n2f)
 
 
-def init_from_duals(p: Problem, alpha, beta, trunc: float, cap: int | None = None,
-                    windows=None) -> State:
+def init_from_duals(p: Problem, alpha, beta, trunc: float, windows=None) -> State:
     """DD state of the plan pi = exp((alpha + beta - c)/eps) mu x nu (the
     diagonal-scaling form of Sec. 4.1) split by basic cells (reading R11):
     nu_i(y) = sum_{x in X_i} pi(x, y), restricted to the basic cell's scan
     window (default: the whole grid), entries below `trunc` dropped, box =
-    bbox of the rest, a box wider than `cap` keeps its central `cap` rows /
-    columns.  The cell plan is pi on X_i x (kept points of the box); P_X pi
+    bbox of the rest.  The cell plan is pi on X_i x (kept points of the box); P_X pi
     and the tracked pieces Hbar_i (cell_piece) are those of the cell plans.
     The first half-iteration from this state is greedy.  Dense: small grids."""
     C = full_cost(p)
@@ -762,10 +740,6 @@ def init_from_duals(p: Problem, alpha, beta, trunc: float, cap: int | None = Non
         r1, r2 = np.nonzero(keep)
         o1, o2 = r1.min(), r2.min()
         l1, l2 = r1.max() + 1 - o1, r2.max() + 1 - o2
-        if cap is not None and l1 > cap:
-            o1, l1 = o1 + (l1 - cap) // 2, cap
-        if cap is not None and l2 > cap:
-            o2, l2 = o2 + (l2 - cap) // 2, cap
         yrect = (o1, o2, l1, l2)
         kb = keep[o1:o1 + l1, o2:o2 + l2]
         yidx = rect_index(yrect, p.n2)
@@ -799,12 +773,3 @@ def certificate(p: Problem, abar) -> dict:
     return dict(pd=pd, dual=D, primal=E, rel=pd / abs(D), beta_hat=bhat.reshape(p.mu.shape),
                 px=px.reshape(p.mu.shape), py=py.reshape(p.mu.shape),
                 l1_x=float(np.abs(px - np.exp(-a / p.lam) * p.mu.ravel()).sum()))
-
-
-def beta_hat_at(p: Problem, abar, y_flat) -> np.ndarray:
-    """beta_hat at selected grid points (dense over all x); for large grids."""
-    pts = uot.grid_points(p.n1, p.n2, p.h)
-    ys = pts if p.ypos is None else p.ypos.reshape(-1, 2)
-    C = uot.sq_cost(pts, ys[np.asarray(y_flat)])
-    kappa = p.lam / (p.lam + p.eps)
-    return -p.eps * kappa * uot.y_log_integral(np.ravel(abar), p.mu, C, p.eps)

@@ -25,7 +25,7 @@ EXPORTED = (
     "dd_uot_iterate", "dd_uot_history", "dd_uot_score", "dd_uot_marginals",
     "dd_uot_basic_marginal", "dd_uot_potentials", "dd_uot_backward", "dd_uot_set_timing",
     "dd_uot_kernel_time", "dd_uot_synchronize", "dd_uot_num_problems", "dd_uot_destroy",
-    "dd_uot_last_error", "dd_uot_refine", "dd_uot_refine_clipped", "dd_uot_default_multiscale",
+    "dd_uot_last_error", "dd_uot_refine", "dd_uot_default_multiscale",
     "dd_uot_solve_multiscale", "dd_uot_init_moved", "dd_uot_init_batch_moved",
     "dd_uot_backward_ypos", "dd_uot_set_graph", "dd_uot_autotune",
     "dd_uot_interpolate_potential", "dd_uot_global_sinkhorn", "dd_uot_init_duals",
@@ -129,7 +129,6 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dd_uot_backward_ypos": (C.c_int, [H, C.c_int32, C.c_double, dp]),
         "dd_uot_set_graph": (C.c_int, [H, C.c_int32]),
         "dd_uot_autotune": (C.c_int, [H, P(C.c_int32), dp]),
-        "dd_uot_refine_clipped": (C.c_int32, [H]),
         "dd_uot_default_multiscale": (None, [P(dduot_multiscale)]),
         "dd_uot_solve_multiscale": (C.c_int, [P(dduot_config), P(dduot_multiscale), dp, dp,
                                               C.c_void_p, P(H), dp, C.c_int32, P(C.c_int32)]),
@@ -229,11 +228,12 @@ def dd_uot_marginals(h, prob, n1, n2):
     return px.reshape(n1, n2), py.reshape(n1, n2)
 
 
-def dd_uot_basic_marginal(h, prob, basic, cap=1 << 16):
+def dd_uot_basic_marginal(h, prob, basic):
     box = (C.c_int32 * 4)()
-    vals = np.zeros(cap)
-    _check(load().dd_uot_basic_marginal(h, prob, basic, box, _dptr(vals), cap))
+    _check(load().dd_uot_basic_marginal(h, prob, basic, box, None, 0))
     o1, o2, l1, l2 = list(box)
+    vals = np.zeros(max(l1 * l2, 1))
+    _check(load().dd_uot_basic_marginal(h, prob, basic, box, _dptr(vals), vals.size))
     return (o1, o2, vals[: l1 * l2].reshape(l1, l2).copy())
 
 
@@ -282,10 +282,6 @@ def dd_uot_refine(coarse, cfg: dduot_config, mu, nu, stream=None):
     h = C.c_void_p()
     _check(load().dd_uot_refine(coarse, C.byref(cfg), _dptr(mu), _dptr(nu), stream, C.byref(h)))
     return h
-
-
-def dd_uot_refine_clipped(h):
-    return load().dd_uot_refine_clipped(h)
 
 
 def dd_uot_interpolate_potential(coarse, stream=None):

@@ -2,6 +2,7 @@
 #include "../../include/dd_uot.h"
 #include "dd_types.h"
 
+#include <limits.h>
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -12,14 +13,17 @@
 #include <vector>
 
 namespace dduot {
-hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int tcap,
+hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int lcap, int tcap,
                              int precision, bool moved, bool balance, int nt, hipStream_t st);
+hipError_t launch_cell_prep(const Dev& d, int cell_base, int ncells, int precision, hipStream_t st);
+hipError_t launch_bound_begin(unsigned long long* acc, long long* bound, hipStream_t st);
+hipError_t launch_bound_step(const Dev& d, Box* tb, int cell_base, int ncell, int nbasic,
+                             int precision, unsigned long long* acc, long long* bound,
+                             hipStream_t st);
 hipError_t set_cell_lds_limit(size_t bytes);
-size_t cell_lds_bytes(int lcap, int cap, int precision, bool moved);
+size_t cell_lds_bytes(int lcap, int cap, int precision, bool moved, bool big);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st);
-hipError_t launch_aggregate(const Box* box, const double* vals, long cap2, const int* basic_prob,
-                            const Prob* probs, unsigned long long* acc, double* P, int nbasic,
-                            long ngrid, hipStream_t st);
+hipError_t launch_aggregate(const Dev& d, double* P, int nbasic, long ngrid, hipStream_t st);
 hipError_t launch_kl_chunks(const int* cp, const int* cs, const int* cl, const Prob* probs,
                             const double* P, const double* Pg, const double* nu, double* part,
                             int nchunk, hipStream_t st);
@@ -31,8 +35,7 @@ hipError_t launch_advance(long long* kstep, hipStream_t st);
 hipError_t launch_line_search(const Dev& d, const int* chunk_prob, const int* chunk_start,
                               const int* chunk_len, int nchunk, int nprob, int rounds,
                               hipStream_t st);
-hipError_t launch_mix(const Dev& d, int part, int glo, int ghi, int nbasic, int cap, hipStream_t st);
-hipError_t set_mix_lds_limit(size_t bytes);
+hipError_t launch_mix(const Dev& d, int part, int glo, int ghi, int nbasic, hipStream_t st);
 hipError_t launch_certificate(const Prob& p, const double* alpha, const double* mu, const double* nu,
                               const double* px, const double* P, const double* ydel, double* bhat,
                               double* dmu, double* dnu, double* scratch, double* part, int nblk,
@@ -41,31 +44,10 @@ hipError_t launch_grad_ypos(const Prob& p, const double* alpha, const double* mu
                             const double* ydel, const double* bhat, double gout, double* scratch,
                             double* mom, double* out, hipStream_t st);
 hipError_t set_rows_lds_limit(size_t bytes);
-hipError_t launch_scatter_slots(const double* src, const long* off, double* vals, long cap2, int nbasic,
-                                hipStream_t st);
-struct RefineArgs {
-  const Box* cbox;
-  const double* cvals;
-  long ccap2;
-  const double* mu_c;
-  const double* nu_c;
-  const double* chbar;
-  int cn2, cs, cnb2;
-  const int2* fxy;
-  const double* mu_f;
-  const double* nu_f;
-  int fn2, fs, fcap;
-  long fcap2;
-  double trunc;
-  Box* fbox;
-  double* fvals;
-  double* fhbar;
-  int* nclip;
-};
 hipError_t launch_refine(const RefineArgs& A, int fnbasic, const double* px_c, const double* abar_c,
                          double* px_f, double* abar_f, int fn1, hipStream_t st);
 hipError_t launch_interp(const double* ac, int n1c, int n2c, double* af, hipStream_t st);
-size_t from_duals_lds(int s, int gcols, int cap);
+size_t from_duals_lds(int s, int gcols, int hrows);
 hipError_t launch_from_duals(const DualsArgs& A, int nbasic, hipStream_t st);
 hipError_t gs_x_update(const Prob& p, const double* beta, const double* nu, double* alpha,
                        double* scratch, hipStream_t st);
@@ -93,13 +75,13 @@ static int fail(int code, const std::string& msg) {
 static const int kChunk = 16384;
 static const int kLineRounds = 40;   // GetWeights line: f' evaluations per step, at most
 static const int kCertBlocks = 1024;
+static const int kPoolCheck = 2;     // half-iterations between pool checks
 
 struct dduot_handle {
   int nprob = 0;
   int precision = 32;
-  int cap = 0;
+  int cap = 0;         // box side of the larger in-LDS cell layout
   int tcap = 0;        // fast launch tier: cells whose Y-box side fits tcap
-  long cap2 = 0;
   hipStream_t stream = nullptr;
   std::vector<Prob> probs;
   std::vector<Cell> cells;
@@ -125,13 +107,25 @@ struct dduot_handle {
   unsigned long long* d_fx = nullptr;   // fixed-point sums of the aggregation
   double *d_mu = nullptr, *d_nu = nullptr, *d_P = nullptr, *d_Pg = nullptr, *d_px = nullptr,
          *d_pxc = nullptr, *d_abar = nullptr;
-  Box *d_box = nullptr, *d_cbox = nullptr;
-  double *d_vals = nullptr, *d_cand = nullptr, *d_hbar = nullptr, *d_htil = nullptr;
+  Box *d_box = nullptr, *d_cbox = nullptr, *d_nbox = nullptr, *d_cellbox = nullptr;
+  long *d_voff = nullptr, *d_coff = nullptr, *d_nsize = nullptr, *d_csize = nullptr,
+       *d_wsize = nullptr, *d_use = nullptr;
+  int2* d_nsub = nullptr;
+  Box* d_tbox = nullptr;                 // pool bounds: simulated boxes
+  unsigned long long* d_bacc = nullptr;  // ... their per-step sums
+  long long* d_bound = nullptr;          // ... and the largest over the coming steps
+  int* d_sp = nullptr;
+  long long* d_need = nullptr;
+  int* d_capfail = nullptr;
+  // pools (grown between steps by ensure_pools; not in `allocs`)
+  double *d_pool[2] = {nullptr, nullptr}, *d_cand = nullptr;
+  unsigned char* d_ws = nullptr;
+  long pool_cap = 0, cand_cap = 0, ws_cap = 0;
+  double *d_hbar = nullptr, *d_htil = nullptr;
   int *d_iters = nullptr, *d_conv = nullptr;
   double* d_bytes = nullptr;
   double* d_terms = nullptr;
   double* d_fall = nullptr;
-  double *d_ws_lnv = nullptr, *d_ws_lrr = nullptr;
   double* d_ydel = nullptr;
   double *d_mom = nullptr, *d_dy = nullptr;   // Y-position gradient (allocated on first use)
   long long* d_kstep = nullptr;               // device copy of k
@@ -147,14 +141,14 @@ struct dduot_handle {
   double* d_chunk_part = nullptr;
   double *d_theta = nullptr, *d_hist = nullptr;
   double *d_line = nullptr, *d_line_part = nullptr;   // GetWeights line search state
-  int *d_overflow = nullptr, *d_force = nullptr;
+  int* d_force = nullptr;
   double *d_bhat = nullptr, *d_dmu = nullptr, *d_dnu = nullptr, *d_scratch = nullptr,
          *d_cpart = nullptr;
   bool have_cert_prob[1] = {false};
   std::vector<int> cert_done;   // per problem: certificate arrays valid
   // timing
-  int clipped = 0;      // refined basic boxes clipped to the slot size
   bool timing = false;
+  bool slot_fail = false;   // some step ran out of pool space (reported by dd_uot_score)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   std::vector<long long> timed_recs;
 };
@@ -226,8 +220,6 @@ static int validate(const dduot_config* c, const double* mu, const double* nu, i
   if (c->box_cap < 2 * c->cell || c->box_cap > 128)
     return fail(DDUOT_EINVAL, pre + "box_cap must be in [2*cell, 128]");
   if (c->fast_cap < 0 || c->fast_cap > 128) return fail(DDUOT_EINVAL, pre + "fast_cap must be in [0, 128]");
-  if (c->init == DDUOT_INIT_PRODUCT && (c->box_cap < c->n1 || c->box_cap < c->n2))
-    return fail(DDUOT_EINVAL, pre + "product start needs box_cap >= grid side");
   const long n = (long)c->n1 * c->n2;
   double sm = 0.0, sn = 0.0;
   for (long i = 0; i < n; ++i) {
@@ -239,6 +231,169 @@ static int validate(const dduot_config* c, const double* mu, const double* nu, i
   // the fixed-point aggregation holds point sums below 2^13
   if (!(sm < 1024.0) || !(sn < 1024.0))
     return fail(DDUOT_EINVAL, pre + "total masses must be below 1024 (rescale the problem)");
+  return DDUOT_OK;
+}
+
+// Candidate doubles and workspace bytes of one step over partition `part`
+// with the basic boxes `box` (the rule of k_cell_prep).
+static void step_need(const dduot_handle* h, const std::vector<Box>& box, int part, long* cand,
+                      long* ws) {
+  const int base = part == 0 ? 0 : h->ncell[0];
+  long c = 0, w = 0;
+  for (int j = 0; j < h->ncell[part]; ++j) {
+    const Cell& C = h->cells[base + j];
+    const Box yb = cell_ybox(C, h->probs[C.prob], box.data());
+    const long ny = (long)yb.l1 * yb.l2;
+    const int side = std::max(yb.l1, yb.l2);
+    c += (long)C.nb * ny;
+    w += (long)cell_ws_layout(h->precision == 64 ? 8 : 4, ny, side, h->moved, side > h->cap).total;
+  }
+  *cand = c;
+  *ws = w;
+}
+
+// Grow the pools to hold at least the given sizes (doubles, doubles, bytes).
+// The state pools keep their content: the current one is copied into the
+// new first pool.  Any captured graph holds the old pointers and is dropped.
+static int ensure_pools(dduot_handle* h, long state, long cand, long ws) {
+  hipStream_t st = h->stream;
+  const long floor_d = 4096;
+  if (state > h->pool_cap) {
+    const long cap = std::max(state, floor_d);
+    double *n0 = nullptr, *n1 = nullptr;
+    hipError_t e = hipMalloc((void**)&n0, sizeof(double) * cap);
+    if (e == hipSuccess) e = hipMalloc((void**)&n1, sizeof(double) * cap);
+    if (e != hipSuccess) {
+      if (n0) (void)hipFree(n0);
+      return fail(DDUOT_ENOMEM, std::string("state pool of ") + std::to_string(cap) +
+                                    " doubles: " + hipGetErrorString(e));
+    }
+    if (h->pool_cap > 0) {
+      int sp = 0;
+      HIPCHK(hipMemcpyAsync(&sp, h->d_sp, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipMemcpyAsync(n0, h->d_pool[sp], sizeof(double) * h->pool_cap,
+                            hipMemcpyDeviceToDevice, st));
+      static const int zero = 0;
+      HIPCHK(hipMemcpyAsync(h->d_sp, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+      (void)hipFree(h->d_pool[0]);
+      (void)hipFree(h->d_pool[1]);
+    }
+    h->d_pool[0] = n0;
+    h->d_pool[1] = n1;
+    h->pool_cap = cap;
+    h->d.pool0 = n0;
+    h->d.pool1 = n1;
+    h->d.pool_cap = cap;
+    if (h->gexec) {
+      (void)hipGraphExecDestroy(h->gexec);
+      h->gexec = nullptr;
+    }
+  }
+  if (cand > h->cand_cap || ws > h->ws_cap) {
+    HIPCHK(hipStreamSynchronize(st));
+    if (cand > h->cand_cap) {
+      const long cap = std::max(cand, floor_d);
+      if (h->d_cand) (void)hipFree(h->d_cand);
+      h->d_cand = nullptr;
+      h->cand_cap = 0;
+      hipError_t e = hipMalloc((void**)&h->d_cand, sizeof(double) * cap);
+      if (e != hipSuccess)
+        return fail(DDUOT_ENOMEM, std::string("candidate pool: ") + hipGetErrorString(e));
+      h->cand_cap = cap;
+    }
+    if (ws > h->ws_cap) {
+      const long cap = std::max(ws, 8 * floor_d);
+      if (h->d_ws) (void)hipFree(h->d_ws);
+      h->d_ws = nullptr;
+      h->ws_cap = 0;
+      hipError_t e = hipMalloc((void**)&h->d_ws, cap);
+      if (e != hipSuccess)
+        return fail(DDUOT_ENOMEM, std::string("cell workspace pool: ") + hipGetErrorString(e));
+      h->ws_cap = cap;
+    }
+    h->d.cand = h->d_cand;
+    h->d.cand_cap = h->cand_cap;
+    h->d.ws = h->d_ws;
+    h->d.ws_cap = h->ws_cap;
+    if (h->gexec) {
+      (void)hipGraphExecDestroy(h->gexec);
+      h->gexec = nullptr;
+    }
+  }
+  return DDUOT_OK;
+}
+
+// Before the next `nhalf` half-iterations: bound their pool needs on the
+// device (k_bound_*: the Y-box rule replayed without truncation, step after
+// step, from the current boxes), read the bounds and the failure flags, and
+// grow every pool below its bound to 1.25 times the bound.  A step that
+// found a pool too small (not expected under these bounds) left the cells
+// that did not fit (or, for the state pool, the whole state) unchanged:
+// DDUOT_ESLOT.
+static int check_pools(dduot_handle* h, int nhalf) {
+  hipStream_t st = h->stream;
+  HIPCHK(launch_bound_begin(h->d_bacc, h->d_bound, st));
+  HIPCHK(hipMemcpyAsync(h->d_tbox, h->d_box, sizeof(Box) * h->nbasic, hipMemcpyDeviceToDevice, st));
+  for (int i = 0; i < nhalf; ++i) {
+    const int part = (int)((h->k + i) % 2);
+    if (h->staggered) {
+      for (int bt = 0; bt < 4; ++bt)
+        HIPCHK(launch_bound_step(h->d, h->d_tbox, h->boff[part][bt], h->bn[part][bt], h->nbasic,
+                                 h->precision, h->d_bacc, h->d_bound, st));
+    } else {
+      HIPCHK(launch_bound_step(h->d, h->d_tbox, h->boff[part][0], h->ncell[part], h->nbasic,
+                               h->precision, h->d_bacc, h->d_bound, st));
+    }
+  }
+  long long bound[3] = {0, 0, 0};
+  std::vector<int> fl(h->nprob, 0);
+  HIPCHK(hipMemcpyAsync(bound, h->d_bound, sizeof(bound), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(fl.data(), h->d_capfail, sizeof(int) * h->nprob, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  auto want = [](long long n, long cap) { return n > cap ? (long)(n + n / 4) : 0L; };
+  CHK(ensure_pools(h, want(bound[0], h->pool_cap), want(bound[1], h->cand_cap),
+                   want(bound[2], h->ws_cap)));
+  bool failed = false;
+  for (int v : fl) failed = failed || v != 0;
+  if (failed) {
+    std::vector<int> zeros(h->nprob, 0);
+    HIPCHK(hipMemcpyAsync(h->d_capfail, zeros.data(), sizeof(int) * h->nprob, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    h->slot_fail = true;
+    return fail(DDUOT_ESLOT, "a step found a pool too small (the cells that did not fit kept "
+                             "their state); the pools have been grown");
+  }
+  return DDUOT_OK;
+}
+
+// After a kernel wrote new basic boxes into d_box: place them compactly in a
+// state pool large enough for them (the first one, made current), sized with
+// the candidate and workspace needs of the next steps.  Synchronises.
+static int place_state(dduot_handle* h) {
+  hipStream_t st = h->stream;
+  std::vector<Box> box(h->nbasic);
+  HIPCHK(hipMemcpyAsync(box.data(), h->d_box, sizeof(Box) * h->nbasic, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<long> off(h->nbasic, 0);
+  long tot = 0;
+  for (int b = 0; b < h->nbasic; ++b) {
+    off[b] = tot;
+    tot += (long)box[b].l1 * box[b].l2;
+  }
+  long cneed = 0, wneed = 0;
+  for (int part = 0; part < 2; ++part) {
+    long c = 0, w = 0;
+    step_need(h, box, part, &c, &w);
+    cneed = std::max(cneed, c);
+    wneed = std::max(wneed, w);
+  }
+  CHK(ensure_pools(h, 2 * tot, 2 * cneed, 2 * wneed));
+  HIPCHK(hipMemcpyAsync(h->d_voff, off.data(), sizeof(long) * h->nbasic, hipMemcpyHostToDevice, st));
+  static const int zero = 0;
+  HIPCHK(hipMemcpyAsync(h->d_sp, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
   return DDUOT_OK;
 }
 
@@ -285,15 +440,13 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
       return fail(DDUOT_EINVAL, "all problems of a handle must share one precision");
     h->cap = std::max(h->cap, cfgs[k].box_cap);
   }
-  h->cap2 = (long)h->cap * h->cap;
   h->staggered = cfgs[0].getweights == DDUOT_GW_STAGGERED;
   for (int k = 0; k < nprob; ++k) h->any_line |= cfgs[k].getweights == DDUOT_GW_LINE;
   for (int k = 0; k < nprob; ++k)
     if ((cfgs[k].getweights == DDUOT_GW_STAGGERED) != h->staggered)
       return fail(DDUOT_EINVAL, "staggered GetWeights: all problems of a handle or none");
-  const size_t lds_cell = cell_lds_bytes(h->cap, h->cap, h->precision, h->moved);
-  const size_t lds_mix = sizeof(double) * h->cap2;
-  if ((long)lds_cell > max_lds || (long)lds_mix > max_lds)
+  const size_t lds_cell = cell_lds_bytes(h->cap, h->cap, h->precision, h->moved, false);
+  if ((long)lds_cell > max_lds)
     return fail(DDUOT_EINVAL, "box_cap too large for the LDS of one workgroup");
   // fast tier: by default the largest box side whose cell LDS lets three
   // workgroups share a CU; cells with larger boxes run in a second launch
@@ -305,13 +458,12 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   int fc = cfgs[0].fast_cap;
   if (fc <= 0)
     for (int c = h->cap; c >= 1; --c)
-      if (3 * cell_lds_bytes(c, h->cap, h->precision, h->moved) <= (size_t)lds_cu) {
+      if (3 * cell_lds_bytes(c, h->cap, h->precision, h->moved, false) <= (size_t)lds_cu) {
         fc = c;
         break;
       }
   h->tcap = (fc <= 0 || fc >= h->cap) ? h->cap : fc;
   HIPCHK(set_cell_lds_limit(lds_cell));
-  HIPCHK(set_mix_lds_limit(lds_mix));
 
   // problems, basic cells, composite cells
   std::vector<int> basic_prob;
@@ -332,7 +484,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
     p.ch = c.h * c.h / c.eps;
     p.err = c.sinkhorn_err; p.trunc = c.trunc; p.lenience = c.lenience;
     p.getweights = c.getweights; p.fixed_iters = c.fixed_inner_iters; p.max_iter = c.sinkhorn_max_iter;
-    p.margin = c.box_margin; p.cap = c.box_cap; p.precision = c.precision;
+    p.margin = c.box_margin; p.precision = c.precision;
     p.translate = c.translate;
     p.balance = c.balance;
     if (c.balance) h->balance = true;
@@ -493,8 +645,21 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_abar, h->ngrid));
   CHK(dalloc(h, &h->d_box, h->nbasic));
   CHK(dalloc(h, &h->d_cbox, h->nbasic));
-  CHK(dalloc(h, &h->d_vals, (size_t)h->nbasic * h->cap2));
-  CHK(dalloc(h, &h->d_cand, (size_t)h->nbasic * h->cap2));
+  CHK(dalloc(h, &h->d_nbox, h->nbasic));
+  CHK(dalloc(h, &h->d_cellbox, h->cells.size()));
+  CHK(dalloc(h, &h->d_voff, h->nbasic));
+  CHK(dalloc(h, &h->d_coff, h->nbasic));
+  CHK(dalloc(h, &h->d_nsize, h->nbasic));
+  CHK(dalloc(h, &h->d_nsub, h->nbasic));
+  CHK(dalloc(h, &h->d_csize, h->cells.size()));
+  CHK(dalloc(h, &h->d_wsize, h->cells.size()));
+  CHK(dalloc(h, &h->d_use, 4));
+  CHK(dalloc(h, &h->d_sp, 1));
+  CHK(dalloc(h, &h->d_need, 4));
+  CHK(dalloc(h, &h->d_tbox, h->nbasic));
+  CHK(dalloc(h, &h->d_bacc, 4));
+  CHK(dalloc(h, &h->d_bound, 4));
+  CHK(dalloc(h, &h->d_capfail, nprob));
   CHK(dalloc(h, &h->d_hbar, h->nbasic));
   CHK(dalloc(h, &h->d_htil, h->nbasic));
   CHK(dalloc(h, &h->d_iters, h->cells.size()));
@@ -502,11 +667,6 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_bytes, h->cells.size()));
   CHK(dalloc(h, &h->d_terms, h->cells.size()));
   CHK(dalloc(h, &h->d_fall, h->cells.size()));
-  // per-cell workspace: FP64 kernels keep log nu and log r there (FP64);
-  // FP32 kernels keep log r there (FP32, cap2 floats per cell)
-  const size_t ncap = h->cells.size() * (size_t)h->cap2;
-  CHK(dalloc(h, &h->d_ws_lnv, h->precision == 64 ? ncap : 1));
-  CHK(dalloc(h, &h->d_ws_lrr, h->precision == 64 ? ncap : (ncap + 1) / 2));
   CHK(dalloc(h, &h->d_chunk_prob, h->nchunk));
   CHK(dalloc(h, &h->d_chunk_start, h->nchunk));
   CHK(dalloc(h, &h->d_chunk_len, h->nchunk));
@@ -515,7 +675,6 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_theta, nprob));
   CHK(dalloc(h, &h->d_line, 8 * (size_t)nprob));
   CHK(dalloc(h, &h->d_hist, (size_t)nprob * h->hist_cap * kHistFields));
-  CHK(dalloc(h, &h->d_overflow, nprob));
   CHK(dalloc(h, &h->d_force, nprob));
   CHK(dalloc(h, &h->d_kstep, 1));
   CHK(dalloc(h, &h->d_bhat, h->ngrid));
@@ -558,13 +717,19 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   HIPCHK(launch_fill(h->d_abar, h->ngrid, 0.0, st));
   HIPCHK(launch_fill(h->d_hist, (long)nprob * h->hist_cap * kHistFields, 0.0, st));
   std::vector<int> zeros(nprob, 0);
-  HIPCHK(hipMemcpyAsync(h->d_overflow, zeros.data(), sizeof(int) * nprob, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_capfail, zeros.data(), sizeof(int) * nprob, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h->d_force, zeros.data(), sizeof(int) * nprob, hipMemcpyHostToDevice, st));
+  static const long long kzeros[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(h->d_need, kzeros, sizeof(kzeros), hipMemcpyHostToDevice, st));
+  static const int kzero_i = 0;
+  HIPCHK(hipMemcpyAsync(h->d_sp, &kzero_i, sizeof(int), hipMemcpyHostToDevice, st));
   static const long long kzero = 0;
   HIPCHK(hipMemcpyAsync(h->d_kstep, &kzero, sizeof(long long), hipMemcpyHostToDevice, st));
 
-  // state slots: block start = nu on the block; product start = |mu_i| nu.
-  // Staged compactly on the host, scattered into the fixed-capacity slots.
+  Dev& d = h->d;
+  d.lcap = h->cap;
+  // start state: block start = nu on the block; product start = |mu_i| nu,
+  // written compactly into the first state pool
   {
     std::vector<long> off(h->nbasic + 1, 0);
     for (int b = 0; b < h->nbasic; ++b) off[b + 1] = off[b] + (long)box[b].l1 * box[b].l2;
@@ -587,19 +752,21 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
           }
       }
     }
-    double* d_stage = nullptr;
-    long* d_off = nullptr;
-    HIPCHK(hipMalloc(&d_stage, sizeof(double) * std::max<size_t>(stage.size(), 1)));
-    HIPCHK(hipMalloc(&d_off, sizeof(long) * off.size()));
-    HIPCHK(hipMemcpyAsync(d_stage, stage.data(), sizeof(double) * stage.size(), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_off, off.data(), sizeof(long) * off.size(), hipMemcpyHostToDevice, st));
-    HIPCHK(launch_scatter_slots(d_stage, d_off, h->d_vals, h->cap2, h->nbasic, st));
+    long cneed = 0, wneed = 0;
+    for (int part = 0; part < 2; ++part) {
+      long c = 0, w = 0;
+      step_need(h, box, part, &c, &w);
+      cneed = std::max(cneed, c);
+      wneed = std::max(wneed, w);
+    }
+    CHK(ensure_pools(h, 2 * off[h->nbasic], 2 * cneed, 2 * wneed));
+    HIPCHK(hipMemcpyAsync(h->d_pool[0], stage.data(), sizeof(double) * stage.size(),
+                          hipMemcpyHostToDevice, st));
+    off.pop_back();
+    HIPCHK(hipMemcpyAsync(h->d_voff, off.data(), sizeof(long) * off.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipFree(d_stage));
-    HIPCHK(hipFree(d_off));
   }
 
-  Dev& d = h->d;
   d.probs = h->d_probs;
   d.cells = h->d_cells;
   d.basic_prob = h->d_basic_prob;
@@ -615,9 +782,20 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   d.pxc = h->d_pxc;
   d.abar = h->d_abar;
   d.box = h->d_box;
-  d.vals = h->d_vals;
+  d.voff = h->d_voff;
+  d.sp = h->d_sp;
   d.cbox = h->d_cbox;
-  d.cand = h->d_cand;
+  d.coff = h->d_coff;
+  d.nbox = h->d_nbox;
+  d.nsub = h->d_nsub;
+  d.nsize = h->d_nsize;
+  d.nuse = h->d_use + 2;
+  d.cellbox = h->d_cellbox;
+  d.csize = h->d_csize;
+  d.wsize = h->d_wsize;
+  d.cuse = h->d_use;
+  d.need = h->d_need;
+  d.cap_fail = h->d_capfail;
   d.hbar = h->d_hbar;
   d.htil = h->d_htil;
   d.cell_iters = h->d_iters;
@@ -625,8 +803,6 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   d.cell_bytes = h->d_bytes;
   d.cell_terms = h->d_terms;
   d.cell_fall = h->d_fall;
-  d.ws_lnv = h->d_ws_lnv;
-  d.ws_lrr = h->d_ws_lrr;
   d.ydel = h->d_ydel;
   d.kstep = h->d_kstep;
   d.chunk_part = h->d_chunk_part;
@@ -634,10 +810,8 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   d.line = h->d_line;
   d.line_part = h->d_line_part;
   d.hist = h->d_hist;
-  d.overflow_any = h->d_overflow;
   d.force_greedy = h->d_force;
   d.hist_cap = h->hist_cap;
-  d.cap2 = h->cap2;
   HIPCHK(hipStreamSynchronize(st));
   return DDUOT_OK;
 }
@@ -651,6 +825,8 @@ static void release(dduot_handle* h) {
     (void)hipEventDestroy(e.second);
   }
   for (void* p : h->allocs) (void)hipFree(p);
+  for (void* p : {(void*)h->d_pool[0], (void*)h->d_pool[1], (void*)h->d_cand, (void*)h->d_ws})
+    if (p) (void)hipFree(p);
   delete h;
 }
 
@@ -730,8 +906,8 @@ extern "C" int dd_uot_set_eps(dduot_handle* h, int32_t prob, double eps) {
 static int dd_step(dduot_handle* h, int part, int lo, int n, int blo, int bhi) {
   hipStream_t st = h->stream;
   const Dev& d = h->d;
-  HIPCHK(launch_aggregate(h->d_box, h->d_vals, h->cap2, h->d_basic_prob, h->d_probs, h->d_fx, h->d_P,
-                          h->nbasic, h->ngrid, st));
+  HIPCHK(launch_aggregate(d, h->d_P, h->nbasic, h->ngrid, st));
+  HIPCHK(launch_cell_prep(d, lo, n, h->precision, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->timing) {
     HIPCHK(hipEventCreate(&e0));
@@ -753,7 +929,7 @@ static int dd_step(dduot_handle* h, int part, int lo, int n, int blo, int bhi) {
   if (h->any_line)
     HIPCHK(launch_line_search(d, h->d_chunk_prob, h->d_chunk_start, h->d_chunk_len, h->nchunk,
                               h->nprob, kLineRounds, st));
-  HIPCHK(launch_mix(d, part, lo, lo + n, h->nbasic, h->cap, st));
+  HIPCHK(launch_mix(d, part, lo, lo + n, h->nbasic, st));
   HIPCHK(launch_advance(h->d_kstep, st));
   h->nrec += 1;
   return DDUOT_OK;
@@ -823,8 +999,9 @@ extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
   hipStream_t st = h->stream;
   const int part = (int)(h->k % 2);
   const int base = h->boff[part][0];
-  HIPCHK(launch_aggregate(h->d_box, h->d_vals, h->cap2, h->d_basic_prob, h->d_probs, h->d_fx, h->d_P,
-                          h->nbasic, h->ngrid, st));
+  CHK(check_pools(h, 1));
+  HIPCHK(launch_aggregate(h->d, h->d_P, h->nbasic, h->ngrid, st));
+  HIPCHK(launch_cell_prep(h->d, base, h->ncell[part], h->precision, st));
   const int cand[3] = {64, 128, 256};
   double best = 1e300;
   int pick = 256;
@@ -875,24 +1052,26 @@ extern "C" int dd_uot_iterate(dduot_handle* h, int32_t n_half_iters, dduot_iter_
   if (!h) return fail(DDUOT_EINVAL, "null handle");
   if (n_half_iters < 0) return fail(DDUOT_EINVAL, "n_half_iters must be >= 0");
   const long long r0 = h->nrec;
-  int i = 0;
-  if (h->use_graph && !h->timing) {
-    if (h->k % 2 == 1 && i < n_half_iters) {
-      CHK(half_iteration(h, 1));
-      ++i;
-    }
-    if (n_half_iters - i >= 2 && !h->gexec) CHK(capture_pair(h));
-    const long long per_pair = h->staggered ? 8 : 2;
-    for (; n_half_iters - i >= 2; i += 2) {
+  // the pools are checked (and grown) before every kPoolCheck half-iterations;
+  // with a graph, A+B pairs are replayed (a B step first runs alone)
+  const bool graph = h->use_graph && !h->timing;
+  for (int i = 0; i < n_half_iters;) {
+    int chunk = std::min(n_half_iters - i, kPoolCheck);
+    if (graph && h->k % 2 == 1) chunk = 1;
+    CHK(check_pools(h, chunk));
+    if (graph && chunk == 2) {
+      if (!h->gexec) CHK(capture_pair(h));
       HIPCHK(hipGraphLaunch(h->gexec, h->stream));
       h->k += 2;
-      h->nrec += per_pair;
+      h->nrec += h->staggered ? 8 : 2;
+    } else {
+      for (int j = 0; j < chunk; ++j) CHK(half_iteration(h, (int)(h->k % 2)));
     }
+    i += chunk;
   }
-  for (; i < n_half_iters; ++i) CHK(half_iteration(h, (int)(h->k % 2)));
   for (int p = 0; p < h->nprob; ++p) h->cert_done[p] = 0;
   if (stats) {
-    HIPCHK(hipStreamSynchronize(h->stream));
+    CHK(check_pools(h, 0));
     memset(stats, 0, sizeof(*stats));
     stats->half_iters = n_half_iters;
     std::vector<double> rec;
@@ -927,9 +1106,7 @@ extern "C" int dd_uot_history(dduot_handle* h, int32_t prob, int32_t max, double
 
 // Re-aggregate the current state into d_P (the state Y-marginal).
 static int refresh_state_marginal(dduot_handle* h) {
-  HIPCHK(launch_aggregate(h->d_box, h->d_vals, h->cap2, h->d_basic_prob, h->d_probs, h->d_fx, h->d_P,
-                          h->nbasic, h->ngrid,
-                          h->stream));
+  HIPCHK(launch_aggregate(h->d, h->d_P, h->nbasic, h->ngrid, h->stream));
   return DDUOT_OK;
 }
 
@@ -951,8 +1128,6 @@ extern "C" int dd_uot_score(dduot_handle* h, int32_t prob, dduot_score* out) {
   HIPCHK(hipMemcpyAsync(part.data(), h->d_cpart, sizeof(double) * part.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(chunks.data(), h->d_chunk_part, sizeof(double) * chunks.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(hb.data(), h->d_hbar + p.basic_off, sizeof(double) * p.nbasic, hipMemcpyDeviceToHost, st));
-  int ovf = 0;
-  HIPCHK(hipMemcpyAsync(&ovf, h->d_overflow + prob, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = 0; b < kCertBlocks; ++b)
@@ -973,7 +1148,7 @@ extern "C" int dd_uot_score(dduot_handle* h, int32_t prob, dduot_score* out) {
   out->mass_x = s[6];
   out->mass_y = s[7];
   out->half_iters = h->k;
-  out->overflow = ovf;
+  out->overflow = h->slot_fail ? 1 : 0;
   h->cert_done[prob] = 1;
   (void)n;
   return DDUOT_OK;
@@ -997,13 +1172,17 @@ extern "C" int dd_uot_basic_marginal(dduot_handle* h, int32_t prob, int32_t basi
   if (basic < 0 || basic >= p.nbasic) return fail(DDUOT_EINVAL, "basic cell out of range");
   const int gb = p.basic_off + basic;
   Box b;
+  long off = 0;
+  int sp = 0;
   HIPCHK(hipMemcpyAsync(&b, h->d_box + gb, sizeof(Box), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(&off, h->d_voff + gb, sizeof(long), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(&sp, h->d_sp, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   box[0] = b.o1; box[1] = b.o2; box[2] = b.l1; box[3] = b.l2;
   const int64_t n = (int64_t)b.l1 * b.l2;
-  if (n > cap) return fail(DDUOT_EINVAL, "values buffer too small");
+  if (values && n > cap) return fail(DDUOT_EINVAL, "values buffer too small");
   if (n > 0 && values) {
-    HIPCHK(hipMemcpyAsync(values, h->d_vals + (size_t)gb * h->cap2, sizeof(double) * n,
+    HIPCHK(hipMemcpyAsync(values, h->d_pool[sp] + off, sizeof(double) * n,
                           hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
   }
@@ -1125,17 +1304,16 @@ extern "C" int dd_uot_refine(dduot_handle* coarse, const dduot_config* cfg, cons
       return fail(DDUOT_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
     }
   }
-  int* d_nclip = nullptr;
   auto body = [&]() -> int {
     hipStream_t st = h->stream;
     const Prob& pf = h->probs[0];
-    CHK(dalloc(h, &d_nclip, 1));
-    static const int zero = 0;
-    HIPCHK(hipMemcpyAsync(d_nclip, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+    int csp = 0;
+    HIPCHK(hipMemcpyAsync(&csp, coarse->d_sp, sizeof(int), hipMemcpyDeviceToHost, coarse->stream));
+    HIPCHK(hipStreamSynchronize(coarse->stream));
     RefineArgs A{};
     A.cbox = coarse->d_box;
-    A.cvals = coarse->d_vals;
-    A.ccap2 = coarse->cap2;
+    A.cvals = coarse->d_pool[csp];
+    A.cvoff = coarse->d_voff;
     A.mu_c = coarse->d_mu;
     A.nu_c = coarse->d_nu;
     A.chbar = coarse->d_hbar;
@@ -1147,22 +1325,21 @@ extern "C" int dd_uot_refine(dduot_handle* coarse, const dduot_config* cfg, cons
     A.nu_f = h->d_nu;
     A.fn2 = pf.n2;
     A.fs = pf.s;
-    A.fcap = h->cap;
-    A.fcap2 = h->cap2;
     A.trunc = pf.trunc;
     A.fbox = h->d_box;
-    A.fvals = h->d_vals;
+    A.fvoff = h->d_voff;
     A.fhbar = h->d_hbar;
-    A.nclip = d_nclip;
+    A.phase = 0;
+    HIPCHK(launch_refine(A, pf.nbasic, coarse->d_px, coarse->d_abar, h->d_px, h->d_abar, pf.n1, st));
+    CHK(place_state(h));
+    A.fvals = h->d_pool[0];
+    A.phase = 1;
     HIPCHK(launch_refine(A, pf.nbasic, coarse->d_px, coarse->d_abar, h->d_px, h->d_abar, pf.n1, st));
     // the tracked pieces of the refined state are only estimates: the next
     // half-iteration is greedy, which recomputes them
     static const int one = 1;
     HIPCHK(hipMemcpyAsync(h->d_force, &one, sizeof(int), hipMemcpyHostToDevice, st));
-    int nclip = 0;
-    HIPCHK(hipMemcpyAsync(&nclip, d_nclip, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    h->clipped = nclip;
     return DDUOT_OK;
   };
   int r = body();
@@ -1176,7 +1353,6 @@ extern "C" int dd_uot_refine(dduot_handle* coarse, const dduot_config* cfg, cons
   return DDUOT_OK;
 }
 
-extern "C" int32_t dd_uot_refine_clipped(const dduot_handle* h) { return h ? h->clipped : 0; }
 
 // ---- global Sinkhorn warm start (Sec. 4.4) and potential-based refinement ----
 static const int kGsBlocks = 256;
@@ -1288,20 +1464,20 @@ static int state_from_duals(dduot_handle* h, const double* d_alpha, const double
                             const std::vector<Box>& win) {
   const Prob& p = h->probs[0];
   hipStream_t st = h->stream;
-  int gcols = 1;
-  for (const Box& b : win) gcols = std::max(gcols, b.l2);
+  int gcols = 1, hrows = 1;
+  for (const Box& b : win) {
+    gcols = std::max(gcols, b.l2);
+    hrows = std::max(hrows, b.l1);
+  }
   int dev = 0, max_lds = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  if ((long)from_duals_lds(p.s, gcols, h->cap) + 4096 > max_lds)
+  if ((long)from_duals_lds(p.s, gcols, hrows) + 4096 > max_lds)
     return fail(DDUOT_EINVAL, "scan window too wide for the LDS of one workgroup");
   Box* d_win = nullptr;
-  int* d_nclip = nullptr;
   CHK(dalloc(h, &d_win, win.size()));
-  CHK(dalloc(h, &d_nclip, 1));
   HIPCHK(hipMemcpyAsync(d_win, win.data(), sizeof(Box) * win.size(), hipMemcpyHostToDevice, st));
-  static const int zero = 0, one = 1;
-  HIPCHK(hipMemcpyAsync(d_nclip, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+  static const int one = 1;
   DualsArgs A{};
   A.alpha = d_alpha;
   A.beta = d_beta;
@@ -1312,26 +1488,26 @@ static int state_from_duals(dduot_handle* h, const double* d_alpha, const double
   A.n1 = p.n1;
   A.n2 = p.n2;
   A.s = p.s;
-  A.cap = h->cap;
   A.gcols = gcols;
-  A.cap2 = h->cap2;
+  A.hrows = hrows;
   A.eps = p.eps;
   A.lam = p.lam;
   A.ch = p.ch;
   A.trunc = p.trunc;
   A.mass_nu = p.mass_nu;
   A.box = h->d_box;
-  A.vals = h->d_vals;
+  A.voff = h->d_voff;
   A.px = h->d_px;
   A.hbar = h->d_hbar;
-  A.nclip = d_nclip;
+  A.phase = 0;
+  HIPCHK(launch_from_duals(A, p.nbasic, st));
+  CHK(place_state(h));
+  A.vals = h->d_pool[0];
+  A.phase = 1;
   HIPCHK(launch_from_duals(A, p.nbasic, st));
   HIPCHK(hipMemcpyAsync(h->d_abar, d_alpha, sizeof(double) * p.n1 * p.n2, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(h->d_force, &one, sizeof(int), hipMemcpyHostToDevice, st));
-  int nclip = 0;
-  HIPCHK(hipMemcpyAsync(&nclip, d_nclip, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  h->clipped = nclip;
   return DDUOT_OK;
 }
 
@@ -1563,7 +1739,7 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
       c.sinkhorn_max_iter = std::max(cfg->sinkhorn_max_iter, ms->coarse_max_iter);
       c.box_cap = std::max(c.box_cap, ms->coarse_box_cap);
       c.lenience = ms->coarse_lenience;
-      // small layers keep whole-grid boxes (no overflow)
+      // small layers: the whole grid fits the in-LDS layout
       if (std::max(c.n1, c.n2) <= 64) c.box_cap = std::max(c.box_cap, std::max(c.n1, c.n2));
     }
     const double h2 = c.h * c.h;

@@ -36,16 +36,14 @@ __global__ void k_fx_finish(const unsigned long long* acc, double* P, long n) {
 }
 
 // P_Y pi = sum_i nu_i (Sec. 4.1): one workgroup per basic cell scatters its box.
-__global__ __launch_bounds__(kBlock) void k_aggregate(const Box* box, const double* vals, long cap2,
-                                                      const int* basic_prob, const Prob* probs,
-                                                      unsigned long long* acc) {
+__global__ __launch_bounds__(kBlock) void k_aggregate(Dev d) {
   const int b = blockIdx.x;
-  const Box bx = box[b];
+  const Box bx = d.box[b];
   if (bx.l1 <= 0 || bx.l2 <= 0) return;
-  const Prob& p = probs[basic_prob[b]];
+  const Prob& p = d.probs[d.basic_prob[b]];
   const long n = (long)bx.l1 * bx.l2;
-  const double* v = vals + b * cap2;
-  unsigned long long* out = acc + 2 * (long)p.grid_off;
+  const double* v = state_pool(d) + d.voff[b];
+  unsigned long long* out = d.fxacc + 2 * (long)p.grid_off;
   for (long o = threadIdx.x; o < n; o += kBlock) {
     const int j1 = (int)(o / bx.l2), j2 = (int)(o - (long)j1 * bx.l2);
     const double x = v[o];
@@ -54,17 +52,17 @@ __global__ __launch_bounds__(kBlock) void k_aggregate(const Box* box, const doub
 }
 
 // Candidate P_Y for GetWeights: the candidate marginal of every basic cell
-// whose composite cell (in partition `part`) lies in [glo, ghi), the state
-// marginal of every other basic cell.
+// whose composite cell (in partition `part`) lies in [glo, ghi) and was
+// solved, the state marginal of every other basic cell.
 __global__ __launch_bounds__(kBlock) void k_aggregate_sel(Dev d, int part, int glo, int ghi) {
   const int b = blockIdx.x;
   const int J = d.basic_cell[part][b];
-  const bool in = J >= glo && J < ghi;
+  const bool in = J >= glo && J < ghi && d.cell_iters[J] >= 0;
   const Box bx = in ? d.cbox[b] : d.box[b];
   if (bx.l1 <= 0 || bx.l2 <= 0) return;
   const Prob& p = d.probs[d.basic_prob[b]];
   const long n = (long)bx.l1 * bx.l2;
-  const double* v = (in ? d.cand : d.vals) + b * d.cap2;
+  const double* v = in ? d.cand + d.coff[b] : state_pool(d) + d.voff[b];
   unsigned long long* out = d.fxacc + 2 * (long)p.grid_off;
   for (long o = threadIdx.x; o < n; o += kBlock) {
     const int j1 = (int)(o / bx.l2), j2 = (int)(o - (long)j1 * bx.l2);
@@ -133,15 +131,15 @@ __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int blo,
   const int pi = blockIdx.x;
   const Prob p = d.probs[pi];
   double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  // [0] sum hbar, [1] sum of the candidate pieces (htil for the step's basic
-  // cells, hbar elsewhere), [2] cells updated, [3] point iters, [4] unconverged,
-  // [5] overflow, [6] inner iters, [7] bytes, [8] log-sum-exp terms, [9] exact
-  // recomputations
+  // [0] sum hbar, [1] sum of the candidate pieces (htil for the step's solved
+  // basic cells, hbar elsewhere), [2] cells updated, [3] point iters,
+  // [4] unconverged, [5] cells not solved (a pool too small), [6] inner
+  // iters, [7] bytes, [8] log-sum-exp terms, [9] exact recomputations
   for (int b = threadIdx.x; b < p.nbasic; b += kBlock) {
     const int gb = p.basic_off + b;
     const int J = d.basic_cell[part][gb];
     acc[0] += d.hbar[gb];
-    acc[1] += (J >= glo && J < ghi) ? d.htil[gb] : d.hbar[gb];
+    acc[1] += (J >= glo && J < ghi && d.cell_iters[J] >= 0) ? d.htil[gb] : d.hbar[gb];
   }
   int maxit = 0;
   for (int bt = blo; bt < bhi; ++bt) {
@@ -318,21 +316,34 @@ hipError_t launch_line_search(const Dev& d, const int* chunk_prob, const int* ch
 
 // Algorithm 4 update: nu_i <- (1 - theta) nu_i + theta nu~_i on the cell box,
 // truncation below `trunc`, shrink to the bbox of the nonzeros; the tracked
-// piece and the X-marginal are mixed with the same weight.
-__global__ __launch_bounds__(kBlock) void k_mix(Dev d, int part, int glo, int ghi) {
-  extern __shared__ __align__(16) double vbuf[];
+// piece and the X-marginal are mixed with the same weight.  Three kernels:
+// k_mix_values mixes into the candidate box in place and finds the new box,
+// the sizes are scanned, and k_mix_copy writes every basic cell's new state
+// compactly into the other state pool (k_flip then makes it the current one).
+__device__ __forceinline__ bool mix_updated(const Dev& d, int part, int glo, int ghi, int b) {
+  const int J = d.basic_cell[part][b];
+  return J >= glo && J < ghi && d.cell_iters[J] >= 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mix_values(Dev d, int part, int glo, int ghi) {
   __shared__ int ired[4 * 4];
   const int b = blockIdx.x;
-  const int pi = d.basic_prob[b];
-  const Prob& p = d.probs[pi];
-  const int J = d.basic_cell[part][b];
-  if (J < glo || J >= ghi || d.cell_iters[J] < 0) return;   // not in this step, or overflowed
-  const double th = d.theta[pi];
+  if (!mix_updated(d, part, glo, ghi, b)) {   // not in this step, or not solved
+    if (threadIdx.x == 0) {
+      const Box ob = d.box[b];
+      d.nbox[b] = ob;
+      d.nsub[b] = make_int2(-1, -1);
+      d.nsize[b] = (long)ob.l1 * ob.l2;
+    }
+    return;
+  }
+  const Prob& p = d.probs[d.basic_prob[b]];
+  const double th = d.theta[d.basic_prob[b]];
   const Box cb = d.cbox[b];
   const Box ob = d.box[b];
   const long n = (long)cb.l1 * cb.l2;
-  const double* cv = d.cand + b * d.cap2;
-  double* sv = d.vals + b * d.cap2;
+  double* cv = d.cand + d.coff[b];
+  const double* sv = state_pool(d) + d.voff[b];
   int lo1 = INT_MAX, lo2 = INT_MAX, hi1 = INT_MIN, hi2 = INT_MIN;
   for (long o = threadIdx.x; o < n; o += kBlock) {
     const int j1 = (int)(o / cb.l2), j2 = (int)(o - (long)j1 * cb.l2);
@@ -344,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_mix(Dev d, int part, int glo, int gh
       v = (1.0 - th) * old + th * v;
     }
     if (v < p.trunc) v = 0.0;
-    vbuf[o] = v;
+    cv[o] = v;
     if (v > 0.0) {
       lo1 = min(lo1, j1); hi1 = max(hi1, j1 + 1);
       lo2 = min(lo2, j2); hi2 = max(hi2, j2 + 1);
@@ -361,6 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_mix(Dev d, int part, int glo, int gh
     ired[w * 4 + 0] = lo1; ired[w * 4 + 1] = lo2; ired[w * 4 + 2] = hi1; ired[w * 4 + 3] = hi2;
   }
   __syncthreads();
+  if (threadIdx.x != 0) return;
   lo1 = INT_MAX; lo2 = INT_MAX; hi1 = INT_MIN; hi2 = INT_MIN;
   for (int ww = 0; ww < kBlock / 64; ++ww) {
     lo1 = min(lo1, ired[ww * 4 + 0]); lo2 = min(lo2, ired[ww * 4 + 1]);
@@ -369,24 +381,62 @@ __global__ __launch_bounds__(kBlock) void k_mix(Dev d, int part, int glo, int gh
   Box nb;
   if (lo1 == INT_MAX) {
     nb.o1 = cb.o1; nb.o2 = cb.o2; nb.l1 = 0; nb.l2 = 0;
+    lo1 = lo2 = 0;
   } else {
     nb.o1 = cb.o1 + lo1; nb.o2 = cb.o2 + lo2; nb.l1 = hi1 - lo1; nb.l2 = hi2 - lo2;
   }
-  const long nn = (long)nb.l1 * nb.l2;
-  for (long o = threadIdx.x; o < nn; o += kBlock) {
-    const int a1 = (int)(o / nb.l2), a2 = (int)(o - (long)a1 * nb.l2);
-    sv[o] = vbuf[(long)(a1 + lo1) * cb.l2 + (a2 + lo2)];
+  d.nbox[b] = nb;
+  d.nsub[b] = make_int2(lo1, lo2);
+  d.nsize[b] = (long)nb.l1 * nb.l2;
+}
+
+// After the scan: nsize holds each new box's offset, nuse[0] the total.  A
+// total beyond the pool leaves the state as it was (reported per problem).
+__global__ __launch_bounds__(kBlock) void k_mix_copy(Dev d, int part, int glo, int ghi) {
+  const int b = blockIdx.x;
+  const int pi = d.basic_prob[b];
+  if (d.nuse[0] > d.pool_cap) {
+    if (threadIdx.x == 0) d.cap_fail[pi] = 1;
+    return;
   }
+  const bool upd = mix_updated(d, part, glo, ghi, b);
+  const int cur = *d.sp;
+  double* dst = (cur ? d.pool0 : d.pool1) + d.nsize[b];
+  const Box nb = d.nbox[b];
+  const long n = (long)nb.l1 * nb.l2;
+  const double* src;
+  long stride;
+  if (upd) {
+    const int2 sub = d.nsub[b];
+    stride = d.cbox[b].l2;
+    src = d.cand + d.coff[b] + (long)sub.x * stride + sub.y;
+  } else {
+    stride = nb.l2;
+    src = (cur ? d.pool1 : d.pool0) + d.voff[b];
+  }
+  for (long o = threadIdx.x; o < n; o += kBlock) {
+    const int a1 = (int)(o / nb.l2), a2 = (int)(o - (long)a1 * nb.l2);
+    dst[o] = src[(long)a1 * stride + a2];
+  }
+  __syncthreads();   // every thread has read voff[b] before it changes
   if (threadIdx.x == 0) {
     d.box[b] = nb;
-    d.hbar[b] = (1.0 - th) * d.hbar[b] + th * d.htil[b];
+    d.voff[b] = d.nsize[b];
   }
+  if (!upd) return;
+  const Prob& p = d.probs[pi];
+  const double th = d.theta[pi];
+  if (threadIdx.x == 0) d.hbar[b] = (1.0 - th) * d.hbar[b] + th * d.htil[b];
   const int2 xy = d.basic_xy[b];
   for (int o = threadIdx.x; o < p.s * p.s; o += kBlock) {
     const int i1 = o / p.s, i2 = o - i1 * p.s;
     const long g = p.grid_off + (long)(xy.x + i1) * p.n2 + (xy.y + i2);
     d.px[g] = th == 1.0 ? d.pxc[g] : (1.0 - th) * d.px[g] + th * d.pxc[g];
   }
+}
+
+__global__ void k_flip(int* sp, const long* nuse, long cap) {
+  if (threadIdx.x == 0 && nuse[0] <= cap) *sp ^= 1;
 }
 
 // ---- certificate: separable global log-sum-exp on one problem's grid --------
@@ -479,20 +529,6 @@ __global__ __launch_bounds__(kBlock) void k_cert_terms(const double* alpha, cons
     for (int k = 0; k < 8; ++k) part[blockIdx.x * 8 + k] = acc[k];
 }
 
-// Copy compactly staged slot contents into the fixed-capacity slots.
-__global__ void k_scatter_slots(const double* src, const long* off, double* vals, long cap2) {
-  const int b = blockIdx.x;
-  const long n = off[b + 1] - off[b];
-  for (long o = threadIdx.x; o < n; o += blockDim.x) vals[b * cap2 + o] = src[off[b] + o];
-}
-
-hipError_t launch_scatter_slots(const double* src, const long* off, double* vals, long cap2, int nbasic,
-                                hipStream_t st) {
-  if (nbasic <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter_slots, dim3(nbasic), dim3(256), 0, st, src, off, vals, cap2);
-  return hipGetLastError();
-}
-
 // The half-iteration counter lives on the device, so a captured step graph
 // writes every replay's history record to its own slot.
 __global__ void k_advance(long long* kstep) {
@@ -525,16 +561,11 @@ hipError_t launch_aggregate_sel(const Dev& d, int part, int glo, int ghi, double
   return hipGetLastError();
 }
 
-// P = sum of the state marginals over all problems' grids (ngrid points);
-// acc: 2 * ngrid integers of workspace.
-hipError_t launch_aggregate(const Box* box, const double* vals, long cap2, const int* basic_prob,
-                            const Prob* probs, unsigned long long* acc, double* P, int nbasic,
-                            long ngrid, hipStream_t st) {
-  hipLaunchKernelGGL(k_fx_zero, dim3(grid_blocks(2 * ngrid)), dim3(256), 0, st, acc, 2 * ngrid);
-  if (nbasic > 0)
-    hipLaunchKernelGGL(k_aggregate, dim3(nbasic), dim3(kBlock), 0, st, box, vals, cap2, basic_prob,
-                       probs, acc);
-  hipLaunchKernelGGL(k_fx_finish, dim3(grid_blocks(ngrid)), dim3(256), 0, st, acc, P, ngrid);
+// P = sum of the state marginals over all problems' grids (ngrid points).
+hipError_t launch_aggregate(const Dev& d, double* P, int nbasic, long ngrid, hipStream_t st) {
+  hipLaunchKernelGGL(k_fx_zero, dim3(grid_blocks(2 * ngrid)), dim3(256), 0, st, d.fxacc, 2 * ngrid);
+  if (nbasic > 0) hipLaunchKernelGGL(k_aggregate, dim3(nbasic), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_fx_finish, dim3(grid_blocks(ngrid)), dim3(256), 0, st, d.fxacc, P, ngrid);
   return hipGetLastError();
 }
 
@@ -553,16 +584,17 @@ hipError_t launch_getweights(const Dev& d, int part, int blo, int bhi, int glo, 
   return hipGetLastError();
 }
 
-hipError_t launch_mix(const Dev& d, int part, int glo, int ghi, int nbasic, int cap, hipStream_t st) {
-  if (nbasic <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mix, dim3(nbasic), dim3(kBlock), sizeof(double) * (size_t)cap * cap, st, d,
-                     part, glo, ghi);
-  return hipGetLastError();
-}
+hipError_t launch_scan2(long* a, long* b, int n, long* tot, long long* need, int ia, int ib,
+                        hipStream_t st);
 
-hipError_t set_mix_lds_limit(size_t bytes) {
-  return hipFuncSetAttribute((const void*)k_mix, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes);
+hipError_t launch_mix(const Dev& d, int part, int glo, int ghi, int nbasic, hipStream_t st) {
+  if (nbasic <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mix_values, dim3(nbasic), dim3(kBlock), 0, st, d, part, glo, ghi);
+  hipError_t e = launch_scan2(d.nsize, nullptr, nbasic, d.nuse, d.need, 0, -1, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mix_copy, dim3(nbasic), dim3(kBlock), 0, st, d, part, glo, ghi);
+  hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, st, d.sp, d.nuse, d.pool_cap);
+  return hipGetLastError();
 }
 
 // out = LSE over the grid of in(x) - ch |x - y|^2 (two separable passes).

@@ -317,23 +317,27 @@ struct CellLds {
   R* qtab;       // -sc ch d^2 for d = -cmax .. cmax (pass costs) [2*cmax+1]
 };
 
-// cmax: largest box side of the launch; qmax: the handle's box cap, which
-// sizes the cost table (so every launch reads the same table entries).
+// cmax: largest box side of the launch; qmax: the largest box side of the
+// in-LDS layouts, which sizes the cost table (every launch reads the same
+// table entries).  big: the box arrays (b, z, the pass buffers, log nu and
+// the displacements) live in the cell's global workspace (cell_ws_layout)
+// and only the tile-sized arrays and the cost table stay in LDS.
 template <typename R>
-__host__ __device__ inline size_t cell_lds_layout(int cmax, int qmax, bool moved, CellLds<R>* L,
-                                                  unsigned char* base) {
+__host__ __device__ inline size_t cell_lds_layout(int cmax, int qmax, bool moved, bool big,
+                                                  CellLds<R>* L, unsigned char* base) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off = (off + bytes + 15) & ~size_t(15);
     return o;
   };
-  const size_t n2 = (size_t)cmax * cmax, nt = (size_t)cmax * kMaxTile;
+  const size_t n2 = big ? 0 : (size_t)cmax * cmax, nt = big ? 0 : (size_t)cmax * kMaxTile;
+  const size_t nc = big ? 0 : (size_t)cmax;
   size_t o_bd = take(8 * n2), o_zp = take(sizeof(R) * n2), o_Tt = take(8 * nt), o_Ud = take(8 * nt);
-  size_t o_Mr = take(8 * cmax), o_MU = take(8 * cmax), o_Mc = take(8 * kMaxTile);
+  size_t o_Mr = take(8 * nc), o_MU = take(8 * nc), o_Mc = take(8 * kMaxTile);
   size_t o_adr = take(8 * kMaxTile * kMaxTile), o_Ma = take(8 * kMaxTile), o_red = take(8 * 4 * 16);
-  // FP32 kernels keep log nu and log r in LDS (FP64 kernels use the global
-  // per-cell workspace, whose full precision the FP64 parity needs)
+  // FP32 kernels keep log nu in LDS (FP64 kernels use the global per-cell
+  // workspace, whose full precision the FP64 parity needs)
   const size_t o_lnv = sizeof(R) == 4 ? take(4 * n2) : 0;
   const size_t o_d1 = moved ? take(sizeof(R) * n2) : 0, o_d2 = moved ? take(sizeof(R) * n2) : 0;
   const size_t o_mx = moved ? take(8 * 3 * kMaxTile * kMaxTile) : 0;
@@ -452,17 +456,15 @@ __device__ __forceinline__ double dense_y_lse(const double* adr, const double* M
 }
 
 // NT threads per cell (64, 128 or 256; at least the tile's point count,
-// since thread t owns tile point t).  Launch tiers (same arithmetic, the Y-box
-// always follows the handle's cap): tier 0 solves every cell of the range
-// with the LDS layout of the cap; tier 1 only the cells whose box fits tcap,
-// with the smaller layout of tcap; tier 2 the others (and the overflowing
-// cells) with the layout of the cap.  The FP32 separable kernel asks for three
-// waves per SIMD (its LDS at box cap 48 allows three workgroups per CU; the
-// register limit costs a few spills outside the hot loops, and the extra
-// wave hides more latency: measured 7 % faster at 1024^2).
+// since thread t owns tile point t).  Launch tiers (same arithmetic; a cell's
+// Y-box never depends on the tier): see k_cell_solve.  The FP32 separable
+// kernel asks for three waves per SIMD (its LDS at box side 48 allows three
+// workgroups per CU; the register limit costs a few spills outside the hot
+// loops, and the extra wave hides more latency: measured 7 % faster at
+// 1024^2).
 // Balancing step of Sec. 4.1 ("Balancing") for one composite cell J, after
 // its solve and before the re-split marginals are truncated.  On entry
-// d.cand holds log nu_k(y) = log nu + beta/eps + z_k(y) of every basic cell k
+// candJ holds log nu_k(y) = log nu + beta/eps + z_k(y) of every basic cell k
 // of J on the Y-box (untruncated), pxb the thread's P_X pi, lmb = -alpha'/lam
 // at the thread's point with alpha' the X-half of the final beta.  Basic cell
 // k should carry m_k = mubar(X_k) |pi| / |mubar| of the mass, mubar =
@@ -475,17 +477,18 @@ __device__ __forceinline__ double dense_y_lse(const double* adr, const double* M
 // form with eps log(g_k/nu) = eps (log nu'_k - z_k - log nu) in place of
 // beta.  A receiver's P_X needs sum_y R(y) e^{-z_k(y)} k(x, y), one more
 // separable pass (FP64, exact maximum then sum) over the rows of X_k.  On
-// exit d.cand holds the balanced, truncated marginals; accy the Y sums
-// (<eps log(g_k/nu), nu'_k>, |nu'_k|), pxb and lpb the balanced P_X and
-// log(P_X/mu) of the thread's point.  wlR: per-cell workspace for log R.
+// exit the candidates hold the balanced, truncated marginals; accy the Y
+// sums (<eps log(g_k/nu), nu'_k>, |nu'_k|), pxb and lpb the balanced P_X and
+// log(P_X/mu) of the thread's point.  candJ: the candidate marginals of the
+// cell's basic cells (NY doubles each, in basic order); wlR: per-cell
+// workspace for log R.
 template <typename R, int NT>
-__device__ void balance_cell(const Dev& d, const Cell& C, const Prob& P, const CellLds<R>& S,
+__device__ void balance_cell(double* candJ, const Cell& C, const Prob& P, const CellLds<R>& S,
                              int ti1, int ti2, int lx, int L1, int L2, int NY, int D1, int D2,
                              int nc, const int* kr, const int* kc, double mux, double lmb,
                              const double* wlnv, R* wlR, double (&accy)[8], double& pxb,
                              double& lpb) {
   const int t = threadIdx.x;
-  const long cap2 = d.cap2;
   const int nb = C.nb, s = P.s;
   const double eps = P.eps, ch = P.ch;
   const int kt = t < lx ? (ti1 / s) * nc + (ti2 / s) : -1;   // basic cell of the thread's point
@@ -534,7 +537,7 @@ __device__ void balance_cell(const Dev& d, const Cell& C, const Prob& P, const C
   auto removed = [&](int o) {   // R(y) at box point o
     double r = 0.0;
     for (int k = 0; k < nb; ++k)
-      if (role[k] > 0) r += give[k] * exp(d.cand[(long)C.basic[k] * cap2 + o]);
+      if (role[k] > 0) r += give[k] * exp(candJ[(long)k * NY + o]);
     return r;
   };
   if (anyr) {
@@ -547,7 +550,7 @@ __device__ void balance_cell(const Dev& d, const Cell& C, const Prob& P, const C
     double add = 0.0;
     for (int k = 0; k < nb; ++k) {
       if (role[k] >= 0) continue;
-      const double* lk = d.cand + (long)C.basic[k] * cap2;
+      const double* lk = candJ + (long)k * NY;
       // pass 1 over y2 for the columns of X_k: T(j1, i) =
       // LSE_j2 [log R - z_k - ch (D2 + kc s + i - j2)^2]
       for (int o = t; o < L1 * s; o += NT) {
@@ -605,7 +608,7 @@ __device__ void balance_cell(const Dev& d, const Cell& C, const Prob& P, const C
     const double bo = S.bd[o];
     const double r = anyr ? removed(o) : 0.0;
     for (int k = 0; k < nb; ++k) {
-      double* ck = d.cand + (long)C.basic[k] * cap2;
+      double* ck = candJ + (long)k * NY;
       const double lnk = ck[o];
       double lv = lnk;
       if (role[k] > 0) {
@@ -626,91 +629,83 @@ __device__ void balance_cell(const Dev& d, const Cell& C, const Prob& P, const C
 }
 
 // kBal: the variant with the balancing step (separable cost only); the
-// plain variant keeps its own register allocation.
-template <typename R, bool kMoved, int NT, bool kBal = false>
-__global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cell_solve(Dev d,
-                                                                                       int cell_base,
-                                                                                       int tcap,
-                                                                                       int tier) {
+// plain variant keeps its own register allocation.  kBig: the variant for
+// boxes wider than the in-LDS layouts (box arrays in the cell's workspace).
+// tier 0: every cell whose box fits d.lcap, LDS layout of d.lcap; tier 1: the
+// cells whose box fits tcap, layout of tcap; tier 2: the cells between tcap
+// and d.lcap, layout of d.lcap; tier 3 (kBig): the cells wider than d.lcap.
+template <typename R, bool kMoved, int NT, bool kBal = false, bool kBig = false>
+__global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) void k_cell_solve(
+    Dev d, int cell_base, int tcap, int tier) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int t = threadIdx.x;
   const int ci = cell_base + blockIdx.x;
   const Cell C = d.cells[ci];
   const Prob P = d.probs[C.prob];
-  const int cap = P.cap;
-  const long cap2 = d.cap2;
+  const int lcap = d.lcap;
 
-  // ---- Y-box of the cell: bbox of the basic boxes, dilated, clipped -------
-  int lo1 = INT_MAX, lo2 = INT_MAX, hi1 = INT_MIN, hi2 = INT_MIN;
-  for (int k = 0; k < C.nb; ++k) {
-    const Box b = d.box[C.basic[k]];
-    if (b.l1 > 0 && b.l2 > 0) {
-      lo1 = min(lo1, b.o1);
-      lo2 = min(lo2, b.o2);
-      hi1 = max(hi1, b.o1 + b.l1);
-      hi2 = max(hi2, b.o2 + b.l2);
-    }
-  }
-  if (lo1 == INT_MAX) {
-    lo1 = C.x1; lo2 = C.x2; hi1 = C.x1 + C.lx1; hi2 = C.x2 + C.lx2;
-  }
-  const int U1 = hi1 - lo1, U2 = hi2 - lo2;
+  // ---- Y-box of the cell (k_cell_prep) and its tier --------------------------
+  const Box yb = d.cellbox[ci];
+  const int o1 = yb.o1, o2 = yb.o2, L1 = yb.l1, L2 = yb.l2;
+  const int NY = L1 * L2;
+  const int side = max(L1, L2);
+  if (kBig ? side <= lcap
+           : (side > lcap || (tier == 1 && side > tcap) || (tier == 2 && side <= tcap)))
+    return;
   const int lx1 = C.lx1, lx2 = C.lx2, lx = lx1 * lx2;
   const int s = P.s;
-  if (U1 > cap || U2 > cap) {
-    if (tier == 1) return;
-    // overflow: keep the old state of every basic cell of J
-    for (int k = 0; k < C.nb; ++k) {
-      const int b = C.basic[k];
-      const Box bx = d.box[b];
-      const long n = (long)bx.l1 * bx.l2;
-      for (long o = t; o < n; o += NT) d.cand[b * cap2 + o] = d.vals[b * cap2 + o];
-      if (t == 0) {
-        d.cbox[b] = bx;
-        d.htil[b] = d.hbar[b];
-      }
-    }
-    if (t < lx) {
-      const int i1 = t / lx2, i2 = t - i1 * lx2;
-      const long g = P.grid_off + (long)(C.x1 + i1) * P.n2 + (C.x2 + i2);
-      d.pxc[g] = d.px[g];
-    }
+  // candidate marginals and workspace from the step's pools; a step whose
+  // pools are too small solves no cell that does not fit (reported)
+  const long coff = d.csize[ci];
+  const long woff = d.wsize[ci];
+  const WsLayout wl = cell_ws_layout((int)sizeof(R), NY, side, kMoved, kBig);
+  if (coff + (long)C.nb * NY > d.cand_cap || woff + (long)wl.total > d.ws_cap) {
     if (t == 0) {
       d.cell_iters[ci] = -1;
       d.cell_conv[ci] = 0;
       d.cell_bytes[ci] = 0.0;
       d.cell_terms[ci] = 0.0;
       d.cell_fall[ci] = 0.0;
-      d.overflow_any[C.prob] = 1;
+      d.cap_fail[C.prob] = 1;
     }
     return;
   }
-  const int m1 = min(P.margin, (cap - U1) / 2), m2 = min(P.margin, (cap - U2) / 2);
-  const int o1 = max(lo1 - m1, 0), o2 = max(lo2 - m2, 0);
-  const int L1 = min(hi1 + m1, P.n1) - o1, L2 = min(hi2 + m2, P.n2) - o2;
-  const int NY = L1 * L2;
-  const bool fits = L1 <= tcap && L2 <= tcap;
-  if ((tier == 1 && !fits) || (tier == 2 && fits)) return;
+  double* candJ = d.cand + coff;
+  unsigned char* wsc = d.ws + woff;
+  const double* vals = state_pool(d);
 
   CellLds<R> S;
-  cell_lds_layout<R>(tier == 1 ? tcap : cap, cap, kMoved, &S, smem_raw);
+  cell_lds_layout<R>(kBig ? 0 : (tier == 1 ? tcap : lcap), lcap, kMoved, kBig, &S, smem_raw);
+  if constexpr (kBig) {
+    S.bd = (double*)(wsc + wl.bd);
+    S.zp = (R*)(wsc + wl.zp);
+    S.Tt = (double*)(wsc + wl.Tt);
+    S.Ud = (double*)(wsc + wl.Ud);
+    S.Mr = (double*)(wsc + wl.Mr);
+    S.MU = (double*)(wsc + wl.MU);
+    if constexpr (sizeof(R) == 4) S.lnvf = (float*)(wsc + wl.lnvf);
+    if constexpr (kMoved) {
+      S.dl1 = (R*)(wsc + wl.d1);
+      S.dl2 = (R*)(wsc + wl.d2);
+    }
+  }
   double* red = S.red;
 
   const double eps = P.eps, lam = P.lam, kap = P.kappa, K = P.K, ch = P.ch;
   const float ichf = ch > 0.0 ? (float)(1.0 / ch) : 0.0f;   // window: 1/ch (unused for ch = 0)
-  // cost table of the separable passes, centred: qc[d] = -sc ch d^2, |d| <= cap
-  const R* qc = S.qtab + cap;
-  for (int i = t; i <= 2 * cap; i += NT) {
-    const double dd = (double)(i - cap);
+  // cost table of the separable passes, centred: qc[d] = -sc ch d^2, |d| <= lcap
+  const R* qc = S.qtab + lcap;
+  for (int i = t; i <= 2 * lcap; i += NT) {
+    const double dd = (double)(i - lcap);
     S.qtab[i] = R(-(double)M<R>::kScale * ch * dd * dd);
   }
   const int D1 = C.x1 - o1, D2 = C.x2 - o2;      // tile origin in box coordinates
   const double* nu = d.nu + P.grid_off;
   const double* mu = d.mu + P.grid_off;
   const double* Pst = d.P + P.grid_off;
-  double* wlnv = d.ws_lnv + (long)ci * cap2;
-  double* wlrr = d.ws_lrr + (long)ci * cap2;
-  float* wlrf = reinterpret_cast<float*>(d.ws_lrr) + (long)ci * cap2;   // FP32 kernels
+  double* wlnv = (double*)(wsc + wl.lnv);   // FP64 kernels
+  double* wlrr = (double*)(wsc + wl.lrr);
+  float* wlrf = (float*)(wsc + wl.lrr);     // FP32 kernels
 
   // ---- X tile inputs (thread t owns tile point t) --------------------------
   const int ti1 = t < lx ? t / lx2 : 0, ti2 = t < lx ? t - ti1 * lx2 : 0;
@@ -733,7 +728,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
       const Box b = d.box[C.basic[k]];
       const int a1 = y1 - b.o1, a2 = y2 - b.o2;
       if (a1 >= 0 && a1 < b.l1 && a2 >= 0 && a2 < b.l2)
-        nj += d.vals[C.basic[k] * cap2 + (long)a1 * b.l2 + a2];
+        nj += vals[d.voff[C.basic[k]] + (long)a1 * b.l2 + a2];
     }
     const double r = fmax(pv - nj, 0.0) / nv;
     acc0[1] += r * nv;
@@ -832,7 +827,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
       __syncthreads();
       for (int o = t; o < L1 * lx2; o += NT) {
         const int j1 = o / lx2, i2 = o - j1 * lx2;
-        S.Tt[o] = lse_pass<R>(S.bd + j1 * L2, 1, 0, L2, (double)(D2 + i2), ch, ichf, qc, cap, have_x,
+        S.Tt[o] = lse_pass<R>(S.bd + j1 * L2, 1, 0, L2, (double)(D2 + i2), ch, ichf, qc, lcap, have_x,
                               S.Tt[o] + xext,
                               S.Mr[j1], nfall);
       }
@@ -841,7 +836,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
       __syncthreads();
       double sv = 0.0;
       if (t < lx)
-        sv = lse_pass<R>(S.Tt + ti2, lx2, 0, L1, (double)(D1 + ti1), ch, ichf, qc, cap, have_x, sprev + xext,
+        sv = lse_pass<R>(S.Tt + ti2, lx2, 0, L1, (double)(D1 + ti1), ch, ichf, qc, lcap, have_x, sprev + xext,
                          S.Mc[ti2],
                          nfall);
       have_x = true;
@@ -880,7 +875,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
   auto y_pass1 = [&](double* Uo, int ib, int ie, bool have, double extra) {
     for (int o = t; o < lx1 * L2; o += NT) {
       const int i1 = o / L2, j2 = o - i1 * L2;
-      Uo[o] = lse_full<R>(S.adr + i1 * lx2, 1, ib, ie, (double)(j2 - D2), ch, qc, cap, have,
+      Uo[o] = lse_full<R>(S.adr + i1 * lx2, 1, ib, ie, (double)(j2 - D2), ch, qc, lcap, have,
                           Uo[o] + extra, nfall);
     }
     __syncthreads();
@@ -923,7 +918,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
         z = dense_y_lse<R>(S.adr, S.Ma, lx1, lx2, (double)D1, (double)D2, j1 + (double)S.dl1[o],
                            j2 + (double)S.dl2[o], ch, have_y, S.zp[o] + ushift, nfall);
       else
-        z = lse_full<R>(S.Ud + j2, L2, 0, lx1, (double)(j1 - D1), ch, qc, cap, have_y,
+        z = lse_full<R>(S.Ud + j2, L2, 0, lx1, (double)(j1 - D1), ch, qc, lcap, have_y,
                         S.zp[o] + ushift, nfall);
       S.zp[o] = R(z);
       double lnv, lrr;
@@ -1002,17 +997,17 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
                                      sizeof(R) == 8 ? 60.0 : 40.0);
           zk = a > R(0) ? S.zp[o] + (double)M<R>::lg(a) : -INFINITY;
         } else {
-          zk = lse_full<R>(Uo + j2, L2, kr[k] * s, (kr[k] + 1) * s, (double)(j1 - D1), ch, qc, cap,
+          zk = lse_full<R>(Uo + j2, L2, kr[k] * s, (kr[k] + 1) * s, (double)(j1 - D1), ch, qc, lcap,
                            true, S.zp[o], nfall);
         }
         if (bal) {
-          d.cand[(long)C.basic[k] * cap2 + o] = S.bd[o] + zk;
+          candJ[(long)k * NY + o] = S.bd[o] + zk;
           continue;
         }
         const double nt = exp(S.bd[o] + zk);   // nu e^{beta/eps} e^{z_k}
         accy[k] += beta * nt;
         accy[4 + k] += nt;
-        d.cand[(long)C.basic[k] * cap2 + o] = nt < P.trunc ? 0.0 : nt;
+        candJ[(long)k * NY + o] = nt < P.trunc ? 0.0 : nt;
       }
     }
     __syncthreads();
@@ -1021,7 +1016,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
   if constexpr (kBal && !kMoved) {
     if (bal) {
       R* wlR = sizeof(R) == 4 ? reinterpret_cast<R*>(wlrf) : reinterpret_cast<R*>(wlrr);
-      balance_cell<R, NT>(d, C, P, S, ti1, ti2, lx, L1, L2, NY, D1, D2, nc, kr, kc, mux,
+      balance_cell<R, NT>(candJ, C, P, S, ti1, ti2, lx, L1, L2, NY, D1, D2, nc, kr, kc, mux,
                           kap * Sfin / K, wlnv, wlR, accy, pxb, lpb);
     }
   }
@@ -1055,9 +1050,8 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
       bytes += 8.0 * ob.l1 * ob.l2;
       d.htil[b] = accx[k] + accy[k] - eps * accy[4 + k] + eps * accx[8 + k] * P.mass_nu +
                   lam * accx[4 + k];
-      Box nb;
-      nb.o1 = o1; nb.o2 = o2; nb.l1 = L1; nb.l2 = L2;
-      d.cbox[b] = nb;
+      d.cbox[b] = yb;
+      d.coff[b] = coff + (long)k * NY;
     }
     // log-sum-exp terms of the separable passes: every Y-half and X-half of
     // the loop, the first X-half, and the re-split passes
@@ -1072,76 +1066,229 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved) ? 3 : 1) void k_cel
   }
 }
 
-size_t cell_lds_bytes(int lcap, int cap, int precision, bool moved) {
-  if (precision == 64) return cell_lds_layout<double>(lcap, cap, moved, nullptr, nullptr);
-  return cell_lds_layout<float>(lcap, cap, moved, nullptr, nullptr);
+size_t cell_lds_bytes(int lcap, int cap, int precision, bool moved, bool big) {
+  if (precision == 64) return cell_lds_layout<double>(lcap, cap, moved, big, nullptr, nullptr);
+  return cell_lds_layout<float>(lcap, cap, moved, big, nullptr, nullptr);
 }
 
-template <typename R, bool kMoved, bool kBal>
-static void launch_nt(const Dev& d, int cell_base, int ncells, size_t lds, int nt, int tcap, int tier,
-                      hipStream_t st) {
-  if (nt == 64)
-    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 64, kBal>), dim3(ncells), dim3(64), lds, st, d,
-                       cell_base, tcap, tier);
-  else if (nt == 128)
-    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 128, kBal>), dim3(ncells), dim3(128), lds, st, d,
-                       cell_base, tcap, tier);
-  else
-    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 256, kBal>), dim3(ncells), dim3(256), lds, st, d,
-                       cell_base, tcap, tier);
+// ---- per-step preparation of the composite cells --------------------------
+// Y-box of every composite cell of the step (cell_ybox), its candidate size
+// (one box per basic cell) and its workspace size.
+__global__ void k_cell_prep(Dev d, int cell_base, int ncell, int rbytes) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncell) return;
+  const int ci = cell_base + j;
+  const Cell C = d.cells[ci];
+  const Prob& P = d.probs[C.prob];
+  const Box yb = cell_ybox(C, P, d.box);
+  d.cellbox[ci] = yb;
+  const long ny = (long)yb.l1 * yb.l2;
+  const int side = max(yb.l1, yb.l2);
+  d.csize[ci] = (long)C.nb * ny;
+  d.wsize[ci] = (long)cell_ws_layout(rbytes, ny, side, P.moved != 0, side > d.lcap).total;
 }
 
-// balance: some problem of the handle takes the balancing step (the host
-// rejects it with moved Y points)
-static void launch_tier(const Dev& d, int cell_base, int ncells, int lcap, int cap, int precision,
-                        bool moved, bool balance, int nt, int tcap, int tier, hipStream_t st) {
-  const size_t lds = cell_lds_bytes(lcap, cap, precision, moved);
-  if (precision == 64) {
-    if (moved) launch_nt<double, true, false>(d, cell_base, ncells, lds, nt, tcap, tier, st);
-    else if (balance) launch_nt<double, false, true>(d, cell_base, ncells, lds, nt, tcap, tier, st);
-    else launch_nt<double, false, false>(d, cell_base, ncells, lds, nt, tcap, tier, st);
-  } else {
-    if (moved) launch_nt<float, true, false>(d, cell_base, ncells, lds, nt, tcap, tier, st);
-    else if (balance) launch_nt<float, false, true>(d, cell_base, ncells, lds, nt, tcap, tier, st);
-    else launch_nt<float, false, false>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+// ---- upper bounds of the pool needs of the coming steps --------------------
+// A step's basic boxes end inside their cell's Y-box (truncation and mixing
+// only shrink or keep them), so replaying the Y-box rule on bound boxes tb,
+// step after step, bounds every step's candidate, workspace and new-state
+// sizes.  acc: [0] candidate doubles, [1] workspace bytes, [2] state doubles.
+__global__ void k_bound_cells(Dev d, Box* tb, int cell_base, int ncell, int rbytes,
+                              unsigned long long* acc) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncell) return;
+  const Cell C = d.cells[cell_base + j];
+  const Prob& P = d.probs[C.prob];
+  const Box yb = cell_ybox(C, P, tb);   // reads only the basic boxes of this cell
+  const long ny = (long)yb.l1 * yb.l2;
+  const int side = max(yb.l1, yb.l2);
+  atomicAdd(acc, (unsigned long long)((long)C.nb * ny));
+  atomicAdd(acc + 1,
+            (unsigned long long)cell_ws_layout(rbytes, ny, side, P.moved != 0, side > d.lcap).total);
+  for (int k = 0; k < C.nb; ++k) tb[C.basic[k]] = yb;
+}
+
+__global__ void k_bound_state(const Box* tb, int nbasic, unsigned long long* acc) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nbasic; b += gridDim.x * blockDim.x)
+    atomicAdd(acc + 2, (unsigned long long)((long)tb[b].l1 * tb[b].l2));
+}
+
+// bound[0..2] = max(bound, (state, candidate, workspace) of acc); acc = 0.
+__global__ void k_bound_fold(unsigned long long* acc, long long* bound) {
+  if (threadIdx.x != 0) return;
+  const long long v[3] = {(long long)acc[2], (long long)acc[0], (long long)acc[1]};
+  for (int k = 0; k < 3; ++k) bound[k] = bound[k] > v[k] ? bound[k] : v[k];
+  acc[0] = acc[1] = acc[2] = 0ull;
+}
+
+__global__ void k_bound_zero(unsigned long long* acc, long long* bound) {
+  if (threadIdx.x < 3) {
+    acc[threadIdx.x] = 0ull;
+    bound[threadIdx.x] = 0;
   }
 }
 
-// tcap < cap: two launches, the cells whose box exceeds tcap first (larger
-// LDS layout, fewer workgroups per CU), then the others.
-hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int cap, int tcap,
+hipError_t launch_bound_begin(unsigned long long* acc, long long* bound, hipStream_t st) {
+  hipLaunchKernelGGL(k_bound_zero, dim3(1), dim3(64), 0, st, acc, bound);
+  return hipGetLastError();
+}
+
+// One coming step over the cells [cell_base, cell_base + ncell).
+hipError_t launch_bound_step(const Dev& d, Box* tb, int cell_base, int ncell, int nbasic,
+                             int precision, unsigned long long* acc, long long* bound,
+                             hipStream_t st) {
+  if (ncell > 0)
+    hipLaunchKernelGGL(k_bound_cells, dim3((ncell + 255) / 256), dim3(256), 0, st, d, tb, cell_base,
+                       ncell, precision == 64 ? 8 : 4, acc);
+  const int blocks = (nbasic + 255) / 256 < 1024 ? (nbasic + 255) / 256 : 1024;
+  if (nbasic > 0) hipLaunchKernelGGL(k_bound_state, dim3(blocks), dim3(256), 0, st, tb, nbasic, acc);
+  hipLaunchKernelGGL(k_bound_fold, dim3(1), dim3(64), 0, st, acc, bound);
+  return hipGetLastError();
+}
+
+// In-place exclusive prefix sums of a[0, n) and (if b) b[0, n) in a fixed
+// order, one workgroup of 1024 threads; totals to tot[0], tot[1], and the
+// largest total seen so far to need[ia], need[ib].
+__global__ __launch_bounds__(1024) void k_scan2(long* a, long* b, int n, long* tot,
+                                                 long long* need, int ia, int ib) {
+  __shared__ long sa[1024], sb[1024];
+  const int t = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int lo = min(n, t * per), hi = min(n, lo + per);
+  long ta = 0, tb = 0;
+  for (int i = lo; i < hi; ++i) {
+    ta += a[i];
+    if (b) tb += b[i];
+  }
+  sa[t] = ta;
+  sb[t] = tb;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {   // inclusive scan of the chunk sums
+    const long va = t >= o ? sa[t - o] : 0, vb = t >= o ? sb[t - o] : 0;
+    __syncthreads();
+    sa[t] += va;
+    sb[t] += vb;
+    __syncthreads();
+  }
+  long ra = sa[t] - ta, rb = sb[t] - tb;
+  for (int i = lo; i < hi; ++i) {
+    const long va = a[i];
+    a[i] = ra;
+    ra += va;
+    if (b) {
+      const long vb = b[i];
+      b[i] = rb;
+      rb += vb;
+    }
+  }
+  if (t == 1023) {
+    tot[0] = sa[1023];
+    if (b) tot[1] = sb[1023];
+    if (ia >= 0 && (long long)sa[1023] > need[ia]) need[ia] = sa[1023];
+    if (b && ib >= 0 && (long long)sb[1023] > need[ib]) need[ib] = sb[1023];
+  }
+}
+
+hipError_t launch_scan2(long* a, long* b, int n, long* tot, long long* need, int ia, int ib,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_scan2, dim3(1), dim3(1024), 0, st, a, b, n, tot, need, ia, ib);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_prep(const Dev& d, int cell_base, int ncells, int precision, hipStream_t st) {
+  if (ncells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cell_prep, dim3((ncells + 255) / 256), dim3(256), 0, st, d, cell_base, ncells,
+                     precision == 64 ? 8 : 4);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_scan2(d.csize + cell_base, d.wsize + cell_base, ncells, d.cuse, d.need, 1, 2, st);
+}
+
+// The wide-box variant always runs 256 threads per cell.
+template <typename R, bool kMoved, bool kBal, bool kBig>
+static void launch_nt(const Dev& d, int cell_base, int ncells, size_t lds, int nt, int tcap, int tier,
+                      hipStream_t st) {
+  if constexpr (kBig)
+    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 256, kBal, true>), dim3(ncells), dim3(256), lds, st,
+                       d, cell_base, tcap, tier);
+  else if (nt == 64)
+    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 64, kBal, false>), dim3(ncells), dim3(64), lds, st, d,
+                       cell_base, tcap, tier);
+  else if (nt == 128)
+    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 128, kBal, false>), dim3(ncells), dim3(128), lds, st,
+                       d, cell_base, tcap, tier);
+  else
+    hipLaunchKernelGGL((k_cell_solve<R, kMoved, 256, kBal, false>), dim3(ncells), dim3(256), lds, st,
+                       d, cell_base, tcap, tier);
+}
+
+template <bool kBig>
+static void launch_kind(const Dev& d, int cell_base, int ncells, size_t lds, int precision,
+                        bool moved, bool balance, int nt, int tcap, int tier, hipStream_t st) {
+  if (precision == 64) {
+    if (moved) launch_nt<double, true, false, kBig>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+    else if (balance) launch_nt<double, false, true, kBig>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+    else launch_nt<double, false, false, kBig>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+  } else {
+    if (moved) launch_nt<float, true, false, kBig>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+    else if (balance) launch_nt<float, false, true, kBig>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+    else launch_nt<float, false, false, kBig>(d, cell_base, ncells, lds, nt, tcap, tier, st);
+  }
+}
+
+// The cell solves of [cell_base, cell_base + ncells) after k_cell_prep: the
+// cells wider than the in-LDS layouts (lcap) first, with their arrays in the
+// workspace; then, when tcap < lcap, the cells between tcap and lcap with the
+// layout of lcap, and last those that fit tcap (more workgroups per CU).
+hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int lcap, int tcap,
                              int precision, bool moved, bool balance, int nt, hipStream_t st) {
   if (ncells <= 0) return hipSuccess;
-  if (tcap >= cap) {
-    launch_tier(d, cell_base, ncells, cap, cap, precision, moved, balance, nt, cap, 0, st);
+  launch_kind<true>(d, cell_base, ncells, cell_lds_bytes(0, lcap, precision, moved, true), precision,
+                    moved, balance, nt, tcap, 3, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t big = cell_lds_bytes(lcap, lcap, precision, moved, false);
+  if (tcap >= lcap) {
+    launch_kind<false>(d, cell_base, ncells, big, precision, moved, balance, nt, lcap, 0, st);
   } else {
-    launch_tier(d, cell_base, ncells, cap, cap, precision, moved, balance, nt, tcap, 2, st);
-    hipError_t e = hipGetLastError();
+    launch_kind<false>(d, cell_base, ncells, big, precision, moved, balance, nt, tcap, 2, st);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    launch_tier(d, cell_base, ncells, tcap, cap, precision, moved, balance, nt, tcap, 1, st);
+    launch_kind<false>(d, cell_base, ncells, cell_lds_bytes(tcap, lcap, precision, moved, false),
+                       precision, moved, balance, nt, tcap, 1, st);
   }
   return hipGetLastError();
 }
 
-template <typename R, bool kMoved, bool kBal = false>
+template <typename R, bool kMoved, bool kBal, bool kBig>
 static hipError_t set_lds_nt(size_t bytes) {
-  const void* fns[3] = {(const void*)k_cell_solve<R, kMoved, 64, kBal>,
-                        (const void*)k_cell_solve<R, kMoved, 128, kBal>,
-                        (const void*)k_cell_solve<R, kMoved, 256, kBal>};
+  const void* fns[3] = {(const void*)k_cell_solve<R, kMoved, 256, kBal, kBig>, nullptr, nullptr};
+  if constexpr (!kBig) {
+    fns[1] = (const void*)k_cell_solve<R, kMoved, 64, kBal, false>;
+    fns[2] = (const void*)k_cell_solve<R, kMoved, 128, kBal, false>;
+  }
   for (const void* f : fns) {
+    if (!f) continue;
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
+template <bool kBig>
+static hipError_t set_lds_kind(size_t bytes) {
+  hipError_t e = set_lds_nt<double, false, false, kBig>(bytes);
+  if (e == hipSuccess) e = set_lds_nt<double, true, false, kBig>(bytes);
+  if (e == hipSuccess) e = set_lds_nt<float, false, false, kBig>(bytes);
+  if (e == hipSuccess) e = set_lds_nt<float, true, false, kBig>(bytes);
+  if (e == hipSuccess) e = set_lds_nt<double, false, true, kBig>(bytes);
+  if (e == hipSuccess) e = set_lds_nt<float, false, true, kBig>(bytes);
+  return e;
+}
+
 hipError_t set_cell_lds_limit(size_t bytes) {
-  hipError_t e = set_lds_nt<double, false>(bytes);
-  if (e == hipSuccess) e = set_lds_nt<double, true>(bytes);
-  if (e == hipSuccess) e = set_lds_nt<float, false>(bytes);
-  if (e == hipSuccess) e = set_lds_nt<float, true>(bytes);
-  if (e == hipSuccess) e = set_lds_nt<double, false, true>(bytes);
-  if (e == hipSuccess) e = set_lds_nt<float, false, true>(bytes);
+  hipError_t e = set_lds_kind<false>(bytes);
+  if (e == hipSuccess) e = set_lds_kind<true>(bytes);
   return e;
 }
 

@@ -18,7 +18,7 @@ struct Prob {
   double ch;        // h^2 / eps: cost / eps = ch * |i - j|^2 in grid units
   double err, trunc, lenience;
   int getweights, fixed_iters, max_iter;
-  int margin, cap;
+  int margin;
   int translate;
   int balance;         // 1: balancing step after every cell solve (Sec. 4.1)
   int precision;
@@ -56,19 +56,42 @@ struct Dev {
   double* px;                 // X-marginal of the state plan
   double* pxc;                // X-marginal of the candidate cell plans
   double* abar;               // stitched alpha of the last cell solves
+  // Basic-cell Y-marginals live in variable-size pools: no box size limit.
+  // The state is double-buffered: every step writes the new state compactly
+  // into the other pool and flips *sp (a device word, so captured graphs stay
+  // valid).
   Box* box;                   // state box of each basic cell
-  double* vals;               // state slots, cap2 doubles per basic cell
+  long* voff;                 // offset of each state box in the current pool
+  double* pool0;              // state pools
+  double* pool1;
+  int* sp;                    // index of the current state pool
+  long pool_cap;              // doubles per state pool
   Box* cbox;                  // candidate box of each basic cell
-  double* cand;               // candidate slots
+  long* coff;                 // offset of each candidate box in the candidate pool
+  double* cand;               // candidate pool
+  long cand_cap;              // doubles
+  Box* nbox;                  // mix: the new state box of each basic cell
+  int2* nsub;                 // mix: its origin inside the candidate box (-1: unchanged)
+  long* nsize;                // mix: its area, then (scanned) its offset in the other pool
+  long* nuse;                 // mix: total doubles of the new state
+  // per composite cell of a step (prepared by k_cell_prep)
+  Box* cellbox;               // Y-box
+  long* csize;                // candidate doubles, then (scanned) candidate offset
+  long* wsize;                // workspace bytes, then (scanned) workspace offset
+  long* cuse;                 // [0] candidate doubles, [1] workspace bytes of the step
+  unsigned char* ws;          // per-cell workspace pool (log nu, log r; large boxes:
+                              // the potentials and pass buffers)
+  long ws_cap;                // bytes
+  long long* need;            // [0] state, [1] candidate, [2] workspace: largest
+                              // need since the host last read it
+  int* cap_fail;              // per problem: a pool was too small for a step
   double* hbar;               // tracked piece of each basic cell
   double* htil;               // candidate piece of each basic cell
-  int* cell_iters;            // Y-halves of the last solve of each cell (-1: skipped)
+  int* cell_iters;            // Y-halves of the last solve of each cell (-1: not solved)
   int* cell_conv;             // converged flag of the last solve
   double* cell_bytes;         // algorithmic bytes of the last solve
   double* cell_terms;         // log-sum-exp terms of the last solve
   double* cell_fall;          // pass outputs recomputed in FP64 (underflow) in the last solve
-  double* ws_lnv;             // per cell: log nu on the Y-box (cap2 entries)
-  double* ws_lrr;             // per cell: log(nu_{-J}/nu) on the Y-box (cap2 entries)
   const double* ydel;         // moved Y: (y'/h - j) per grid point, 2 doubles each
   long long* kstep;           // half-iterations done (history record index)
   double* chunk_part;         // 2 doubles per reduction chunk
@@ -76,11 +99,75 @@ struct Dev {
   double* line;               // per problem, GetWeights line search: lo, a, b, z, dH, phase, active, -
   double* line_part;          // 2 doubles per reduction chunk (line search sums)
   double* hist;               // per problem ring of records
-  int* overflow_any;          // per problem
   int* force_greedy;          // per problem: next GetWeights takes theta = 1
   int hist_cap;
-  long cap2;                  // doubles per slot
+  int lcap;                   // largest box side of the in-LDS cell layouts
 };
+
+// Per-cell workspace in global memory (byte offsets from the cell's base):
+// log r on the box (R), log nu (FP64 kernels: FP64); for a box wider than
+// the in-LDS layouts also b, z, log nu (FP32 kernels), the pass buffers, the
+// row / column maxima and the displacements.
+struct WsLayout {
+  size_t lrr, lnv, bd, zp, lnvf, Tt, Ud, Mr, MU, d1, d2, total;
+};
+__host__ __device__ inline WsLayout cell_ws_layout(int rbytes, long ny, int cmax, bool moved,
+                                                   bool big) {
+  WsLayout w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = (off + bytes + 15) & ~size_t(15);
+    return o;
+  };
+  const size_t n = (size_t)ny;
+  w.lrr = take((size_t)rbytes * n);
+  w.lnv = take(rbytes == 8 ? 8 * n : 0);
+  const size_t nb = big ? n : 0, nt = big ? (size_t)cmax * kMaxTile : 0, nc = big ? (size_t)cmax : 0;
+  w.bd = take(8 * nb);
+  w.zp = take((size_t)rbytes * nb);
+  w.lnvf = take(rbytes == 4 ? 4 * nb : 0);
+  w.Tt = take(8 * nt);
+  w.Ud = take(8 * nt);
+  w.Mr = take(8 * nc);
+  w.MU = take(8 * nc);
+  w.d1 = take(moved ? (size_t)rbytes * nb : 0);
+  w.d2 = take(moved ? (size_t)rbytes * nb : 0);
+  w.total = (off + 255) & ~size_t(255);
+  return w;
+}
+
+// Y-box of composite cell J (Sec. 4.1: nu_{-J} is needed on the support of
+// nu_J): the bounding box of its basic cells' boxes, dilated by the margin
+// and clipped to the grid (the X rectangle of J when every basic box is
+// empty).  Used by the step preparation, the pool bounds and the host.
+__host__ __device__ inline Box cell_ybox(const Cell& C, const Prob& P, const Box* box) {
+  int lo1 = 0x7fffffff, lo2 = 0x7fffffff, hi1 = -0x7fffffff, hi2 = -0x7fffffff;
+  for (int k = 0; k < C.nb; ++k) {
+    const Box b = box[C.basic[k]];
+    if (b.l1 > 0 && b.l2 > 0) {
+      lo1 = lo1 < b.o1 ? lo1 : b.o1;
+      lo2 = lo2 < b.o2 ? lo2 : b.o2;
+      hi1 = hi1 > b.o1 + b.l1 ? hi1 : b.o1 + b.l1;
+      hi2 = hi2 > b.o2 + b.l2 ? hi2 : b.o2 + b.l2;
+    }
+  }
+  if (lo1 == 0x7fffffff) {
+    lo1 = C.x1; lo2 = C.x2; hi1 = C.x1 + C.lx1; hi2 = C.x2 + C.lx2;
+  }
+  const int m = P.margin;
+  Box yb;
+  yb.o1 = lo1 - m > 0 ? lo1 - m : 0;
+  yb.o2 = lo2 - m > 0 ? lo2 - m : 0;
+  yb.l1 = (hi1 + m < P.n1 ? hi1 + m : P.n1) - yb.o1;
+  yb.l2 = (hi2 + m < P.n2 ? hi2 + m : P.n2) - yb.o2;
+  return yb;
+}
+
+// The current state pool.
+__device__ __forceinline__ const double* state_pool(const Dev& d) {
+  return *d.sp ? d.pool1 : d.pool0;
+}
 
 // Basic-cell state from a pair of global potentials (warmstart.hip).
 struct DualsArgs {
@@ -90,15 +177,40 @@ struct DualsArgs {
   const double* nu;
   const int2* bxy;       // X origin of each basic cell
   const Box* win;        // Y scan window of each basic cell
-  int n1, n2, s, cap;
+  int n1, n2, s;
   int gcols;             // largest window width (LDS rows of G)
-  long cap2;
+  int hrows;             // largest window height (LDS rows of H)
   double eps, lam, ch, trunc, mass_nu;
-  Box* box;
-  double* vals;
+  Box* box;              // phase 0: written; phase 1: read
+  const long* voff;      // phase 1: offset of each box in vals
+  double* vals;          // the state pool
   double* px;
   double* hbar;
-  int* nclip;
+  int phase;
+};
+
+// Refinement of a single-problem state to the grid with twice the points per
+// axis (multiscale.hip).
+struct RefineArgs {
+  // coarse problem (one problem, grid offset 0)
+  const Box* cbox;
+  const double* cvals;   // the coarse handle's current state pool
+  const long* cvoff;
+  const double* mu_c;
+  const double* nu_c;
+  const double* chbar;
+  int cn2, cs, cnb2;
+  // fine problem
+  const int2* fxy;
+  const double* mu_f;
+  const double* nu_f;
+  int fn2, fs;
+  double trunc;
+  Box* fbox;
+  const long* fvoff;     // phase 1: offsets of the fine boxes in fvals
+  double* fvals;
+  double* fhbar;
+  int phase;             // 0: boxes, pieces, P_X; 1: values
 };
 
 }  // namespace dduot

@@ -12,34 +12,15 @@
 // |mu_f(X_i)| / |mu_c(X_I)| of the refined marginal of I (exact when the
 // coarse plan splits X_I proportionally to mu, the only information the stored
 // state keeps).  Boxes double; entries below the truncation threshold are
-// dropped and the box shrinks to the bounding box of what is left.
+// dropped and the box shrinks to the bounding box of what is left.  Two
+// launches: the new boxes (phase 0), then, once the host has placed them in
+// the fine state pool, the values (phase 1).
 #include "dd_types.h"
 
 #include <limits.h>
 
 namespace dduot {
 
-struct RefineArgs {
-  // coarse problem (one problem, grid offset 0)
-  const Box* cbox;
-  const double* cvals;
-  long ccap2;
-  const double* mu_c;
-  const double* nu_c;
-  const double* chbar;
-  int cn2, cs, cnb2;
-  // fine problem
-  const int2* fxy;
-  const double* mu_f;
-  const double* nu_f;
-  int fn2, fs, fcap;
-  long fcap2;
-  double trunc;
-  Box* fbox;
-  double* fvals;
-  double* fhbar;
-  int* nclip;
-};
 
 __device__ __forceinline__ void block_minmax4(int (&v)[4], int* red) {
   // v = {min o1, min o2, max e1, max e2} over the workgroup (256 threads)
@@ -101,16 +82,29 @@ __global__ __launch_bounds__(kBlock) void k_refine_slots(RefineArgs A) {
   mc = block_sum1(mc, redd);
   const double f = mf / mc;
   const Box cb = A.cbox[I];
-  const double* cv = A.cvals + (long)I * A.ccap2;
+  const double* cv = A.cvals + A.cvoff[I];
+  auto value = [&](int y1, int y2) {
+    const int Y1 = y1 / 2, Y2 = y2 / 2;
+    return f * cv[(long)(Y1 - cb.o1) * cb.l2 + (Y2 - cb.o2)] * A.nu_f[(long)y1 * A.fn2 + y2] /
+           A.nu_c[(long)Y1 * A.cn2 + Y2];
+  };
+  if (A.phase == 1) {
+    const Box nb = A.fbox[b];
+    double* fv = A.fvals + A.fvoff[b];
+    for (long o = t; o < (long)nb.l1 * nb.l2; o += kBlock) {
+      const int a1 = (int)(o / nb.l2), a2 = (int)(o - (long)a1 * nb.l2);
+      const double v = value(nb.o1 + a1, nb.o2 + a2);
+      fv[o] = v >= A.trunc ? v : 0.0;
+    }
+    return;
+  }
   const int o1 = 2 * cb.o1, o2 = 2 * cb.o2, L1 = 2 * cb.l1, L2 = 2 * cb.l2;
   // bounding box of the refined entries that survive truncation
   int bb[4] = {INT_MAX, INT_MAX, INT_MIN, INT_MIN};
   for (long o = t; o < (long)L1 * L2; o += kBlock) {
     const int a1 = (int)(o / L2), a2 = (int)(o - (long)a1 * L2);
     const int y1 = o1 + a1, y2 = o2 + a2;
-    const int Y1 = y1 / 2, Y2 = y2 / 2;
-    const double v = f * cv[(long)(Y1 - cb.o1) * cb.l2 + (Y2 - cb.o2)] *
-                     A.nu_f[(long)y1 * A.fn2 + y2] / A.nu_c[(long)Y1 * A.cn2 + Y2];
+    const double v = value(y1, y2);
     if (v >= A.trunc && v > 0.0) {
       bb[0] = min(bb[0], y1);
       bb[1] = min(bb[1], y2);
@@ -125,25 +119,6 @@ __global__ __launch_bounds__(kBlock) void k_refine_slots(RefineArgs A) {
     nb.o2 = bb[1];
     nb.l1 = bb[2] - bb[0];
     nb.l2 = bb[3] - bb[1];
-    // a box wider than the slot keeps the central fcap rows / columns
-    if (nb.l1 > A.fcap) {
-      nb.o1 += (nb.l1 - A.fcap) / 2;
-      nb.l1 = A.fcap;
-    }
-    if (nb.l2 > A.fcap) {
-      nb.o2 += (nb.l2 - A.fcap) / 2;
-      nb.l2 = A.fcap;
-    }
-    if (t == 0 && (nb.l1 != bb[2] - bb[0] || nb.l2 != bb[3] - bb[1])) atomicAdd(A.nclip, 1);
-  }
-  double* fv = A.fvals + (long)b * A.fcap2;
-  for (long o = t; o < (long)nb.l1 * nb.l2; o += kBlock) {
-    const int a1 = (int)(o / nb.l2), a2 = (int)(o - (long)a1 * nb.l2);
-    const int y1 = nb.o1 + a1, y2 = nb.o2 + a2;
-    const int Y1 = y1 / 2, Y2 = y2 / 2;
-    const double v = f * cv[(long)(Y1 - cb.o1) * cb.l2 + (Y2 - cb.o2)] *
-                     A.nu_f[(long)y1 * A.fn2 + y2] / A.nu_c[(long)Y1 * A.cn2 + Y2];
-    fv[o] = v >= A.trunc ? v : 0.0;
   }
   if (t == 0) {
     A.fbox[b] = nb;
@@ -164,11 +139,13 @@ __global__ void k_refine_grid(const double* px_c, const double* abar_c, const do
   }
 }
 
+// Phase 0 (the boxes, hbar, P_X and the stitched potential) or phase 1 (the
+// values at A.fvoff).
 hipError_t launch_refine(const RefineArgs& A, int fnbasic, const double* px_c, const double* abar_c,
                          double* px_f, double* abar_f, int fn1, hipStream_t st) {
   if (fnbasic > 0) hipLaunchKernelGGL(k_refine_slots, dim3(fnbasic), dim3(kBlock), 0, st, A);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || A.phase == 1) return e;
   const long n = (long)fn1 * A.fn2;
   const int blocks = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
   hipLaunchKernelGGL(k_refine_grid, dim3(blocks), dim3(256), 0, st, px_c, abar_c, A.mu_c, A.mu_f,

@@ -8,8 +8,9 @@
 //     pi(x, y) = exp((alpha(x) + beta(y) - c(x, y)) / eps) mu(x) nu(y),
 // split by basic cells: nu_i(y) = sum_{x in X_i} pi(x, y), scanned over a
 // window of Y points per basic cell, entries below the truncation threshold
-// dropped, box = bbox of the rest (a box wider than the slot keeps its central
-// rows / columns).  The cell plan is pi on X_i x (kept points of the box);
+// dropped, box = bbox of the rest.  Two launches: the boxes (phase 0), then,
+// once the host has placed them in the state pool, the values, P_X and the
+// tracked pieces (phase 1).  The cell plan is pi on X_i x (kept points of the box);
 // P_X pi and the tracked piece
 //     Hbar_i = <alpha, P_X pi_i> + <beta, nu_i> - eps |nu_i| + eps |mu_i| |nu|
 //              + lam KL(P_X pi_i | mu_i)
@@ -113,7 +114,7 @@ __device__ __forceinline__ void sumN(double (&v)[N], double* red) {
   __syncthreads();
 }
 
-// One workgroup per basic cell.  Dynamic LDS: G (s x gcols) then H (cap x s).
+// One workgroup per basic cell.  Dynamic LDS: G (s x gcols) then H (hrows x s).
 __global__ __launch_bounds__(kBlock) void k_from_duals(DualsArgs A) {
   extern __shared__ __align__(16) double sm[];
   __shared__ double sa[kMaxS * kMaxS];
@@ -165,35 +166,31 @@ __global__ __launch_bounds__(kBlock) void k_from_duals(DualsArgs A) {
   };
   auto kept = [&](double v) { return v >= A.trunc && v > 0.0; };
   // 1. bounding box of the kept points of the window
-  int bb[4] = {INT_MAX, INT_MAX, INT_MIN, INT_MIN};
-  for (long o = t; o < (long)w.l1 * w.l2; o += kBlock) {
-    const int y1 = w.o1 + (int)(o / w.l2), y2 = w.o2 + (int)(o % w.l2);
-    if (kept(nu_i(y1, y2))) {
-      bb[0] = min(bb[0], y1);
-      bb[1] = min(bb[1], y2);
-      bb[2] = max(bb[2], y1 + 1);
-      bb[3] = max(bb[3], y2 + 1);
+  if (A.phase == 0) {
+    int bb[4] = {INT_MAX, INT_MAX, INT_MIN, INT_MIN};
+    for (long o = t; o < (long)w.l1 * w.l2; o += kBlock) {
+      const int y1 = w.o1 + (int)(o / w.l2), y2 = w.o2 + (int)(o % w.l2);
+      if (kept(nu_i(y1, y2))) {
+        bb[0] = min(bb[0], y1);
+        bb[1] = min(bb[1], y2);
+        bb[2] = max(bb[2], y1 + 1);
+        bb[3] = max(bb[3], y2 + 1);
+      }
     }
+    minmax4(bb, redi);
+    Box nb{X1, X2, 0, 0};
+    if (bb[0] != INT_MAX) {
+      nb.o1 = bb[0];
+      nb.o2 = bb[1];
+      nb.l1 = bb[2] - bb[0];
+      nb.l2 = bb[3] - bb[1];
+    }
+    if (t == 0) A.box[b] = nb;
+    return;
   }
-  minmax4(bb, redi);
-  Box nb{X1, X2, 0, 0};
-  if (bb[0] != INT_MAX) {
-    nb.o1 = bb[0];
-    nb.o2 = bb[1];
-    nb.l1 = bb[2] - bb[0];
-    nb.l2 = bb[3] - bb[1];
-    if (nb.l1 > A.cap) {
-      nb.o1 += (nb.l1 - A.cap) / 2;
-      nb.l1 = A.cap;
-    }
-    if (nb.l2 > A.cap) {
-      nb.o2 += (nb.l2 - A.cap) / 2;
-      nb.l2 = A.cap;
-    }
-    if (t == 0 && (nb.l1 != bb[2] - bb[0] || nb.l2 != bb[3] - bb[1])) atomicAdd(A.nclip, 1);
-  }
+  const Box nb = A.box[b];
   // 2. slot values, <beta, nu_i> and |nu_i|
-  double* v = A.vals + (long)b * A.cap2;
+  double* v = A.vals + A.voff[b];
   double acc2[2] = {0.0, 0.0};
   for (long o = t; o < (long)nb.l1 * nb.l2; o += kBlock) {
     const int y1 = nb.o1 + (int)(o / nb.l2), y2 = nb.o2 + (int)(o % nb.l2);
@@ -256,19 +253,16 @@ __global__ __launch_bounds__(kBlock) void k_from_duals(DualsArgs A) {
     acc3[0] += A.alpha[g] * p + A.lam * klx + A.eps * mu * A.mass_nu;
   }
   sumN<1>(acc3, red);
-  if (t == 0) {
-    A.box[b] = nb;
-    A.hbar[b] = acc3[0] + acc2[0] - A.eps * acc2[1];
-  }
+  if (t == 0) A.hbar[b] = acc3[0] + acc2[0] - A.eps * acc2[1];
 }
 
-size_t from_duals_lds(int s, int gcols, int cap) {
-  return sizeof(double) * ((size_t)s * gcols + (size_t)cap * s);
+size_t from_duals_lds(int s, int gcols, int hrows) {
+  return sizeof(double) * ((size_t)s * gcols + (size_t)hrows * s);
 }
 
 hipError_t launch_from_duals(const DualsArgs& A, int nbasic, hipStream_t st) {
   if (nbasic <= 0) return hipSuccess;
-  const size_t lds = from_duals_lds(A.s, A.gcols, A.cap);
+  const size_t lds = from_duals_lds(A.s, A.gcols, A.hrows);
   hipError_t e = hipFuncSetAttribute((const void*)k_from_duals,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

@@ -48,7 +48,7 @@ def test_batched_fp64_follows_each_oracle(balance):
             p = dd.make_problem(data[k][0], data[k][1], c.eps, c.lambda_, c.h, c.cell)
             probs.append(p)
             states.append(dd.init_product(p))
-        opts = [dd.Options(fixed_iters=8, lenience=0.0, cap=32, trunc=1e-15, margin=2, translate=True,
+        opts = [dd.Options(fixed_iters=8, lenience=0.0, trunc=1e-15, margin=2, translate=True,
                            balance=bool(b)) for b in balance]
         for step in range(4):
             print(f"[batched] step {step}", flush=True)

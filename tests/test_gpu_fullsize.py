@@ -56,7 +56,7 @@ def test_first_half_iteration_sampled_cells(marg, oracle_problem, precision, rto
     p, st = oracle_problem
     cfg = cfg_for(precision, B.GW_GREEDY)
     opt = dd.Options(err=cfg.sinkhorn_err, max_iter=MAX_INNER, trunc=cfg.trunc,
-                     lenience=cfg.lenience, margin=cfg.box_margin, cap=CAP, getweights="greedy",
+                     lenience=cfg.lenience, margin=cfg.box_margin, getweights="greedy",
                      translate=bool(cfg.translate))
     print(f"[fullsize] 1024^2 first half-iteration, precision {precision}", flush=True)
     h = B.dd_uot_init(cfg, mu, nu)

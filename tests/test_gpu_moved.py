@@ -34,7 +34,7 @@ def test_moved_fp64_follows_the_oracle():
     c = cfg(n, s, fixed_inner_iters=8)
     p = dd.make_problem(mu, nu, c.eps, 1.0, c.h, s, ypos=y)
     st = dd.init_product(p)
-    opt = dd.Options(fixed_iters=8, lenience=0.0, cap=n, trunc=1e-15, margin=2, translate=True)
+    opt = dd.Options(fixed_iters=8, lenience=0.0, trunc=1e-15, margin=2, translate=True)
     h = B.dd_uot_init_moved(c, mu, nu, y)
     try:
         assert B.dd_uot_score(h, 0)["tracked"] == pytest.approx(dd.tracked_score(p, st), rel=1e-12)
@@ -119,7 +119,7 @@ def test_moved_fp32_sampled_cells_512():
                                 box_cap=32, box_margin=2, getweights=B.GW_GREEDY)
     p = dd.make_problem(mu, nu, c.eps, c.lambda_, c.h, s, ypos=y)
     st = dd.init_block(p)
-    opt = dd.Options(err=c.sinkhorn_err, max_iter=100, trunc=c.trunc, margin=2, cap=32,
+    opt = dd.Options(err=c.sinkhorn_err, max_iter=100, trunc=c.trunc, margin=2,
                      getweights="greedy", translate=True)
     print("[moved] 512^2 FP32 first half-iteration", flush=True)
     h = B.dd_uot_init_moved(c, mu, nu, y)

@@ -29,14 +29,14 @@ def test_refine_matches_oracle(sc, sf):
     pc = dd.make_problem(muc, nuc, ec, 1.0, 1.0 / nc, sc)
     pf = dd.make_problem(muf, nuf, ef, 1.0, 1.0 / nf, sf)
     stc = dd.init_block(pc)
-    opt = dd.Options(fixed_iters=20, lenience=0.0, cap=32, margin=2, trunc=1e-15, translate=True)
+    opt = dd.Options(fixed_iters=20, lenience=0.0, margin=2, trunc=1e-15, translate=True)
     dd.run(pc, stc, 3, opt)
     hc = B.dd_uot_init(cc, muc, nuc)
     hf = None
     try:
         B.dd_uot_iterate(hc, 3)
         hf = B.dd_uot_refine(hc, cf, muf, nuf)
-        stf = dd.refine(pc, stc, pf, 1e-15, 32)
+        stf = dd.refine(pc, stc, pf, 1e-15)
         px, _ = B.dd_uot_marginals(hf, 0, nf, nf)
         np.testing.assert_allclose(px, stf.px, rtol=0, atol=1e-10 * stf.px.max())
         for b in range(pf.nb1 * pf.nb2):
@@ -80,13 +80,13 @@ def oracle_multiscale(mu, nu, c, ms):
         opt = dd.Options(err=c.sinkhorn_err, max_iter=c.sinkhorn_max_iter if fin else
                          max(c.sinkhorn_max_iter, ms.coarse_max_iter), trunc=c.trunc,
                          lenience=c.lenience if fin else ms.coarse_lenience,
-                         margin=c.box_margin, cap=cap, getweights="swift", translate=True)
+                         margin=c.box_margin, getweights="swift", translate=True)
         pn = dd.make_problem(mus[l], nus[l], ms.eps_start_h2 * h * h, c.lambda_, h, s)
         if l == 0:
             st = dd.init_product(pn) if cap >= n else dd.init_block(pn)
         else:
             halves += st.k if hasattr(st, "k") else 0
-            st = dd.refine(p, st, pn, c.trunc, cap)
+            st = dd.refine(p, st, pn, c.trunc)
         p = pn
         e_end = c.eps if fin else ms.eps_end_h2 * h * h
         e = p.eps

@@ -23,7 +23,7 @@ def config(n, s, eps, lam, h, **kw):
 def oracle_options(cfg):
     return dd.Options(err=cfg.sinkhorn_err, max_iter=cfg.sinkhorn_max_iter,
                       fixed_iters=cfg.fixed_inner_iters, trunc=cfg.trunc, lenience=cfg.lenience,
-                      margin=cfg.box_margin, cap=cfg.box_cap, getweights=GW[cfg.getweights],
+                      margin=cfg.box_margin, getweights=GW[cfg.getweights],
                       translate=bool(cfg.translate), balance=bool(cfg.balance))
 
 
@@ -249,21 +249,28 @@ def test_certificate_and_backward_match_oracle(grid32):
         B.dd_uot_destroy(h)
 
 
-def test_box_overflow_is_reported_and_keeps_state(grid32):
-    # B cells gather basic boxes grown inside four different A boxes; with a
-    # cap of 12 their union no longer fits, so those cells are skipped
+@pytest.mark.parametrize("precision", [64, 32])
+def test_boxes_wider_than_the_lds_layout_follow_the_oracle(grid32, precision):
+    # B cells gather basic boxes grown inside four different A boxes; with an
+    # in-LDS layout of side 12 their union no longer fits, so those cells run
+    # the variant whose box arrays live in the cell workspace: every cell is
+    # solved, on the same trajectory as the oracle (which has no box limit)
     mu, nu = grid32
     n = 32
-    cfg = config(n, 4, 4.0 / n ** 2, 1.0, 1.0 / n, precision=64, init=B.INIT_BLOCK,
-                 sinkhorn_err=1e-8, sinkhorn_max_iter=150, lenience=0.0, box_cap=12, box_margin=2)
-    h, p, st = run_pair(mu, nu, cfg, 4)
+    cfg = config(n, 4, 4.0 / n ** 2, 1.0, 1.0 / n, precision=precision, init=B.INIT_BLOCK,
+                 sinkhorn_err=1e-8, sinkhorn_max_iter=150, lenience=0.0, box_cap=12, box_margin=2,
+                 fixed_inner_iters=20 if precision == 32 else 0)
+    h, p, st = run_pair(mu, nu, cfg, 4, rtol=1e-10 if precision == 64 else 1e-5)
     try:
         hist = B.dd_uot_history(h, 0)
-        ref = [x["n_overflow"] for x in st.history]
-        assert sum(ref) > 0
-        assert list(hist[:, 7].astype(int)) == ref
-        assert B.dd_uot_score(h, 0)["overflow"] == 1
-        compare_boxes(h, p, st, 1e-10)
+        assert np.all(hist[:, 7] == 0)
+        assert list(hist[:, 3].astype(int)) == [x["n_updated"] for x in st.history]
+        wide = sum(1 for _, _, arr in st.boxes if arr.size and max(arr.shape) > 12)
+        print(f"[parity] FP{precision}: {wide} basic boxes wider than the layout", flush=True)
+        assert wide > 0
+        assert B.dd_uot_score(h, 0)["overflow"] == 0
+        if precision == 64:   # FP32 may round entries near the truncation level either way
+            compare_boxes(h, p, st, 1e-10)
     finally:
         B.dd_uot_destroy(h)
 

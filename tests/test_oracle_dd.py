@@ -91,7 +91,7 @@ def test_cell_piece_formula_for_diagonal_scaling_plan():
 def test_resplit_sums():
     p = small_problem(8, 2)
     st = dd.init_block(p)
-    opt = dd.Options(margin=2, cap=8, trunc=0.0)
+    opt = dd.Options(margin=2, trunc=0.0)
     P = dd.aggregate(p, st.boxes)
     for cell in dd.composite_cells(p, "B"):
         r = dd.process_cell(p, cell, st.boxes, P, opt)
@@ -111,7 +111,7 @@ def test_global_optimum_is_a_fixed_point_of_the_cell_step():
     for b in range(p.nb1 * p.nb2):
         rows = dd.rect_index(dd.basic_rect(p, b), p.n2)
         st.boxes[b] = (0, 0, pi[rows].sum(0).reshape(p.n1, p.n2))
-    opt = dd.Options(cap=8, trunc=0.0, getweights="greedy", err=1e-14, max_iter=5000)
+    opt = dd.Options(trunc=0.0, getweights="greedy", err=1e-14, max_iter=5000)
     ref = [arr.copy() for _, _, arr in st.boxes]
     dd.half_iteration(p, st, "A", opt)
     for b in range(p.nb1 * p.nb2):
@@ -128,7 +128,7 @@ def test_monotone_scores(gw):
     # above the (smaller) exact score of the mixture.
     p = small_problem(8, 2)
     st = dd.init_product(p, dense_plan=True)
-    opt = dd.Options(cap=8, trunc=0.0, getweights=gw, err=1e-13, max_iter=5000)
+    opt = dd.Options(trunc=0.0, getweights=gw, err=1e-13, max_iter=5000)
     E = [dd.exact_score(p, st)]
     Eb = [dd.tracked_score(p, st)]
     assert Eb[0] == pytest.approx(E[0], rel=1e-13)
@@ -152,7 +152,7 @@ def test_monotone_scores(gw):
 def test_sequential_monotone():
     p = small_problem(8, 2)
     st = dd.init_product(p, dense_plan=True)
-    opt = dd.Options(cap=8, trunc=0.0, err=1e-13, max_iter=5000)
+    opt = dd.Options(trunc=0.0, err=1e-13, max_iter=5000)
     E = [dd.exact_score(p, st)]
     for _ in range(4):
         dd.run(p, st, 1, opt, sequential=True)
@@ -165,7 +165,7 @@ def test_dd_converges_to_global_optimum():
     p = small_problem(8, 2)
     pi, sol, C = global_optimum(p)
     st = dd.init_product(p, dense_plan=True)
-    opt = dd.Options(cap=8, trunc=0.0, getweights="swift", err=1e-15, max_iter=20000)
+    opt = dd.Options(trunc=0.0, getweights="swift", err=1e-15, max_iter=20000)
     dd.run(p, st, 160, opt)
     np.testing.assert_allclose(st.plan, pi, rtol=5e-6, atol=1e-15)
     np.testing.assert_allclose(st.px.ravel(), pi.sum(1), rtol=5e-6)
@@ -181,7 +181,7 @@ def test_certificate_gap_identity():
     # PD of the certificate pair equals E(pi_hat) - D(alpha_bar, beta_hat)
     p = small_problem(8, 2)
     st = dd.init_block(p)
-    dd.run(p, st, 3, dd.Options(cap=8, margin=2))
+    dd.run(p, st, 3, dd.Options(margin=2))
     cert = dd.certificate(p, st.abar)
     assert cert["primal"] - cert["dual"] == pytest.approx(cert["pd"], rel=1e-8)
     assert cert["pd"] > 0
@@ -192,7 +192,7 @@ def test_zero_cost_dd_reaches_product_plan():
     p = small_problem(8, 2, h=0.0)
     p.eps = 4.0 / 64
     st = dd.init_product(p, dense_plan=True)
-    dd.run(p, st, 40, dd.Options(cap=8, trunc=0.0, err=1e-15, max_iter=20000))
+    dd.run(p, st, 40, dd.Options(trunc=0.0, err=1e-15, max_iter=20000))
     s = (p.mu.sum() * p.nu.sum()) ** (-p.lam / (p.eps + 2 * p.lam))
     np.testing.assert_allclose(st.plan, s * np.outer(p.mu.ravel(), p.nu.ravel()), rtol=1e-8)
 
@@ -204,7 +204,7 @@ def toy(gw, iters):
     mu = uniform_masses(1, N, 1.0)
     p = dd.make_problem(mu, mu.copy(), 2.0 / N ** 2, 1.0, 1.0 / N, 1, 1)
     st = dd.init_product(p, dense_plan=True)
-    opt = dd.Options(cap=64, trunc=0.0, getweights=gw, err=1e-7, max_iter=1500)
+    opt = dd.Options(trunc=0.0, getweights=gw, err=1e-7, max_iter=1500)
     E = [dd.exact_score(p, st)]
     for _ in range(iters):
         dd.run(p, st, 1, opt)
@@ -234,7 +234,7 @@ def test_toy_getweights_behaviour():
 def test_translation_shift_is_the_line_maximiser_and_keeps_the_solution():
     p = small_problem(16, 4, eps_h2=1.0, lam=1.0)
     st = dd.init_block(p)
-    opt = dd.Options(margin=2, cap=16)
+    opt = dd.Options(margin=2)
     P = dd.aggregate(p, st.boxes)
     cell = dd.composite_cells(p, "A")[1]
     box = dd.cell_box(p, cell, st.boxes, opt)
@@ -251,7 +251,7 @@ def test_translation_shift_is_the_line_maximiser_and_keeps_the_solution():
     # same converged cell solution with and without the step
     sols = []
     for tr in (False, True):
-        o = dd.Options(margin=2, cap=16, translate=tr, err=1e-14, max_iter=200000)
+        o = dd.Options(margin=2, translate=tr, err=1e-14, max_iter=200000)
         sols.append(dd.solve_cell(mu_x, nu_y, r, beta0, C, p.eps, p.lam, 1e-14 * mu_x.sum(), o))
     assert sols[1]["iters"] < sols[0]["iters"]
     np.testing.assert_allclose(sols[1]["px"], sols[0]["px"], rtol=1e-6)
@@ -272,7 +272,7 @@ def test_dd_with_displaced_support_converges_to_global_optimum():
     sol = uot.sinkhorn(p.mu, p.nu, C, p.eps, p.lam, tol=None, step_tol=1e-15)
     pi = uot.plan(sol["alpha"], sol["beta"], p.mu, p.nu, C, p.eps)
     st = dd.init_product(p, dense_plan=True)
-    opt = dd.Options(cap=8, trunc=0.0, getweights="swift", err=1e-15, max_iter=20000,
+    opt = dd.Options(trunc=0.0, getweights="swift", err=1e-15, max_iter=20000,
                      translate=True)
     dd.run(p, st, 160, opt)
     np.testing.assert_allclose(st.plan, pi, rtol=5e-6, atol=1e-15)
@@ -289,7 +289,7 @@ def _coarse_pair(n=16, s=2):
 def test_refined_product_plan_is_the_fine_product_plan():
     # mu_c x nu_c split in proportion to the fine masses is mu_f x nu_f
     pc, pf = _coarse_pair()
-    st = dd.refine(pc, dd.init_product(pc), pf, 0.0, 64)
+    st = dd.refine(pc, dd.init_product(pc), pf, 0.0)
     ref = dd.init_product(pf)
     np.testing.assert_allclose(st.px, ref.px, rtol=1e-13)
     for (a1, a2, a), (b1, b2, b) in zip(st.boxes, ref.boxes):
@@ -302,7 +302,7 @@ def test_refined_block_start_with_double_cell_is_the_fine_block_start():
     # cell side doubles: one fine basic cell per coarse one, nu on the block
     pf = small_problem(16, 4)
     pc = dd.make_problem(dd.coarsen(pf.mu), dd.coarsen(pf.nu), pf.eps * 4, pf.lam, pf.h * 2, 2)
-    st = dd.refine(pc, dd.init_block(pc), pf, 0.0, 64)
+    st = dd.refine(pc, dd.init_block(pc), pf, 0.0)
     ref = dd.init_block(pf)
     np.testing.assert_allclose(st.px, ref.px, rtol=1e-13)
     for (a1, a2, a), (b1, b2, b) in zip(st.boxes, ref.boxes):
@@ -313,8 +313,8 @@ def test_refined_block_start_with_double_cell_is_the_fine_block_start():
 def test_refinement_keeps_mass_and_the_prolonged_y_marginal():
     pc, pf = _coarse_pair()
     stc = dd.init_block(pc)
-    dd.run(pc, stc, 3, dd.Options(cap=16, margin=2, trunc=0.0, translate=True))
-    st = dd.refine(pc, stc, pf, 0.0, 64)
+    dd.run(pc, stc, 3, dd.Options(margin=2, trunc=0.0, translate=True))
+    st = dd.refine(pc, stc, pf, 0.0)
     Pc = dd.aggregate(pc, stc.boxes)
     Pf = dd.aggregate(pf, st.boxes)
     np.testing.assert_allclose(dd.coarsen(Pf), Pc, rtol=1e-12)
@@ -341,7 +341,7 @@ def test_staggered_scores_decrease_and_reach_the_optimum():
     p = small_problem(8, 2)
     pi, sol, C = global_optimum(p)
     st = dd.init_product(p, dense_plan=True)
-    opt = dd.Options(cap=8, trunc=0.0, getweights="staggered", err=1e-15, max_iter=20000,
+    opt = dd.Options(trunc=0.0, getweights="staggered", err=1e-15, max_iter=20000,
                      lenience=0.0)
     prev = dd.tracked_score(p, st)
     for _ in range(120):
@@ -402,23 +402,19 @@ def test_state_from_potentials_truncates_and_boxes_tightly():
     pi, sol, C = global_optimum(p)
     a, b = sol["alpha"].reshape(16, 16), sol["beta"].reshape(16, 16)
     trunc = 1e-9
-    st = dd.init_from_duals(p, a, b, trunc, cap=10)
+    st = dd.init_from_duals(p, a, b, trunc)
     for bi, (o1, o2, arr) in enumerate(st.boxes):
         full = pi[dd.rect_index(dd.basic_rect(p, bi), p.n2)].sum(0).reshape(16, 16)
         kept = arr > 0
-        assert arr.shape[0] <= 10 and arr.shape[1] <= 10
         assert np.all(arr[kept] >= trunc)
         np.testing.assert_allclose(arr[kept], full[o1:o1 + arr.shape[0], o2:o2 + arr.shape[1]][kept],
                                    rtol=1e-13)
+        # the box is the bbox of the entries >= trunc, whatever its size
         big = full >= trunc
         r1, r2 = np.nonzero(big)
-        if r1.max() + 1 - r1.min() <= 10 and r2.max() + 1 - r2.min() <= 10:
-            # unclipped: the box is the bbox of the entries >= trunc
-            assert (o1, o2, arr.shape) == (r1.min(), r2.min(),
-                                           (r1.max() + 1 - r1.min(), r2.max() + 1 - r2.min()))
-        else:
-            # clipped: the central cap rows / columns of that bbox
-            assert arr.shape[0] == 10 or arr.shape[1] == 10
+        assert (o1, o2, arr.shape) == (r1.min(), r2.min(),
+                                       (r1.max() + 1 - r1.min(), r2.max() + 1 - r2.min()))
+        assert np.count_nonzero(kept) == np.count_nonzero(big)
     # px is the X-marginal of the kept cell plans: at most the full row sums
     assert np.all(st.px <= pi.sum(1).reshape(16, 16) * (1 + 1e-13))
 
@@ -430,7 +426,7 @@ def test_optimal_state_is_a_fixed_point_of_a_dd_half_iteration():
     pi, sol, C = global_optimum(p)
     st = dd.init_from_duals(p, sol["alpha"].reshape(8, 8), sol["beta"].reshape(8, 8), 0.0)
     ref = [arr.copy() for _, _, arr in st.boxes]
-    opt = dd.Options(cap=8, trunc=0.0, getweights="greedy", err=1e-14, max_iter=5000)
+    opt = dd.Options(trunc=0.0, getweights="greedy", err=1e-14, max_iter=5000)
     out = dd.half_iteration(p, st, "B", opt)
     assert out["theta"] == 1.0
     P = dd.aggregate(p, st.boxes)
@@ -458,8 +454,8 @@ def test_line_weight_minimises_the_tracked_score_of_the_mixture():
     # weight (checked by evaluating the score itself, not its derivative)
     p = small_problem(16, 2, eps_h2=2.0)
     st = dd.init_product(p)
-    opt = dd.Options(cap=16, trunc=0.0, err=1e-12, max_iter=3000, margin=2)
-    dd.run(p, st, 1, dd.Options(cap=16, trunc=0.0, err=1e-12, max_iter=3000, margin=2,
+    opt = dd.Options(trunc=0.0, err=1e-12, max_iter=3000, margin=2)
+    dd.run(p, st, 1, dd.Options(trunc=0.0, err=1e-12, max_iter=3000, margin=2,
                                 getweights="greedy"))
     found_interior = False
     for part in ("B", "A", "B"):
@@ -486,7 +482,7 @@ def test_line_weight_minimises_the_tracked_score_of_the_mixture():
             for dz in (1e-3, 1e-5):
                 assert fz <= f(min(z + dz, 1.0)) + 1e-13 * abs(fz)
                 assert fz <= f(max(z - dz, 1.0 / n)) + 1e-13 * abs(fz)
-        dd.half_iteration(p, st, part, dd.Options(cap=16, trunc=0.0, err=1e-12, max_iter=3000,
+        dd.half_iteration(p, st, part, dd.Options(trunc=0.0, err=1e-12, max_iter=3000,
                                                    margin=2, getweights="line"))
         assert st.history[-1]["theta"] == pytest.approx(z, rel=1e-12)
     assert found_interior
@@ -501,7 +497,7 @@ def test_balancing_moves_mass_horizontally_to_the_targets():
     st = dd.init_block(p)
     P = dd.aggregate(p, st.boxes)
     # a solve stopped early leaves P_X away from mubar, so there is mass to move
-    opt = dd.Options(cap=16, trunc=0.0, err=1e-10, max_iter=3, margin=2, translate=True)
+    opt = dd.Options(trunc=0.0, err=1e-10, max_iter=3, margin=2, translate=True)
     cell = dd.composite_cells(p, "A")[5]
     plain = dd.process_cell(p, cell, st.boxes, P, opt)
     opt.balance = True
