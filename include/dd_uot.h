@@ -349,6 +349,9 @@ typedef struct {
   int32_t coarse_box_cap;    /* DD layers other than the finest use the in-LDS
                                 layout max(cfg->box_cap, coarse_box_cap) (<= 128) */
   double coarse_lenience;    /* ... and this GetWeights lenience */
+  int32_t verbose;           /* 1: one progress line per layer and eps stage on
+                                stderr (layer, eps, half-iterations, gaps,
+                                elapsed time); 0: silent */
 } dduot_multiscale;
 
 /* levels 7, coarse_cell 4, eps 2 h^2 -> h^2/2 per layer, 4..16 half-iterations

@@ -24,9 +24,16 @@ them also fixed in the design notes):
      margin M per axis, clipped to the grid; boxes of any size (Sec. 4.1 keeps
      nu_{-J} on the support of nu_J, whatever its extent).  An all-empty union
      uses the X rectangle of J instead.
-  R5 warm start: beta^0 = -lam log(P_Y pi / nu) on the box (0 where P_Y pi = 0),
-     i.e. the Y optimality condition eq. (optimality-conditions-KL) evaluated
-     for the current plan.
+  R5 warm start (the paper only says "for a given initialization beta^0"):
+     when every basic cell of J holds a stored X-potential (the stitched
+     alpha of the last solve covering it, of a refinement or of a potential
+     start), the solve starts from alpha^0 = that alpha on X_J with a
+     Y-half; otherwise beta^0 = -lam log(P_Y pi / nu) on the box (0 where
+     P_Y pi = 0), i.e. the Y optimality condition eq.
+     (optimality-conditions-KL) evaluated for the current plan, followed by
+     an X-half.  (beta^0 carries lam/eps times the relative error of P_Y pi,
+     10^6 on the finest grids; alpha^0 carries no such factor.)  beta^0 also
+     enters the first translation step (R6).
   R6 inner loop: X-half, then repeat {Y-half (Newton), X-half, PD check};
      with `translate`, every Y-half is preceded by the exact maximisation of
      the cell dual along (alpha + s, beta - s), which has the closed form
@@ -210,6 +217,7 @@ class State:
     hbar: np.ndarray          # (nbasic,) tracked cell-restricted scores
     abar: np.ndarray          # (n1, n2) last cell potential alpha
     plan: np.ndarray | None = None   # dense plan (tiny problems only)
+    warm: np.ndarray | None = None   # (nbasic,) abar holds a potential on X_i (R5)
     k: int = 0                # half-iterations done
     force_greedy: bool = False
     history: list = field(default_factory=list)
@@ -334,16 +342,17 @@ def translation_shift(alpha, beta, mu_x, nu_y, r_y, lam):
     return lam * np.log(w)
 
 
-def solve_cell(mu_x, nu_y, r_y, beta0, C, eps, lam, tol, opt: Options):
+def solve_cell(mu_x, nu_y, r_y, beta0, C, eps, lam, tol, opt: Options, alpha0=None):
     """Cell Sinkhorn of Sec. 4.1 (reading R6).
 
     alpha from eq. (sinkhorn-X-iteration); beta from eq. (proxdiv-problem)
-    with r = d nu_{-J} / d nu; PD from eq. (PD-gap-KL).
+    with r = d nu_{-J} / d nu; PD from eq. (PD-gap-KL).  alpha0 (reading R5):
+    start from this alpha instead of the X-half of beta0.
     Returns dict(alpha, beta, px, iters, converged, pd)."""
     with np.errstate(divide="ignore"):
         lr = np.log(r_y)
     beta = beta0.copy()
-    alpha = uot.x_update(beta, nu_y, C, eps, lam)
+    alpha = uot.x_update(beta, nu_y, C, eps, lam) if alpha0 is None else alpha0.copy()
     it, pd, conv = 0, np.inf, False
     while True:
         it += 1
@@ -422,12 +431,14 @@ def balance_cell(p: Problem, cell, sol, pi, mu_x, nu_y, C, rows_of):
     return pi
 
 
-def process_cell(p: Problem, cell, boxes, P, opt: Options):
+def process_cell(p: Problem, cell, boxes, P, opt: Options, abar=None, warm=None):
     """Solve one composite cell and re-split its plan into basic cells.
 
-    Returns a dict with the box, the cell potentials, the candidate basic
-    marginals (untruncated), their pieces H_i (definition cell_piece), P_X of
-    the cell plan, iteration count."""
+    abar, warm: the stitched X-potential and its per-basic-cell validity
+    (warm start of reading R5; None: the beta^0 start).  Returns a dict with
+    the box, the cell potentials, the candidate basic marginals
+    (untruncated), their pieces H_i (definition cell_piece), P_X of the cell
+    plan, iteration count."""
     box = cell_box(p, cell, boxes, opt)
     rect = cell["rect"]
     xi = rect_index(rect, p.n2)
@@ -437,7 +448,10 @@ def process_cell(p: Problem, cell, boxes, P, opt: Options):
     C = rect_cost(p, rect, box)
     r, beta0 = cell_inputs(p, cell, box, boxes, P)
     tol = opt.err * mu_x.sum()
-    sol = solve_cell(mu_x, nu_y, r, beta0, C, p.eps, p.lam, tol, opt)
+    alpha0 = None
+    if abar is not None and warm is not None and all(warm[b] for b in cell["basic"]):
+        alpha0 = np.ravel(abar)[xi]
+    sol = solve_cell(mu_x, nu_y, r, beta0, C, p.eps, p.lam, tol, opt, alpha0)
     pi = uot.plan(sol["alpha"], sol["beta"], mu_x, nu_y, C, p.eps)
     nu_tot = p.nu.sum()
     cand, pieces = {}, {}
@@ -518,12 +532,20 @@ def line_weight(p: Problem, P, Pg, dH: float, n_upd: int) -> float:
     return float(brentq(fprime, lo, 1.0, xtol=1e-16, rtol=1e-15, maxiter=500))
 
 
+def _mark_warm(p: Problem, st: State, cell):
+    """abar on the basic cells of `cell` now holds a cell potential (R5)."""
+    if st.warm is None:
+        st.warm = np.zeros(p.nb1 * p.nb2, dtype=bool)
+    for b in cell["basic"]:
+        st.warm[b] = True
+
+
 def _dd_step(p: Problem, st: State, cells, part: str, rule: str, opt: Options,
              force: bool) -> dict:
     """One parallel DomDecIter (Algorithm 4) over `cells`, with GetWeights
     `rule` (reading R9; force = greedy).  Mutates `st`."""
     P = aggregate(p, st.boxes)
-    upd = [(c, process_cell(p, c, st.boxes, P, opt)) for c in cells]
+    upd = [(c, process_cell(p, c, st.boxes, P, opt, st.abar, st.warm)) for c in cells]
     n_upd = len(upd)
 
     # candidate state for the greedy choice
@@ -559,6 +581,7 @@ def _dd_step(p: Problem, st: State, cells, part: str, rule: str, opt: Options,
         pxf = st.px.ravel()
         pxf[r["xi"]] = (1.0 - theta) * pxf[r["xi"]] + theta * r["px"]
         st.abar.ravel()[r["xi"]] = r["alpha"]
+        _mark_warm(p, st, c)
         if st.plan is not None:
             rows = r["xi"]
             new = np.zeros((rows.size, p.n1 * p.n2))
@@ -598,7 +621,7 @@ def half_iteration_sequential(p: Problem, st: State, part: str, opt: Options) ->
     iters = []
     for c in cells:
         P = aggregate(p, st.boxes)
-        r = process_cell(p, c, st.boxes, P, opt)
+        r = process_cell(p, c, st.boxes, P, opt, st.abar, st.warm)
         iters.append(r["iters"])
         o1, o2 = r["box"][0], r["box"][1]
         for b in c["basic"]:
@@ -606,6 +629,7 @@ def half_iteration_sequential(p: Problem, st: State, part: str, opt: Options) ->
             st.hbar[b] = r["pieces"][b]
         st.px.ravel()[r["xi"]] = r["px"]
         st.abar.ravel()[r["xi"]] = r["alpha"]
+        _mark_warm(p, st, c)
         if st.plan is not None:
             new = np.zeros((r["xi"].size, p.n1 * p.n2))
             new[:, r["yi"]] = r["pi"]
@@ -653,7 +677,11 @@ def refine(pc: Problem, stc: State, pf: Problem, trunc: float) -> State:
     cell i inside the coarse basic cell I takes the share |mu_f(X_i)| /
     |mu_c(X_I)| of the refined marginal of I.  Boxes double, then entries
     below `trunc` are dropped and the box shrinks (R7).  The tracked pieces
-    are scaled alike (estimates: the next step is forced greedy)."""
+    are scaled alike (estimates: the next step is forced greedy).  The stitched
+    X-potential (cost units) is interpolated linearly to the fine grid (as in
+    R11), which keeps its error at the curvature of the potential times h^2
+    where a copy per 2 x 2 block would leave its gradient times h; it stays a
+    warm start (R5) where the coarse basic cell's was."""
     ones = np.ones((2, 2))
     nbasic = pf.nb1 * pf.nb2
     boxes, hbar = [], np.zeros(nbasic)
@@ -675,8 +703,15 @@ def refine(pc: Problem, stc: State, pf: Problem, trunc: float) -> State:
             pf.nu[2 * o1:2 * (o1 + l1), 2 * o2:2 * (o2 + l2)] * f
         boxes.append(truncate_to_box(2 * o1, 2 * o2, fine, trunc))
     px = np.kron(stc.px / pc.mu, ones) * pf.mu
-    abar = np.kron(stc.abar, ones)
-    return State(boxes, px, hbar, abar, force_greedy=True)
+    # the stored X-potential (cost units) is interpolated linearly (R11's
+    # interpolate_potential); its validity follows the coarse basic cell
+    abar = interpolate_potential(stc.abar, pf.n1, pf.n2)
+    warm = np.zeros(nbasic, dtype=bool)
+    if stc.warm is not None:
+        for b in range(nbasic):
+            x1, x2 = basic_rect(pf, b)[:2]
+            warm[b] = stc.warm[((x1 // 2) // pc.s1) * pc.nb2 + (x2 // 2) // pc.s2]
+    return State(boxes, px, hbar, abar, force_greedy=True, warm=warm)
 
 
 def interpolate_potential(a_c, n1f: int, n2f: int) -> np.ndarray:
@@ -749,7 +784,7 @@ def init_from_duals(p: Problem, alpha, beta, trunc: float, windows=None) -> Stat
         hbar[bi] = cell_piece(pi_box, mu_x, p.nu.ravel()[yidx], nu_tot,
                               rect_cost(p, rect, yrect), p.eps, p.lam)
     return State(boxes, px, hbar, np.asarray(alpha, dtype=np.float64).reshape(p.mu.shape).copy(),
-                 force_greedy=True)
+                 force_greedy=True, warm=np.ones(nbasic, dtype=bool))
 
 
 # --------------------------------------------------------------------------

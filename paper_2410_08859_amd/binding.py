@@ -80,6 +80,7 @@ class dduot_multiscale(C.Structure):
         ("dd_from", C.c_int32), ("global_max_iter", C.c_int32),
         ("global_tol", C.c_double),
         ("coarse_box_cap", C.c_int32), ("coarse_lenience", C.c_double),
+        ("verbose", C.c_int32),
     ]
 
 

@@ -107,6 +107,9 @@ struct dduot_handle {
   unsigned long long* d_fx = nullptr;   // fixed-point sums of the aggregation
   double *d_mu = nullptr, *d_nu = nullptr, *d_P = nullptr, *d_Pg = nullptr, *d_px = nullptr,
          *d_pxc = nullptr, *d_abar = nullptr;
+  int* d_awarm = nullptr;     // per basic cell: d_abar holds a cell potential there
+  double* d_abar_keep = nullptr;   // autotune: the stored potential and flags,
+  int* d_awarm_keep = nullptr;     // restored before every timed solve
   Box *d_box = nullptr, *d_cbox = nullptr, *d_nbox = nullptr, *d_cellbox = nullptr;
   long *d_voff = nullptr, *d_coff = nullptr, *d_nsize = nullptr, *d_csize = nullptr,
        *d_wsize = nullptr, *d_use = nullptr;
@@ -643,6 +646,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_px, h->ngrid));
   CHK(dalloc(h, &h->d_pxc, h->ngrid));
   CHK(dalloc(h, &h->d_abar, h->ngrid));
+  CHK(dalloc(h, &h->d_awarm, h->nbasic));
   CHK(dalloc(h, &h->d_box, h->nbasic));
   CHK(dalloc(h, &h->d_cbox, h->nbasic));
   CHK(dalloc(h, &h->d_nbox, h->nbasic));
@@ -715,6 +719,11 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   HIPCHK(hipMemcpyAsync(h->d_chunk_start, chunk_start.data(), sizeof(int) * h->nchunk, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h->d_chunk_len, chunk_len.data(), sizeof(int) * h->nchunk, hipMemcpyHostToDevice, st));
   HIPCHK(launch_fill(h->d_abar, h->ngrid, 0.0, st));
+  {
+    std::vector<int> zw(h->nbasic, 0);
+    HIPCHK(hipMemcpyAsync(h->d_awarm, zw.data(), sizeof(int) * h->nbasic, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   HIPCHK(launch_fill(h->d_hist, (long)nprob * h->hist_cap * kHistFields, 0.0, st));
   std::vector<int> zeros(nprob, 0);
   HIPCHK(hipMemcpyAsync(h->d_capfail, zeros.data(), sizeof(int) * nprob, hipMemcpyHostToDevice, st));
@@ -781,6 +790,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   d.px = h->d_px;
   d.pxc = h->d_pxc;
   d.abar = h->d_abar;
+  d.awarm = h->d_awarm;
   d.box = h->d_box;
   d.voff = h->d_voff;
   d.sp = h->d_sp;
@@ -992,8 +1002,8 @@ static int capture_pair(dduot_handle* h) {
 // Threads per cell workgroup: time the cell solve of the next partition on
 // the current state for every admissible size (at least the largest tile's
 // point count) and keep the fastest.  The timed solves write only candidate
-// buffers and the stitched potentials, which the next step rewrites with the
-// same values, so the state is unchanged.
+// buffers and the stitched potentials; the potentials and their flags are
+// restored, so the state is unchanged.
 extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
   if (!h) return fail(DDUOT_EINVAL, "null handle");
   hipStream_t st = h->stream;
@@ -1002,6 +1012,19 @@ extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
   CHK(check_pools(h, 1));
   HIPCHK(launch_aggregate(h->d, h->d_P, h->nbasic, h->ngrid, st));
   HIPCHK(launch_cell_prep(h->d, base, h->ncell[part], h->precision, st));
+  // every timed solve starts from the same stored potentials (their warm
+  // start), and the state is left as it was
+  if (!h->d_abar_keep) CHK(dalloc(h, &h->d_abar_keep, h->ngrid));
+  if (!h->d_awarm_keep) CHK(dalloc(h, &h->d_awarm_keep, h->nbasic));
+  HIPCHK(hipMemcpyAsync(h->d_abar_keep, h->d_abar, sizeof(double) * h->ngrid, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_awarm_keep, h->d_awarm, sizeof(int) * h->nbasic, hipMemcpyDeviceToDevice, st));
+  auto restore = [&]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(h->d_abar, h->d_abar_keep, sizeof(double) * h->ngrid,
+                                  hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h->d_awarm, h->d_awarm_keep, sizeof(int) * h->nbasic, hipMemcpyDeviceToDevice, st);
+    return e;
+  };
   const int cand[3] = {64, 128, 256};
   double best = 1e300;
   int pick = 256;
@@ -1015,7 +1038,8 @@ extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
       continue;
     }
     float t = 0.0f;
-    hipError_t e = hipEventRecord(e0, st);
+    hipError_t e = restore();
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
     if (e == hipSuccess) e = launch_cell_solve(h->d, base, h->ncell[part], h->cap, h->tcap, h->precision, h->moved, h->balance, nt, st);
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1033,6 +1057,8 @@ extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  HIPCHK(restore());
+  HIPCHK(hipStreamSynchronize(st));
   h->nt = pick;
   if (h->gexec) {   // the captured step used the old size
     (void)hipGraphExecDestroy(h->gexec);
@@ -1327,6 +1353,8 @@ extern "C" int dd_uot_refine(dduot_handle* coarse, const dduot_config* cfg, cons
     A.fs = pf.s;
     A.trunc = pf.trunc;
     A.fbox = h->d_box;
+    A.fwarm = h->d_awarm;
+    A.cwarm = coarse->d_awarm;
     A.fvoff = h->d_voff;
     A.fhbar = h->d_hbar;
     A.phase = 0;
@@ -1506,6 +1534,8 @@ static int state_from_duals(dduot_handle* h, const double* d_alpha, const double
   A.phase = 1;
   HIPCHK(launch_from_duals(A, p.nbasic, st));
   HIPCHK(hipMemcpyAsync(h->d_abar, d_alpha, sizeof(double) * p.n1 * p.n2, hipMemcpyDeviceToDevice, st));
+  std::vector<int> ones(h->nbasic, 1);
+  HIPCHK(hipMemcpyAsync(h->d_awarm, ones.data(), sizeof(int) * h->nbasic, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h->d_force, &one, sizeof(int), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   return DDUOT_OK;
@@ -1692,6 +1722,9 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
         double pd = 0.0;
         CHK(gs_solve(p, g_mu, g_nu, g_a, g_b, g_s, g_part, ms->global_max_iter, ms->global_tol * mass,
                      st, &it, &pd));
+        if (ms->verbose)
+          fprintf(stderr, "[multiscale] global %dx%d eps %.3g h^2: %d iterations, KL/|mu| %.3g, %.0f ms\n",
+                  c.n1, c.n2, e / h2, it, pd / mass, now_ms() - t0);
         if (e <= e_end * (1.0 + 1e-12)) break;
         e = std::max(e * 0.5, e_end);
       }
@@ -1770,15 +1803,35 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
     double e = c.eps;
     for (;;) {
       int done = 0;
+      dduot_score sc{};
+      bool have_sc = false;
+      long long inner = 0, cells = 0, unconv = 0;
       for (;;) {
-        int r = dd_uot_iterate(h, ms->halves_per_stage, nullptr);
+        dduot_iter_stats it{};
+        int r = dd_uot_iterate(h, ms->halves_per_stage, ms->verbose ? &it : nullptr);
         if (r != DDUOT_OK) return fail_out(r);
+        inner += it.inner_iters;
+        cells += it.n_cells;
+        unconv += it.n_unconverged;
         done += ms->halves_per_stage;
+        have_sc = false;
         if (done + ms->halves_per_stage > ms->stage_max_halves) break;
-        dduot_score sc;
         r = dd_uot_score(h, 0, &sc);
         if (r != DDUOT_OK) return fail_out(r);
+        have_sc = true;
         if (sc.rel_pd_gap <= ms->stage_gap) break;
+      }
+      if (ms->verbose) {
+        if (!have_sc) {
+          const int r = dd_uot_score(h, 0, &sc);
+          if (r != DDUOT_OK) return fail_out(r);
+        }
+        fprintf(stderr,
+                "[multiscale] DD %dx%d cell %d eps %.3g h^2: %d half-iterations (%.1f inner "
+                "iterations per cell, %lld unconverged), certificate gap %.3g, DD-plan gap %.3g, "
+                "%.0f ms\n",
+                c.n1, c.n2, c.cell, e / h2, done, cells ? (double)inner / cells : 0.0, unconv,
+                sc.rel_pd_gap, (sc.tracked - sc.dual) / fabs(sc.dual), now_ms() - t0);
       }
       if (e <= e_end * (1.0 + 1e-12)) break;
       e = std::max(e * 0.5, e_end);
@@ -1800,6 +1853,10 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
         r = dd_uot_score(h, 0, &sc);
         if (r != DDUOT_OK) return fail_out(r);
         record(h, sc);
+        if (ms->verbose)
+          fprintf(stderr, "[multiscale] final %dx%d: %d half-iterations, certificate gap %.3g, "
+                  "DD-plan gap %.3g, %.0f ms\n", c.n1, c.n2, done, sc.rel_pd_gap,
+                  (sc.tracked - sc.dual) / fabs(sc.dual), now_ms() - t0);
       }
     }
   }

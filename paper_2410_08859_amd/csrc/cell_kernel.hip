@@ -846,8 +846,18 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
     }
   };
 
-  double Sx = x_half(0.0);
-  double aeps = -kap * Sx;   // alpha/eps of the thread's point
+  // warm start: the stored potential alpha on X_J when every basic cell of J
+  // has one (the loop then starts with a Y-half), else the X-half of beta^0
+  bool warm = true;
+  for (int k = 0; k < C.nb; ++k) warm = warm && d.awarm[C.basic[k]] != 0;
+  double Sx = 0.0;
+  double aeps = 0.0;   // alpha/eps of the thread's point
+  if (warm) {
+    if (t < lx) aeps = d.abar[P.grid_off + gx] / eps;
+  } else {
+    Sx = x_half(0.0);
+    aeps = -kap * Sx;
+  }
 
   const double tol = P.err * muJ;
   const double iK1 = 1.0 / (K + 1.0);   // q_ref = z / (1 + K), one divide per cell
@@ -1052,6 +1062,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
                   lam * accx[4 + k];
       d.cbox[b] = yb;
       d.coff[b] = coff + (long)k * NY;
+      d.awarm[b] = 1;
     }
     // log-sum-exp terms of the separable passes: every Y-half and X-half of
     // the loop, the first X-half, and the re-split passes

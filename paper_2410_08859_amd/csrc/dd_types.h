@@ -56,6 +56,7 @@ struct Dev {
   double* px;                 // X-marginal of the state plan
   double* pxc;                // X-marginal of the candidate cell plans
   double* abar;               // stitched alpha of the last cell solves
+  int* awarm;                 // per basic cell: abar holds a potential on X_i
   // Basic-cell Y-marginals live in variable-size pools: no box size limit.
   // The state is double-buffered: every step writes the new state compactly
   // into the other pool and flips *sp (a device word, so captured graphs stay
@@ -207,6 +208,8 @@ struct RefineArgs {
   int fn2, fs;
   double trunc;
   Box* fbox;
+  int* fwarm;            // stored-potential flags of the fine basic cells
+  const int* cwarm;      // ... of the coarse ones
   const long* fvoff;     // phase 1: offsets of the fine boxes in fvals
   double* fvals;
   double* fhbar;

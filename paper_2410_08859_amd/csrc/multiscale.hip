@@ -123,24 +123,25 @@ __global__ __launch_bounds__(kBlock) void k_refine_slots(RefineArgs A) {
   if (t == 0) {
     A.fbox[b] = nb;
     A.fhbar[b] = f * A.chbar[I];
+    A.fwarm[b] = A.cwarm[I];
   }
 }
 
-// Fine X-marginal and stitched potential from the coarse ones.
-__global__ void k_refine_grid(const double* px_c, const double* abar_c, const double* mu_c,
-                              const double* mu_f, double* px_f, double* abar_f, int fn1, int fn2,
-                              int cn2) {
+// Fine X-marginal from the coarse one.
+__global__ void k_refine_grid(const double* px_c, const double* mu_c, const double* mu_f,
+                              double* px_f, int fn1, int fn2, int cn2) {
   const long n = (long)fn1 * fn2;
   for (long g = blockIdx.x * (long)blockDim.x + threadIdx.x; g < n; g += (long)gridDim.x * blockDim.x) {
     const int x1 = (int)(g / fn2), x2 = (int)(g - (long)x1 * fn2);
     const long G = (long)(x1 / 2) * cn2 + x2 / 2;
     px_f[g] = px_c[G] * mu_f[g] / mu_c[G];
-    abar_f[g] = abar_c[G];
   }
 }
 
-// Phase 0 (the boxes, hbar, P_X and the stitched potential) or phase 1 (the
-// values at A.fvoff).
+hipError_t launch_interp(const double* ac, int n1c, int n2c, double* af, hipStream_t st);
+
+// Phase 0 (the boxes, hbar, P_X, the stitched potential and its flags) or
+// phase 1 (the values at A.fvoff).
 hipError_t launch_refine(const RefineArgs& A, int fnbasic, const double* px_c, const double* abar_c,
                          double* px_f, double* abar_f, int fn1, hipStream_t st) {
   if (fnbasic > 0) hipLaunchKernelGGL(k_refine_slots, dim3(fnbasic), dim3(kBlock), 0, st, A);
@@ -148,9 +149,13 @@ hipError_t launch_refine(const RefineArgs& A, int fnbasic, const double* px_c, c
   if (e != hipSuccess || A.phase == 1) return e;
   const long n = (long)fn1 * A.fn2;
   const int blocks = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
-  hipLaunchKernelGGL(k_refine_grid, dim3(blocks), dim3(256), 0, st, px_c, abar_c, A.mu_c, A.mu_f,
-                     px_f, abar_f, fn1, A.fn2, A.cn2);
-  return hipGetLastError();
+  hipLaunchKernelGGL(k_refine_grid, dim3(blocks), dim3(256), 0, st, px_c, A.mu_c, A.mu_f, px_f, fn1,
+                     A.fn2, A.cn2);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // the stored potential (cost units), interpolated linearly: an error of its
+  // curvature times h^2 instead of its gradient times h for a block copy
+  return launch_interp(abar_c, fn1 / 2, A.fn2 / 2, abar_f, st);
 }
 
 }  // namespace dduot

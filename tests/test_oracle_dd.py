@@ -194,7 +194,11 @@ def test_zero_cost_dd_reaches_product_plan():
     st = dd.init_product(p, dense_plan=True)
     dd.run(p, st, 40, dd.Options(trunc=0.0, err=1e-15, max_iter=20000))
     s = (p.mu.sum() * p.nu.sum()) ** (-p.lam / (p.eps + 2 * p.lam))
-    np.testing.assert_allclose(st.plan, s * np.outer(p.mu.ravel(), p.nu.ravel()), rtol=1e-8)
+    # the cell stopping rule bounds KL(P_X pi | e^{-alpha/lam} mu) <= Err |mu_J|,
+    # which is quadratic in the relative marginal error: Err = 1e-15 leaves
+    # up to sqrt(2e-15) ~ 4.5e-8 (a warm-started cell at the fixed point stops
+    # at its first check)
+    np.testing.assert_allclose(st.plan, s * np.outer(p.mu.ravel(), p.nu.ravel()), rtol=5e-8)
 
 
 def toy(gw, iters):
@@ -461,17 +465,14 @@ def test_line_weight_minimises_the_tracked_score_of_the_mixture():
     for part in ("B", "A", "B"):
         cells = dd.composite_cells(p, part)
         P = dd.aggregate(p, st.boxes)
-        res = [dd.process_cell(p, c, st.boxes, P, opt) for c in cells]
+        res = [dd.process_cell(p, c, st.boxes, P, opt, st.abar, st.warm) for c in cells]
         cand = list(st.boxes)
         for c, r in zip(cells, res):
-            if r is None:
-                continue
             for b in c["basic"]:
                 cand[b] = dd.truncate_to_box(r["box"][0], r["box"][1], r["cand"][b], 0.0)
         Pg = dd.aggregate(p, cand)
-        n = sum(r is not None for r in res)
-        dH = sum(r["pieces"][b] - st.hbar[b] for c, r in zip(cells, res) if r is not None
-                 for b in c["basic"])
+        n = len(res)
+        dH = sum(r["pieces"][b] - st.hbar[b] for c, r in zip(cells, res) for b in c["basic"])
         z = dd.line_weight(p, P, Pg, dH, n)
         assert 1.0 / n <= z <= 1.0
         f = lambda th: _mixed_tracked(p, st, cells, res, th, P, Pg)
