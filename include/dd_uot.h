@@ -144,6 +144,21 @@ typedef struct {
   double mass_x, mass_y;     /* |P_X pi|, |P_Y pi| of the state plan */
   int64_t half_iters;        /* half-iterations done so far */
   int32_t overflow;          /* nonzero if any step ever found a pool too small */
+  int32_t polish_iters;      /* global Sinkhorn iterations of the polished bounds
+                                (dd_uot_set_polish; 0 for moved Y points) */
+  double dual_polished;      /* max_k D(alpha_k, beta_k) over alpha_0 = alpha_bar
+                                and k global iterations (Definition sinkhorn,
+                                eq. sinkhorn-iters-ot): a lower bound of the
+                                optimal value, >= dual */
+  double primal_polished;    /* min(tracked, min_k E(pi_k)) with E(pi_k) = D + PD of
+                                the pair k (eq. PD-gap-KL): an upper bound of the
+                                optimal value (tracked itself bounds E of the plan) */
+  double rel_gap_polished;   /* (primal_polished - dual_polished) / |dual_polished|:
+                                a certified relative gap of the state */
+  int64_t nnz;               /* stored basic-marginal entries above 1e-14 (the
+                                sparsity measure of Sec. 4.2) */
+  int64_t n_safe;            /* recorded steps whose weight was below 1 */
+  int64_t n_unconverged;     /* recorded cell solves that hit the iteration cap */
 } dduot_score;
 
 /* Fill *cfg with the paper's defaults (Err 2e-5, trunc 1e-15, lenience 0.005,
@@ -225,6 +240,11 @@ int dd_uot_history(dduot_handle* h, int32_t prob, int32_t max, double* out);
    Y-update with nu_- = 0 (eq. sinkhorn-iters-ot) giving beta_hat, and the
    gap of eq. PD-gap-KL for the plan pi_hat they define.  Synchronises. */
 int dd_uot_score(dduot_handle* h, int32_t prob, dduot_score* out);
+
+/* Number of global Sinkhorn iterations dd_uot_score runs from the stitched
+   potential for the polished bounds (default 0: the polished fields repeat
+   the certificate's pair).  0 <= n_iters <= 10000. */
+int dd_uot_set_polish(dduot_handle* h, int32_t n_iters);
 
 /* X- and Y-marginal of the current state plan (P_X pi and sum_i nu_i).
    px, py: host, n1*n2 doubles each (either may be NULL).  Synchronises. */
@@ -352,6 +372,9 @@ typedef struct {
   int32_t verbose;           /* 1: one progress line per layer and eps stage on
                                 stderr (layer, eps, half-iterations, gaps,
                                 elapsed time); 0: silent */
+  int32_t polish_iters;      /* global Sinkhorn iterations of the polished bounds
+                                of the final-stage certificates (dd_uot_set_polish);
+                                > 0: the final stage stops on rel_gap_polished */
 } dduot_multiscale;
 
 /* levels 7, coarse_cell 4, eps 2 h^2 -> h^2/2 per layer, 4..16 half-iterations
@@ -374,11 +397,13 @@ void dd_uot_default_multiscale(dduot_multiscale* m);
    On every DD layer run the eps stages, then refine (dd_uot_refine); on the
    finest layer continue to cfg->eps and then iterate until the
    certificate's relative gap is <= target_rel_gap or final_max_halves are
-   done.  trace (nullable, trace_cap records of 4 doubles): per certificate of
+   done.  trace (nullable, trace_cap records of 5 doubles): per certificate of
    the final stage, (total half-iterations, elapsed ms since the call,
    relative certificate gap pd_gap/|dual|, relative gap of the DD plan
-   (tracked - dual)/|dual|); *trace_len gets their count.  *out receives the finest handle (its
-   state, score, backward). */
+   (tracked - dual)/|dual|, rel_gap_polished); *trace_len gets their count;
+   the final stage stops on the certificate gap, or on the polished gap when
+   polish_iters > 0.  *out receives the finest handle (its state, score,
+   backward). */
 int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_multiscale* ms,
                             const double* mu, const double* nu, void* hip_stream,
                             dduot_handle** out, double* trace, int32_t trace_cap,

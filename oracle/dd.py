@@ -790,11 +790,17 @@ def init_from_duals(p: Problem, alpha, beta, trunc: float, windows=None) -> Stat
 # --------------------------------------------------------------------------
 # certificate (global primal-dual gap of a DD state)
 # --------------------------------------------------------------------------
-def certificate(p: Problem, abar) -> dict:
+def certificate(p: Problem, abar, polish: int = 0) -> dict:
     """Dual candidate alpha_bar (stitched cell potentials) -> beta_hat by one
     global Y-update with nu_- = 0 (eq. sinkhorn-iters-ot) -> pi_hat; the gap is
     PD = lam KL(P_X pi_hat | exp(-alpha/lam) mu), exact by eq. (PD-gap-KL) with
-    J = I.  Dense: for small grids only.  Also returns primal and dual."""
+    J = I.  Dense: for small grids only.  Also returns primal and dual.
+
+    polish: `polish` more global Sinkhorn iterations (X-update, then Y-update,
+    eq. sinkhorn-iters-ot) from that pair; every pair k gives a lower bound
+    D(alpha_k, beta_k) and an upper bound E(pi_k) of the optimal value
+    (weak duality), returned as the best of each (dual_polished,
+    primal_polished), the pair 0 included."""
     C = full_cost(p)
     a = np.ravel(abar)
     kappa = p.lam / (p.lam + p.eps)
@@ -805,6 +811,15 @@ def certificate(p: Problem, abar) -> dict:
     pd = uot.pd_gap_kl(a, px, p.mu, p.lam)
     D = uot.dual(a, bhat, p.mu, p.nu, C, p.eps, p.lam)
     E = uot.primal(pi, p.mu, p.nu, C, p.eps, p.lam)
+    dbest, ebest = D, E
+    ak, bk = a, bhat
+    for _ in range(polish):
+        ak = uot.x_update(bk, p.nu, C, p.eps, p.lam)
+        bk = -p.eps * kappa * uot.y_log_integral(ak, p.mu, C, p.eps)
+        pik = uot.plan(ak, bk, p.mu, p.nu, C, p.eps)
+        dbest = max(dbest, uot.dual(ak, bk, p.mu, p.nu, C, p.eps, p.lam))
+        ebest = min(ebest, uot.primal(pik, p.mu, p.nu, C, p.eps, p.lam))
     return dict(pd=pd, dual=D, primal=E, rel=pd / abs(D), beta_hat=bhat.reshape(p.mu.shape),
                 px=px.reshape(p.mu.shape), py=py.reshape(p.mu.shape),
-                l1_x=float(np.abs(px - np.exp(-a / p.lam) * p.mu.ravel()).sum()))
+                l1_x=float(np.abs(px - np.exp(-a / p.lam) * p.mu.ravel()).sum()),
+                dual_polished=dbest, primal_polished=ebest)

@@ -29,7 +29,7 @@ EXPORTED = (
     "dd_uot_solve_multiscale", "dd_uot_init_moved", "dd_uot_init_batch_moved",
     "dd_uot_backward_ypos", "dd_uot_set_graph", "dd_uot_autotune",
     "dd_uot_interpolate_potential", "dd_uot_global_sinkhorn", "dd_uot_init_duals",
-    "dd_uot_launch_caps",
+    "dd_uot_launch_caps", "dd_uot_set_polish",
 )
 
 
@@ -65,6 +65,9 @@ class dduot_score(C.Structure):
         ("l1_err_x", C.c_double), ("l1_err_y", C.c_double),
         ("mass_x", C.c_double), ("mass_y", C.c_double),
         ("half_iters", C.c_int64), ("overflow", C.c_int32),
+        ("polish_iters", C.c_int32), ("dual_polished", C.c_double),
+        ("primal_polished", C.c_double), ("rel_gap_polished", C.c_double),
+        ("nnz", C.c_int64), ("n_safe", C.c_int64), ("n_unconverged", C.c_int64),
     ]
 
 
@@ -80,7 +83,7 @@ class dduot_multiscale(C.Structure):
         ("dd_from", C.c_int32), ("global_max_iter", C.c_int32),
         ("global_tol", C.c_double),
         ("coarse_box_cap", C.c_int32), ("coarse_lenience", C.c_double),
-        ("verbose", C.c_int32),
+        ("verbose", C.c_int32), ("polish_iters", C.c_int32),
     ]
 
 
@@ -129,6 +132,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                               C.c_void_p, P(H)]),
         "dd_uot_backward_ypos": (C.c_int, [H, C.c_int32, C.c_double, dp]),
         "dd_uot_set_graph": (C.c_int, [H, C.c_int32]),
+        "dd_uot_set_polish": (C.c_int, [H, C.c_int32]),
         "dd_uot_autotune": (C.c_int, [H, P(C.c_int32), dp]),
         "dd_uot_default_multiscale": (None, [P(dduot_multiscale)]),
         "dd_uot_solve_multiscale": (C.c_int, [P(dduot_config), P(dduot_multiscale), dp, dp,
@@ -340,15 +344,15 @@ def dd_uot_default_multiscale(**kw) -> dduot_multiscale:
 def dd_uot_solve_multiscale(cfg: dduot_config, ms: dduot_multiscale, mu, nu, stream=None,
                             trace_cap=1024):
     """Returns (handle, trace) with trace rows (half-iterations, elapsed ms,
-    certificate rel. gap, DD-plan rel. gap)."""
+    certificate rel. gap, DD-plan rel. gap, polished rel. gap)."""
     mu = _grid(mu, cfg.n1, cfg.n2)
     nu = _grid(nu, cfg.n1, cfg.n2)
     h = C.c_void_p()
-    tr = np.zeros(4 * trace_cap)
+    tr = np.zeros(5 * trace_cap)
     n = C.c_int32()
     _check(load().dd_uot_solve_multiscale(C.byref(cfg), C.byref(ms), _dptr(mu), _dptr(nu), stream,
                                           C.byref(h), _dptr(tr), trace_cap, C.byref(n)))
-    return h, tr[: 4 * n.value].reshape(-1, 4)
+    return h, tr[: 5 * n.value].reshape(-1, 5)
 
 
 def dd_uot_init_moved(cfg: dduot_config, mu, nu, ypos, stream=None):
@@ -386,6 +390,10 @@ def dd_uot_backward_ypos(h, prob, n1, n2, gout=1.0):
 
 def dd_uot_set_graph(h, enable=True):
     _check(load().dd_uot_set_graph(h, 1 if enable else 0))
+
+
+def dd_uot_set_polish(h, n_iters):
+    _check(load().dd_uot_set_polish(h, n_iters))
 
 
 def dd_uot_autotune(h):

@@ -54,6 +54,11 @@ hipError_t gs_x_update(const Prob& p, const double* beta, const double* nu, doub
 hipError_t gs_iteration(const Prob& p, const double* alpha, const double* mu, const double* nu,
                         double* beta, double* scratch, double* part, int nblk, hipStream_t st);
 hipError_t gs_alpha_from_s(const Prob& p, const double* scratch, double* alpha, hipStream_t st);
+hipError_t launch_pair_terms(const Prob& p, const double* alpha, const double* beta,
+                             const double* scratch, const double* mu, const double* nu,
+                             double* part, int nblk, hipStream_t st);
+hipError_t launch_count_nnz(const Dev& d, int b0, int nb, double thr, unsigned long long* count,
+                            hipStream_t st);
 }  // namespace dduot
 
 using namespace dduot;
@@ -152,6 +157,9 @@ struct dduot_handle {
   // timing
   bool timing = false;
   bool slot_fail = false;   // some step ran out of pool space (reported by dd_uot_score)
+  int polish = 0;           // global Sinkhorn iterations of the polished score bounds
+  double *d_pa = nullptr, *d_pb = nullptr;   // their potentials (allocated on first use)
+  unsigned long long* d_cnt = nullptr;       // per basic cell counts (allocated on first use)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   std::vector<long long> timed_recs;
 };
@@ -1176,7 +1184,67 @@ extern "C" int dd_uot_score(dduot_handle* h, int32_t prob, dduot_score* out) {
   out->half_iters = h->k;
   out->overflow = h->slot_fail ? 1 : 0;
   h->cert_done[prob] = 1;
+  // sparsity (Sec. 4.2: entries above 1e-14) and the weights / convergence of
+  // the recorded steps
+  if (!h->d_cnt) CHK(dalloc(h, &h->d_cnt, h->nbasic));
+  HIPCHK(launch_count_nnz(h->d, p.basic_off, p.nbasic, 1e-14, h->d_cnt, st));
+  std::vector<unsigned long long> cnt(p.nbasic);
+  HIPCHK(hipMemcpyAsync(cnt.data(), h->d_cnt, sizeof(unsigned long long) * p.nbasic,
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  out->nnz = 0;
+  for (unsigned long long c : cnt) out->nnz += (int64_t)c;
+  std::vector<double> rec;
+  CHK(read_records(h, prob, 0, h->nrec, rec));
+  out->n_safe = 0;
+  out->n_unconverged = 0;
+  for (size_t r = 0; r + kHistFields <= rec.size(); r += kHistFields) {
+    if (rec[r] < 1.0) out->n_safe += 1;
+    out->n_unconverged += (int64_t)rec[r + 6];
+  }
+  // polished bounds: pairs (alpha_k, beta_k) of global Sinkhorn iterations
+  // from alpha_0 = alpha_bar (k = 0 is the certificate's pair)
+  out->polish_iters = 0;
+  out->dual_polished = dual;
+  out->primal_polished = std::min(out->tracked, out->primal);
+  if (h->polish > 0 && !h->moved) {
+    if (!h->d_pa) CHK(dalloc(h, &h->d_pa, h->maxgrid));
+    if (!h->d_pb) CHK(dalloc(h, &h->d_pb, h->maxgrid));
+    HIPCHK(hipMemcpyAsync(h->d_pa, h->d_abar + g, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(set_rows_lds_limit(std::max<size_t>(rows, 1024)));
+    std::vector<double> pt((size_t)kCertBlocks * 4);
+    for (int k = 1; k <= h->polish; ++k) {
+      // alpha_k = X-update(beta_{k-1}), i.e. -eps kappa S of the previous pair
+      if (k == 1) {
+        HIPCHK(gs_x_update(p, h->d_bhat + g, h->d_nu + g, h->d_pa, h->d_scratch, st));
+      } else {
+        HIPCHK(gs_alpha_from_s(p, h->d_scratch, h->d_pa, st));
+      }
+      HIPCHK(gs_iteration(p, h->d_pa, h->d_mu + g, h->d_nu + g, h->d_pb, h->d_scratch,
+                          h->d_cpart + 4 * kCertBlocks, kCertBlocks, st));
+      HIPCHK(launch_pair_terms(p, h->d_pa, h->d_pb, h->d_scratch, h->d_mu + g, h->d_nu + g,
+                               h->d_cpart, kCertBlocks, st));
+      HIPCHK(hipMemcpyAsync(pt.data(), h->d_cpart, sizeof(double) * pt.size(), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      double q[4] = {0, 0, 0, 0};
+      for (int b = 0; b < kCertBlocks; ++b)
+        for (int j = 0; j < 4; ++j) q[j] += pt[(size_t)b * 4 + j];
+      const double dk = p.eps * (p.mass_mu * p.mass_nu - q[1]) - q[2] - q[3];
+      const double ek = dk + p.lam * q[0];
+      out->dual_polished = std::max(out->dual_polished, dk);
+      out->primal_polished = std::min(out->primal_polished, ek);
+      out->polish_iters = k;
+    }
+  }
+  out->rel_gap_polished = (out->primal_polished - out->dual_polished) / fabs(out->dual_polished);
   (void)n;
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_set_polish(dduot_handle* h, int32_t n_iters) {
+  if (!h) return fail(DDUOT_EINVAL, "null handle");
+  if (n_iters < 0 || n_iters > 10000) return fail(DDUOT_EINVAL, "n_iters must be in [0, 10000]");
+  h->polish = n_iters;
   return DDUOT_OK;
 }
 
@@ -1603,6 +1671,8 @@ extern "C" void dd_uot_default_multiscale(dduot_multiscale* m) {
   m->global_tol = 5e-6;
   m->coarse_box_cap = 80;
   m->coarse_lenience = 0.0;
+  m->verbose = 0;
+  m->polish_iters = 0;
 }
 
 static double now_ms() {
@@ -1659,10 +1729,11 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
   long long halves_before = 0;   // half-iterations of the coarser layers
   auto record = [&](dduot_handle* h, const dduot_score& sc) {
     if (tl < trace_cap) {
-      trace[4 * tl + 0] = (double)(halves_before + h->k);
-      trace[4 * tl + 1] = now_ms() - t0;
-      trace[4 * tl + 2] = sc.rel_pd_gap;
-      trace[4 * tl + 3] = (sc.tracked - sc.dual) / fabs(sc.dual);
+      trace[5 * tl + 0] = (double)(halves_before + h->k);
+      trace[5 * tl + 1] = now_ms() - t0;
+      trace[5 * tl + 2] = sc.rel_pd_gap;
+      trace[5 * tl + 3] = (sc.tracked - sc.dual) / fabs(sc.dual);
+      trace[5 * tl + 4] = sc.rel_gap_polished;
       ++tl;
     }
   };
@@ -1841,11 +1912,16 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
     if (finest) {
       // final stage: iterate, certificate every check_every half-iterations
       dduot_score sc;
-      int r = dd_uot_score(h, 0, &sc);
+      int r = dd_uot_set_polish(h, ms->polish_iters);
+      if (r != DDUOT_OK) return fail_out(r);
+      r = dd_uot_score(h, 0, &sc);
       if (r != DDUOT_OK) return fail_out(r);
       record(h, sc);
       int done = 0;
-      while (!(sc.rel_pd_gap <= ms->target_rel_gap) && done < ms->final_max_halves) {
+      auto gap = [&](const dduot_score& q) {
+        return ms->polish_iters > 0 ? q.rel_gap_polished : q.rel_pd_gap;
+      };
+      while (!(gap(sc) <= ms->target_rel_gap) && done < ms->final_max_halves) {
         const int k = std::min(ms->check_every, ms->final_max_halves - done);
         r = dd_uot_iterate(h, k, nullptr);
         if (r != DDUOT_OK) return fail_out(r);
@@ -1855,8 +1931,9 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
         record(h, sc);
         if (ms->verbose)
           fprintf(stderr, "[multiscale] final %dx%d: %d half-iterations, certificate gap %.3g, "
-                  "DD-plan gap %.3g, %.0f ms\n", c.n1, c.n2, done, sc.rel_pd_gap,
-                  (sc.tracked - sc.dual) / fabs(sc.dual), now_ms() - t0);
+                  "DD-plan gap %.3g, polished gap %.3g, %.0f ms\n", c.n1, c.n2, done,
+                  sc.rel_pd_gap, (sc.tracked - sc.dual) / fabs(sc.dual), sc.rel_gap_polished,
+                  now_ms() - t0);
       }
     }
   }

@@ -703,6 +703,68 @@ hipError_t gs_iteration(const Prob& p, const double* alpha, const double* mu, co
   return hipGetLastError();
 }
 
+// Dual and gap terms of a global pair (alpha, beta) with S = LSE_y[beta/eps +
+// log nu - c/eps] (Definition unbalanced-entropic-transport with nu_- = 0):
+// [0] PD/lam terms (eq. PD-gap-KL), [1] |pi|, [2] sum lam (e^{-alpha/lam} - 1) mu,
+// [3] sum lam (e^{-beta/lam} - 1) nu; 4 partial sums per workgroup.
+__global__ __launch_bounds__(kBlock) void k_pair_terms(const double* alpha, const double* beta,
+                                                       const double* S, const double* mu,
+                                                       const double* nu, long n, double eps,
+                                                       double lam, double* part) {
+  __shared__ double red[4 * 4];
+  double acc[4] = {0, 0, 0, 0};
+  for (long i = blockIdx.x * (long)kBlock + threadIdx.x; i < n; i += (long)gridDim.x * kBlock) {
+    const double a = alpha[i], m = mu[i];
+    const double lp = a / eps + S[i];
+    const double pxh = m * exp(lp);
+    const double aol = a / lam;
+    const double ea = exp(-aol);
+    acc[0] += pxh * (lp + aol) - pxh + m * ea;
+    acc[1] += pxh;
+    acc[2] += lam * (ea - 1.0) * m;
+    acc[3] += lam * (exp(-beta[i] / lam) - 1.0) * nu[i];
+  }
+  block_sum_aux<4>(acc, red);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) part[blockIdx.x * 4 + k] = acc[k];
+}
+
+hipError_t launch_pair_terms(const Prob& p, const double* alpha, const double* beta,
+                             const double* scratch, const double* mu, const double* nu,
+                             double* part, int nblk, hipStream_t st) {
+  const long n = (long)p.n1 * p.n2;
+  hipLaunchKernelGGL(k_pair_terms, dim3(nblk), dim3(kBlock), 0, st, alpha, beta, scratch + n, mu, nu,
+                     n, p.eps, p.lam, part);
+  return hipGetLastError();
+}
+
+// Stored entries above `thr` of the basic cells [b0, b0 + nb) (the sparsity
+// measure of Sec. 4.2); one workgroup per basic cell, one count each.
+__global__ __launch_bounds__(kBlock) void k_count_nnz(Dev d, int b0, double thr,
+                                                      unsigned long long* count) {
+  __shared__ unsigned long long red[kBlock / 64];
+  const int b = b0 + blockIdx.x;
+  const Box bx = d.box[b];
+  const long n = (long)bx.l1 * bx.l2;
+  const double* v = state_pool(d) + d.voff[b];
+  unsigned long long c = 0;
+  for (long o = threadIdx.x; o < n; o += kBlock) c += v[o] > thr ? 1ull : 0ull;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+    count[blockIdx.x] = t;
+  }
+}
+
+hipError_t launch_count_nnz(const Dev& d, int b0, int nb, double thr, unsigned long long* count,
+                            hipStream_t st) {
+  if (nb > 0) hipLaunchKernelGGL(k_count_nnz, dim3(nb), dim3(kBlock), 0, st, d, b0, thr, count);
+  return hipGetLastError();
+}
+
 // alpha = -eps kappa S with S from the last gs_iteration
 hipError_t gs_alpha_from_s(const Prob& p, const double* scratch, double* alpha, hipStream_t st) {
   const long n = (long)p.n1 * p.n2;

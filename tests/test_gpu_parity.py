@@ -250,6 +250,39 @@ def test_certificate_and_backward_match_oracle(grid32):
         B.dd_uot_destroy(h)
 
 
+def test_polished_bounds_sparsity_and_counts_match_oracle(grid32):
+    # the polished score bounds (global Sinkhorn pairs from alpha_bar), the
+    # sparsity count of Sec. 4.2 and the safe / unconverged counts of the
+    # recorded steps, against the oracle's state and certificate
+    mu, nu = grid32
+    n = 32
+    cfg = config(n, 4, 4.0 / n ** 2, 1.0, 1.0 / n, precision=64, init=B.INIT_BLOCK,
+                 sinkhorn_err=1e-8, sinkhorn_max_iter=40, lenience=0.0, box_cap=32,
+                 getweights=B.GW_SWIFT)
+    h, p, st = run_pair(mu, nu, cfg, 5, check_every=False)
+    try:
+        for m in (0, 7):
+            B.dd_uot_set_polish(h, m)
+            s = B.dd_uot_score(h, 0)
+            cert = dd.certificate(p, st.abar, polish=m)
+            tracked = dd.tracked_score(p, st)
+            print(f"[parity] polish {m}: rel gap {s['rel_gap_polished']:.3e}", flush=True)
+            assert s["polish_iters"] == m
+            assert s["dual_polished"] == pytest.approx(cert["dual_polished"], rel=1e-10)
+            assert s["primal_polished"] == pytest.approx(min(tracked, cert["primal_polished"]),
+                                                         rel=1e-10)
+            ref = (min(tracked, cert["primal_polished"]) - cert["dual_polished"]) / \
+                abs(cert["dual_polished"])
+            assert s["rel_gap_polished"] == pytest.approx(ref, rel=1e-6, abs=1e-12)
+        assert s["dual_polished"] >= s["dual"] and s["primal_polished"] <= s["tracked"]
+        assert s["nnz"] == sum(int(np.count_nonzero(arr > 1e-14)) for _, _, arr in st.boxes)
+        assert s["n_safe"] == sum(1 for x in st.history if x["theta"] < 1.0)
+        assert s["n_unconverged"] == sum(x["n_unconverged"] for x in st.history)
+        assert s["n_unconverged"] > 0
+    finally:
+        B.dd_uot_destroy(h)
+
+
 @pytest.mark.parametrize("precision", [64, 32])
 def test_boxes_wider_than_the_lds_layout_follow_the_oracle(grid32, precision):
     # B cells gather basic boxes grown inside four different A boxes; with an

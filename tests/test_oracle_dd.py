@@ -187,6 +187,30 @@ def test_certificate_gap_identity():
     assert cert["pd"] > 0
 
 
+def test_polished_bounds_bracket_the_optimum_and_tighten():
+    # weak duality (Definition unbalanced-entropic-transport): every pair of
+    # the global Sinkhorn iteration gives D <= W <= E; the iteration raises D
+    # (block coordinate ascent), so more polishing never loosens the bounds,
+    # and they close in on the optimal value W
+    p = small_problem(8, 2)
+    _, sol, C = global_optimum(p)
+    W = uot.dual(sol["alpha"], sol["beta"], p.mu, p.nu, C, p.eps, p.lam)
+    st = dd.init_block(p)
+    dd.run(p, st, 3, dd.Options(margin=2, trunc=0.0, err=1e-6, max_iter=2000))
+    gaps = []
+    prev_d, prev_e = -np.inf, np.inf
+    for m in (0, 2, 10, 200):
+        c = dd.certificate(p, st.abar, polish=m)
+        assert c["dual_polished"] <= W * (1 + 1e-12) + 1e-15
+        assert c["primal_polished"] >= W * (1 - 1e-12) - 1e-15
+        assert c["dual_polished"] >= prev_d - 1e-15 and c["primal_polished"] <= prev_e + 1e-15
+        if m == 0:
+            assert c["dual_polished"] == c["dual"] and c["primal_polished"] == c["primal"]
+        prev_d, prev_e = c["dual_polished"], c["primal_polished"]
+        gaps.append((c["primal_polished"] - c["dual_polished"]) / abs(W))
+    assert gaps[-1] < 1e-6 * gaps[0] and gaps[-1] < 1e-9
+
+
 def test_zero_cost_dd_reaches_product_plan():
     # h = 0 makes c = 0; the optimum is s mu x nu, s = (|mu||nu|)^(-lam/(eps+2lam))
     p = small_problem(8, 2, h=0.0)
