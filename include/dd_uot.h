@@ -115,6 +115,13 @@ typedef struct {
                                 the re-split; 0 (default): no balancing.
                                 Regular Y points only (DDUOT_EINVAL with moved
                                 Y points) */
+  int32_t support_only;      /* 1 (default): the cell problem lives on the support
+                                of nu_J = sum of its basic marginals (Sec. 4.1):
+                                box points where nu_J = 0 are left out, so
+                                supports grow only through the alternation of
+                                the partitions and box_margin has no effect;
+                                0: the whole Y-box (then the margin lets
+                                supports grow by box_margin per step) */
 } dduot_config;
 
 /* Per call of dd_uot_iterate, summed over all problems of the handle. */
@@ -163,7 +170,7 @@ typedef struct {
 
 /* Fill *cfg with the paper's defaults (Err 2e-5, trunc 1e-15, lenience 0.005,
    swift, FP32, block start, margin 2, box_cap 64, max 1000 inner iterations,
-   translation step on, no balancing). */
+   translation step on, no balancing, cell problems on the support of nu_J). */
 void dd_uot_default_config(dduot_config* cfg);
 
 /* Create a solver for one problem.  mu, nu: host, n1*n2 each, every entry
@@ -256,6 +263,30 @@ int dd_uot_marginals(dduot_handle* h, int32_t prob, double* px, double* py);
    only the box).  Synchronises. */
 int dd_uot_basic_marginal(dduot_handle* h, int32_t prob, int32_t basic, int32_t box[4],
                           double* values, int64_t cap);
+
+/* Whole state of a single-problem handle (checkpoint / resume; moving a state
+   between handles of the same problem, e.g. FP64 -> FP32): the basic-cell
+   Y-marginals (Algorithm 4 state) on their boxes, P_X pi, the tracked pieces
+   Hbar_i, the stitched potential and its per-cell flags, and the count of
+   half-iterations done.  Layouts: boxes nbasic*4 int32 (o1, o2, L1, L2 per
+   basic cell, row-major basic ids); values the boxes' entries concatenated in
+   basic order (row-major inside a box); px, abar n1*n2 doubles; hbar nbasic
+   doubles; warm nbasic int32.  All host memory.
+   dd_uot_get_state: *n_values receives the number of values; values may be
+   NULL (then only *n_values and the other outputs), else it must hold
+   cap >= *n_values doubles (else DDUOT_EINVAL).  Any other pointer may be
+   NULL.  Synchronises.
+   dd_uot_set_state: replaces the state (every pointer required; boxes inside
+   the grid, values finite and >= 0, n_values their total area); the next
+   half-iteration uses partition A if k is even, B otherwise, and is greedy
+   (force_greedy != 0) or follows GetWeights.  Synchronises.  Both:
+   DDUOT_EINVAL for a handle with several problems. */
+int dd_uot_get_state(dduot_handle* h, int32_t* boxes, double* values, int64_t cap,
+                     int64_t* n_values, double* px, double* hbar, double* abar, int32_t* warm,
+                     int64_t* k);
+int dd_uot_set_state(dduot_handle* h, const int32_t* boxes, const double* values,
+                     int64_t n_values, const double* px, const double* hbar, const double* abar,
+                     const int32_t* warm, int64_t k, int32_t force_greedy);
 
 /* alpha_bar (stitched cell potentials) and, after dd_uot_score, beta_hat.
    Either pointer may be NULL; n1*n2 doubles each.  Synchronises. */

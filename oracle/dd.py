@@ -20,10 +20,15 @@ them also fixed in the design notes):
   R3 state: the basic-cell Y-marginals nu_i stored on bounding boxes, plus the
      X-marginal P_X pi, plus per basic cell a tracked score Hbar_i and the
      last cell potential alpha (stitched).
-  R4 cell Y-box: bbox of the union of the basic boxes of J, dilated by the
-     margin M per axis, clipped to the grid; boxes of any size (Sec. 4.1 keeps
-     nu_{-J} on the support of nu_J, whatever its extent).  An all-empty union
-     uses the X rectangle of J instead.
+  R4 cell Y-domain: Sec. 4.1 keeps the cell problem on the (sparse) support
+     of nu_J = sum of the basic marginals of J, whatever its extent; it is
+     stored as a box, the bbox of the union of the basic boxes of J dilated by
+     the margin M per axis and clipped to the grid, and (support = True, the
+     paper's rule) the points of the box where nu_J = 0 are left out of the
+     cell problem, so supports grow only through the alternation of the
+     partitions.  support = False solves on the whole box (the margin then
+     lets supports grow by M per step).  An all-empty union uses the X
+     rectangle of J, with the whole box as domain.
   R5 warm start (the paper only says "for a given initialization beta^0"):
      when every basic cell of J holds a stored X-potential (the stitched
      alpha of the last solve covering it, of a refinement or of a potential
@@ -113,6 +118,7 @@ class Options:
     lenience: float = 0.0      # 0.005 in Sec. 4.4; 0 = strict
     margin: int = 2
     getweights: str = "swift"  # greedy | safe | swift | staggered | line
+    support: bool = True       # cell problem on the support of nu_J (R4)
     translate: bool = False    # dual line search along (alpha + s, beta - s)
     balance: bool = False      # balancing step of Sec. 4.1 (reading R13)
 
@@ -377,7 +383,8 @@ def solve_cell(mu_x, nu_y, r_y, beta0, C, eps, lam, tol, opt: Options, alpha0=No
 
 def cell_inputs(p: Problem, cell, box, boxes, P):
     """nu_J, nu_{-J} = P_Y pi - nu_J (Sec. 4.1, clamped at 0), r = nu_{-J}/nu and
-    the warm start beta^0 of reading R5, all on the cell Y-box."""
+    the warm start beta^0 of reading R5, all on the cell Y-box.  Returns
+    (r, beta^0, nu_J), flattened."""
     o1, o2, L1, L2 = box
     nuJ = np.zeros((L1, L2))
     for b in cell["basic"]:
@@ -389,7 +396,7 @@ def cell_inputs(p: Problem, cell, box, boxes, P):
     r = np.maximum(Pb - nuJ, 0.0) / nub
     with np.errstate(divide="ignore"):
         beta0 = np.where(Pb > 0, -p.lam * np.log(Pb / nub), 0.0)
-    return r.ravel(), beta0.ravel()
+    return r.ravel(), beta0.ravel(), nuJ.ravel()
 
 
 def balance_cell(p: Problem, cell, sol, pi, mu_x, nu_y, C, rows_of):
@@ -436,17 +443,21 @@ def process_cell(p: Problem, cell, boxes, P, opt: Options, abar=None, warm=None)
 
     abar, warm: the stitched X-potential and its per-basic-cell validity
     (warm start of reading R5; None: the beta^0 start).  Returns a dict with
-    the box, the cell potentials, the candidate basic marginals
-    (untruncated), their pieces H_i (definition cell_piece), P_X of the cell
-    plan, iteration count."""
+    the box, its domain mask `dom` (R4), the cell potentials and plan on the
+    domain, the candidate basic marginals on the box (untruncated), their
+    pieces H_i (definition cell_piece), P_X of the cell plan, iteration
+    count."""
     box = cell_box(p, cell, boxes, opt)
     rect = cell["rect"]
     xi = rect_index(rect, p.n2)
     yi = rect_index(box, p.n2)
+    C = rect_cost(p, rect, box)
+    r, beta0, nuJ = cell_inputs(p, cell, box, boxes, P)
+    # the cell's Y-domain (R4): the support of nu_J inside the box
+    dom = nuJ > 0 if (opt.support and np.any(nuJ > 0)) else np.ones(nuJ.size, dtype=bool)
+    yi, C, r, beta0 = yi[dom], C[:, dom], r[dom], beta0[dom]
     mu_x = p.mu.ravel()[xi]
     nu_y = p.nu.ravel()[yi]
-    C = rect_cost(p, rect, box)
-    r, beta0 = cell_inputs(p, cell, box, boxes, P)
     tol = opt.err * mu_x.sum()
     alpha0 = None
     if abar is not None and warm is not None and all(warm[b] for b in cell["basic"]):
@@ -461,10 +472,11 @@ def process_cell(p: Problem, cell, boxes, P, opt: Options, abar=None, warm=None)
     for b in cell["basic"]:
         rows = rows_of[b]
         pib = pi[rows]
-        nut = pib.sum(0).reshape(box[2], box[3])
+        nut = np.zeros(box[2] * box[3])
+        nut[dom] = pib.sum(0)
         pieces[b] = cell_piece(pib, mu_x[rows], nu_y, nu_tot, C[rows], p.eps, p.lam)
-        cand[b] = nut
-    return dict(box=box, rect=rect, xi=xi, yi=yi, alpha=sol["alpha"], beta=sol["beta"],
+        cand[b] = nut.reshape(box[2], box[3])
+    return dict(box=box, rect=rect, xi=xi, yi=yi, dom=dom, alpha=sol["alpha"], beta=sol["beta"],
                 px=pi.sum(1), pi=pi, cand=cand, pieces=pieces, iters=sol["iters"],
                 converged=sol["converged"], pd=sol["pd"])
 

@@ -29,7 +29,7 @@ EXPORTED = (
     "dd_uot_solve_multiscale", "dd_uot_init_moved", "dd_uot_init_batch_moved",
     "dd_uot_backward_ypos", "dd_uot_set_graph", "dd_uot_autotune",
     "dd_uot_interpolate_potential", "dd_uot_global_sinkhorn", "dd_uot_init_duals",
-    "dd_uot_launch_caps", "dd_uot_set_polish",
+    "dd_uot_launch_caps", "dd_uot_set_polish", "dd_uot_get_state", "dd_uot_set_state",
 )
 
 
@@ -45,7 +45,7 @@ class dduot_config(C.Structure):
         ("trunc", C.c_double), ("lenience", C.c_double),
         ("box_margin", C.c_int32), ("box_cap", C.c_int32),
         ("translate", C.c_int32), ("fast_cap", C.c_int32),
-        ("balance", C.c_int32),
+        ("balance", C.c_int32), ("support_only", C.c_int32),
     ]
 
 
@@ -133,6 +133,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dd_uot_backward_ypos": (C.c_int, [H, C.c_int32, C.c_double, dp]),
         "dd_uot_set_graph": (C.c_int, [H, C.c_int32]),
         "dd_uot_set_polish": (C.c_int, [H, C.c_int32]),
+        "dd_uot_get_state": (C.c_int, [H, P(C.c_int32), dp, C.c_int64, P(C.c_int64), dp, dp, dp,
+                                       P(C.c_int32), P(C.c_int64)]),
+        "dd_uot_set_state": (C.c_int, [H, P(C.c_int32), dp, C.c_int64, dp, dp, dp, P(C.c_int32),
+                                       C.c_int64, C.c_int32]),
         "dd_uot_autotune": (C.c_int, [H, P(C.c_int32), dp]),
         "dd_uot_default_multiscale": (None, [P(dduot_multiscale)]),
         "dd_uot_solve_multiscale": (C.c_int, [P(dduot_config), P(dduot_multiscale), dp, dp,
@@ -394,6 +398,36 @@ def dd_uot_set_graph(h, enable=True):
 
 def dd_uot_set_polish(h, n_iters):
     _check(load().dd_uot_set_polish(h, n_iters))
+
+
+def dd_uot_get_state(h, n1, n2, nbasic):
+    """dict(boxes (nbasic, 4) int32, values, px, hbar, abar, warm, k)."""
+    lib = load()
+    nv = C.c_int64()
+    _check(lib.dd_uot_get_state(h, None, None, 0, C.byref(nv), None, None, None, None, None))
+    boxes = np.zeros(4 * nbasic, dtype=np.int32)
+    vals = np.zeros(max(nv.value, 1))
+    px, abar, hbar = np.zeros(n1 * n2), np.zeros(n1 * n2), np.zeros(nbasic)
+    warm = np.zeros(nbasic, dtype=np.int32)
+    k = C.c_int64()
+    _check(lib.dd_uot_get_state(h, boxes.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(vals), vals.size,
+                                C.byref(nv), _dptr(px), _dptr(hbar), _dptr(abar),
+                                warm.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(k)))
+    return dict(boxes=boxes.reshape(nbasic, 4), values=vals[: nv.value], px=px.reshape(n1, n2),
+                hbar=hbar, abar=abar.reshape(n1, n2), warm=warm, k=k.value)
+
+
+def dd_uot_set_state(h, state, force_greedy=False):
+    boxes = np.ascontiguousarray(state["boxes"], dtype=np.int32).ravel()
+    vals = np.ascontiguousarray(state["values"], dtype=np.float64)
+    warm = np.ascontiguousarray(state["warm"], dtype=np.int32)
+    px = np.ascontiguousarray(state["px"], dtype=np.float64).ravel()
+    abar = np.ascontiguousarray(state["abar"], dtype=np.float64).ravel()
+    hbar = np.ascontiguousarray(state["hbar"], dtype=np.float64)
+    _check(load().dd_uot_set_state(h, boxes.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(vals),
+                                   vals.size, _dptr(px), _dptr(hbar), _dptr(abar),
+                                   warm.ctypes.data_as(C.POINTER(C.c_int32)), int(state["k"]),
+                                   1 if force_greedy else 0))
 
 
 def dd_uot_autotune(h):

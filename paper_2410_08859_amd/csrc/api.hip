@@ -200,6 +200,7 @@ extern "C" void dd_uot_default_config(dduot_config* c) {
   c->box_margin = 2;
   c->box_cap = 64;
   c->translate = 1;
+  c->support_only = 1;
 }
 
 extern "C" const char* dd_uot_last_error(void) { return g_err.c_str(); }
@@ -228,6 +229,8 @@ static int validate(const dduot_config* c, const double* mu, const double* nu, i
   if (c->box_margin < 0) return fail(DDUOT_EINVAL, pre + "box_margin must be >= 0");
   if (c->translate != 0 && c->translate != 1) return fail(DDUOT_EINVAL, pre + "translate must be 0 or 1");
   if (c->balance != 0 && c->balance != 1) return fail(DDUOT_EINVAL, pre + "balance must be 0 or 1");
+  if (c->support_only != 0 && c->support_only != 1)
+    return fail(DDUOT_EINVAL, pre + "support_only must be 0 or 1");
   if (c->box_cap < 2 * c->cell || c->box_cap > 128)
     return fail(DDUOT_EINVAL, pre + "box_cap must be in [2*cell, 128]");
   if (c->fast_cap < 0 || c->fast_cap > 128) return fail(DDUOT_EINVAL, pre + "fast_cap must be in [0, 128]");
@@ -498,6 +501,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
     p.margin = c.box_margin; p.precision = c.precision;
     p.translate = c.translate;
     p.balance = c.balance;
+    p.support = c.support_only;
     if (c.balance) h->balance = true;
     p.moved = h->moved ? 1 : 0;
     p.grid_off = (int)goff;
@@ -1283,6 +1287,81 @@ extern "C" int dd_uot_basic_marginal(dduot_handle* h, int32_t prob, int32_t basi
   return DDUOT_OK;
 }
 
+extern "C" int dd_uot_get_state(dduot_handle* h, int32_t* boxes, double* values, int64_t cap,
+                                int64_t* n_values, double* px, double* hbar, double* abar,
+                                int32_t* warm, int64_t* k) {
+  if (!h || h->nprob != 1) return fail(DDUOT_EINVAL, "state access needs a single-problem handle");
+  hipStream_t st = h->stream;
+  const long n = (long)h->probs[0].n1 * h->probs[0].n2;
+  std::vector<Box> bx(h->nbasic);
+  std::vector<long> off(h->nbasic);
+  int sp = 0;
+  HIPCHK(hipMemcpyAsync(bx.data(), h->d_box, sizeof(Box) * h->nbasic, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(off.data(), h->d_voff, sizeof(long) * h->nbasic, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&sp, h->d_sp, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  // the pool is compact in basic order: its first `tot` entries are the values
+  long tot = 0;
+  for (int b = 0; b < h->nbasic; ++b) {
+    if (off[b] != tot) return fail(DDUOT_EHIP, "state pool not compact");
+    tot += (long)bx[b].l1 * bx[b].l2;
+  }
+  if (n_values) *n_values = tot;
+  if (values && cap < tot) return fail(DDUOT_EINVAL, "values buffer too small");
+  if (boxes)
+    for (int b = 0; b < h->nbasic; ++b) {
+      boxes[4 * b] = bx[b].o1; boxes[4 * b + 1] = bx[b].o2;
+      boxes[4 * b + 2] = bx[b].l1; boxes[4 * b + 3] = bx[b].l2;
+    }
+  if (values && tot > 0)
+    HIPCHK(hipMemcpyAsync(values, h->d_pool[sp], sizeof(double) * tot, hipMemcpyDeviceToHost, st));
+  if (px) HIPCHK(hipMemcpyAsync(px, h->d_px, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  if (hbar) HIPCHK(hipMemcpyAsync(hbar, h->d_hbar, sizeof(double) * h->nbasic, hipMemcpyDeviceToHost, st));
+  if (abar) HIPCHK(hipMemcpyAsync(abar, h->d_abar, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  if (warm) HIPCHK(hipMemcpyAsync(warm, h->d_awarm, sizeof(int) * h->nbasic, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (k) *k = h->k;
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_set_state(dduot_handle* h, const int32_t* boxes, const double* values,
+                                int64_t n_values, const double* px, const double* hbar,
+                                const double* abar, const int32_t* warm, int64_t k,
+                                int32_t force_greedy) {
+  if (!h || h->nprob != 1) return fail(DDUOT_EINVAL, "state access needs a single-problem handle");
+  if (!boxes || !values || !px || !hbar || !abar || !warm || k < 0)
+    return fail(DDUOT_EINVAL, "null state array or negative k");
+  const Prob& p = h->probs[0];
+  const long n = (long)p.n1 * p.n2;
+  std::vector<Box> bx(h->nbasic);
+  long tot = 0;
+  for (int b = 0; b < h->nbasic; ++b) {
+    Box q{boxes[4 * b], boxes[4 * b + 1], boxes[4 * b + 2], boxes[4 * b + 3]};
+    if (q.l1 < 0 || q.l2 < 0 || q.o1 < 0 || q.o2 < 0 || q.o1 + q.l1 > p.n1 || q.o2 + q.l2 > p.n2)
+      return fail(DDUOT_EINVAL, "box outside the grid");
+    bx[b] = q;
+    tot += (long)q.l1 * q.l2;
+  }
+  if (tot != n_values) return fail(DDUOT_EINVAL, "n_values differs from the boxes' total area");
+  for (long i = 0; i < tot; ++i)
+    if (!(values[i] >= 0.0) || !isfinite(values[i])) return fail(DDUOT_EINVAL, "values must be finite and >= 0");
+  hipStream_t st = h->stream;
+  HIPCHK(hipMemcpyAsync(h->d_box, bx.data(), sizeof(Box) * h->nbasic, hipMemcpyHostToDevice, st));
+  CHK(place_state(h));   // offsets, pools sized for the boxes, first pool current
+  if (tot > 0)
+    HIPCHK(hipMemcpyAsync(h->d_pool[0], values, sizeof(double) * tot, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_px, px, sizeof(double) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_hbar, hbar, sizeof(double) * h->nbasic, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_abar, abar, sizeof(double) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_awarm, warm, sizeof(int) * h->nbasic, hipMemcpyHostToDevice, st));
+  const int fg = force_greedy ? 1 : 0;
+  HIPCHK(hipMemcpyAsync(h->d_force, &fg, sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  h->k = k;
+  h->cert_done[0] = 0;
+  return DDUOT_OK;
+}
+
 extern "C" int dd_uot_potentials(dduot_handle* h, int32_t prob, double* alpha, double* beta_hat) {
   if (!h || prob < 0 || prob >= h->nprob) return fail(DDUOT_EINVAL, "bad arguments");
   const Prob& p = h->probs[prob];
@@ -1860,6 +1939,13 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
       if (r != DDUOT_OK) return r;
     }
     h = nh;
+    if (ms->verbose && ms->polish_iters > 0) {
+      const int r = dd_uot_set_polish(h, ms->polish_iters);
+      if (r != DDUOT_OK) {
+        destroy_keep_error(h);
+        return r;
+      }
+    }
     auto fail_out = [&](int r) {
       std::string keep = g_err;
       dd_uot_destroy(h);
@@ -1900,9 +1986,10 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
         fprintf(stderr,
                 "[multiscale] DD %dx%d cell %d eps %.3g h^2: %d half-iterations (%.1f inner "
                 "iterations per cell, %lld unconverged), certificate gap %.3g, DD-plan gap %.3g, "
-                "%.0f ms\n",
+                "polished gap %.3g, %.0f ms\n",
                 c.n1, c.n2, c.cell, e / h2, done, cells ? (double)inner / cells : 0.0, unconv,
-                sc.rel_pd_gap, (sc.tracked - sc.dual) / fabs(sc.dual), now_ms() - t0);
+                sc.rel_pd_gap, (sc.tracked - sc.dual) / fabs(sc.dual), sc.rel_gap_polished,
+                now_ms() - t0);
       }
       if (e <= e_end * (1.0 + 1e-12)) break;
       e = std::max(e * 0.5, e_end);

@@ -174,6 +174,8 @@ __device__ __forceinline__ double lse_pass(const double* base, int stride, int k
   // its shifted sum stays above e^-22, so every skipped term is below e^-(W-22)
   // of the output (e^-18 in FP32, e^-38 in FP64), i.e. under the R rounding.
   constexpr double W = sizeof(R) == 8 ? 60.0 : 40.0;
+  // every base value -inf (a row outside the cell's Y-domain): no terms
+  if (!(bmax > -INFINITY)) return -INFINITY;
   // A sum outside the accepted range but still representable says where the
   // output moved: one more windowed pass with the shift corrected by its log.
   for (int attempt = 0; have_shift && attempt < 2; ++attempt) {
@@ -559,6 +561,7 @@ __device__ void balance_cell(double* candJ, const Cell& C, const Prob& P, const 
         const int row = j1 * L2;
         double m = -INFINITY;
         for (int j2 = 0; j2 < L2; ++j2) {
+          if (!(S.bd[row + j2] > -INFINITY)) continue;   // outside the Y-domain
           const double dd = c2 - j2;
           m = fmax(m, (double)wlR[row + j2] - lk[row + j2] + S.bd[row + j2] - ch * dd * dd);
         }
@@ -566,6 +569,7 @@ __device__ void balance_cell(double* candJ, const Cell& C, const Prob& P, const 
         if (m > -INFINITY) {
           double a = 0.0;
           for (int j2 = 0; j2 < L2; ++j2) {
+            if (!(S.bd[row + j2] > -INFINITY)) continue;
             const double dd = c2 - j2;
             a += exp((double)wlR[row + j2] - lk[row + j2] + S.bd[row + j2] - ch * dd * dd - m);
           }
@@ -717,7 +721,12 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
   }
 
   // ---- Y box inputs: nu_{-J}, r, log nu, warm start -------------------------
-  double acc0[3] = {mux, 0.0, 0.0};
+  // The cell's Y-domain is the support of nu_J in the box (P.support; Sec.
+  // 4.1), or the whole box: points outside it carry b = -inf (no plan mass,
+  // excluded from every sum), and Newton skips them.  An empty support falls
+  // back to the whole box.  acc0: |mu_J|, then |nu_{-J}| and the sum of
+  // e^{-beta0/lam} nu over the support, the same over the box, support size.
+  double acc0[6] = {mux, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int o = t; o < NY; o += NT) {
     const int j1 = o / L2, j2 = o - j1 * L2;
     const int y1 = o1 + j1, y2 = o2 + j2;
@@ -731,8 +740,15 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
         nj += vals[d.voff[C.basic[k]] + (long)a1 * b.l2 + a2];
     }
     const double r = fmax(pv - nj, 0.0) / nv;
-    acc0[1] += r * nv;
-    acc0[2] += pv > 0.0 ? pv : nv;
+    const bool in = !P.support || nj > 0.0;
+    const double b0 = pv > 0.0 ? pv : nv;
+    acc0[3] += r * nv;
+    acc0[4] += b0;
+    if (in) {
+      acc0[1] += r * nv;
+      acc0[2] += b0;
+      acc0[5] += 1.0;
+    }
     double lnv = log(nv);
     const double lr = r > 0.0 ? log(r) : -INFINITY;
     if constexpr (sizeof(R) == 4) {
@@ -744,16 +760,28 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
       wlnv[o] = lnv;
     }
     // beta^0/eps = -K log(P/nu); b = beta/eps + log nu
-    S.bd[o] = (pv > 0.0 ? -K * log(pv / nv) : 0.0) + lnv;
+    S.bd[o] = in ? (pv > 0.0 ? -K * log(pv / nv) : 0.0) + lnv : -INFINITY;
     if constexpr (kMoved) {
       S.dl1[o] = R(d.ydel[2 * (P.grid_off + g)]);
       S.dl2[o] = R(d.ydel[2 * (P.grid_off + g) + 1]);
     }
   }
-  block_sum<NT, 3>(acc0, red);
+  block_sum<NT, 6>(acc0, red);
+  if (!(acc0[5] > 0.0) && P.support) {
+    // empty support: the whole box
+    for (int o = t; o < NY; o += NT) {
+      const long g = (long)(o1 + o / L2) * P.n2 + (o2 + o % L2);
+      const double pv = Pst[g], nv = nu[g];
+      const double lnv = sizeof(R) == 4 ? (double)S.lnvf[o] : wlnv[o];
+      S.bd[o] = (pv > 0.0 ? -K * log(pv / nv) : 0.0) + lnv;
+    }
+    acc0[1] = acc0[3];
+    acc0[2] = acc0[4];
+    __syncthreads();
+  }
   const double muJ = acc0[0];
-  const double Rmass = acc0[1];    // |nu_{-J}| on the box
-  const double B0mass = acc0[2];   // sum of e^{-beta0/lam} nu on the box
+  const double Rmass = acc0[1];    // |nu_{-J}| on the domain
+  const double B0mass = acc0[2];   // sum of e^{-beta0/lam} nu on the domain
   double pxsum = 0.0;              // |P_X pi| of the last evaluated pair
   double nfall = 0.0;             // pass outputs recomputed exactly
 
@@ -931,6 +959,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
         z = lse_full<R>(S.Ud + j2, L2, 0, lx1, (double)(j1 - D1), ch, qc, lcap, have_y,
                         S.zp[o] + ushift, nfall);
       S.zp[o] = R(z);
+      if (!(S.bd[o] > -INFINITY)) continue;   // outside the cell's Y-domain
       double lnv, lrr;
       if constexpr (sizeof(R) == 4) {
         lnv = (double)S.lnvf[o];
@@ -1015,8 +1044,10 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
           continue;
         }
         const double nt = exp(S.bd[o] + zk);   // nu e^{beta/eps} e^{z_k}
-        accy[k] += beta * nt;
-        accy[4 + k] += nt;
+        if (nt > 0.0) {   // 0 outside the cell's Y-domain (b = -inf)
+          accy[k] += beta * nt;
+          accy[4 + k] += nt;
+        }
         candJ[(long)k * NY + o] = nt < P.trunc ? 0.0 : nt;
       }
     }

@@ -21,6 +21,7 @@ struct Prob {
   int margin;
   int translate;
   int balance;         // 1: balancing step after every cell solve (Sec. 4.1)
+  int support;         // 1: the cell problem lives on the support of nu_J (Sec. 4.1)
   int precision;
   int moved;           // 1: Y points displaced (dense, non-separable cost)
   int grid_off;     // offset of this problem's grid arrays

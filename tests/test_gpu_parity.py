@@ -24,7 +24,8 @@ def oracle_options(cfg):
     return dd.Options(err=cfg.sinkhorn_err, max_iter=cfg.sinkhorn_max_iter,
                       fixed_iters=cfg.fixed_inner_iters, trunc=cfg.trunc, lenience=cfg.lenience,
                       margin=cfg.box_margin, getweights=GW[cfg.getweights],
-                      translate=bool(cfg.translate), balance=bool(cfg.balance))
+                      translate=bool(cfg.translate), balance=bool(cfg.balance),
+                      support=bool(cfg.support_only))
 
 
 def oracle_start(p, cfg):
