@@ -53,13 +53,18 @@ enum {
    (parity of the cell position), one swift step per batch in turn, line =
    the one weight in [1/(cells updated), 1] for every cell that minimises
    the tracked score of the mixture (Proposition converging-getweights,
-   item line; the pieces are linear in the weight and the KL term convex). */
+   item line; the pieces are linear in the weight and the KL term convex),
+   opt = one weight per cell in [1/(cells updated), 1] minimising the tracked
+   score of the mixture (eq. opt-weights-problem; from the line weight,
+   rounds of a projected diagonal Newton direction with an exact search along
+   it). */
 enum {
   DDUOT_GW_GREEDY = 0,
   DDUOT_GW_SAFE = 1,
   DDUOT_GW_SWIFT = 2,
   DDUOT_GW_STAGGERED = 3,
-  DDUOT_GW_LINE = 4
+  DDUOT_GW_LINE = 4,
+  DDUOT_GW_OPT = 5
 };
 enum { DDUOT_INIT_BLOCK = 0, DDUOT_INIT_PRODUCT = 1 };
 
@@ -205,6 +210,10 @@ int dd_uot_init_batch_moved(int32_t nprob, const dduot_config* cfgs, const doubl
    were computed for the old eps, so the next half-iteration of that problem
    takes greedy weights, which makes them exact again. */
 int dd_uot_set_eps(dduot_handle* h, int32_t prob, double eps);
+
+/* Set the cell tolerance Err of problem `prob` (the stopping rule of
+   eq. PD-gap-KL: PD/lambda <= Err |mu_J|).  err >= 0. */
+int dd_uot_set_err(dduot_handle* h, int32_t prob, double err);
 
 /* Run n_half_iters parallel DomDecIter steps (Algorithm 4), alternating
    partitions A and B (Algorithm 2; the first step after init uses A).
@@ -406,6 +415,12 @@ typedef struct {
   int32_t polish_iters;      /* global Sinkhorn iterations of the polished bounds
                                 of the final-stage certificates (dd_uot_set_polish);
                                 > 0: the final stage stops on rel_gap_polished */
+  double final_err_ratio;    /* > 0: after every final-stage certificate the cell
+                                tolerance becomes max(final_err_min,
+                                min(Err, final_err_ratio * gap)) (the cell
+                                solves' error bounds the reachable gap);
+                                0: Err stays fixed */
+  double final_err_min;
 } dduot_multiscale;
 
 /* levels 7, coarse_cell 4, eps 2 h^2 -> h^2/2 per layer, 4..16 half-iterations

@@ -62,6 +62,7 @@ them also fixed in the design notes):
      position), one swift step each, in batch order.
   R10 multiscale refinement (warm start of a finer layer): see `refine`.
   R12 GetWeights `line` on the tracked score: see `line_weight`.
+  R14 GetWeights `opt` on the tracked score: see `opt_weights`.
   R13 balancing step: see `balance_cell`.
   R11 global Sinkhorn warm start: the coarse layers are solved by the global
      Sinkhorn iteration (uot.sinkhorn), each warm-started from the previous
@@ -117,7 +118,7 @@ class Options:
     trunc: float = 1e-15       # Sec. 4.4
     lenience: float = 0.0      # 0.005 in Sec. 4.4; 0 = strict
     margin: int = 2
-    getweights: str = "swift"  # greedy | safe | swift | staggered | line
+    getweights: str = "swift"  # greedy | safe | swift | staggered | line | opt
     support: bool = True       # cell problem on the support of nu_J (R4)
     translate: bool = False    # dual line search along (alpha + s, beta - s)
     balance: bool = False      # balancing step of Sec. 4.1 (reading R13)
@@ -544,6 +545,35 @@ def line_weight(p: Problem, P, Pg, dH: float, n_upd: int) -> float:
     return float(brentq(fprime, lo, 1.0, xtol=1e-16, rtol=1e-15, maxiter=500))
 
 
+def opt_weights(p: Problem, P, deltas, dH, n_upd: int, z0: float) -> np.ndarray:
+    """GetWeights `opt` (eq. opt-weights-problem) on the tracked score
+    (reading R14): one weight theta_J per updated cell minimising
+        f(theta) = sum_J theta_J dH_J + lam KL(P + sum_J theta_J Delta_J | nu)
+    over [1/n, 1]^J (the safe weight as the lower bound, as for `line`),
+    Delta_J = the change of the cell's basic marginals, dH_J = the change of
+    its pieces.  f is convex (linear pieces, convex KL of an affine map), so
+    the minimiser is found by a bounded quasi-Newton method (L-BFGS-B) with
+    the exact gradient g_J = dH_J + lam sum_y Delta_J log(P_theta / nu),
+    started at the line weight z0."""
+    from scipy.optimize import minimize
+    lo = 1.0 / max(n_upd, 1)
+    D = np.stack([np.ravel(x) for x in deltas])          # (cells, grid)
+    P0 = np.ravel(P)
+    nu = p.nu.ravel()
+    dH = np.asarray(dH, dtype=np.float64)
+
+    def fg(th):
+        Pt = P0 + th @ D
+        with np.errstate(divide="ignore", invalid="ignore"):
+            lg = np.where(Pt > 0, np.log(Pt) - np.log(nu), 0.0)
+        f = float(th @ dH) + p.lam * float(np.sum(np.where(Pt > 0, Pt * lg, 0.0) - Pt + nu))
+        return f, dH + p.lam * (D @ lg)
+    x0 = np.full(len(deltas), min(max(z0, lo), 1.0))
+    res = minimize(fg, x0, jac=True, method="L-BFGS-B", bounds=[(lo, 1.0)] * len(deltas),
+                   options=dict(ftol=1e-16, gtol=1e-14, maxiter=20000, maxcor=30))
+    return np.clip(res.x, lo, 1.0)
+
+
 def _mark_warm(p: Problem, st: State, cell):
     """abar on the basic cells of `cell` now holds a cell potential (R5)."""
     if st.warm is None:
@@ -578,13 +608,27 @@ def _dd_step(p: Problem, st: State, cells, part: str, rule: str, opt: Options,
         theta = 1.0 / max(n_upd, 1)
     elif rule == "swift":
         theta = 1.0 if e_grd <= e_cur + opt.lenience * abs(e_cur) else 1.0 / max(n_upd, 1)
-    elif rule == "line":
+    elif rule in ("line", "opt"):
         theta = line_weight(p, P, Pg, float(htil.sum() - st.hbar.sum()), n_upd)
     else:
         raise ValueError(rule)
+    thetas = [theta] * n_upd
+    if rule == "opt" and not force:
+        deltas, dHs = [], []
+        for c, r in upd:
+            dl = np.zeros((p.n1, p.n2))
+            for b in c["basic"]:
+                for sign, (o1, o2, arr) in ((1.0, cand_boxes[b]), (-1.0, st.boxes[b])):
+                    if arr.size:
+                        dl[o1:o1 + arr.shape[0], o2:o2 + arr.shape[1]] += sign * arr
+            deltas.append(dl)
+            dHs.append(sum(htil[b] - st.hbar[b] for b in c["basic"]))
+        thetas = list(opt_weights(p, P, deltas, dHs, n_upd, theta))
+        theta = float(np.mean(thetas))
 
-    # Algorithm 4: pi' = sum_J (1 - theta) pi_J + theta pi~_J
-    for c, r in upd:
+    # Algorithm 4: pi' = sum_J (1 - theta_J) pi_J + theta_J pi~_J
+    for (c, r), theta_c in zip(upd, thetas):
+        theta = theta_c
         box = r["box"]
         for b in c["basic"]:
             v = (1.0 - theta) * _on_box(st.boxes[b], box) + theta * _on_box(cand_boxes[b], box)
@@ -599,8 +643,9 @@ def _dd_step(p: Problem, st: State, cells, part: str, rule: str, opt: Options,
             new = np.zeros((rows.size, p.n1 * p.n2))
             new[:, r["yi"]] = r["pi"]
             st.plan[rows] = (1.0 - theta) * st.plan[rows] + theta * new
-    stats = dict(part=part, theta=theta, e_cur=e_cur, e_greedy=e_grd, n_cells=len(cells),
-                 n_updated=n_upd,
+    theta = float(np.mean(thetas)) if thetas else 1.0
+    stats = dict(part=part, theta=theta, thetas=np.asarray(thetas), e_cur=e_cur, e_greedy=e_grd,
+                 n_cells=len(cells), n_updated=n_upd,
                  iters=[r["iters"] for _, r in upd],
                  n_unconverged=sum(1 for _, r in upd if not r["converged"]),
                  point_iters=sum(r["iters"] * r["xi"].size for _, r in upd))

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdd_uot.so")
 
 OK, EINVAL, ENOMEM, EHIP, ESLOT, ESTATE = 0, -1, -2, -3, -4, -5
-GW_GREEDY, GW_SAFE, GW_SWIFT, GW_STAGGERED, GW_LINE = 0, 1, 2, 3, 4
+GW_GREEDY, GW_SAFE, GW_SWIFT, GW_STAGGERED, GW_LINE, GW_OPT = 0, 1, 2, 3, 4, 5
 INIT_BLOCK, INIT_PRODUCT = 0, 1
 HIST_FIELDS = ("theta", "e_cur", "e_greedy", "n_updated", "point_iters", "max_inner",
                "n_unconverged", "n_overflow", "inner_iters", "algo_bytes", "lse_terms",
@@ -30,6 +30,7 @@ EXPORTED = (
     "dd_uot_backward_ypos", "dd_uot_set_graph", "dd_uot_autotune",
     "dd_uot_interpolate_potential", "dd_uot_global_sinkhorn", "dd_uot_init_duals",
     "dd_uot_launch_caps", "dd_uot_set_polish", "dd_uot_get_state", "dd_uot_set_state",
+    "dd_uot_set_err",
 )
 
 
@@ -84,6 +85,7 @@ class dduot_multiscale(C.Structure):
         ("global_tol", C.c_double),
         ("coarse_box_cap", C.c_int32), ("coarse_lenience", C.c_double),
         ("verbose", C.c_int32), ("polish_iters", C.c_int32),
+        ("final_err_ratio", C.c_double), ("final_err_min", C.c_double),
     ]
 
 
@@ -133,6 +135,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dd_uot_backward_ypos": (C.c_int, [H, C.c_int32, C.c_double, dp]),
         "dd_uot_set_graph": (C.c_int, [H, C.c_int32]),
         "dd_uot_set_polish": (C.c_int, [H, C.c_int32]),
+        "dd_uot_set_err": (C.c_int, [H, C.c_int32, C.c_double]),
         "dd_uot_get_state": (C.c_int, [H, P(C.c_int32), dp, C.c_int64, P(C.c_int64), dp, dp, dp,
                                        P(C.c_int32), P(C.c_int64)]),
         "dd_uot_set_state": (C.c_int, [H, P(C.c_int32), dp, C.c_int64, dp, dp, dp, P(C.c_int32),
@@ -394,6 +397,10 @@ def dd_uot_backward_ypos(h, prob, n1, n2, gout=1.0):
 
 def dd_uot_set_graph(h, enable=True):
     _check(load().dd_uot_set_graph(h, 1 if enable else 0))
+
+
+def dd_uot_set_err(h, prob, err):
+    _check(load().dd_uot_set_err(h, prob, err))
 
 
 def dd_uot_set_polish(h, n_iters):

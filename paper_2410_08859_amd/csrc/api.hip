@@ -36,6 +36,12 @@ hipError_t launch_line_search(const Dev& d, const int* chunk_prob, const int* ch
                               const int* chunk_len, int nchunk, int nprob, int rounds,
                               hipStream_t st);
 hipError_t launch_mix(const Dev& d, int part, int glo, int ghi, int nbasic, hipStream_t st);
+hipError_t launch_cell_theta(const Dev& d, int glo, int ghi, hipStream_t st);
+hipError_t launch_opt_weights(const Dev& d, int part, int blo, int bhi, int glo, int ghi,
+                              int nbasic, long ngrid, int nprob, const int* chunk_prob,
+                              const int* chunk_start, const int* chunk_len, int nchunk,
+                              int rounds, int line_rounds, double* Pt, double* Pd,
+                              hipStream_t st);
 hipError_t launch_certificate(const Prob& p, const double* alpha, const double* mu, const double* nu,
                               const double* px, const double* P, const double* ydel, double* bhat,
                               double* dmu, double* dnu, double* scratch, double* part, int nblk,
@@ -79,6 +85,7 @@ static int fail(int code, const std::string& msg) {
 
 static const int kChunk = 16384;
 static const int kLineRounds = 40;   // GetWeights line: f' evaluations per step, at most
+static const int kOptRounds = 12;    // GetWeights opt: direction + search rounds per step
 static const int kCertBlocks = 1024;
 static const int kPoolCheck = 2;     // half-iterations between pool checks
 
@@ -93,7 +100,10 @@ struct dduot_handle {
   int ncell[2] = {0, 0};
   int boff[2][4] = {}, bn[2][4] = {};   // staggered batches: global cell ranges
   bool staggered = false;
-  bool any_line = false;                 // some problem uses GetWeights line
+  bool any_line = false;                 // some problem uses GetWeights line (or opt)
+  bool any_opt = false;                  // some problem uses GetWeights opt
+  double *d_cell_theta = nullptr, *d_cell_dir = nullptr, *d_cell_ddh = nullptr;
+  double *d_Pt = nullptr, *d_Pd = nullptr;   // opt: P_theta and P_{theta + d}
   long long nrec = 0;                    // history records written (steps of batches)
   int nbasic = 0;
   long ngrid = 0;
@@ -218,7 +228,7 @@ static int validate(const dduot_config* c, const double* mu, const double* nu, i
   if (!(c->h >= 0.0) || !isfinite(c->h)) return fail(DDUOT_EINVAL, pre + "h must be >= 0");
   if (c->precision != 32 && c->precision != 64)
     return fail(DDUOT_EINVAL, pre + "precision must be 32 or 64");
-  if (c->getweights < 0 || c->getweights > 4) return fail(DDUOT_EINVAL, pre + "bad getweights");
+  if (c->getweights < 0 || c->getweights > 5) return fail(DDUOT_EINVAL, pre + "bad getweights");
   if (c->init != DDUOT_INIT_BLOCK && c->init != DDUOT_INIT_PRODUCT)
     return fail(DDUOT_EINVAL, pre + "bad init");
   if (!(c->sinkhorn_err >= 0.0)) return fail(DDUOT_EINVAL, pre + "sinkhorn_err must be >= 0");
@@ -455,7 +465,10 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
     h->cap = std::max(h->cap, cfgs[k].box_cap);
   }
   h->staggered = cfgs[0].getweights == DDUOT_GW_STAGGERED;
-  for (int k = 0; k < nprob; ++k) h->any_line |= cfgs[k].getweights == DDUOT_GW_LINE;
+  for (int k = 0; k < nprob; ++k) {
+    h->any_line |= cfgs[k].getweights == DDUOT_GW_LINE || cfgs[k].getweights == DDUOT_GW_OPT;
+    h->any_opt |= cfgs[k].getweights == DDUOT_GW_OPT;
+  }
   for (int k = 0; k < nprob; ++k)
     if ((cfgs[k].getweights == DDUOT_GW_STAGGERED) != h->staggered)
       return fail(DDUOT_EINVAL, "staggered GetWeights: all problems of a handle or none");
@@ -689,6 +702,13 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   CHK(dalloc(h, &h->d_chunk_part, 2 * (size_t)h->nchunk));
   CHK(dalloc(h, &h->d_line_part, 2 * (size_t)h->nchunk));
   CHK(dalloc(h, &h->d_theta, nprob));
+  CHK(dalloc(h, &h->d_cell_theta, h->cells.size()));
+  CHK(dalloc(h, &h->d_cell_dir, h->cells.size()));
+  CHK(dalloc(h, &h->d_cell_ddh, h->cells.size()));
+  if (h->any_opt) {
+    CHK(dalloc(h, &h->d_Pt, h->ngrid));
+    CHK(dalloc(h, &h->d_Pd, h->ngrid));
+  }
   CHK(dalloc(h, &h->d_line, 8 * (size_t)nprob));
   CHK(dalloc(h, &h->d_hist, (size_t)nprob * h->hist_cap * kHistFields));
   CHK(dalloc(h, &h->d_force, nprob));
@@ -829,6 +849,9 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
   d.kstep = h->d_kstep;
   d.chunk_part = h->d_chunk_part;
   d.theta = h->d_theta;
+  d.cell_theta = h->d_cell_theta;
+  d.cell_dir = h->d_cell_dir;
+  d.cell_ddh = h->d_cell_ddh;
   d.line = h->d_line;
   d.line_part = h->d_line_part;
   d.hist = h->d_hist;
@@ -923,6 +946,16 @@ extern "C" int dd_uot_set_eps(dduot_handle* h, int32_t prob, double eps) {
   return DDUOT_OK;
 }
 
+extern "C" int dd_uot_set_err(dduot_handle* h, int32_t prob, double err) {
+  if (!h || prob < 0 || prob >= h->nprob) return fail(DDUOT_EINVAL, "bad handle or problem");
+  if (!(err >= 0.0) || !isfinite(err)) return fail(DDUOT_EINVAL, "err must be >= 0");
+  Prob& p = h->probs[prob];
+  p.err = err;
+  HIPCHK(hipMemcpyAsync(h->d_probs + prob, &p, sizeof(Prob), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DDUOT_OK;
+}
+
 // One parallel DomDecIter (Algorithm 4) over the cells [lo, lo + n) of
 // partition `part` (all problems), GetWeights over batches [blo, bhi).
 static int dd_step(dduot_handle* h, int part, int lo, int n, int blo, int bhi) {
@@ -951,6 +984,11 @@ static int dd_step(dduot_handle* h, int part, int lo, int n, int blo, int bhi) {
   if (h->any_line)
     HIPCHK(launch_line_search(d, h->d_chunk_prob, h->d_chunk_start, h->d_chunk_len, h->nchunk,
                               h->nprob, kLineRounds, st));
+  HIPCHK(launch_cell_theta(d, lo, lo + n, st));
+  if (h->any_opt)
+    HIPCHK(launch_opt_weights(d, part, blo, bhi, lo, lo + n, h->nbasic, h->ngrid, h->nprob,
+                              h->d_chunk_prob, h->d_chunk_start, h->d_chunk_len, h->nchunk,
+                              kOptRounds, kLineRounds, h->d_Pt, h->d_Pd, st));
   HIPCHK(launch_mix(d, part, lo, lo + n, h->nbasic, st));
   HIPCHK(launch_advance(h->d_kstep, st));
   h->nrec += 1;
@@ -1752,6 +1790,8 @@ extern "C" void dd_uot_default_multiscale(dduot_multiscale* m) {
   m->coarse_lenience = 0.0;
   m->verbose = 0;
   m->polish_iters = 0;
+  m->final_err_ratio = 0.0;
+  m->final_err_min = 0.0;
 }
 
 static double now_ms() {
@@ -1776,6 +1816,9 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
       ms->stage_max_halves < ms->halves_per_stage || ms->coarse_max_iter < 1 ||
       ms->coarse_cell < 1 || 2 * ms->coarse_cell > kMaxTile)
     return fail(DDUOT_EINVAL, "bad iteration counts or coarse cell");
+  if (!(ms->final_err_ratio >= 0.0) || !(ms->final_err_min >= 0.0) || ms->polish_iters < 0 ||
+      ms->polish_iters > 10000)
+    return fail(DDUOT_EINVAL, "final_err_ratio, final_err_min >= 0, polish_iters in [0, 10000]");
   if (ms->dd_from < 0 || ms->global_max_iter < 1 || !(ms->global_tol >= 0.0))
     return fail(DDUOT_EINVAL, "bad global Sinkhorn settings");
   if (ms->coarse_box_cap < 0 || ms->coarse_box_cap > 128 || !(ms->coarse_lenience >= 0.0))
@@ -2016,11 +2059,19 @@ extern "C" int dd_uot_solve_multiscale(const dduot_config* cfg, const dduot_mult
         r = dd_uot_score(h, 0, &sc);
         if (r != DDUOT_OK) return fail_out(r);
         record(h, sc);
+        if (ms->final_err_ratio > 0.0) {
+          const double cur = h->probs[0].err;
+          const double want = std::max(ms->final_err_min, std::min(cur, ms->final_err_ratio * gap(sc)));
+          if (want < cur) {
+            r = dd_uot_set_err(h, 0, want);
+            if (r != DDUOT_OK) return fail_out(r);
+          }
+        }
         if (ms->verbose)
           fprintf(stderr, "[multiscale] final %dx%d: %d half-iterations, certificate gap %.3g, "
-                  "DD-plan gap %.3g, polished gap %.3g, %.0f ms\n", c.n1, c.n2, done,
+                  "DD-plan gap %.3g, polished gap %.3g, Err %.3g, %.0f ms\n", c.n1, c.n2, done,
                   sc.rel_pd_gap, (sc.tracked - sc.dual) / fabs(sc.dual), sc.rel_gap_polished,
-                  now_ms() - t0);
+                  h->probs[0].err, now_ms() - t0);
       }
     }
   }

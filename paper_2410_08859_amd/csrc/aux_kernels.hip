@@ -179,12 +179,12 @@ __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int blo,
     double th;
     if (d.force_greedy[pi] || p.getweights == 0) th = 1.0;
     else if (p.getweights == 1) th = 1.0 / n;
-    else if (p.getweights == 4) th = 1.0 / n;   // provisional: the line search sets it
+    else if (p.getweights >= 4) th = 1.0 / n;   // provisional: the line search sets it
     else th = (egr <= ecur + p.lenience * fabs(ecur)) ? 1.0 : 1.0 / n;
     // line search state (k_line_*): phase 0 evaluates f' at 1/n, 1 at 1, 2 inside
     // the bracket, 3 = done
     double* ls = d.line + 8 * pi;
-    const bool line = p.getweights == 4 && !d.force_greedy[pi];
+    const bool line = p.getweights >= 4 && !d.force_greedy[pi];
     ls[0] = 1.0 / n;
     ls[1] = 1.0 / n;
     ls[2] = 1.0;
@@ -192,6 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_getweights(Dev d, int part, int blo,
     ls[4] = acc[1] - acc[0];
     ls[5] = line ? 0.0 : 3.0;
     ls[6] = line ? 1.0 : 0.0;
+    ls[7] = (line && p.getweights == 5) ? 1.0 / n : 0.0;   // opt: per-cell rounds follow
     if (last) d.force_greedy[pi] = 0;   // a forced greedy half-iteration covers every batch
     d.theta[pi] = th;
     double* r = d.hist + ((long)pi * d.hist_cap + (rec % d.hist_cap)) * kHistFields;
@@ -314,6 +315,183 @@ hipError_t launch_line_search(const Dev& d, const int* chunk_prob, const int* ch
   return hipGetLastError();
 }
 
+// Weight of every cell of the step: its problem's weight (GetWeights opt
+// then refines it per cell).
+__global__ void k_cell_theta(Dev d, int glo, int ghi) {
+  for (int J = glo + blockIdx.x * blockDim.x + threadIdx.x; J < ghi; J += gridDim.x * blockDim.x)
+    d.cell_theta[J] = d.theta[d.cells[J].prob];
+}
+
+// ---- GetWeights opt (eq. opt-weights-problem) on the tracked score ----------
+// One weight theta_J in [1/n, 1] per cell of the step, minimising
+//   f(theta) = sum_J theta_J dH_J + lam KL(P + sum_J theta_J Delta_J | nu),
+// Delta_J = sum_{i in J} (nu~_i - nu_i), dH_J = sum_{i in J} (H~_i - Hbar_i)
+// (the pieces are linear in the weights, the KL term convex).  Starting from
+// the line-search weight, every round takes the projected diagonal Newton
+// direction d_J = clamp(theta_J - g_J / h_J, 1/n, 1) - theta_J (g the
+// gradient, h the diagonal of the Hessian of f) and minimises f exactly along
+// theta + t d, t in [0, 1], with the line-search kernels (P := P_theta,
+// Pg := P_{theta + d}).  line[7] = 1/n marks a problem under opt.
+__device__ __forceinline__ bool opt_active(const Dev& d, int pi) { return d.line[8 * pi + 7] > 0.0; }
+
+// P_w = sum over basic cells of the mixture with weight w_J = theta_J (+ d_J
+// when with_d) for the step's solved cells, the state elsewhere (fixed point).
+__global__ __launch_bounds__(kBlock) void k_opt_mixture(Dev d, int part, int glo, int ghi,
+                                                        int with_d) {
+  const int b = blockIdx.x;
+  const int J = d.basic_cell[part][b];
+  const bool in = J >= glo && J < ghi && d.cell_iters[J] >= 0;
+  const Prob& p = d.probs[d.basic_prob[b]];
+  unsigned long long* out = d.fxacc + 2 * (long)p.grid_off;
+  const Box ob = d.box[b];
+  const double* sv = state_pool(d) + d.voff[b];
+  if (!in) {
+    const long n = (long)ob.l1 * ob.l2;
+    for (long o = threadIdx.x; o < n; o += kBlock) {
+      const int j1 = (int)(o / ob.l2), j2 = (int)(o - (long)j1 * ob.l2);
+      const double x = sv[o];
+      if (x != 0.0) fx_add(out + 2 * ((long)(ob.o1 + j1) * p.n2 + (ob.o2 + j2)), x);
+    }
+    return;
+  }
+  double w = d.cell_theta[J];
+  const int pi = d.basic_prob[b];
+  if (with_d && opt_active(d, pi) && d.line[8 * pi + 6] != 0.0) w += d.cell_dir[J];
+  const Box cb = d.cbox[b];
+  const double* cv = d.cand + d.coff[b];
+  const long n = (long)cb.l1 * cb.l2;
+  for (long o = threadIdx.x; o < n; o += kBlock) {
+    const int j1 = (int)(o / cb.l2), j2 = (int)(o - (long)j1 * cb.l2);
+    const int a1 = cb.o1 + j1 - ob.o1, a2 = cb.o2 + j2 - ob.o2;
+    const double old = (a1 >= 0 && a1 < ob.l1 && a2 >= 0 && a2 < ob.l2) ? sv[(long)a1 * ob.l2 + a2] : 0.0;
+    const double x = (1.0 - w) * old + w * cv[o];
+    if (x != 0.0) fx_add(out + 2 * ((long)(cb.o1 + j1) * p.n2 + (cb.o2 + j2)), x);
+  }
+}
+
+// Per cell of an opt problem: gradient and Hessian diagonal of f at theta
+// (P_theta in d.Pg), the projected Newton direction and d_J dH_J.
+__global__ __launch_bounds__(kBlock) void k_opt_direction(Dev d, int glo) {
+  __shared__ double red[4 * 2];
+  const int J = glo + blockIdx.x;
+  const Cell C = d.cells[J];
+  const int pi = C.prob;
+  if (!opt_active(d, pi) || d.line[8 * pi + 6] == 0.0) return;   // not opt, or converged
+  const Prob& p = d.probs[pi];
+  double dH = 0.0;
+  for (int k = 0; k < C.nb; ++k) dH += d.htil[C.basic[k]] - d.hbar[C.basic[k]];
+  double s[2] = {0.0, 0.0};
+  const bool solved = d.cell_iters[J] >= 0;
+  if (solved) {
+    const Box yb = d.cellbox[J];
+    const long n = (long)yb.l1 * yb.l2;
+    const double* pool = state_pool(d);
+    for (long o = threadIdx.x; o < n; o += kBlock) {
+      const int j1 = (int)(o / yb.l2), j2 = (int)(o - (long)j1 * yb.l2);
+      const int y1 = yb.o1 + j1, y2 = yb.o2 + j2;
+      double dl = 0.0;
+      for (int k = 0; k < C.nb; ++k) {
+        const int b = C.basic[k];
+        dl += d.cand[d.coff[b] + o];
+        const Box ob = d.box[b];
+        const int a1 = y1 - ob.o1, a2 = y2 - ob.o2;
+        if (a1 >= 0 && a1 < ob.l1 && a2 >= 0 && a2 < ob.l2) dl -= pool[d.voff[b] + (long)a1 * ob.l2 + a2];
+      }
+      if (dl == 0.0) continue;
+      const long g = p.grid_off + (long)y1 * p.n2 + y2;
+      const double pt = d.Pg[g];
+      if (!(pt > 0.0)) continue;
+      s[0] += dl * (log(pt) - log(d.nu[g]));
+      s[1] += dl * dl / pt;
+    }
+  }
+  block_sum_aux<2>(s, red);
+  if (threadIdx.x != 0) return;
+  const double lo = d.line[8 * pi + 7];
+  const double th = d.cell_theta[J];
+  double dir = 0.0;
+  if (solved) {
+    const double g = dH + p.lam * s[0], hh = p.lam * s[1];
+    double tn;
+    if (hh > 0.0) tn = th - g / hh;
+    else tn = g < 0.0 ? 1.0 : (g > 0.0 ? lo : th);
+    tn = fmin(1.0, fmax(lo, tn));
+    dir = tn - th;
+  }
+  d.cell_dir[J] = dir;
+  d.cell_ddh[J] = dir * dH;
+}
+
+// Per opt problem: the line-search state for t in [0, 1] along d (dH = sum
+// d_J dH_J in a fixed order), or converged when d = 0.
+__global__ __launch_bounds__(kBlock) void k_opt_line_init(Dev d, int part, int blo, int bhi) {
+  __shared__ double red[4 * 2];
+  const int pi = blockIdx.x;
+  if (!opt_active(d, pi) || d.line[8 * pi + 6] == 0.0) return;
+  const Prob& p = d.probs[pi];
+  double s[2] = {0.0, 0.0};
+  for (int bt = blo; bt < bhi; ++bt) {
+    const int c0 = p.cell_off[part][bt], nc = p.ncell[part][bt];
+    for (int c = threadIdx.x; c < nc; c += kBlock) {
+      s[0] += d.cell_ddh[c0 + c];
+      s[1] = fmax(s[1], fabs(d.cell_dir[c0 + c]));
+    }
+  }
+  // s[1] is a maximum: combine it apart from the sum
+  double m = s[1];
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+  __shared__ double mred[4];
+  if ((threadIdx.x & 63) == 0) mred[threadIdx.x >> 6] = m;
+  s[1] = 0.0;
+  block_sum_aux<2>(s, red);
+  if (threadIdx.x != 0) return;
+  m = fmax(fmax(mred[0], mred[1]), fmax(mred[2], mred[3]));
+  double* ls = d.line + 8 * pi;
+  if (!(m > 1e-15)) {
+    ls[5] = 3.0;
+    ls[6] = 0.0;
+    return;
+  }
+  ls[0] = 0.0;
+  ls[1] = 0.0;
+  ls[2] = 1.0;
+  ls[3] = 0.0;
+  ls[4] = s[0];
+  ls[5] = 0.0;
+}
+
+// theta_J += t d_J for the cells of opt problems still searching.
+__global__ void k_opt_step(Dev d, int glo, int ghi) {
+  for (int J = glo + blockIdx.x * blockDim.x + threadIdx.x; J < ghi; J += gridDim.x * blockDim.x) {
+    const int pi = d.cells[J].prob;
+    if (!opt_active(d, pi) || d.line[8 * pi + 6] == 0.0) continue;
+    const double lo = d.line[8 * pi + 7];
+    d.cell_theta[J] = fmin(1.0, fmax(lo, d.cell_theta[J] + d.line[8 * pi + 3] * d.cell_dir[J]));
+  }
+}
+
+// Per opt problem: the record's weight is the mean of the cells' weights.
+__global__ __launch_bounds__(kBlock) void k_opt_finish(Dev d, int part, int blo, int bhi) {
+  __shared__ double red[4 * 2];
+  const int pi = blockIdx.x;
+  if (!opt_active(d, pi)) return;
+  const Prob& p = d.probs[pi];
+  double s[2] = {0.0, 0.0};
+  for (int bt = blo; bt < bhi; ++bt) {
+    const int c0 = p.cell_off[part][bt], nc = p.ncell[part][bt];
+    for (int c = threadIdx.x; c < nc; c += kBlock)
+      if (d.cell_iters[c0 + c] >= 0) {
+        s[0] += d.cell_theta[c0 + c];
+        s[1] += 1.0;
+      }
+  }
+  block_sum_aux<2>(s, red);
+  if (threadIdx.x != 0) return;
+  const double th = s[1] > 0.0 ? s[0] / s[1] : 1.0;
+  d.theta[pi] = th;
+  d.hist[((long)pi * d.hist_cap + (d.kstep[0] % d.hist_cap)) * kHistFields] = th;
+}
+
 // Algorithm 4 update: nu_i <- (1 - theta) nu_i + theta nu~_i on the cell box,
 // truncation below `trunc`, shrink to the bbox of the nonzeros; the tracked
 // piece and the X-marginal are mixed with the same weight.  Three kernels:
@@ -338,7 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_mix_values(Dev d, int part, int glo,
     return;
   }
   const Prob& p = d.probs[d.basic_prob[b]];
-  const double th = d.theta[d.basic_prob[b]];
+  const double th = d.cell_theta[d.basic_cell[part][b]];
   const Box cb = d.cbox[b];
   const Box ob = d.box[b];
   const long n = (long)cb.l1 * cb.l2;
@@ -425,7 +603,7 @@ __global__ __launch_bounds__(kBlock) void k_mix_copy(Dev d, int part, int glo, i
   }
   if (!upd) return;
   const Prob& p = d.probs[pi];
-  const double th = d.theta[pi];
+  const double th = d.cell_theta[d.basic_cell[part][b]];
   if (threadIdx.x == 0) d.hbar[b] = (1.0 - th) * d.hbar[b] + th * d.htil[b];
   const int2 xy = d.basic_xy[b];
   for (int o = threadIdx.x; o < p.s * p.s; o += kBlock) {
@@ -586,6 +764,47 @@ hipError_t launch_getweights(const Dev& d, int part, int blo, int bhi, int glo, 
 
 hipError_t launch_scan2(long* a, long* b, int n, long* tot, long long* need, int ia, int ib,
                         hipStream_t st);
+
+hipError_t launch_cell_theta(const Dev& d, int glo, int ghi, hipStream_t st) {
+  const int n = ghi - glo;
+  if (n > 0) hipLaunchKernelGGL(k_cell_theta, dim3((n + 255) / 256), dim3(256), 0, st, d, glo, ghi);
+  return hipGetLastError();
+}
+
+// GetWeights opt: `rounds` rounds of direction + exact search after the line
+// search set the uniform weight (k_cell_theta must have run).  Pt: a grid
+// for P_theta; the line kernels see P := Pt and Pg := P_{theta + d}.
+hipError_t launch_opt_weights(const Dev& d, int part, int blo, int bhi, int glo, int ghi,
+                              int nbasic, long ngrid, int nprob, const int* chunk_prob,
+                              const int* chunk_start, const int* chunk_len, int nchunk,
+                              int rounds, int line_rounds, double* Pt, double* Pd,
+                              hipStream_t st) {
+  Dev dt = d;
+  dt.Pg = Pt;   // k_opt_direction reads P_theta from Pg
+  Dev dl = d;
+  dl.P = Pt;
+  dl.Pg = Pd;
+  const int ncell = ghi - glo;
+  for (int r = 0; r < rounds; ++r) {
+    hipLaunchKernelGGL(k_fx_zero, dim3(grid_blocks(2 * ngrid)), dim3(256), 0, st, d.fxacc, 2 * ngrid);
+    hipLaunchKernelGGL(k_opt_mixture, dim3(nbasic), dim3(kBlock), 0, st, d, part, glo, ghi, 0);
+    hipLaunchKernelGGL(k_fx_finish, dim3(grid_blocks(ngrid)), dim3(256), 0, st, d.fxacc, Pt, ngrid);
+    if (ncell > 0) hipLaunchKernelGGL(k_opt_direction, dim3(ncell), dim3(kBlock), 0, st, dt, glo);
+    hipLaunchKernelGGL(k_opt_line_init, dim3(nprob), dim3(kBlock), 0, st, d, part, blo, bhi);
+    hipLaunchKernelGGL(k_fx_zero, dim3(grid_blocks(2 * ngrid)), dim3(256), 0, st, d.fxacc, 2 * ngrid);
+    hipLaunchKernelGGL(k_opt_mixture, dim3(nbasic), dim3(kBlock), 0, st, d, part, glo, ghi, 1);
+    hipLaunchKernelGGL(k_fx_finish, dim3(grid_blocks(ngrid)), dim3(256), 0, st, d.fxacc, Pd, ngrid);
+    for (int q = 0; q < line_rounds; ++q) {
+      hipLaunchKernelGGL(k_line_partials, dim3(nchunk), dim3(kBlock), 0, st, dl, chunk_prob,
+                         chunk_start, chunk_len);
+      hipLaunchKernelGGL(k_line_update, dim3(nprob), dim3(64), 0, st, dl);
+    }
+    if (ncell > 0)
+      hipLaunchKernelGGL(k_opt_step, dim3((ncell + 255) / 256), dim3(256), 0, st, d, glo, ghi);
+  }
+  hipLaunchKernelGGL(k_opt_finish, dim3(nprob), dim3(kBlock), 0, st, d, part, blo, bhi);
+  return hipGetLastError();
+}
 
 hipError_t launch_mix(const Dev& d, int part, int glo, int ghi, int nbasic, hipStream_t st) {
   if (nbasic <= 0) return hipSuccess;

@@ -98,7 +98,11 @@ struct Dev {
   long long* kstep;           // half-iterations done (history record index)
   double* chunk_part;         // 2 doubles per reduction chunk
   double* theta;              // per problem
-  double* line;               // per problem, GetWeights line search: lo, a, b, z, dH, phase, active, -
+  double* cell_theta;         // per cell: the weight of its last step (GetWeights)
+  double* cell_dir;           // per cell: GetWeights opt direction
+  double* cell_ddh;           // per cell: direction times the change of its pieces
+  double* line;               // per problem, GetWeights line search: lo, a, b, z, dH,
+                              // phase, active, opt lower bound (0: no opt rounds)
   double* line_part;          // 2 doubles per reduction chunk (line search sums)
   double* hist;               // per problem ring of records
   int* force_greedy;          // per problem: next GetWeights takes theta = 1

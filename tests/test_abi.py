@@ -59,7 +59,7 @@ def test_default_config_values():
 
 @pytest.mark.parametrize("field,value", [("n1", 30), ("cell", 0), ("cell", 9), ("eps", 0.0),
                                          ("lambda_", -1.0), ("precision", 16), ("box_cap", 4),
-                                         ("getweights", 7), ("getweights", 5), ("translate", 2),
+                                         ("getweights", 7), ("getweights", 6), ("translate", 2),
                                          ("balance", 2)])
 def test_invalid_configs_are_rejected_before_any_device_work(field, value):
     import numpy as np

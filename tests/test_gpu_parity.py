@@ -13,7 +13,7 @@ from paper_2410_08859_amd.inputs import gaussian_mixture, workload_marginals
 
 pytestmark = pytest.mark.gpu
 
-GW = {0: "greedy", 1: "safe", 2: "swift", 3: "staggered", 4: "line"}
+GW = {0: "greedy", 1: "safe", 2: "swift", 3: "staggered", 4: "line", 5: "opt"}
 
 
 def config(n, s, eps, lam, h, **kw):
@@ -280,6 +280,50 @@ def test_polished_bounds_sparsity_and_counts_match_oracle(grid32):
         assert s["n_safe"] == sum(1 for x in st.history if x["theta"] < 1.0)
         assert s["n_unconverged"] == sum(x["n_unconverged"] for x in st.history)
         assert s["n_unconverged"] > 0
+    finally:
+        B.dd_uot_destroy(h)
+
+
+def gpu_state_of(st, k):
+    """The oracle's state in the layout of dd_uot_set_state."""
+    boxes = np.array([[o1, o2, arr.shape[0], arr.shape[1]] for o1, o2, arr in st.boxes],
+                     dtype=np.int32).reshape(-1, 4)
+    vals = np.concatenate([arr.ravel() for _, _, arr in st.boxes] + [np.zeros(0)])
+    warm = np.zeros(len(st.boxes), dtype=np.int32) if st.warm is None else st.warm.astype(np.int32)
+    return dict(boxes=boxes, values=vals, px=st.px, hbar=st.hbar, abar=st.abar, warm=warm, k=k)
+
+
+def test_fp64_opt_weights_match_the_oracle_minimiser(grid32):
+    # GetWeights opt (eq. opt-weights-problem): the device's rounds of
+    # projected diagonal Newton with exact searches against the oracle's
+    # bounded minimiser, one step at a time from the oracle's state
+    mu, nu = grid32
+    n = 32
+    cfg = config(n, 4, 4.0 / n ** 2, 1.0, 1.0 / n, precision=64, init=B.INIT_PRODUCT,
+                 fixed_inner_iters=15, lenience=0.0, box_cap=32, getweights=B.GW_OPT, trunc=0.0)
+    p = dd.make_problem(mu, nu, cfg.eps, cfg.lambda_, cfg.h, cfg.cell)
+    st = dd.init_product(p)
+    opt = oracle_options(cfg)
+    h = B.dd_uot_init(cfg, mu, nu)
+    try:
+        for k in range(4):
+            if k > 0:
+                B.dd_uot_set_state(h, gpu_state_of(st, k))
+            out = dd.half_iteration(p, st, "A" if k % 2 == 0 else "B", opt)
+            B.dd_uot_iterate(h, 1)
+            rec = B.dd_uot_history(h, 0)[-1]
+            s = B.dd_uot_score(h, 0)
+            ref = dd.tracked_score(p, st)
+            print(f"[parity] opt step {k}: mean weight {rec[0]:.6f} vs {out['theta']:.6f}, "
+                  f"weights in [{out['thetas'].min():.3g}, {out['thetas'].max():.3g}], tracked "
+                  f"{s['tracked']:.12g} vs {ref:.12g}", flush=True)
+            # the optimal value is unique; the weights of this ill-conditioned
+            # minimiser move by ~1e-4 for score changes of ~1e-10
+            assert s["tracked"] == pytest.approx(ref, rel=1e-9)
+            assert rec[0] == pytest.approx(out["theta"], rel=1e-3)
+            px, py = B.dd_uot_marginals(h, 0, n, n)
+            rel_close(px, st.px, 1e-6, f"P_X at {k}")
+            rel_close(py, dd.aggregate(p, st.boxes), 1e-6, f"P_Y at {k}")
     finally:
         B.dd_uot_destroy(h)
 

@@ -120,7 +120,7 @@ def test_global_optimum_is_a_fixed_point_of_the_cell_step():
     np.testing.assert_allclose(st.px, pi.sum(1).reshape(p.mu.shape), rtol=1e-6)
 
 
-@pytest.mark.parametrize("gw", ["swift", "safe", "line"])
+@pytest.mark.parametrize("gw", ["swift", "safe", "line", "opt"])
 def test_monotone_scores(gw):
     # Safe decrement proof (Sec. 3.4): with safe weights the exact score of the
     # mixed plan never rises.  The tracked score Ebar (reading R8) bounds E from
@@ -512,6 +512,60 @@ def test_line_weight_minimises_the_tracked_score_of_the_mixture():
                                                    margin=2, getweights="line"))
         assert st.history[-1]["theta"] == pytest.approx(z, rel=1e-12)
     assert found_interior
+
+
+def test_opt_weights_minimise_the_tracked_score_of_the_mixture():
+    # GetWeights opt (eq. opt-weights-problem, reading R14): the per-cell
+    # weights minimise the mixture's tracked score over [1/n, 1]^J, so they do
+    # at least as well as the uniform line weight, greedy and safe, satisfy
+    # the bound-constrained optimality conditions, and no single weight can be
+    # moved to improve (checked on the score itself)
+    p = small_problem(16, 2, eps_h2=2.0)
+    st = dd.init_product(p)
+    opt = dd.Options(trunc=0.0, err=1e-12, max_iter=3000, margin=2)
+    dd.run(p, st, 1, dd.Options(trunc=0.0, err=1e-12, max_iter=3000, margin=2,
+                                getweights="greedy"))
+    for part in ("B", "A"):
+        cells = dd.composite_cells(p, part)
+        P = dd.aggregate(p, st.boxes)
+        res = [dd.process_cell(p, c, st.boxes, P, opt, st.abar, st.warm) for c in cells]
+        deltas, dHs = [], []
+        for c, r in zip(cells, res):
+            dl = np.zeros((p.n1, p.n2))
+            for b in c["basic"]:
+                o1, o2, arr = dd.truncate_to_box(r["box"][0], r["box"][1], r["cand"][b], 0.0)
+                if arr.size:
+                    dl[o1:o1 + arr.shape[0], o2:o2 + arr.shape[1]] += arr
+                o1, o2, arr = st.boxes[b]
+                if arr.size:
+                    dl[o1:o1 + arr.shape[0], o2:o2 + arr.shape[1]] -= arr
+            deltas.append(dl)
+            dHs.append(sum(r["pieces"][b] - st.hbar[b] for b in c["basic"]))
+        n = len(cells)
+        D = np.stack([x.ravel() for x in deltas])
+        dH = np.array(dHs)
+        f = lambda th: float(th @ dH) + p.lam * uot.kl(P.ravel() + th @ D, p.nu.ravel())
+        z = dd.line_weight(p, P, P + D.sum(0).reshape(P.shape), float(dH.sum()), n)
+        th = dd.opt_weights(p, P, deltas, dHs, n, z)
+        fz = f(th)
+        for ref in (np.full(n, z), np.ones(n), np.full(n, 1.0 / n)):
+            assert fz <= f(ref) + 1e-13 * abs(fz)
+        g = dH + p.lam * (D @ (np.log(P.ravel() + th @ D) - np.log(p.nu.ravel())))
+        scale = np.abs(dH).max()
+        lo, hi = th <= 1.0 / n + 1e-12, th >= 1.0 - 1e-12
+        assert np.all(g[lo] >= -1e-7 * scale) and np.all(g[hi] <= 1e-7 * scale)
+        mid = ~lo & ~hi
+        assert np.all(np.abs(g[mid]) <= 1e-7 * scale)
+        rng = np.random.default_rng(5)
+        for J in rng.choice(n, 6, replace=False):
+            for dz in (1e-3, -1e-3):
+                t2 = th.copy()
+                t2[J] = min(1.0, max(1.0 / n, t2[J] + dz))
+                assert fz <= f(t2) + 1e-13 * abs(fz)
+        assert np.ptp(th) > 0      # the weights differ between cells
+        dd.half_iteration(p, st, part, dd.Options(trunc=0.0, err=1e-12, max_iter=3000, margin=2,
+                                                   getweights="opt"))
+        np.testing.assert_allclose(st.history[-1]["thetas"], th, rtol=1e-12, atol=0)
 
 
 def test_balancing_moves_mass_horizontally_to_the_targets():
