@@ -49,7 +49,7 @@ EXP_PEAK = 256 * 64 * 2.4e9 / 4.0
 HBM_PEAK = 8.0e12
 
 GW_NAMES = {B.GW_GREEDY: "greedy", B.GW_SAFE: "safe", B.GW_SWIFT: "swift",
-            B.GW_STAGGERED: "staggered", B.GW_LINE: "line"}
+            B.GW_STAGGERED: "staggered", B.GW_LINE: "line", B.GW_OPT: "opt"}
 GW_IDS = {v: k for k, v in GW_NAMES.items()}
 PROFILE = os.path.join(ROOT, "profiles", "k_cell_solve_grid1024_fp32_multiscale.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2410_08859_amd", "csrc", "cell_kernel.hip")
@@ -99,7 +99,8 @@ def multiscale_solve(name, precision, final_max, polish, args, stream):
     cfg = workload_config(name, precision, args.max_inner, args.err, GW_IDS[args.getweights])
     levels = int(round(np.log2(cfg.n1 / 16))) + 1
     ms = B.dd_uot_default_multiscale(levels=levels, final_max_halves=final_max, check_every=4,
-                                     target_rel_gap=min(TARGETS), polish_iters=polish)
+                                     target_rel_gap=min(TARGETS), polish_iters=polish,
+                                     final_err_ratio=args.err_ratio, final_err_min=1e-10)
     h, tr = B.dd_uot_solve_multiscale(cfg, ms, mu, nu, stream=stream)
     progress(f"multiscale {name} FP{precision}: {tr[-1, 1] / 1e3:.1f} s, certified gap "
              f"{tr[-1, 4]:.3g}, DD-plan gap {tr[-1, 3]:.3g}")
@@ -123,8 +124,9 @@ def multiscale_solve(name, precision, final_max, polish, args, stream):
                        f"the finest; DD 4-16 half-iterations per stage; then at most {final_max} "
                        f"half-iterations with a certificate every 4 (polished by {polish} global "
                        f"Sinkhorn iterations); GetWeights {args.getweights} (lenience 0), Err "
-                       f"{args.err:g}, at most {args.max_inner} inner iterations per cell, cells "
-                       f"{cfg.cell}x{cfg.cell} on the finest layer, 4x4 below"}
+                       f"{args.err:g} (final stage: min(Err, {args.err_ratio:g} x certified gap)), "
+                       f"at most {args.max_inner} inner iterations per cell, cell problems on the "
+                       f"support of nu_J, cells {cfg.cell}x{cfg.cell} on the finest layer, 4x4 below"}
     return h, rec
 
 
@@ -459,11 +461,13 @@ def main():
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
     ap.add_argument("--max-inner", type=int, default=1000)
     ap.add_argument("--err", type=float, default=2e-5, help="cell tolerance Err (Sec. 4.4)")
-    ap.add_argument("--getweights", default="line", choices=("swift", "staggered", "line"))
-    ap.add_argument("--final32", type=int, default=12,
+    ap.add_argument("--getweights", default="line", choices=("swift", "staggered", "line", "opt"))
+    ap.add_argument("--final32", type=int, default=32,
                     help="half-iterations of the final stage of the FP32 solve, at most")
-    ap.add_argument("--final64", type=int, default=8,
+    ap.add_argument("--final64", type=int, default=16,
                     help="half-iterations of the final stage of the FP64 solve, at most")
+    ap.add_argument("--err-ratio", type=float, default=0.01,
+                    help="final stage: cell tolerance min(Err, ratio x certified gap)")
     ap.add_argument("--polish", type=int, default=10,
                     help="global Sinkhorn iterations polishing each certificate")
     ap.add_argument("--other-precision", type=int, default=1,
