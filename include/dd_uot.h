@@ -178,7 +178,9 @@ typedef struct {
    translation step on, no balancing, cell problems on the support of nu_J). */
 void dd_uot_default_config(dduot_config* cfg);
 
-/* Create a solver for one problem.  mu, nu: host, n1*n2 each, every entry
+/* Create a solver for one problem.  mu, nu: n1*n2 doubles each, in host or
+   device memory (told apart by hipPointerGetAttributes; device inputs are
+   read once, on hip_stream, into host memory for the set-up), every entry
    finite and > 0 (Assumption full support, Sec. 3.2), each total below 1024
    (the aggregation of the basic-cell marginals sums in fixed point, so its
    results do not depend on the order of the adds), else DDUOT_EINVAL.
@@ -188,14 +190,16 @@ int dd_uot_init(const dduot_config* cfg, const double* mu, const double* nu,
 
 /* Create one solver holding nprob independent problems (sizes and parameters
    may differ); every kernel launch covers all problems' cells at once, and
-   GetWeights decides per problem.  mus[k], nus[k]: host arrays of problem k. */
+   GetWeights decides per problem.  mus[k], nus[k]: arrays of problem k (host
+   or device memory, each on its own). */
 int dd_uot_init_batch(int32_t nprob, const dduot_config* cfgs, const double* const* mus,
                       const double* const* nus, void* hip_stream, dduot_handle** out);
 
 /* Moved Y points (the differentiable form): the Y masses sit at y' instead of
    the grid, cost c(x, y') = |x - y'|^2, which is no longer separable, so the
    cell solves and the certificate use dense sums over explicit point pairs.
-   ypos: host, n1*n2*2 doubles (y'_1, y'_2 of grid point j, row-major), finite;
+   ypos: n1*n2*2 doubles (y'_1, y'_2 of grid point j, row-major; host or
+   device memory), finite;
    needs h > 0.  Boxes and partitions stay those of the grid indices, so
    displacements should be small against the cell size.
    dd_uot_init_batch_moved: ypos[k] for every problem, or ypos == NULL for
@@ -234,6 +238,26 @@ int dd_uot_iterate(dduot_handle* h, int32_t n_half_iters, dduot_iter_stats* stat
    128, 256 threads (-1: not admissible).  Synchronises. */
 int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms);
 
+/* Gangs for the wide cells (boxes wider than box_cap and at most 512
+   columns, plain separable problems: no moved Y points, no balancing).  The
+   wide cells of a step are listed heaviest first (box points times the
+   iterations of the cell's previous solve); the heavy ones, above an even
+   share of the total per workgroup, are solved by G workgroups together
+   (the box rows split between them; two barriers per inner iteration), the
+   light ones by one workgroup each, taken from a queue.  The gang kernel
+   keeps at most wgs_per_cu workgroups per CU (within its occupancy; the
+   grid is a multiple of 8 G, so every workgroup is resident at once), and
+   the members of a gang share one XCD (gangs are formed from the XCD id
+   each workgroup reads; workgroups left over on an XCD only take light
+   cells).
+   G = 0: one workgroup per wide cell.  Default G = 4, wgs_per_cu = 2.  Same
+   arithmetic either way; a gang adds its members' partial sums in member
+   order, so results depend on G only through rounding.  A barrier that
+   waits past 2 s (not expected) abandons the launch's wide cells, and the
+   next dd_uot_iterate reports DDUOT_EHIP.  Returns the G in effect (0 when
+   gangs do not apply), *nwg (if not NULL) the gang kernel's workgroups. */
+int dd_uot_set_gang(dduot_handle* h, int32_t G, int32_t wgs_per_cu, int32_t* nwg);
+
 /* enable != 0: dd_uot_iterate runs pairs of half-iterations (A then B) by
    replaying one captured hipGraph of all their kernels (captured on first
    use; the step's kernels read every parameter from device memory, so the
@@ -263,7 +287,8 @@ int dd_uot_score(dduot_handle* h, int32_t prob, dduot_score* out);
 int dd_uot_set_polish(dduot_handle* h, int32_t n_iters);
 
 /* X- and Y-marginal of the current state plan (P_X pi and sum_i nu_i).
-   px, py: host, n1*n2 doubles each (either may be NULL).  Synchronises. */
+   px, py: n1*n2 doubles each, host or device memory (either may be NULL).
+   Synchronises. */
 int dd_uot_marginals(dduot_handle* h, int32_t prob, double* px, double* py);
 
 /* Stored Y-marginal nu_i of basic cell `basic` (row-major ids over the
@@ -298,15 +323,17 @@ int dd_uot_set_state(dduot_handle* h, const int32_t* boxes, const double* values
                      const int32_t* warm, int64_t k, int32_t force_greedy);
 
 /* alpha_bar (stitched cell potentials) and, after dd_uot_score, beta_hat.
-   Either pointer may be NULL; n1*n2 doubles each.  Synchronises. */
+   Either pointer may be NULL; n1*n2 doubles each, host or device memory.
+   Synchronises. */
 int dd_uot_potentials(dduot_handle* h, int32_t prob, double* alpha, double* beta_hat);
 
 /* Gradient of the optimal value W(mu, nu) at the certificate pair (envelope
    theorem on the dual of Definition unbalanced-entropic-transport):
    dW/dmu = eps|nu| - eps P_X pi_hat/mu - lambda (e^{-alpha/lambda} - 1),
    dW/dnu = eps|mu| - eps P_Y pi_hat/nu - lambda (e^{-beta/lambda} - 1),
-   scaled by gout.  Exact at the optimum; call after dd_uot_score.
-   dmu, dnu: host, n1*n2 doubles each (either may be NULL). */
+   scaled by gout on the device.  Exact at the optimum; call after
+   dd_uot_score.  dmu, dnu: n1*n2 doubles each, host or device memory
+   (either may be NULL).  Synchronises. */
 int dd_uot_backward(dduot_handle* h, int32_t prob, double gout, double* dmu, double* dnu);
 
 /* Gradient of the optimal value with respect to the Y positions at the
@@ -314,7 +341,7 @@ int dd_uot_backward(dduot_handle* h, int32_t prob, double gout, double* dmu, dou
    cost derivative integrated against the plan; exact at the optimum), for
    the grid or the moved points, scaled by gout.  The plan is recomputed on
    the fly by dense pruned sums (no stored plan).  Call after dd_uot_score.
-   dypos: host, n1*n2*2 doubles.  Needs h > 0. */
+   dypos: n1*n2*2 doubles, host or device memory.  Needs h > 0. */
 int dd_uot_backward_ypos(dduot_handle* h, int32_t prob, double gout, double* dypos);
 
 /* Cell-kernel timing with HIP events recorded on the handle's stream around
@@ -325,6 +352,16 @@ int dd_uot_backward_ypos(dduot_handle* h, int32_t prob, double gout, double* dyp
 int dd_uot_set_timing(dduot_handle* h, int32_t enable);
 int dd_uot_kernel_time(dduot_handle* h, int64_t* launches, double* total_ms,
                        double* algo_bytes);
+
+/* Per composite cell of partition `part` (0: A, 1: B; all problems, in cell
+   order) as of the last step that solved it: its Y-box (o1, o2, l1, l2 in
+   `boxes`, 4 int32 per cell), its inner Sinkhorn iterations (-1: not solved
+   for lack of pool space) and its log-sum-exp terms.  Host arrays of at
+   least `max` entries (per cell); any may be NULL.  Returns the partition's
+   cell count, or a negative error code (max too small, bad part).
+   Synchronises. */
+int dd_uot_cell_stats(dduot_handle* h, int32_t part, int32_t max, int32_t* boxes,
+                      int32_t* iters, double* terms);
 
 /* ---- Multiscale (Sec. 4.4 "Multi-scale and eps-scaling") ----------------- */
 

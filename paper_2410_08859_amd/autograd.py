@@ -9,8 +9,8 @@ convergence, Theorem existence-global-solution); backward returns the
 envelope-theorem gradients computed on the device by dd_uot_backward and
 dd_uot_backward_ypos (d/dy' = sum_x pi(x, y') 2 (y' - x), the plan recomputed
 on the fly), and d/dtheta = B^T (d/dy') B through the linear B-spline map.
-The tensors only carry data in and out; every step of the solve runs in
-libdd_uot.so.
+The tensors only carry data in and out (their device memory is handed to the
+library directly); every step of the solve runs in libdd_uot.so.
 """
 from __future__ import annotations
 
@@ -24,9 +24,12 @@ from .inputs import displaced_points, displacement_basis
 class UOTValue(torch.autograd.Function):
     @staticmethod
     def forward(ctx, mu, nu, theta, cfg, half_iters):
-        m = mu.detach().to("cpu", torch.float64).numpy()
-        v = nu.detach().to("cpu", torch.float64).numpy()
-        stream = torch.cuda.current_stream().cuda_stream if mu.is_cuda else None
+        # the marginals go to the library as they are (device or host
+        # memory, FP64), on the tensors' stream; the gradients come back
+        # into tensors on the same device
+        m = mu.detach().to(torch.float64).contiguous().view(-1)
+        v = nu.detach().to(torch.float64).contiguous().view(-1)
+        stream = torch.cuda.current_stream(mu.device).cuda_stream if mu.is_cuda else None
         n1, n2 = cfg.n1, cfg.n2
         if theta is None:
             h = B.dd_uot_init(cfg, m, v, stream=stream)
@@ -37,7 +40,9 @@ class UOTValue(torch.autograd.Function):
         try:
             B.dd_uot_iterate(h, half_iters, stats=False)
             s = B.dd_uot_score(h, 0)
-            dmu, dnu = B.dd_uot_backward(h, 0, n1, n2)
+            dmu = torch.empty(n1 * n2, dtype=torch.float64, device=mu.device)
+            dnu = torch.empty(n1 * n2, dtype=torch.float64, device=nu.device)
+            B.dd_uot_backward(h, 0, n1, n2, out=(dmu, dnu))
             dth = None
             if theta is not None:
                 dy = B.dd_uot_backward_ypos(h, 0, n1, n2)
@@ -47,8 +52,7 @@ class UOTValue(torch.autograd.Function):
                 dth = np.stack([B1.T @ dy[..., c] @ B2 for c in range(2)])
         finally:
             B.dd_uot_destroy(h)
-        ctx.save_for_backward(torch.from_numpy(dmu).to(mu.device, mu.dtype),
-                              torch.from_numpy(dnu).to(nu.device, nu.dtype))
+        ctx.save_for_backward(dmu.view(n1, n2).to(mu.dtype), dnu.view(n1, n2).to(nu.dtype))
         ctx.dth = None if dth is None else torch.from_numpy(dth).to(theta.device, theta.dtype)
         ctx.score = s
         return mu.new_tensor(s["dual"])

@@ -24,13 +24,13 @@ EXPORTED = (
     "dd_uot_default_config", "dd_uot_init", "dd_uot_init_batch", "dd_uot_set_eps",
     "dd_uot_iterate", "dd_uot_history", "dd_uot_score", "dd_uot_marginals",
     "dd_uot_basic_marginal", "dd_uot_potentials", "dd_uot_backward", "dd_uot_set_timing",
-    "dd_uot_kernel_time", "dd_uot_synchronize", "dd_uot_num_problems", "dd_uot_destroy",
+    "dd_uot_kernel_time", "dd_uot_cell_stats", "dd_uot_synchronize", "dd_uot_num_problems", "dd_uot_destroy",
     "dd_uot_last_error", "dd_uot_refine", "dd_uot_default_multiscale",
     "dd_uot_solve_multiscale", "dd_uot_init_moved", "dd_uot_init_batch_moved",
     "dd_uot_backward_ypos", "dd_uot_set_graph", "dd_uot_autotune",
     "dd_uot_interpolate_potential", "dd_uot_global_sinkhorn", "dd_uot_init_duals",
     "dd_uot_launch_caps", "dd_uot_set_polish", "dd_uot_get_state", "dd_uot_set_state",
-    "dd_uot_set_err",
+    "dd_uot_set_err", "dd_uot_set_gang",
 )
 
 
@@ -124,6 +124,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dd_uot_backward": (C.c_int, [H, C.c_int32, C.c_double, dp, dp]),
         "dd_uot_set_timing": (C.c_int, [H, C.c_int32]),
         "dd_uot_kernel_time": (C.c_int, [H, P(C.c_int64), dp, dp]),
+        "dd_uot_cell_stats": (C.c_int, [H, C.c_int32, C.c_int32, P(C.c_int32), P(C.c_int32), dp]),
+        "dd_uot_set_gang": (C.c_int, [H, C.c_int32, C.c_int32, P(C.c_int32)]),
         "dd_uot_synchronize": (C.c_int, [H]),
         "dd_uot_num_problems": (C.c_int32, [H]),
         "dd_uot_destroy": (None, [H]),
@@ -170,8 +172,39 @@ def _check(rc):
     return rc
 
 
-def _dptr(a: np.ndarray):
+def _is_tensor(a) -> bool:
+    return hasattr(a, "data_ptr") and hasattr(a, "is_contiguous")
+
+
+def _dptr(a):
+    """double* of a NumPy array (host) or of a contiguous float64 torch
+    tensor (host or device memory: the library tells them apart)."""
+    if _is_tensor(a):
+        return C.cast(C.c_void_p(a.data_ptr()), C.POINTER(C.c_double))
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _tensor_arg(a, n):
+    import torch
+    if a.dtype != torch.float64 or not a.is_contiguous() or a.numel() != n:
+        raise ValueError("tensor arguments must be contiguous float64 with the grid's size")
+    return a
+
+
+def _out(n, given):
+    """A given output buffer (NumPy array or tensor of n doubles), else a new array."""
+    if given is None:
+        return np.zeros(n)
+    if _is_tensor(given):
+        return _tensor_arg(given, n)
+    if not (isinstance(given, np.ndarray) and given.dtype == np.float64 and given.flags.c_contiguous
+            and given.size == n):
+        raise ValueError("output arrays must be contiguous float64 with the grid's size")
+    return given
+
+
+def _shaped(a, n1, n2):
+    return a.view(n1, n2) if _is_tensor(a) else a.reshape(n1, n2)
 
 
 def dd_uot_default_config(**kw) -> dduot_config:
@@ -183,6 +216,8 @@ def dd_uot_default_config(**kw) -> dduot_config:
 
 
 def _grid(a, n1, n2):
+    if _is_tensor(a):
+        return _tensor_arg(a, n1 * n2)
     a = np.ascontiguousarray(a, dtype=np.float64)
     if a.size != n1 * n2:
         raise ValueError("marginal size does not match the grid")
@@ -233,11 +268,13 @@ def dd_uot_score(h, prob=0):
     return {f: getattr(s, f) for f, _ in dduot_score._fields_}
 
 
-def dd_uot_marginals(h, prob, n1, n2):
-    px = np.zeros(n1 * n2)
-    py = np.zeros(n1 * n2)
+def dd_uot_marginals(h, prob, n1, n2, out=None):
+    """(P_X, P_Y) of the state plan; `out`: two buffers to fill (arrays or
+    float64 tensors, host or device)."""
+    px = _out(n1 * n2, out[0] if out else None)
+    py = _out(n1 * n2, out[1] if out else None)
     _check(load().dd_uot_marginals(h, prob, _dptr(px), _dptr(py)))
-    return px.reshape(n1, n2), py.reshape(n1, n2)
+    return _shaped(px, n1, n2), _shaped(py, n1, n2)
 
 
 def dd_uot_basic_marginal(h, prob, basic):
@@ -256,11 +293,13 @@ def dd_uot_potentials(h, prob, n1, n2, beta=True):
     return a.reshape(n1, n2), (b.reshape(n1, n2) if beta else None)
 
 
-def dd_uot_backward(h, prob, n1, n2, gout=1.0):
-    dmu = np.zeros(n1 * n2)
-    dnu = np.zeros(n1 * n2)
+def dd_uot_backward(h, prob, n1, n2, gout=1.0, out=None):
+    """gout * (dW/dmu, dW/dnu); `out`: two buffers to fill (arrays or float64
+    tensors, host or device)."""
+    dmu = _out(n1 * n2, out[0] if out else None)
+    dnu = _out(n1 * n2, out[1] if out else None)
     _check(load().dd_uot_backward(h, prob, gout, _dptr(dmu), _dptr(dnu)))
-    return dmu.reshape(n1, n2), dnu.reshape(n1, n2)
+    return _shaped(dmu, n1, n2), _shaped(dnu, n1, n2)
 
 
 def dd_uot_set_timing(h, enable=True):
@@ -273,6 +312,19 @@ def dd_uot_kernel_time(h):
     by = C.c_double()
     _check(load().dd_uot_kernel_time(h, C.byref(n), C.byref(ms), C.byref(by)))
     return n.value, ms.value, by.value
+
+
+def dd_uot_cell_stats(h, part):
+    """Y-boxes (n, 4), inner iterations (n,) and terms (n,) of the cells of `part`."""
+    lib = load()
+    n = max(1, _check(lib.dd_uot_cell_stats(h, part, 1 << 30, None, None, None)))
+    boxes = np.zeros((n, 4), np.int32)
+    iters = np.zeros(n, np.int32)
+    terms = np.zeros(n, np.float64)
+    rc = lib.dd_uot_cell_stats(h, part, n, boxes.ctypes.data_as(C.POINTER(C.c_int32)),
+                               iters.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(terms))
+    _check(rc if rc < 0 else 0)
+    return boxes, iters, terms
 
 
 def dd_uot_synchronize(h):
@@ -393,6 +445,13 @@ def dd_uot_backward_ypos(h, prob, n1, n2, gout=1.0):
     out = np.zeros(2 * n1 * n2)
     _check(load().dd_uot_backward_ypos(h, prob, gout, _dptr(out)))
     return out.reshape(n1, n2, 2)
+
+
+def dd_uot_set_gang(h, G, wgs_per_cu=2):
+    """Gangs of G workgroups for the wide cells; returns (G in effect, workgroups)."""
+    nwg = C.c_int32()
+    g = _check(load().dd_uot_set_gang(h, G, wgs_per_cu, C.byref(nwg)))
+    return g, nwg.value
 
 
 def dd_uot_set_graph(h, enable=True):

@@ -14,15 +14,19 @@
 
 namespace dduot {
 hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int lcap, int tcap,
-                             int precision, bool moved, bool balance, int nt, hipStream_t st);
+                             int precision, bool moved, bool balance, int nt, const GangLaunch& gl,
+                             hipStream_t st);
+hipError_t gang_occupancy(int precision, int minb, size_t lds, int* occ);
 hipError_t launch_cell_prep(const Dev& d, int cell_base, int ncells, int precision, hipStream_t st);
 hipError_t launch_bound_begin(unsigned long long* acc, long long* bound, hipStream_t st);
 hipError_t launch_bound_step(const Dev& d, Box* tb, int cell_base, int ncell, int nbasic,
                              int precision, unsigned long long* acc, long long* bound,
                              hipStream_t st);
-hipError_t set_cell_lds_limit(size_t bytes);
+hipError_t set_cell_lds_limit(size_t bytes, size_t gang_bytes);
+size_t gang_lds_bytes(int precision, int lcap);
 size_t cell_lds_bytes(int lcap, int cap, int precision, bool moved, bool big);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st);
+hipError_t launch_scale_copy(double* dst, const double* src, long n, double a, hipStream_t st);
 hipError_t launch_aggregate(const Dev& d, double* P, int nbasic, long ngrid, hipStream_t st);
 hipError_t launch_kl_chunks(const int* cp, const int* cs, const int* cl, const Prob* probs,
                             const double* P, const double* Pg, const double* nu, double* part,
@@ -146,10 +150,17 @@ struct dduot_handle {
   double* d_fall = nullptr;
   double* d_ydel = nullptr;
   double *d_mom = nullptr, *d_dy = nullptr;   // Y-position gradient (allocated on first use)
+  double* d_gtmp = nullptr;                   // scaled gradients for host destinations
   long long* d_kstep = nullptr;               // device copy of k
   // captured A+B step pair (hipGraph), replayed by dd_uot_iterate
   bool use_graph = false;
   int nt = 256;        // threads per cell workgroup (dd_uot_autotune)
+  // gangs for the wide cells (plain separable problems): G workgroups per
+  // cell, at most wpc workgroups of the gang kernel per CU
+  int gang_g = 4, gang_wpc = 2;
+  int gang_occ[2] = {0, 0}, n_cu = 0;   // occupancy of the variants minb = 1, 2
+  GangLaunch gl{0, 0, 1, 0};
+  int* d_gabort = nullptr;
   int max_tile = 0;    // largest composite tile (points)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -356,6 +367,21 @@ static int ensure_pools(dduot_handle* h, long state, long cand, long ws) {
 // found a pool too small (not expected under these bounds) left the cells
 // that did not fit (or, for the state pool, the whole state) unchanged:
 // DDUOT_ESLOT.
+// Launch shape of the gangs from gang_g and gang_wpc (G = 0 when gangs are
+// off or do not apply).
+static void gang_shape(dduot_handle* h) {
+  h->gl.G = 0;
+  h->gl.nwg = 0;
+  h->gl.minb = h->gang_wpc >= 2 ? 2 : 1;
+  const int occ = h->gang_occ[h->gl.minb - 1];
+  if (h->gang_g <= 0 || h->moved || h->balance || occ <= 0) return;
+  const int per = 8 * h->gang_g;
+  const int nwg = std::min(occ, h->gang_wpc) * h->n_cu / per * per;
+  if (nwg < per) return;
+  h->gl.G = h->gang_g;
+  h->gl.nwg = nwg;
+}
+
 static int check_pools(dduot_handle* h, int nhalf) {
   hipStream_t st = h->stream;
   HIPCHK(launch_bound_begin(h->d_bacc, h->d_bound, st));
@@ -375,7 +401,15 @@ static int check_pools(dduot_handle* h, int nhalf) {
   std::vector<int> fl(h->nprob, 0);
   HIPCHK(hipMemcpyAsync(bound, h->d_bound, sizeof(bound), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(fl.data(), h->d_capfail, sizeof(int) * h->nprob, hipMemcpyDeviceToHost, st));
+  int gab = 0;
+  if (h->d_gabort) HIPCHK(hipMemcpyAsync(&gab, h->d_gabort, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  if (gab) {
+    HIPCHK(hipMemsetAsync(h->d_gabort, 0, sizeof(int), st));
+    HIPCHK(hipStreamSynchronize(st));
+    return fail(DDUOT_EHIP, "a gang kernel wait ran past its limit (workgroups not co-resident); "
+                            "the wide cells of the steps since the last check were abandoned");
+  }
   auto want = [](long long n, long cap) { return n > cap ? (long)(n + n / 4) : 0L; };
   CHK(ensure_pools(h, want(bound[0], h->pool_cap), want(bound[1], h->cand_cap),
                    want(bound[2], h->ws_cap)));
@@ -490,7 +524,7 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
         break;
       }
   h->tcap = (fc <= 0 || fc >= h->cap) ? h->cap : fc;
-  HIPCHK(set_cell_lds_limit(lds_cell));
+  HIPCHK(set_cell_lds_limit(lds_cell, gang_lds_bytes(h->precision, h->cap)));
 
   // problems, basic cells, composite cells
   std::vector<int> basic_prob;
@@ -769,6 +803,31 @@ static int build(dduot_handle* h, int nprob, const dduot_config* cfgs, const dou
 
   Dev& d = h->d;
   d.lcap = h->cap;
+  // gangs: the wide cells' list, the gangs' slots and barrier counters, sized
+  // for the most workgroups the gang kernel can keep resident
+  {
+    int rate_khz = 0;
+    HIPCHK(hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+    const size_t lds_g = gang_lds_bytes(h->precision, h->cap);
+    HIPCHK(gang_occupancy(h->precision, 1, lds_g, &h->gang_occ[0]));
+    HIPCHK(gang_occupancy(h->precision, 2, lds_g, &h->gang_occ[1]));
+    h->gl.limit = (long long)std::max(rate_khz, 1000) * 2000;   // 2 s
+    const size_t nwg = (size_t)std::max(1, std::max(h->gang_occ[0], h->gang_occ[1])) *
+                       std::max(1, h->n_cu);
+    CHK(dalloc(h, &d.glist, h->cells.size()));
+    CHK(dalloc(h, &d.gcount, 3));
+    CHK(dalloc(h, &d.gpart, 2 * nwg * 256));
+    CHK(dalloc(h, &d.gxch, 2 * nwg * 16));
+    CHK(dalloc(h, &d.gcnt, nwg * 64));
+    CHK(dalloc(h, &h->d_gabort, 1));
+    HIPCHK(hipMemsetAsync(h->d_gabort, 0, sizeof(int), st));
+    HIPCHK(hipMemsetAsync(h->d_iters, 0, sizeof(int) * h->cells.size(), st));
+    CHK(dalloc(h, &d.gxcd, 32));
+    CHK(dalloc(h, &d.gsolo, nwg * (2 * 256 + 2 * 16)));
+    d.gabort = h->d_gabort;
+    gang_shape(h);
+  }
   // start state: block start = nu on the block; product start = |mu_i| nu,
   // written compactly into the first state pool
   {
@@ -875,6 +934,38 @@ static void release(dduot_handle* h) {
   delete h;
 }
 
+// Does p point to device (or managed) memory?  Host memory, registered or
+// not, gives false.
+static bool on_device(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();   // plain host memory is not known to HIP
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// Host copies of the inputs given in device memory (the set-up reads them on
+// the host: validation, masses, start state); host inputs are used in place.
+static int stage_inputs(int nprob, const dduot_config* cfgs, const double* const* in, int per_point,
+                        hipStream_t st, std::vector<std::vector<double>>& keep,
+                        std::vector<const double*>& out) {
+  out.assign(in, in + nprob);
+  keep.resize(nprob);
+  bool any = false;
+  for (int k = 0; k < nprob; ++k) {
+    if (!on_device(in[k])) continue;
+    const size_t n = (size_t)per_point * cfgs[k].n1 * cfgs[k].n2;
+    keep[k].resize(n);
+    HIPCHK(hipMemcpyAsync(keep[k].data(), in[k], sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    out[k] = keep[k].data();
+    any = true;
+  }
+  if (any) HIPCHK(hipStreamSynchronize(st));
+  return DDUOT_OK;
+}
+
 extern "C" int dd_uot_init_batch_moved(int32_t nprob, const dduot_config* cfgs,
                                        const double* const* mus, const double* const* nus,
                                        const double* const* ypos, void* hip_stream,
@@ -882,9 +973,17 @@ extern "C" int dd_uot_init_batch_moved(int32_t nprob, const dduot_config* cfgs,
   if (!out) return fail(DDUOT_EINVAL, "out is NULL");
   *out = nullptr;
   if (nprob < 1 || !cfgs || !mus || !nus) return fail(DDUOT_EINVAL, "need at least one problem");
+  for (int k = 0; k < nprob; ++k)
+    if (cfgs[k].n1 <= 0 || cfgs[k].n2 <= 0) return fail(DDUOT_EINVAL, "grid sides must be positive");
+  std::vector<std::vector<double>> km, kn, ky;
+  std::vector<const double*> hm, hn, hy;
+  const hipStream_t st0 = static_cast<hipStream_t>(hip_stream);
+  CHK(stage_inputs(nprob, cfgs, mus, 1, st0, km, hm));
+  CHK(stage_inputs(nprob, cfgs, nus, 1, st0, kn, hn));
+  if (ypos) CHK(stage_inputs(nprob, cfgs, ypos, 2, st0, ky, hy));
   dduot_handle* h = new dduot_handle();
-  h->stream = static_cast<hipStream_t>(hip_stream);
-  int r = build(h, nprob, cfgs, mus, nus, ypos);
+  h->stream = st0;
+  int r = build(h, nprob, cfgs, hm.data(), hn.data(), ypos ? hy.data() : nullptr);
   if (r != DDUOT_OK) {
     std::string keep = g_err;
     release(h);
@@ -969,7 +1068,8 @@ static int dd_step(dduot_handle* h, int part, int lo, int n, int blo, int bhi) {
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, st));
   }
-  HIPCHK(launch_cell_solve(d, lo, n, h->cap, h->tcap, h->precision, h->moved, h->balance, h->nt, st));
+  HIPCHK(launch_cell_solve(d, lo, n, h->cap, h->tcap, h->precision, h->moved, h->balance, h->nt, h->gl,
+                           st));
   if (h->timing) {
     HIPCHK(hipEventRecord(e1, st));
     h->events.push_back({e0, e1});
@@ -1090,7 +1190,9 @@ extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
     float t = 0.0f;
     hipError_t e = restore();
     if (e == hipSuccess) e = hipEventRecord(e0, st);
-    if (e == hipSuccess) e = launch_cell_solve(h->d, base, h->ncell[part], h->cap, h->tcap, h->precision, h->moved, h->balance, nt, st);
+    if (e == hipSuccess)
+      e = launch_cell_solve(h->d, base, h->ncell[part], h->cap, h->tcap, h->precision, h->moved,
+                            h->balance, nt, h->gl, st);
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
@@ -1116,6 +1218,20 @@ extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
   }
   if (chosen) *chosen = pick;
   return DDUOT_OK;
+}
+
+extern "C" int dd_uot_set_gang(dduot_handle* h, int32_t G, int32_t wgs_per_cu, int32_t* nwg) {
+  if (!h) return fail(DDUOT_EINVAL, "null handle");
+  if (G < 0 || G > 64 || wgs_per_cu < 1) return fail(DDUOT_EINVAL, "need 0 <= G <= 64, wgs_per_cu >= 1");
+  h->gang_g = G;
+  h->gang_wpc = wgs_per_cu;
+  gang_shape(h);
+  if (h->gexec) {   // the captured step used the old launch shape
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  if (nwg) *nwg = h->gl.nwg;
+  return h->gl.G;
 }
 
 extern "C" int dd_uot_set_graph(dduot_handle* h, int32_t enable) {
@@ -1295,8 +1411,8 @@ extern "C" int dd_uot_marginals(dduot_handle* h, int32_t prob, double* px, doubl
   const Prob& p = h->probs[prob];
   const long n = (long)p.n1 * p.n2;
   CHK(refresh_state_marginal(h));
-  if (px) HIPCHK(hipMemcpyAsync(px, h->d_px + p.grid_off, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
-  if (py) HIPCHK(hipMemcpyAsync(py, h->d_P + p.grid_off, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+  if (px) HIPCHK(hipMemcpyAsync(px, h->d_px + p.grid_off, sizeof(double) * n, hipMemcpyDefault, h->stream));
+  if (py) HIPCHK(hipMemcpyAsync(py, h->d_P + p.grid_off, sizeof(double) * n, hipMemcpyDefault, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return DDUOT_OK;
 }
@@ -1405,8 +1521,8 @@ extern "C" int dd_uot_potentials(dduot_handle* h, int32_t prob, double* alpha, d
   const Prob& p = h->probs[prob];
   const long n = (long)p.n1 * p.n2;
   if (beta_hat && !h->cert_done[prob]) return fail(DDUOT_ESTATE, "beta_hat needs dd_uot_score first");
-  if (alpha) HIPCHK(hipMemcpyAsync(alpha, h->d_abar + p.grid_off, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
-  if (beta_hat) HIPCHK(hipMemcpyAsync(beta_hat, h->d_bhat + p.grid_off, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+  if (alpha) HIPCHK(hipMemcpyAsync(alpha, h->d_abar + p.grid_off, sizeof(double) * n, hipMemcpyDefault, h->stream));
+  if (beta_hat) HIPCHK(hipMemcpyAsync(beta_hat, h->d_bhat + p.grid_off, sizeof(double) * n, hipMemcpyDefault, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return DDUOT_OK;
 }
@@ -1416,18 +1532,21 @@ extern "C" int dd_uot_backward(dduot_handle* h, int32_t prob, double gout, doubl
   if (!h->cert_done[prob]) return fail(DDUOT_ESTATE, "call dd_uot_score before dd_uot_backward");
   const Prob& p = h->probs[prob];
   const long n = (long)p.n1 * p.n2;
-  std::vector<double> tmp;
-  if (dmu) {
-    HIPCHK(hipMemcpyAsync(dmu, h->d_dmu + p.grid_off, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
-  }
-  if (dnu) {
-    HIPCHK(hipMemcpyAsync(dnu, h->d_dnu + p.grid_off, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+  // gout * gradient on the device: into a device destination directly, else
+  // into a device buffer copied out
+  if ((dmu && !on_device(dmu)) || (dnu && !on_device(dnu)))
+    if (!h->d_gtmp) CHK(dalloc(h, &h->d_gtmp, 2 * (size_t)h->maxgrid));
+  double* outs[2] = {dmu, dnu};
+  const double* src[2] = {h->d_dmu + p.grid_off, h->d_dnu + p.grid_off};
+  for (int q = 0; q < 2; ++q) {
+    if (!outs[q]) continue;
+    const bool dev = on_device(outs[q]);
+    double* dst = dev ? outs[q] : h->d_gtmp + (size_t)q * h->maxgrid;
+    HIPCHK(launch_scale_copy(dst, src[q], n, gout, h->stream));
+    if (!dev)
+      HIPCHK(hipMemcpyAsync(outs[q], dst, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
   }
   HIPCHK(hipStreamSynchronize(h->stream));
-  if (gout != 1.0) {
-    for (long i = 0; dmu && i < n; ++i) dmu[i] *= gout;
-    for (long i = 0; dnu && i < n; ++i) dnu[i] *= gout;
-  }
   return DDUOT_OK;
 }
 
@@ -1443,7 +1562,7 @@ extern "C" int dd_uot_backward_ypos(dduot_handle* h, int32_t prob, double gout, 
   HIPCHK(launch_grad_ypos(p, h->d_abar + g, h->d_mu + g, h->d_nu + g,
                           h->moved ? h->d_ydel + 2 * g : nullptr, h->d_bhat + g, gout, h->d_scratch,
                           h->d_mom, h->d_dy, h->stream));
-  HIPCHK(hipMemcpyAsync(dypos, h->d_dy, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(dypos, h->d_dy, sizeof(double) * 2 * n, hipMemcpyDefault, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return DDUOT_OK;
 }
@@ -1481,6 +1600,28 @@ extern "C" int dd_uot_kernel_time(dduot_handle* h, int64_t* launches, double* to
   if (total_ms) *total_ms = ms;
   if (algo_bytes) *algo_bytes = bytes;
   return DDUOT_OK;
+}
+
+extern "C" int dd_uot_cell_stats(dduot_handle* h, int32_t part, int32_t max, int32_t* boxes,
+                                 int32_t* iters, double* terms) {
+  if (!h) return fail(DDUOT_EINVAL, "null handle");
+  if (part != 0 && part != 1) return fail(DDUOT_EINVAL, "part must be 0 (A) or 1 (B)");
+  const int base = h->boff[part][0], n = h->ncell[part];
+  if (max < n) return fail(DDUOT_EINVAL, "max smaller than the partition's cell count");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (boxes) {
+    std::vector<Box> b(n);
+    HIPCHK(hipMemcpy(b.data(), h->d_cellbox + base, sizeof(Box) * n, hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i) {
+      boxes[4 * i] = b[i].o1;
+      boxes[4 * i + 1] = b[i].o2;
+      boxes[4 * i + 2] = b[i].l1;
+      boxes[4 * i + 3] = b[i].l2;
+    }
+  }
+  if (iters) HIPCHK(hipMemcpy(iters, h->d_iters + base, sizeof(int) * n, hipMemcpyDeviceToHost));
+  if (terms) HIPCHK(hipMemcpy(terms, h->d_terms + base, sizeof(double) * n, hipMemcpyDeviceToHost));
+  return n;
 }
 
 // ---------------------------------------------------------------------------

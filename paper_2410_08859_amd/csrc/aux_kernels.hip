@@ -728,6 +728,18 @@ hipError_t launch_fill(double* p, long n, double v, hipStream_t st) {
 
 static int grid_blocks(long n) { return (int)min((n + 255) / 256, (long)8192); }
 
+// dst = a * src over n doubles (the gradient times the caller's seed).
+__global__ void k_scale_copy(double* dst, const double* src, long n, double a) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = a * src[i];
+}
+
+hipError_t launch_scale_copy(double* dst, const double* src, long n, double a, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_copy, dim3(grid_blocks(n)), dim3(256), 0, st, dst, src, n, a);
+  return hipGetLastError();
+}
+
 // P over all problems' grids (ngrid points) from the candidate marginals of
 // the cells in [glo, ghi) and the state marginals of every other cell.
 hipError_t launch_aggregate_sel(const Dev& d, int part, int glo, int ghi, double* P, int nbasic,

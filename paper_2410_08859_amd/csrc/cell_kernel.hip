@@ -632,18 +632,170 @@ __device__ void balance_cell(double* candJ, const Cell& C, const Prob& P, const 
   __syncthreads();
 }
 
-// kBal: the variant with the balancing step (separable cost only); the
-// plain variant keeps its own register allocation.  kBig: the variant for
-// boxes wider than the in-LDS layouts (box arrays in the cell's workspace).
-// tier 0: every cell whose box fits d.lcap, LDS layout of d.lcap; tier 1: the
-// cells whose box fits tcap, layout of tcap; tier 2: the cells between tcap
-// and d.lcap, layout of d.lcap; tier 3 (kBig): the cells wider than d.lcap.
-template <typename R, bool kMoved, int NT, bool kBal = false, bool kBig = false>
-__global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) void k_cell_solve(
-    Dev d, int cell_base, int tcap, int tier) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+// ---- gangs: one wide cell solved by G co-resident workgroups --------------
+// Member m of a gang owns the box rows [L1 m / G, L1 (m + 1) / G) (b, z, the
+// X pass 1 rows, the Newton updates, the re-split candidates) and the box
+// columns [L2 m / G, L2 (m + 1) / G) of the Y pass 1 outputs, which every
+// member reads.  Tile-sized work (the X potential, the stopping rule, the
+// translation step) is done by every member on identical data, so all
+// members take the same branches and meet at the same barriers.  Partial
+// results cross workgroups through the gang's slots, double-buffered by
+// barrier parity: a slot written for barrier e is read after it, and the
+// next write to it comes after barrier e + 1, which no member passes before
+// every member has finished reading.
+//
+// Coherence.  The members of a gang sit on one XCD (k_cell_gang forms the
+// gangs from the XCD id register), so they share one L2, which is the point
+// of coherence among them: a member's
+// stores reach that L2 before it arrives at a barrier (every wave waits for
+// its stores), and every read of another member's data after a barrier
+// bypasses the CU's L1 (agent-scope loads).  No L2 writeback or invalidate
+// is needed, which other gangs on the XCD would pay for.
+constexpr int kGangUmax = 512;   // widest box (columns) a gang solves: its LDS copy
+
+struct Gang {
+  int G, m;
+  double* part;      // [2][G][256]: X pass 2 partial sums or maxima per tile point
+  double* xch;       // [2][G][16]: partial reductions
+  unsigned* cnt;     // arrivals at this gang's barriers (zero at launch)
+  int* abort_flag;   // launch-wide: some wait timed out
+  int* lflag;        // LDS: the last barrier's outcome
+  long long limit;   // wall-clock ticks a barrier may wait
+  unsigned epoch;    // barriers passed
+};
+
+// Load of data another member of the gang wrote before the last barrier:
+// an agent-scope load, which misses the CU's L1 and reads the XCD's L2.
+__device__ __forceinline__ double gang_ld(const double* p) {
+  const unsigned long long v =
+      __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __longlong_as_double((long long)v);
+}
+
+// Barrier of the G workgroups of one gang.  The launch keeps every workgroup
+// resident (grid within the occupancy), so every wait ends; the wait is
+// still bounded: past `limit` ticks it flags the launch and returns false,
+// and so does every later wait, so every workgroup leaves (the host reports
+// the failed step).
+__device__ __forceinline__ bool gang_sync(Gang& g) {
+  __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have reached the L2
+  __syncthreads();
+  if (g.G == 1) {   // a workgroup on its own: its waves only
+    g.epoch += 1u;
+    return true;
+  }
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned target = (g.epoch + 1u) * (unsigned)g.G;
+    __hip_atomic_fetch_add(g.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long t0 = wall_clock64();
+    while (__hip_atomic_load(g.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(g.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          wall_clock64() - t0 > g.limit) {
+        __hip_atomic_store(g.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    *g.lflag = ok;
+  }
+  __syncthreads();
+  g.epoch += 1u;
+  return *g.lflag != 0;
+}
+
+// v[lo, N) summed over the gang's members in member order (every member
+// gets the same bits).  Call with identical N and lo in every member.
+template <int N>
+__device__ bool gang_sum(Gang& g, double (&v)[N], int lo) {
+  static_assert(N <= 16, "gang_sum: at most 16 values");
+  double* slot = g.xch + (size_t)(g.epoch & 1u) * g.G * 16;
+  if (threadIdx.x == 0)
+    for (int k = lo; k < N; ++k) slot[g.m * 16 + k] = v[k];
+  if (!gang_sync(g)) return false;
+  for (int k = lo; k < N; ++k) {
+    double a = 0.0;
+    for (int q = 0; q < g.G; ++q) a += gang_ld(slot + q * 16 + k);
+    v[k] = a;
+  }
+  return true;
+}
+
+// X pass 2 partial over the rows [k0, k1): sum of exp(base_k - shift -
+// ch (k - c)^2) in R, terms below e^-W of the shift skipped (window from the
+// rows' maximum bmax); 0 when there is none.
+template <typename R>
+__device__ __forceinline__ R lse_partial(const double* base, int stride, int k0, int k1, double c,
+                                         double ch, float ichf, const R* qc, int qlim,
+                                         double shift, double bmax) {
+  constexpr double W = sizeof(R) == 8 ? 60.0 : 40.0;
+  if (!(bmax > -INFINITY) || k1 <= k0) return R(0);
+  int a = k0, b = k1;
+  if (ch > 0.0) {
+    const float r2 = (float)(bmax - shift + W) * ichf;
+    if (r2 < 0.0f) return R(0);
+    const float rr = fminf(__fsqrt_rn(r2), 1e6f) + 1e-3f, cf = (float)c;
+    a = max(k0, (int)ceilf(cf - rr));
+    b = min(k1, (int)floorf(cf + rr) + 1);
+  }
+  const R sc = M<R>::kScale;
+  R acc0 = R(0), acc1 = R(0);
+  const int ci = (int)c;
+  if (a < b && a - ci >= -qlim && b - 1 - ci <= qlim) {
+    const R* q = qc + (a - ci);
+    const double* p = base + (long)a * stride;
+    int k = a;
+    for (; k + 2 <= b; k += 2, p += 2 * stride, q += 2) {
+      acc0 += M<R>::ex2s(R(p[0] - shift) * sc + q[0]);
+      acc1 += M<R>::ex2s(R(p[stride] - shift) * sc + q[1]);
+    }
+    if (k < b) acc0 += M<R>::ex2s(R(p[0] - shift) * sc + q[0]);
+  } else {
+    const R chs = R(ch) * sc;
+    R dk = R(a - ci);
+    const double* p = base + (long)a * stride;
+    for (int k = a; k < b; ++k, p += stride, dk += R(1))
+      acc0 += M<R>::ex2s(R(p[0] - shift) * sc - chs * dk * dk);
+  }
+  return acc0 + acc1;
+}
+
+// Exact pieces of the X pass 2 over the rows [k0, k1): the maximum of
+// base_k - ch (k - c)^2 in FP64, and the sum of exp of the terms minus m.
+__device__ __forceinline__ double rows_max(const double* base, int stride, int k0, int k1, double c,
+                                           double ch) {
+  double m = -INFINITY;
+  for (int k = k0; k < k1; ++k) {
+    const double d = k - c;
+    m = fmax(m, base[k * stride] - ch * d * d);
+  }
+  return m;
+}
+template <typename R>
+__device__ __forceinline__ double rows_sum(const double* base, int stride, int k0, int k1, double c,
+                                           double ch, double m) {
+  R acc = R(0);
+  for (int k = k0; k < k1; ++k) {
+    const double d = k - c;
+    acc += M<R>::ex(R(base[k * stride] - ch * d * d - m));
+  }
+  return (double)acc;
+}
+
+// The solve of composite cell ci by one workgroup, or (kGang) by member
+// g->m of a gang.  kBal: the variant with the balancing step (separable cost
+// only); the plain variant keeps its own register allocation.  kBig: the
+// variant for boxes wider than the in-LDS layouts (box arrays in the cell's
+// workspace).  tier 0: every cell whose box fits d.lcap, LDS layout of
+// d.lcap; tier 1: the cells whose box fits tcap, layout of tcap; tier 2: the
+// cells between tcap and d.lcap, layout of d.lcap; tier 3 (kBig): the cells
+// wider than d.lcap.  Returns false only when a gang barrier failed.
+template <typename R, bool kMoved, int NT, bool kBal, bool kBig, bool kGang>
+__device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int tier, Gang* g,
+                                          unsigned char* smem_raw) {
+  static_assert(!kGang || (kBig && !kMoved && !kBal), "gangs solve plain separable wide cells");
   const int t = threadIdx.x;
-  const int ci = cell_base + blockIdx.x;
   const Cell C = d.cells[ci];
   const Prob P = d.probs[C.prob];
   const int lcap = d.lcap;
@@ -653,9 +805,15 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
   const int o1 = yb.o1, o2 = yb.o2, L1 = yb.l1, L2 = yb.l2;
   const int NY = L1 * L2;
   const int side = max(L1, L2);
-  if (kBig ? side <= lcap
+  if (kBig ? (side <= lcap || (!kGang && L2 <= d.gumax))
            : (side > lcap || (tier == 1 && side > tcap) || (tier == 2 && side <= tcap)))
-    return;
+    return true;
+  // this workgroup's box rows [r0, r1) and Y pass 1 columns [c0, c1)
+  const int gG = kGang ? g->G : 1, gm = kGang ? g->m : 0;
+  const int r0 = L1 * gm / gG, r1 = L1 * (gm + 1) / gG;
+  const int c0 = L2 * gm / gG, c1 = L2 * (gm + 1) / gG;
+  const int ya = r0 * L2, yz = r1 * L2;   // box points of the rows
+  const bool lead = gm == 0;              // writes the cell's outputs
   const int lx1 = C.lx1, lx2 = C.lx2, lx = lx1 * lx2;
   const int s = P.s;
   // candidate marginals and workspace from the step's pools; a step whose
@@ -664,7 +822,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
   const long woff = d.wsize[ci];
   const WsLayout wl = cell_ws_layout((int)sizeof(R), NY, side, kMoved, kBig);
   if (coff + (long)C.nb * NY > d.cand_cap || woff + (long)wl.total > d.ws_cap) {
-    if (t == 0) {
+    if (t == 0 && lead) {
       d.cell_iters[ci] = -1;
       d.cell_conv[ci] = 0;
       d.cell_bytes[ci] = 0.0;
@@ -672,7 +830,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
       d.cell_fall[ci] = 0.0;
       d.cap_fail[C.prob] = 1;
     }
-    return;
+    return true;
   }
   double* candJ = d.cand + coff;
   unsigned char* wsc = d.ws + woff;
@@ -727,7 +885,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
   // back to the whole box.  acc0: |mu_J|, then |nu_{-J}| and the sum of
   // e^{-beta0/lam} nu over the support, the same over the box, support size.
   double acc0[6] = {mux, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int o = t; o < NY; o += NT) {
+  for (int o = ya + t; o < yz; o += NT) {
     const int j1 = o / L2, j2 = o - j1 * L2;
     const int y1 = o1 + j1, y2 = o2 + j2;
     const long g = (long)y1 * P.n2 + y2;
@@ -767,9 +925,11 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
     }
   }
   block_sum<NT, 6>(acc0, red);
+  if constexpr (kGang)
+    if (!gang_sum(*g, acc0, 1)) return false;
   if (!(acc0[5] > 0.0) && P.support) {
     // empty support: the whole box
-    for (int o = t; o < NY; o += NT) {
+    for (int o = ya + t; o < yz; o += NT) {
       const long g = (long)(o1 + o / L2) * P.n2 + (o2 + o % L2);
       const double pv = Pst[g], nv = nu[g];
       const double lnv = sizeof(R) == 4 ? (double)S.lnvf[o] : wlnv[o];
@@ -789,6 +949,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
   // Returns S for the thread's point; sprev is that point's previous S.
   bool have_x = false;
   double xext = 0.0;   // expected move of the X-half outputs since the last X-half
+  bool gfail = false;  // a gang barrier failed (the cell is abandoned)
   auto x_half = [&](double sprev) -> double {
     if constexpr (kMoved) {
       // dense: tile point xi summed over the box by np threads, each over a
@@ -851,22 +1012,74 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
       __syncthreads();
       return sv;
     } else {
-      seg_max<NT, 8>(S.bd, L1, L2, L2, 1, S.Mr);
+      // pass 1 over the rows [r0, r1) (a gang member's rows; all rows otherwise)
+      seg_max<NT, 8>(S.bd + ya, r1 - r0, L2, L2, 1, S.Mr + r0);
       __syncthreads();
-      for (int o = t; o < L1 * lx2; o += NT) {
+      for (int o = r0 * lx2 + t; o < r1 * lx2; o += NT) {
         const int j1 = o / lx2, i2 = o - j1 * lx2;
         S.Tt[o] = lse_pass<R>(S.bd + j1 * L2, 1, 0, L2, (double)(D2 + i2), ch, ichf, qc, lcap, have_x,
                               S.Tt[o] + xext,
                               S.Mr[j1], nfall);
       }
       __syncthreads();
-      seg_max<NT, 16>(S.Tt, lx2, L1, 1, lx2, S.Mc);
+      seg_max<NT, 16>(S.Tt + r0 * lx2, lx2, r1 - r0, 1, lx2, S.Mc);
       __syncthreads();
       double sv = 0.0;
-      if (t < lx)
-        sv = lse_pass<R>(S.Tt + ti2, lx2, 0, L1, (double)(D1 + ti1), ch, ichf, qc, lcap, have_x, sprev + xext,
-                         S.Mc[ti2],
-                         nfall);
+      if constexpr (kGang) {
+        // pass 2: the members' shifted partial sums over their rows, added in
+        // member order; outputs whose sum leaves [e^-22, e^60] (or without a
+        // shift) are recomputed exactly from the maximum over all rows
+        const double shift = sprev + xext;
+        double* pb = g->part + (size_t)(g->epoch & 1u) * gG * 256;
+        if (t < lx)
+          pb[gm * 256 + t] = have_x ? (double)lse_partial<R>(S.Tt + ti2, lx2, r0, r1, (double)(D1 + ti1),
+                                                             ch, ichf, qc, lcap, shift, S.Mc[ti2])
+                                    : 0.0;
+        if (!gang_sync(*g)) {
+          gfail = true;
+          return 0.0;
+        }
+        int need = 0;
+        if (t < lx) {
+          double a = 0.0;
+          for (int q = 0; q < gG; ++q) a += gang_ld(pb + q * 256 + t);
+          if (have_x && a > 2.8e-10 && a < 1.1e26)
+            sv = shift + log(a);
+          else
+            need = 1;
+        }
+        if (__syncthreads_or(need)) {
+          double* pm = g->part + (size_t)(g->epoch & 1u) * gG * 256;
+          if (t < lx)
+            pm[gm * 256 + t] = need ? rows_max(S.Tt + ti2, lx2, r0, r1, (double)(D1 + ti1), ch) : -INFINITY;
+          if (!gang_sync(*g)) {
+            gfail = true;
+            return 0.0;
+          }
+          double mx = -INFINITY;
+          if (t < lx && need)
+            for (int q = 0; q < gG; ++q) mx = fmax(mx, gang_ld(pm + q * 256 + t));
+          double* ps = g->part + (size_t)(g->epoch & 1u) * gG * 256;
+          if (t < lx)
+            ps[gm * 256 + t] = (need && mx > -INFINITY)
+                                   ? rows_sum<R>(S.Tt + ti2, lx2, r0, r1, (double)(D1 + ti1), ch, mx)
+                                   : 0.0;
+          if (!gang_sync(*g)) {
+            gfail = true;
+            return 0.0;
+          }
+          if (t < lx && need) {
+            double a = 0.0;
+            for (int q = 0; q < gG; ++q) a += gang_ld(ps + q * 256 + t);
+            sv = mx > -INFINITY ? mx + log(a) : mx;
+            if (lead) nfall += 1.0;
+          }
+        }
+      } else {
+        if (t < lx)
+          sv = lse_pass<R>(S.Tt + ti2, lx2, 0, L1, (double)(D1 + ti1), ch, ichf, qc, lcap, have_x,
+                           sprev + xext, S.Mc[ti2], nfall);
+      }
       have_x = true;
       xext = 0.0;
       __syncthreads();
@@ -884,6 +1097,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
     if (t < lx) aeps = d.abar[P.grid_off + gx] / eps;
   } else {
     Sx = x_half(0.0);
+    if (gfail) return false;
     aeps = -kap * Sx;
   }
 
@@ -909,14 +1123,31 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
       __syncthreads();
     }
   };
+  // a gang member's LDS copy of the Y pass 1 outputs (L2 <= kGangUmax)
+  double* Ul = nullptr;
+  if constexpr (kGang)
+    Ul = (double*)(smem_raw + cell_lds_layout<R>(0, lcap, false, true, nullptr, nullptr));
   // Y pass 1 over tile columns [ib, ie): Uo(i1, j2) = LSE_i2 [a - ch (i2 - (j2 - D2))^2]
-  auto y_pass1 = [&](double* Uo, int ib, int ie, bool have, double extra) {
-    for (int o = t; o < lx1 * L2; o += NT) {
-      const int i1 = o / L2, j2 = o - i1 * L2;
+  // for the box columns [c0, c1) (a gang member's columns; all otherwise);
+  // false when a gang barrier failed
+  auto y_pass1 = [&](double* Uo, int ib, int ie, bool have, double extra) -> bool {
+    const int w = c1 - c0;
+    for (int q = t; q < lx1 * w; q += NT) {
+      const int i1 = q / w, j2 = c0 + (q - i1 * w);
+      const int o = i1 * L2 + j2;
       Uo[o] = lse_full<R>(S.adr + i1 * lx2, 1, ib, ie, (double)(j2 - D2), ch, qc, lcap, have,
                           Uo[o] + extra, nfall);
     }
-    __syncthreads();
+    if constexpr (kGang) {
+      // every member reads all columns: a copy in LDS (agent-scope loads)
+      if (!gang_sync(*g)) return false;
+      for (int q = t; q < lx1 * L2; q += NT) Ul[q] = gang_ld(Uo + q);
+      __syncthreads();
+      return true;
+    } else {
+      __syncthreads();
+      return true;
+    }
   };
 
   for (;;) {
@@ -943,23 +1174,26 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
       aeps += sh;
       ushift += sh;
       xext -= sh;   // b = beta/eps + log nu moves by about -s/eps through the Y-half
-      for (int o = t; o < NY; o += NT) S.bd[o] -= sh;
+      for (int o = ya + t; o < yz; o += NT) S.bd[o] -= sh;
       __syncthreads();
     }
     // ---- Y-half: z by two passes, Newton per point --------------------------
     y_prepare();
-    if constexpr (!kMoved) y_pass1(S.Ud, 0, lx2, have_y, ushift);
-    for (int o = t; o < NY; o += NT) {
+    if constexpr (!kMoved)
+      if (!y_pass1(S.Ud, 0, lx2, have_y, ushift)) return false;
+    for (int o = ya + t; o < yz; o += NT) {
+      // outside the cell's Y-domain (b = -inf for the whole solve): no plan
+      // mass, and its z is never read
+      if (!(S.bd[o] > -INFINITY)) continue;
       const int j1 = o / L2, j2 = o - j1 * L2;
       double z;
       if constexpr (kMoved)
         z = dense_y_lse<R>(S.adr, S.Ma, lx1, lx2, (double)D1, (double)D2, j1 + (double)S.dl1[o],
                            j2 + (double)S.dl2[o], ch, have_y, S.zp[o] + ushift, nfall);
       else
-        z = lse_full<R>(S.Ud + j2, L2, 0, lx1, (double)(j1 - D1), ch, qc, lcap, have_y,
+        z = lse_full<R>((kGang ? Ul : S.Ud) + j2, L2, 0, lx1, (double)(j1 - D1), ch, qc, lcap, have_y,
                         S.zp[o] + ushift, nfall);
       S.zp[o] = R(z);
-      if (!(S.bd[o] > -INFINITY)) continue;   // outside the cell's Y-domain
       double lnv, lrr;
       if constexpr (sizeof(R) == 4) {
         lnv = (double)S.lnvf[o];
@@ -980,6 +1214,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
 
     // ---- next X-half (gives P_X of the pair for the stopping rule) ----------
     const double Sn = x_half(Sx);
+    if (gfail) return false;
     Sfin = Sn;
     double term = 0.0;
     if (t < lx) {
@@ -1020,14 +1255,20 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
   for (int k = 0; k < 8; ++k) accy[k] = 0.0;
   for (int c = 0; c < nc; ++c) {
     double* Uo = c == 0 ? S.Ud : S.Tt;
-    if constexpr (!kMoved) y_pass1(Uo, c * s, (c + 1) * s, false, 0.0);
-    for (int o = t; o < NY; o += NT) {
+    if constexpr (!kMoved)
+      if (!y_pass1(Uo, c * s, (c + 1) * s, false, 0.0)) return false;
+    for (int o = ya + t; o < yz; o += NT) {
       const int j1 = o / L2, j2 = o - j1 * L2;
       const double beta =
           eps * (S.bd[o] - (sizeof(R) == 4 ? (double)S.lnvf[o] : wlnv[o]));
+      const bool dom = S.bd[o] > -INFINITY;   // in the cell's Y-domain (z defined)
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (k >= C.nb || kc[k] != c) continue;
+        if (!dom) {
+          candJ[(long)k * NY + o] = bal ? -INFINITY : 0.0;
+          continue;
+        }
         double zk;
         if constexpr (kMoved) {
           const R a = dense_y_sum<R>(S.adr, S.Ma, lx2, kr[k] * s, (kr[k] + 1) * s, kc[k] * s,
@@ -1036,7 +1277,7 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
                                      sizeof(R) == 8 ? 60.0 : 40.0);
           zk = a > R(0) ? S.zp[o] + (double)M<R>::lg(a) : -INFINITY;
         } else {
-          zk = lse_full<R>(Uo + j2, L2, kr[k] * s, (kr[k] + 1) * s, (double)(j1 - D1), ch, qc, lcap,
+          zk = lse_full<R>((kGang ? Ul : Uo) + j2, L2, kr[k] * s, (kr[k] + 1) * s, (double)(j1 - D1), ch, qc, lcap,
                            true, S.zp[o], nfall);
         }
         if (bal) {
@@ -1078,12 +1319,25 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
       accx[4 + q] = pxb > 0.0 ? mux * (e * lpb - e + 1.0) : mux;
       accx[8 + q] = mux;
     }
-    d.pxc[P.grid_off + gx] = pxb;
-    d.abar[P.grid_off + gx] = alpha;
+    if (lead) {
+      d.pxc[P.grid_off + gx] = pxb;
+      d.abar[P.grid_off + gx] = alpha;
+    }
   }
   accx[12] = nfall;
   block_sum<NT, 13>(accx, red);
-  if (t == 0) {
+  if constexpr (kGang) {
+    // the members' Y sums (their rows) and recomputation counts
+    double gx9[9];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) gx9[k] = accy[k];
+    gx9[8] = accx[12];
+    if (!gang_sum(*g, gx9, 0)) return false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) accy[k] = gx9[k];
+    accx[12] = gx9[8];
+  }
+  if (t == 0 && lead) {
     double bytes = 8.0 * (2.0 * NY + 3.0 * lx + (double)C.nb * NY);
     for (int k = 0; k < C.nb; ++k) {
       const int b = C.basic[k];
@@ -1106,7 +1360,159 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) v
     d.cell_terms[ci] = it * (xh + yh) + xh + rs;
     d.cell_fall[ci] = accx[12];
   }
+  return true;
 }
+
+template <typename R, bool kMoved, int NT, bool kBal = false, bool kBig = false>
+__global__ __launch_bounds__(NT, (sizeof(R) == 4 && !kMoved && !kBig) ? 3 : 1) void k_cell_solve(
+    Dev d, int cell_base, int tcap, int tier) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cell_body<R, kMoved, NT, kBal, kBig, false>(d, cell_base + blockIdx.x, tcap, tier, nullptr, smem_raw);
+}
+
+// Gangs of G workgroups solve the heavy wide cells of the list (k_gang_list),
+// gang k the cells k, k + ngang, ...; then every workgroup alone solves the
+// light ones, taking the next from a queue (no waits on other workgroups).
+// A gang's members must share an XCD (its L2 is their point of coherence),
+// and the dispatcher's placement of workgroups on XCDs is not assumed: every
+// workgroup reads its XCD id and takes the next slot on that XCD; once all
+// workgroups have arrived (the grid is within the kernel's occupancy, so all
+// are resident at once; the wait is bounded like a gang barrier), each XCD's
+// slots form floor(count / G) gangs of consecutive slots, numbered XCD after
+// XCD, and the workgroups left over only take light cells.
+// MINB: workgroups per CU the register allocation must allow (1: no
+// spills; 2: twice the workgroups, a few spills).
+template <typename R, int MINB>
+__global__ __launch_bounds__(256, MINB) void k_cell_gang(Dev d, int G, long long limit) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int lflag, sh_gang, sh_m, sh_ngang;
+  const int nwg = (int)gridDim.x;
+  if (threadIdx.x == 0) {
+    const int xcc = __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 15;   // HW_REG_XCC_ID
+    const unsigned slot = atomicAdd(&d.gxcd[xcc], 1u);
+    __hip_atomic_fetch_add(&d.gxcd[16], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    const long long t0 = wall_clock64();
+    while (__hip_atomic_load(&d.gxcd[16], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)nwg) {
+      if (__hip_atomic_load(d.gabort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          wall_clock64() - t0 > limit) {
+        __hip_atomic_store(d.gabort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    int gang = -1, m = 0, ngang = 0;
+    if (ok) {
+      for (int x = 0; x < 16; ++x) {
+        const int full = (int)__hip_atomic_load(&d.gxcd[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / G;
+        if (x == xcc && (int)slot < full * G) {
+          gang = ngang + (int)slot / G;
+          m = (int)slot % G;
+        }
+        ngang += full;
+      }
+    }
+    lflag = ok;
+    sh_gang = gang;
+    sh_m = m;
+    sh_ngang = ngang;
+  }
+  __syncthreads();
+  if (!lflag) return;
+  const int gang = sh_gang, m = sh_m, ngang = sh_ngang;
+  const int n = d.gcount[0], nheavy = ngang > 0 ? d.gcount[1] : 0;
+  if (gang >= 0) {
+    Gang g;
+    g.G = G;
+    g.m = m;
+    g.part = d.gpart + (size_t)gang * 2 * G * 256;
+    g.xch = d.gxch + (size_t)gang * 2 * G * 16;
+    g.cnt = d.gcnt + (size_t)gang * 64;
+    g.abort_flag = d.gabort;
+    g.lflag = &lflag;
+    g.limit = limit;
+    g.epoch = 0u;
+    for (int q = gang; q < nheavy; q += ngang)
+      if (!cell_body<R, false, 256, false, true, true>(d, d.glist[q], 0, 3, &g, smem_raw)) return;
+  }
+  Gang solo;
+  solo.G = 1;
+  solo.m = 0;
+  solo.part = d.gsolo + (size_t)blockIdx.x * (2 * 256 + 2 * 16);
+  solo.xch = solo.part + 2 * 256;
+  solo.cnt = nullptr;
+  solo.abort_flag = d.gabort;
+  solo.lflag = &lflag;
+  solo.limit = limit;
+  solo.epoch = 0u;
+  __shared__ int qnext;
+  for (;;) {   // the light cells from a queue, heaviest first
+    if (threadIdx.x == 0) qnext = nheavy + atomicAdd(&d.gcount[2], 1);
+    __syncthreads();
+    const int q = qnext;
+    __syncthreads();
+    if (q >= n) break;
+    if (!cell_body<R, false, 256, false, true, true>(d, d.glist[q], 0, 3, &solo, smem_raw)) return;
+  }
+}
+
+// The wide cells of [cell_base, cell_base + ncell) for the gang kernel (at
+// most kGangUmax box columns; wider ones keep one workgroup each), heaviest
+// first: keyed by the work estimate w = box points x the iterations of the
+// cell's previous solve, in half-octave buckets (the order inside a bucket
+// is arbitrary; no cell's result depends on it).  The heavy cells, solved by
+// whole gangs, are the buckets down to the one holding the even share
+// sum(w) / nwg of one workgroup: a lighter cell alone does not lengthen the
+// launch.  gcount[0]: cells, gcount[1]: heavy cells, gcount[2]: the light
+// cells' queue head.  Also clears the gangs' barrier counters and the XCD
+// slot counters of the gang formation.
+__global__ __launch_bounds__(1024) void k_gang_list(Dev d, int cell_base, int ncell, int ngang,
+                                                    int nwg) {
+  __shared__ int hist[64], off[64];
+  __shared__ double wsum[16];
+  const int t = threadIdx.x;
+  for (int i = t; i < ngang; i += 1024) d.gcnt[(size_t)i * 64] = 0u;
+  if (t < 32) d.gxcd[t] = 0u;
+  if (t < 64) hist[t] = 0;
+  __syncthreads();
+  auto work = [&](int ci) -> double {
+    const Box yb = d.cellbox[ci];
+    if (max(yb.l1, yb.l2) <= d.lcap || yb.l2 > kGangUmax) return -1.0;
+    return (double)yb.l1 * yb.l2 * (double)max(d.cell_iters[ci], 1);
+  };
+  auto bucket_of = [](double w) { return 63 - min(63, (int)(2.0 * log2(w))); };
+  double mine = 0.0;
+  for (int j = t; j < ncell; j += 1024) {
+    const double w = work(cell_base + j);
+    if (w < 0.0) continue;
+    atomicAdd(&hist[bucket_of(w)], 1);
+    mine += w;
+  }
+  for (int o = 32; o > 0; o >>= 1) mine += __shfl_down(mine, o, 64);
+  if ((t & 63) == 0) wsum[t >> 6] = mine;
+  __syncthreads();
+  if (t == 0) {
+    double tot = 0.0;
+    for (int k = 0; k < 16; ++k) tot += wsum[k];
+    const int kthr = tot > 0.0 ? bucket_of(fmax(tot / nwg, 1.0)) : 63;
+    int a = 0, heavy = 0;
+    for (int k = 0; k < 64; ++k) {
+      off[k] = a;
+      a += hist[k];
+      if (k <= kthr) heavy = a;
+    }
+    d.gcount[0] = a;
+    d.gcount[1] = heavy;
+    d.gcount[2] = 0;
+  }
+  __syncthreads();
+  for (int j = t; j < ncell; j += 1024) {
+    const double w = work(cell_base + j);
+    if (w >= 0.0) d.glist[atomicAdd(&off[bucket_of(w)], 1)] = cell_base + j;
+  }
+}
+
 
 size_t cell_lds_bytes(int lcap, int cap, int precision, bool moved, bool big) {
   if (precision == 64) return cell_lds_layout<double>(lcap, cap, moved, big, nullptr, nullptr);
@@ -1278,15 +1684,53 @@ static void launch_kind(const Dev& d, int cell_base, int ncells, size_t lds, int
   }
 }
 
+// LDS of the gang kernel: the wide-cell layout, then the copy of the Y pass 1
+// outputs (16 x kGangUmax doubles).
+size_t gang_lds_bytes(int precision, int lcap) {
+  return cell_lds_bytes(0, lcap, precision, false, true) + (size_t)kMaxTile * kGangUmax * 8;
+}
+
+// Workgroups of the gang kernel (variant minb) that fit one CU at once.
+hipError_t gang_occupancy(int precision, int minb, size_t lds, int* occ) {
+  if (precision == 64)
+    return minb >= 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_cell_gang<double, 2>, 256, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_cell_gang<double, 1>, 256, lds);
+  return minb >= 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_cell_gang<float, 2>, 256, lds)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_cell_gang<float, 1>, 256, lds);
+}
+
 // The cell solves of [cell_base, cell_base + ncells) after k_cell_prep: the
 // cells wider than the in-LDS layouts (lcap) first, with their arrays in the
-// workspace; then, when tcap < lcap, the cells between tcap and lcap with the
+// workspace (by gangs of gl.G workgroups when gl.G > 0, else one workgroup
+// each); then, when tcap < lcap, the cells between tcap and lcap with the
 // layout of lcap, and last those that fit tcap (more workgroups per CU).
 hipError_t launch_cell_solve(const Dev& d, int cell_base, int ncells, int lcap, int tcap,
-                             int precision, bool moved, bool balance, int nt, hipStream_t st) {
+                             int precision, bool moved, bool balance, int nt, const GangLaunch& gl,
+                             hipStream_t st) {
   if (ncells <= 0) return hipSuccess;
-  launch_kind<true>(d, cell_base, ncells, cell_lds_bytes(0, lcap, precision, moved, true), precision,
-                    moved, balance, nt, tcap, 3, st);
+  const size_t lds_wide = cell_lds_bytes(0, lcap, precision, moved, true);
+  Dev dw = d;
+  dw.gumax = 0;
+  if (gl.G > 0 && !moved && !balance) {
+    // gangs for the wide cells up to kGangUmax columns, then one workgroup
+    // for each wider one
+    dw.gumax = kGangUmax;
+    const size_t lds_g = gang_lds_bytes(precision, lcap);
+    hipLaunchKernelGGL(k_gang_list, dim3(1), dim3(1024), 0, st, dw, cell_base, ncells, gl.nwg / gl.G,
+                       gl.nwg);
+    if (precision == 64) {
+      if (gl.minb >= 2)
+        hipLaunchKernelGGL((k_cell_gang<double, 2>), dim3(gl.nwg), dim3(256), lds_g, st, dw, gl.G, gl.limit);
+      else
+        hipLaunchKernelGGL((k_cell_gang<double, 1>), dim3(gl.nwg), dim3(256), lds_g, st, dw, gl.G, gl.limit);
+    } else {
+      if (gl.minb >= 2)
+        hipLaunchKernelGGL((k_cell_gang<float, 2>), dim3(gl.nwg), dim3(256), lds_g, st, dw, gl.G, gl.limit);
+      else
+        hipLaunchKernelGGL((k_cell_gang<float, 1>), dim3(gl.nwg), dim3(256), lds_g, st, dw, gl.G, gl.limit);
+    }
+  }
+  launch_kind<true>(dw, cell_base, ncells, lds_wide, precision, moved, balance, nt, tcap, 3, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t big = cell_lds_bytes(lcap, lcap, precision, moved, false);
@@ -1328,10 +1772,17 @@ static hipError_t set_lds_kind(size_t bytes) {
   return e;
 }
 
-hipError_t set_cell_lds_limit(size_t bytes) {
+hipError_t set_cell_lds_limit(size_t bytes, size_t gang_bytes) {
   hipError_t e = set_lds_kind<false>(bytes);
   if (e == hipSuccess) e = set_lds_kind<true>(bytes);
+  const void* gk[4] = {(const void*)k_cell_gang<float, 1>, (const void*)k_cell_gang<float, 2>,
+                       (const void*)k_cell_gang<double, 1>, (const void*)k_cell_gang<double, 2>};
+  for (const void* f : gk)
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gang_bytes);
   return e;
 }
+
+
 
 }  // namespace dduot

@@ -108,6 +108,27 @@ struct Dev {
   int* force_greedy;          // per problem: next GetWeights takes theta = 1
   int hist_cap;
   int lcap;                   // largest box side of the in-LDS cell layouts
+  // gangs (several workgroups per wide cell; cell_kernel.hip)
+  int* glist;                 // the step's wide cells, longest first
+  int* gcount;                // their number, and how many of them are heavy
+  double* gpart;              // per gang: [2][G][256] X pass 2 partials
+  double* gxch;               // per gang: [2][G][16] partial reductions
+  unsigned* gcnt;             // per gang (stride 64): barrier arrivals
+  unsigned* gxcd;             // gang formation: [0, 16) slots taken per XCD, [16] arrivals
+  double* gsolo;              // per workgroup of the gang kernel: its slots when alone
+  int* gabort;                // a gang barrier timed out (sticky until read)
+  int gumax;                  // set per launch: gangs solve the wide cells with at
+                              // most gumax box columns (0: no gangs)
+};
+
+// Launch shape of the gangs that solve the wide cells (G = 0: one
+// workgroup per wide cell): G workgroups per gang, nwg workgroups in all (a
+// multiple of 8 G within the occupancy), the kernel variant, a barrier's
+// wait limit in wall-clock ticks.
+struct GangLaunch {
+  int G, nwg;
+  int minb;          // kernel variant: workgroups per CU its registers allow
+  long long limit;
 };
 
 // Per-cell workspace in global memory (byte offsets from the cell's base):
