@@ -43,8 +43,9 @@ from paper_2410_08859_amd.inputs import (WORKLOADS, batched_problems,  # noqa: E
                                          displaced_points, displacement_theta,
                                          workload_marginals)
 
-# MI355X: 256 CUs x 64 lanes at 2.4 GHz issue 3.93e13 FP32 lane-ops/s; the
-# transcendental unit (v_exp_f32) runs at a quarter of that rate.
+# MI355X: each of 256 CUs issues one wave64 VALU instruction per cycle (4
+# SIMDs, each busy 4 cycles per instruction), 256 x 64 x 2.4e9 = 3.93e13
+# lane-ops/s; the transcendental unit (v_exp_f32) runs at a quarter of that.
 EXP_PEAK = 256 * 64 * 2.4e9 / 4.0
 HBM_PEAK = 8.0e12
 
@@ -462,9 +463,9 @@ def main():
     ap.add_argument("--max-inner", type=int, default=1000)
     ap.add_argument("--err", type=float, default=2e-5, help="cell tolerance Err (Sec. 4.4)")
     ap.add_argument("--getweights", default="line", choices=("swift", "staggered", "line", "opt"))
-    ap.add_argument("--final32", type=int, default=32,
+    ap.add_argument("--final32", type=int, default=64,
                     help="half-iterations of the final stage of the FP32 solve, at most")
-    ap.add_argument("--final64", type=int, default=16,
+    ap.add_argument("--final64", type=int, default=24,
                     help="half-iterations of the final stage of the FP64 solve, at most")
     ap.add_argument("--err-ratio", type=float, default=0.01,
                     help="final stage: cell tolerance min(Err, ratio x certified gap)")
