@@ -77,7 +77,7 @@ def profiled(args):
         return {}
     out = {}
     for name in ("traffic_bytes_per_launch", "valu_issue_frac", "valu_instr_per_term"):
-        m = re.search(name + r": ([0-9.eE+-]+)", txt)
+        m = re.search(r"^" + name + r": ([0-9.eE+-]+)\s*$", txt, re.M)
         if m:
             out[name] = float(m.group(1))
     return out
