@@ -403,6 +403,24 @@ int dd_uot_global_sinkhorn(const dduot_config* cfg, const double* mu, const doub
                            double* alpha, double* beta, int32_t max_iter, double tol,
                            void* hip_stream, int32_t* iters, double* pd);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the global
+   Sinkhorn of dd_uot_global_sinkhorn on caller-owned device buffers, with no
+   hipMalloc, hipFree or other allocating call.  mu, nu (in), alpha (out),
+   beta (in: warm start, out): device memory, n1*n2 doubles each, else
+   DDUOT_EINVAL; the masses finite and > 0, beta finite (checked on the
+   device).  The iteration's scratch (five grids and the partial sums) is a
+   file-scope device array of the library sized for grids of at most
+   256 x 256 = 65 536 points (2.6 MB per GPU, held until the process ends):
+   larger grids give DDUOT_EINVAL.  Every call on one GPU uses that GPU's
+   one array, so calls that overlap on one GPU (other threads, other
+   streams) race; nothing in it needs clearing between calls.  Same
+   iterations, results and gap as dd_uot_global_sinkhorn.  Synchronises
+   hip_stream (once per iteration, reading the gap). */
+int dd_uot_global_sinkhorn_noalloc(const dduot_config* cfg, const double* mu, const double* nu,
+                                   double* alpha, double* beta, int32_t max_iter, double tol,
+                                   void* hip_stream, int32_t* iters, double* pd);
+
 /* New single-problem handle whose state is the plan of the potentials
    (alpha, beta) (cost units), pi = exp((alpha + beta - c)/eps) mu x nu
    (Sec. 4.1), split by basic cells (Sec. 4.4 Sinkhorn warm start):

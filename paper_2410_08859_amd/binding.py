@@ -30,7 +30,7 @@ EXPORTED = (
     "dd_uot_backward_ypos", "dd_uot_set_graph", "dd_uot_autotune",
     "dd_uot_interpolate_potential", "dd_uot_global_sinkhorn", "dd_uot_init_duals",
     "dd_uot_launch_caps", "dd_uot_set_polish", "dd_uot_get_state", "dd_uot_set_state",
-    "dd_uot_set_err", "dd_uot_set_gang",
+    "dd_uot_set_err", "dd_uot_set_gang", "dd_uot_global_sinkhorn_noalloc",
 )
 
 
@@ -126,6 +126,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dd_uot_kernel_time": (C.c_int, [H, P(C.c_int64), dp, dp]),
         "dd_uot_cell_stats": (C.c_int, [H, C.c_int32, C.c_int32, P(C.c_int32), P(C.c_int32), dp]),
         "dd_uot_set_gang": (C.c_int, [H, C.c_int32, C.c_int32, P(C.c_int32)]),
+        "dd_uot_global_sinkhorn_noalloc": (C.c_int, [P(dduot_config), dp, dp, dp, dp, C.c_int32,
+                                                     C.c_double, C.c_void_p, P(C.c_int32), dp]),
         "dd_uot_synchronize": (C.c_int, [H]),
         "dd_uot_num_problems": (C.c_int32, [H]),
         "dd_uot_destroy": (None, [H]),
@@ -372,6 +374,24 @@ def dd_uot_global_sinkhorn(cfg: dduot_config, mu, nu, beta0=None, max_iter=1000,
                                          _dptr(beta), int(max_iter), float(tol), stream,
                                          C.byref(it), C.byref(pd)))
     return dict(alpha=alpha, beta=beta, iters=it.value, pd=pd.value)
+
+
+def dd_uot_global_sinkhorn_noalloc(cfg: dduot_config, mu, nu, alpha, beta, max_iter=1000,
+                                   tol=0.0, stream=None):
+    """The global Sinkhorn on caller-owned device buffers (float64 tensors of
+    n1*n2 entries: mu, nu in; alpha out; beta in and out); no allocation.
+    Returns dict(iters, pd)."""
+    n = cfg.n1 * cfg.n2
+    for t in (mu, nu, alpha, beta):
+        if not _is_tensor(t):
+            raise ValueError("the no-allocation entry point takes device tensors")
+        _tensor_arg(t, n)
+    it = C.c_int32()
+    pd = C.c_double()
+    _check(load().dd_uot_global_sinkhorn_noalloc(C.byref(cfg), _dptr(mu), _dptr(nu), _dptr(alpha),
+                                                 _dptr(beta), int(max_iter), float(tol), stream,
+                                                 C.byref(it), C.byref(pd)))
+    return dict(iters=it.value, pd=pd.value)
 
 
 def dd_uot_init_duals(cfg: dduot_config, mu, nu, alpha, beta, stream=None):

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,6 +28,8 @@ size_t gang_lds_bytes(int precision, int lcap);
 size_t cell_lds_bytes(int lcap, int cap, int precision, bool moved, bool big);
 hipError_t launch_fill(double* p, long n, double v, hipStream_t st);
 hipError_t launch_scale_copy(double* dst, const double* src, long n, double a, hipStream_t st);
+hipError_t launch_check_grids(const double* mu, const double* nu, const double* beta, long n,
+                              double* flag, hipStream_t st);
 hipError_t launch_aggregate(const Dev& d, double* P, int nbasic, long ngrid, hipStream_t st);
 hipError_t launch_kl_chunks(const int* cp, const int* cs, const int* cl, const Prob* probs,
                             const double* P, const double* Pg, const double* nu, double* part,
@@ -1730,12 +1733,12 @@ static int gs_solve(const Prob& p, const double* mu, const double* nu, double* a
                     int* iters, double* pd_out) {
   HIPCHK(set_rows_lds_limit(std::max<size_t>(sizeof(double) * std::max(p.n1, p.n2), 1024)));
   HIPCHK(gs_x_update(p, beta, nu, alpha, scratch, st));
-  std::vector<double> hp(kGsBlocks);
+  double hp[kGsBlocks];
   double pd = INFINITY;
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
     HIPCHK(gs_iteration(p, alpha, mu, nu, beta, scratch, part, kGsBlocks, st));
-    HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * kGsBlocks, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hp, part, sizeof(double) * kGsBlocks, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     pd = 0.0;
     for (double v : hp) pd += v;
@@ -1789,6 +1792,69 @@ extern "C" int dd_uot_global_sinkhorn(const dduot_config* cfg, const double* mu,
   const int r = body();
   for (void* p : mem) (void)hipFree(p);
   return r;
+}
+
+// ---- the global Sinkhorn without allocations ---------------------------------
+// Its device scratch (the five grid buffers of the iteration and the
+// per-block partial sums, for grids of at most kNoAllocPoints points) is a
+// file-scope array: one copy per GPU, held until the process ends.  In host
+// code `scratch` only names the symbol; its device address on the current
+// GPU comes from hipGetSymbolAddress, once per device, and only that address
+// is used.
+static constexpr long kNoAllocPoints = 256L * 256L;
+static constexpr long kNoAllocDoubles = 5 * kNoAllocPoints + kGsBlocks + 64;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+static constexpr int kMaxDevices = 64;
+static double* g_noalloc_ptr[kMaxDevices] = {};
+static std::mutex g_noalloc_mu;
+
+static int noalloc_scratch(double** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(DDUOT_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_noalloc_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_global_sinkhorn_noalloc(const dduot_config* cfg, const double* mu,
+                                              const double* nu, double* alpha, double* beta,
+                                              int32_t max_iter, double tol, void* hip_stream,
+                                              int32_t* iters, double* pd) {
+  if (!cfg || !mu || !nu || !alpha || !beta) return fail(DDUOT_EINVAL, "null argument");
+  if (cfg->n1 <= 0 || cfg->n2 <= 0) return fail(DDUOT_EINVAL, "grid sides must be positive");
+  if (!(cfg->lambda > 0.0) || !isfinite(cfg->lambda) || !(cfg->eps > 0.0) || !isfinite(cfg->eps) ||
+      !(cfg->h >= 0.0) || !isfinite(cfg->h))
+    return fail(DDUOT_EINVAL, "lambda, eps must be > 0 and h >= 0");
+  if (max_iter < 1) return fail(DDUOT_EINVAL, "max_iter must be >= 1");
+  if (!(tol >= 0.0)) return fail(DDUOT_EINVAL, "tol must be >= 0");
+  const long n = (long)cfg->n1 * cfg->n2;
+  if (n > kNoAllocPoints)
+    return fail(DDUOT_EINVAL, "grid larger than the scratch of the no-allocation entry point (" +
+                                  std::to_string(kNoAllocPoints) + " points)");
+  if (!on_device(mu) || !on_device(nu) || !on_device(alpha) || !on_device(beta))
+    return fail(DDUOT_EINVAL, "mu, nu, alpha, beta must be device memory");
+  hipStream_t st = (hipStream_t)hip_stream;
+  double* sc = nullptr;
+  CHK(noalloc_scratch(&sc));
+  double* part = sc + 5 * n;
+  double* flag = part + kGsBlocks;
+  // the masses finite and > 0, beta finite, checked on the device
+  HIPCHK(launch_fill(flag, 1, 0.0, st));
+  HIPCHK(launch_check_grids(mu, nu, beta, n, flag, st));
+  double bad = 0.0;
+  HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bad != 0.0) return fail(DDUOT_EINVAL, "masses must be finite and > 0, beta finite");
+  const Prob p = grid_prob(cfg);
+  CHK(gs_solve(p, mu, nu, alpha, beta, sc, part, max_iter, tol, st, iters, pd));
+  HIPCHK(hipStreamSynchronize(st));
+  return DDUOT_OK;
 }
 
 extern "C" int dd_uot_interpolate_potential(const double* coarse, int32_t n1c, int32_t n2c,

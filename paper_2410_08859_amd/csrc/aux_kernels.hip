@@ -734,6 +734,22 @@ __global__ void k_scale_copy(double* dst, const double* src, long n, double a) {
     dst[i] = a * src[i];
 }
 
+// *flag = 1 if some mass is not finite and > 0 or some beta is not finite
+// (the flag is cleared before; every offender writes the same value).
+__global__ void k_check_grids(const double* mu, const double* nu, const double* beta, long n,
+                              double* flag) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    if (!(mu[i] > 0.0) || !isfinite(mu[i]) || !(nu[i] > 0.0) || !isfinite(nu[i]) || !isfinite(beta[i]))
+      *flag = 1.0;
+}
+
+hipError_t launch_check_grids(const double* mu, const double* nu, const double* beta, long n,
+                              double* flag, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_grids, dim3(grid_blocks(n)), dim3(256), 0, st, mu, nu, beta, n, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_scale_copy(double* dst, const double* src, long n, double a, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scale_copy, dim3(grid_blocks(n)), dim3(256), 0, st, dst, src, n, a);
