@@ -21,10 +21,11 @@
 // cost |x - y|^2/eps = ch |i - j|^2 is separable: each log-sum-exp over the
 // tile (lx1 x lx2) or the box (L1 x L2) is two 1-D passes.  Every pass output
 // is evaluated as
-//     out = s + log sum_k exp(R(base_k - s) - ch (k - c)^2)
+//     out = s + log sum_k exp(R(base_k - s - ch (k - c)^2))
 // with an FP64 shift s equal to the same output's value at the previous
-// Sinkhorn iteration (so the sum is O(1)), the subtraction base_k - s in FP64
-// and exp / accumulation in the kernel precision R.  Terms provably below
+// Sinkhorn iteration (so the sum is O(1)), the exponent in FP64 (base and
+// cost can both be large and cancel) and exp / accumulation in the kernel
+// precision R.  Terms provably below
 // e^-W of the shift are skipped (window from the row maximum).  When the sum
 // leaves [e^-22, e^60] it is redone once with the shift corrected by its log;
 // when it is not representable (first iteration, very large change) the
@@ -167,7 +168,7 @@ __device__ __forceinline__ double newton_v(double a, double v0, double K, R tol,
 // in nfall.
 template <typename R>
 __device__ __forceinline__ double lse_pass(const double* base, int stride, int k0, int k1, double c,
-                                           double ch, float ichf, const R* qc, int qlim,
+                                           double ch, float ichf, const double* qc, int qlim,
                                            bool have_shift, double shift, double bmax,
                                            double& nfall) {
   // Terms more than W below the shift are skipped; an output is accepted when
@@ -191,32 +192,32 @@ __device__ __forceinline__ double lse_pass(const double* base, int stride, int k
         b = min(k1, (int)floorf(cf + rr) + 1);
       }
     }
-    // Terms are evaluated as 2^(sc (base_k - shift) - sc ch d^2) in FP32 (sc =
-    // log2 e, one v_exp_f32 each) and as exp() in FP64, the cost read from
-    // the table qc[d] = -sc ch d^2 (d = k - c is an integer); four terms per
-    // trip with their LDS reads issued together.
-    const R sc = M<R>::kScale;
+    // Terms are exp(base_k - shift - ch d^2) (d = k - c an integer): the
+    // exponent in FP64, since base_k - shift and the cost ch d^2 can both be
+    // large and cancel (a potential that pays for a long transport), then
+    // rounded to R for the exponential and the sum; the cost read from the
+    // FP64 table qc[d] = -ch d^2; four terms per trip with their reads
+    // issued together.
     R acc0 = R(0), acc1 = R(0);
     const int ci = (int)c;
     if (a - ci >= -qlim && b - 1 - ci <= qlim) {
-      const R* q = qc + (a - ci);
+      const double* q = qc + (a - ci);
       const double* p = base + (long)a * stride;
       int k = a;
       for (; k + 4 <= b; k += 4, p += 4 * stride, q += 4) {
         const double v0 = p[0], v1 = p[stride], v2 = p[2 * stride], v3 = p[3 * stride];
-        acc0 += M<R>::ex2s(R(v0 - shift) * sc + q[0]);
-        acc1 += M<R>::ex2s(R(v1 - shift) * sc + q[1]);
-        acc0 += M<R>::ex2s(R(v2 - shift) * sc + q[2]);
-        acc1 += M<R>::ex2s(R(v3 - shift) * sc + q[3]);
+        acc0 += M<R>::ex(R((v0 - shift) + q[0]));
+        acc1 += M<R>::ex(R((v1 - shift) + q[1]));
+        acc0 += M<R>::ex(R((v2 - shift) + q[2]));
+        acc1 += M<R>::ex(R((v3 - shift) + q[3]));
       }
-      for (; k < b; ++k, p += stride, ++q) acc0 += M<R>::ex2s(R(p[0] - shift) * sc + q[0]);
+      for (; k < b; ++k, p += stride, ++q) acc0 += M<R>::ex(R((p[0] - shift) + q[0]));
     } else {
       // offsets beyond the table (a Y-box far from its tile): costs computed
-      const R chs = R(ch) * sc;
-      R dk = R(a - ci);
+      double dk = (double)(a - ci);
       const double* p = base + (long)a * stride;
-      for (int k = a; k < b; ++k, p += stride, dk += R(1))
-        acc0 += M<R>::ex2s(R(p[0] - shift) * sc - chs * dk * dk);
+      for (int k = a; k < b; ++k, p += stride, dk += 1.0)
+        acc0 += M<R>::ex(R((p[0] - shift) - ch * dk * dk));
     }
     const R acc = acc0 + acc1;
     if (acc > R(2.8e-10) && acc < R(1.1e26)) return shift + (double)M<R>::lg(acc);   // e^-22 .. e^60
@@ -252,11 +253,10 @@ __device__ __forceinline__ double lse_pass(const double* base, int stride, int k
 // Otherwise one retry with the corrected shift, then the exact two passes.
 template <typename R>
 __device__ __forceinline__ double lse_full(const double* base, int stride, int k0, int k1, double c,
-                                           double ch, const R* qc, int qlim, bool have_shift,
+                                           double ch, const double* qc, int qlim, bool have_shift,
                                            double shift, double& nfall) {
   constexpr R lo = sizeof(R) == 8 ? R(1e-304) : R(1.8e-35);
   constexpr R hi = sizeof(R) == 8 ? R(1e304) : R(5.5e34);
-  const R sc = M<R>::kScale;
   const int ci = (int)c;
   const bool tab = k0 - ci >= -qlim && k1 - 1 - ci <= qlim;
   for (int attempt = 0; have_shift && attempt < 2; ++attempt) {
@@ -264,20 +264,19 @@ __device__ __forceinline__ double lse_full(const double* base, int stride, int k
     const double* p = base + (long)k0 * stride;
     int k = k0;
     if (tab) {
-      const R* q = qc + (k0 - ci);
+      const double* q = qc + (k0 - ci);
       for (; k + 4 <= k1; k += 4, p += 4 * stride, q += 4) {
         const double v0 = p[0], v1 = p[stride], v2 = p[2 * stride], v3 = p[3 * stride];
-        acc0 += M<R>::ex2s(R(v0 - shift) * sc + q[0]);
-        acc1 += M<R>::ex2s(R(v1 - shift) * sc + q[1]);
-        acc0 += M<R>::ex2s(R(v2 - shift) * sc + q[2]);
-        acc1 += M<R>::ex2s(R(v3 - shift) * sc + q[3]);
+        acc0 += M<R>::ex(R((v0 - shift) + q[0]));
+        acc1 += M<R>::ex(R((v1 - shift) + q[1]));
+        acc0 += M<R>::ex(R((v2 - shift) + q[2]));
+        acc1 += M<R>::ex(R((v3 - shift) + q[3]));
       }
-      for (; k < k1; ++k, p += stride, ++q) acc0 += M<R>::ex2s(R(p[0] - shift) * sc + q[0]);
+      for (; k < k1; ++k, p += stride, ++q) acc0 += M<R>::ex(R((p[0] - shift) + q[0]));
     } else {
-      const R chs = R(ch) * sc;
-      R dk = R(k0 - ci);
-      for (; k < k1; ++k, p += stride, dk += R(1))
-        acc0 += M<R>::ex2s(R(p[0] - shift) * sc - chs * dk * dk);
+      double dk = (double)(k0 - ci);
+      for (; k < k1; ++k, p += stride, dk += 1.0)
+        acc0 += M<R>::ex(R((p[0] - shift) - ch * dk * dk));
     }
     const R acc = acc0 + acc1;
     if (acc > lo && acc < hi) return shift + (double)M<R>::lg(acc);
@@ -316,7 +315,7 @@ struct CellLds {
   R* dl1;        // moved Y: displacement (pixels) on the box      [cmax^2]
   R* dl2;
   double* mx;    // moved Y: partial sums, shifts, flags           [3*256]
-  R* qtab;       // -sc ch d^2 for d = -cmax .. cmax (pass costs) [2*cmax+1]
+  double* qtab;  // -ch d^2 for d = -cmax .. cmax (pass costs)      [2*cmax+1]
 };
 
 // cmax: largest box side of the launch; qmax: the largest box side of the
@@ -343,7 +342,7 @@ __host__ __device__ inline size_t cell_lds_layout(int cmax, int qmax, bool moved
   const size_t o_lnv = sizeof(R) == 4 ? take(4 * n2) : 0;
   const size_t o_d1 = moved ? take(sizeof(R) * n2) : 0, o_d2 = moved ? take(sizeof(R) * n2) : 0;
   const size_t o_mx = moved ? take(8 * 3 * kMaxTile * kMaxTile) : 0;
-  const size_t o_q = take(sizeof(R) * (2 * (size_t)qmax + 1));
+  const size_t o_q = take(8 * (2 * (size_t)qmax + 1));
   if (L) {
     L->bd = (double*)(base + o_bd);
     L->zp = (R*)(base + o_zp);
@@ -359,7 +358,7 @@ __host__ __device__ inline size_t cell_lds_layout(int cmax, int qmax, bool moved
     L->dl1 = moved ? (R*)(base + o_d1) : nullptr;
     L->dl2 = moved ? (R*)(base + o_d2) : nullptr;
     L->mx = moved ? (double*)(base + o_mx) : nullptr;
-    L->qtab = (R*)(base + o_q);
+    L->qtab = (double*)(base + o_q);
   }
   return off;
 }
@@ -727,7 +726,7 @@ __device__ bool gang_sum(Gang& g, double (&v)[N], int lo) {
 // rows' maximum bmax); 0 when there is none.
 template <typename R>
 __device__ __forceinline__ R lse_partial(const double* base, int stride, int k0, int k1, double c,
-                                         double ch, float ichf, const R* qc, int qlim,
+                                         double ch, float ichf, const double* qc, int qlim,
                                          double shift, double bmax) {
   constexpr double W = sizeof(R) == 8 ? 60.0 : 40.0;
   if (!(bmax > -INFINITY) || k1 <= k0) return R(0);
@@ -739,24 +738,22 @@ __device__ __forceinline__ R lse_partial(const double* base, int stride, int k0,
     a = max(k0, (int)ceilf(cf - rr));
     b = min(k1, (int)floorf(cf + rr) + 1);
   }
-  const R sc = M<R>::kScale;
   R acc0 = R(0), acc1 = R(0);
   const int ci = (int)c;
   if (a < b && a - ci >= -qlim && b - 1 - ci <= qlim) {
-    const R* q = qc + (a - ci);
+    const double* q = qc + (a - ci);
     const double* p = base + (long)a * stride;
     int k = a;
     for (; k + 2 <= b; k += 2, p += 2 * stride, q += 2) {
-      acc0 += M<R>::ex2s(R(p[0] - shift) * sc + q[0]);
-      acc1 += M<R>::ex2s(R(p[stride] - shift) * sc + q[1]);
+      acc0 += M<R>::ex(R((p[0] - shift) + q[0]));
+      acc1 += M<R>::ex(R((p[stride] - shift) + q[1]));
     }
-    if (k < b) acc0 += M<R>::ex2s(R(p[0] - shift) * sc + q[0]);
+    if (k < b) acc0 += M<R>::ex(R((p[0] - shift) + q[0]));
   } else {
-    const R chs = R(ch) * sc;
-    R dk = R(a - ci);
+    double dk = (double)(a - ci);
     const double* p = base + (long)a * stride;
-    for (int k = a; k < b; ++k, p += stride, dk += R(1))
-      acc0 += M<R>::ex2s(R(p[0] - shift) * sc - chs * dk * dk);
+    for (int k = a; k < b; ++k, p += stride, dk += 1.0)
+      acc0 += M<R>::ex(R((p[0] - shift) - ch * dk * dk));
   }
   return acc0 + acc1;
 }
@@ -855,11 +852,11 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
 
   const double eps = P.eps, lam = P.lam, kap = P.kappa, K = P.K, ch = P.ch;
   const float ichf = ch > 0.0 ? (float)(1.0 / ch) : 0.0f;   // window: 1/ch (unused for ch = 0)
-  // cost table of the separable passes, centred: qc[d] = -sc ch d^2, |d| <= lcap
-  const R* qc = S.qtab + lcap;
+  // cost table of the separable passes, centred: qc[d] = -ch d^2, |d| <= lcap
+  const double* qc = S.qtab + lcap;
   for (int i = t; i <= 2 * lcap; i += NT) {
     const double dd = (double)(i - lcap);
-    S.qtab[i] = R(-(double)M<R>::kScale * ch * dd * dd);
+    S.qtab[i] = -ch * dd * dd;
   }
   const int D1 = C.x1 - o1, D2 = C.x2 - o2;      // tile origin in box coordinates
   const double* nu = d.nu + P.grid_off;

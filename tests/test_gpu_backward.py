@@ -88,3 +88,64 @@ def test_autograd_wrapper():
     # so both runs do the same arithmetic
     np.testing.assert_allclose(tm.grad.cpu().numpy(), dmu, rtol=1e-12, atol=0)
     np.testing.assert_allclose(tn.grad.cpu().numpy(), dnu, rtol=1e-12, atol=0)
+
+
+# FP32 cells at 64^2: the backward pass of the differentiable form (the
+# certificate pair and its gradients are FP64 arithmetic on the FP32 state).
+# eps = 16 h^2 without truncation: after 1000 half-iterations the stitched
+# certificate's relative gap is below 1e-6 in both precisions, so the pair is
+# near-optimal and the envelope gradient applies.
+M = 64
+
+
+def cfg_m(precision):
+    return B.dd_uot_default_config(n1=M, n2=M, h=1.0 / M, eps=16.0 / M ** 2, lam=1.0, cell=4,
+                                   precision=precision, init=B.INIT_BLOCK, sinkhorn_err=1e-12,
+                                   sinkhorn_max_iter=3000, lenience=0.0, box_cap=48, trunc=0.0)
+
+
+def marginals_m():
+    return (gaussian_mixture(M, M, 3, 1e-3, 1.0, 93), gaussian_mixture(M, M, 3, 1e-3, 1.2, 94))
+
+
+def solve_m(mu, nu, precision, half=1000):
+    h = B.dd_uot_init(cfg_m(precision), mu, nu)
+    try:
+        B.dd_uot_iterate(h, half)
+        s = B.dd_uot_score(h, 0)
+        dmu, dnu = B.dd_uot_backward(h, 0, M, M)
+    finally:
+        B.dd_uot_destroy(h)
+    return s, dmu, dnu
+
+
+def test_fp32_gradient_matches_fp64_at_equal_gap():
+    mu, nu = marginals_m()
+    s32, a32, b32 = solve_m(mu, nu, 32)
+    s64, a64, b64 = solve_m(mu, nu, 64)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    print(f"[backward] gaps FP32 {s32['rel_pd_gap']:.2e} FP64 {s64['rel_pd_gap']:.2e}; "
+          f"dmu {rel(a32, a64):.2e} dnu {rel(b32, b64):.2e}", flush=True)
+    assert s32["rel_pd_gap"] < 1e-6 and s64["rel_pd_gap"] < 1e-6
+    assert s32["dual"] == pytest.approx(s64["dual"], rel=1e-6)
+    assert rel(a32, a64) < 1e-4 and rel(b32, b64) < 1e-4
+
+
+def test_fp32_gradient_matches_central_differences():
+    # step 1e-4 on the masses; the value is the certificate's dual, within
+    # its gap (< 1e-6 relative) of the optimum, so the central difference
+    # carries an error of at most about 1e-6 / 1e-4 of the value
+    mu, nu = marginals_m()
+    s, dmu, dnu = solve_m(mu, nu, 32)
+    rng = np.random.default_rng(55)
+    for _ in range(3):
+        xm = rng.normal(size=mu.shape)
+        xn = rng.normal(size=nu.shape)
+        t = 1e-4
+        wp = solve_m(mu * (1 + t * xm), nu * (1 + t * xn), 32)[0]["dual"]
+        wm = solve_m(mu * (1 - t * xm), nu * (1 - t * xn), 32)[0]["dual"]
+        fd = (wp - wm) / (2 * t)
+        an = (dmu * mu * xm).sum() + (dnu * nu * xn).sum()
+        print(f"[backward] FP32 central difference {fd:.8e} analytic {an:.8e} "
+              f"rel {abs(fd - an) / abs(an):.2e}", flush=True)
+        assert fd == pytest.approx(an, rel=1e-3, abs=1e-2 * abs(s["dual"]))

@@ -204,3 +204,40 @@ def test_two_launch_tiers_keep_the_trajectory(precision, balance):
     finally:
         B.dd_uot_destroy(ha)
         B.dd_uot_destroy(hb)
+
+
+def test_three_problems_of_the_batched_workload_follow_their_oracles():
+    # the bench's batched workload (64 problems, sides 64..512, lambda in
+    # [0.1, 10], eps = h^2, FP32, GetWeights line): one half-iteration of
+    # the whole batch; problems 3, 20 and 25 (64^2, lambda 0.67, 9.3, 0.13)
+    # against the FP64 oracle, within the FP32 bound (1e-5 relative)
+    probs = batched_problems(64)
+    cfgs = [B.dd_uot_default_config(n1=q["n"], n2=q["n"], h=1.0 / q["n"], eps=1.0 / q["n"] ** 2,
+                                    lam=q["lam"], cell=4, precision=32, sinkhorn_max_iter=100,
+                                    box_cap=48, getweights=B.GW_LINE, lenience=0.0) for q in probs]
+    h = B.dd_uot_init_batch(cfgs, [q["mu"] for q in probs], [q["nu"] for q in probs])
+    try:
+        print("[batched] one half-iteration of 64 problems", flush=True)
+        B.dd_uot_iterate(h, 1)
+        for k in (3, 20, 25):
+            q, c = probs[k], cfgs[k]
+            n = q["n"]
+            assert n == 64
+            p = dd.make_problem(q["mu"], q["nu"], c.eps, c.lambda_, c.h, c.cell)
+            st = dd.init_block(p)
+            opt = dd.Options(err=c.sinkhorn_err, max_iter=c.sinkhorn_max_iter, trunc=c.trunc,
+                             lenience=0.0, margin=c.box_margin, getweights="line", translate=True)
+            out = dd.half_iteration(p, st, "A", opt)
+            rec = B.dd_uot_history(h, k)[-1]
+            print(f"[batched] problem {k}: lambda {q['lam']:.3g} theta {rec[0]:.6g} / "
+                  f"{out['theta']:.6g}, inner {rec[4]:.0f} / {out['point_iters']}", flush=True)
+            assert rec[3] == out["n_updated"]
+            assert rec[0] == pytest.approx(out["theta"], rel=1e-5)
+            assert rec[1] == pytest.approx(out["e_cur"], rel=1e-5)
+            assert rec[2] == pytest.approx(out["e_greedy"], rel=1e-5)
+            px, py = B.dd_uot_marginals(h, k, n, n)
+            P = dd.aggregate(p, st.boxes)
+            assert np.abs(px - st.px).sum() <= 1e-5 * np.abs(st.px).sum()
+            assert np.abs(py - P).sum() <= 1e-5 * np.abs(P).sum()
+    finally:
+        B.dd_uot_destroy(h)
