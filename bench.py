@@ -83,28 +83,34 @@ def profiled(args):
     return out
 
 
-def workload_config(name, precision, max_inner, err=2e-5, getweights=B.GW_LINE, cap=48):
+def workload_config(name, precision, max_inner, err=2e-5, getweights=B.GW_LINE, cap=48, lam=None):
     w = WORKLOADS[name]
     n = w["n"]
     return B.dd_uot_default_config(
-        n1=n, n2=n, h=1.0 / n, eps=w["eps_h2"] / n ** 2, lam=w["lam"], cell=w["cell"],
+        n1=n, n2=n, h=1.0 / n, eps=w["eps_h2"] / n ** 2, lam=w["lam"] if lam is None else lam,
+        cell=w["cell"],
         precision=precision, init=B.INIT_BLOCK, getweights=getweights, sinkhorn_err=err,
         sinkhorn_max_iter=max_inner, trunc=1e-15, lenience=0.0, box_margin=2, box_cap=cap)
 
 
-def multiscale_solve(name, precision, final_max, polish, args, stream):
+def multiscale_solve(name, precision, final_max, polish, args, stream, lam=None, coarsest=16,
+                     eps_start_h2=2.0):
     """The whole multiscale solve from the host marginals; returns the finest
     handle and the time to each target of the certified (polished) gap and
-    of the DD-plan gap (tracked score against the certificate's dual)."""
+    of the DD-plan gap (tracked score against the certificate's dual).
+    Layers from coarsest^2 up; every layer's eps starts at eps_start_h2 of
+    its own h^2."""
     mu, nu = workload_marginals(name)
-    cfg = workload_config(name, precision, args.max_inner, args.err, GW_IDS[args.getweights])
-    levels = int(round(np.log2(cfg.n1 / 16))) + 1
+    cfg = workload_config(name, precision, args.max_inner, args.err, GW_IDS[args.getweights],
+                          lam=lam)
+    levels = int(round(np.log2(cfg.n1 / coarsest))) + 1
+    extra = dict(eps_start_h2=float(eps_start_h2))
     ms = B.dd_uot_default_multiscale(levels=levels, final_max_halves=final_max, check_every=4,
                                      target_rel_gap=min(TARGETS), polish_iters=polish,
-                                     final_err_ratio=args.err_ratio, final_err_min=1e-10)
+                                     final_err_ratio=args.err_ratio, final_err_min=1e-10, **extra)
     h, tr = B.dd_uot_solve_multiscale(cfg, ms, mu, nu, stream=stream)
-    progress(f"multiscale {name} FP{precision}: {tr[-1, 1] / 1e3:.1f} s, certified gap "
-             f"{tr[-1, 4]:.3g}, DD-plan gap {tr[-1, 3]:.3g}")
+    progress(f"multiscale {name} FP{precision} lambda {cfg.lambda_:g}: {tr[-1, 1] / 1e3:.1f} s, "
+             f"certified gap {tr[-1, 4]:.3g}, DD-plan gap {tr[-1, 3]:.3g}")
 
     def reached(col):
         out = {}
@@ -113,16 +119,20 @@ def multiscale_solve(name, precision, final_max, polish, args, stream):
             out[f"{t:g}"] = None if hit.size == 0 else {"ms": float(tr[hit[0], 1]),
                                                         "half_iters": int(tr[hit[0], 0])}
         return out
-    rec = {"workload": name, "precision": precision, "getweights": args.getweights,
+    first = eps_start_h2 * (cfg.n1 / coarsest) ** 2
+    sched = (f"{levels} layers from {coarsest}^2 (eps from {first:g} h^2 of the finest grid); "
+             f"global Sinkhorn below 256^2 (tolerance {ms.global_tol:g} |mu|); eps "
+             f"{eps_start_h2:g} h_l^2 -> h_l^2/2 per layer, then down to "
+             f"{cfg.eps * cfg.n1 ** 2:g} h^2 on the finest")
+    rec = {"workload": name, "precision": precision, "lambda": cfg.lambda_,
+           "getweights": args.getweights,
            "certified_gap": reached(4), "dd_plan_gap": reached(3),
            "final": {"certified_gap": float(tr[-1, 4]), "dd_plan_gap": float(tr[-1, 3]),
                      "certificate_gap": float(tr[-1, 2]), "ms": float(tr[-1, 1]),
                      "half_iters": int(tr[-1, 0])},
            "not_reached": f"levels below the final certified gap {tr[-1, 4]:.3g} are not reached "
                           f"within the final stage's {final_max} half-iterations (null)",
-           "schedule": f"{levels} layers from 16^2; global Sinkhorn below 256^2 (tolerance "
-                       f"{ms.global_tol:g} |mu|); eps 2h^2 -> h^2/2 per layer, then eps = h^2 on "
-                       f"the finest; DD 4-16 half-iterations per stage; then at most {final_max} "
+           "schedule": f"{sched}; DD 4-16 half-iterations per stage; then at most {final_max} "
                        f"half-iterations with a certificate every 4 (polished by {polish} global "
                        f"Sinkhorn iterations); GetWeights {args.getweights} (lenience 0), Err "
                        f"{args.err:g} (final stage: min(Err, {args.err_ratio:g} x certified gap)), "
@@ -159,7 +169,7 @@ def box_stats(st):
             "stored_values_per_grid_point": float(st["values"].size / st["px"].size)}
 
 
-def fp32_step_error(h64, name, args, stream):
+def fp32_step_error(h64, name, args, stream, lam=None):
     """The FP32 error of one step: from the FP64 handle's state, one FP64 and
     one FP32 half-iteration; relative L1 differences of P_X, P_Y and the
     relative difference of the tracked score."""
@@ -168,7 +178,7 @@ def fp32_step_error(h64, name, args, stream):
     nb = (n // w["cell"]) ** 2
     mu, nu = workload_marginals(name)
     st = B.dd_uot_get_state(h64, n, n, nb)
-    c32 = workload_config(name, 32, args.max_inner, args.err, GW_IDS[args.getweights])
+    c32 = workload_config(name, 32, args.max_inner, args.err, GW_IDS[args.getweights], lam=lam)
     h32 = B.dd_uot_init(c32, mu, nu, stream=stream)
     try:
         B.dd_uot_set_state(h32, st)
@@ -184,6 +194,35 @@ def fp32_step_error(h64, name, args, stream):
            "tracked_score_rel": abs(s32["tracked"] - s64["tracked"]) / abs(s64["tracked"])}
     progress(f"FP32 step error: P_X {out['px_rel_l1']:.2e}, P_Y {out['py_rel_l1']:.2e}, score "
              f"{out['tracked_score_rel']:.2e}")
+    return out
+
+
+def config2(args, stream):
+    """The 256^2 workload (masses 1.0 / 0.8, cells 4x4, eps = h^2) at lambda
+    in {0.1, 1, 10}: eps from 64 h^2 (the 64^2 layer at 4 of its h^2) down to
+    h^2 through the 64^2, 128^2 and 256^2 layers, FP64 and FP32 solves with
+    the time to each gap, and the FP32 error against FP64: the FP32 step from
+    the FP64 solve's final state, and the two solves' final scores."""
+    out = []
+    for lam in (0.1, 1.0, 10.0):
+        res = {"lambda": lam}
+        h64, res["fp64"] = multiscale_solve("grid256", 64, args.final256, args.polish, args,
+                                            stream, lam=lam, coarsest=64, eps_start_h2=4.0)
+        try:
+            s64 = B.dd_uot_score(h64, 0)
+            h32, res["fp32"] = multiscale_solve("grid256", 32, args.final256, args.polish, args,
+                                                stream, lam=lam, coarsest=64, eps_start_h2=4.0)
+            try:
+                s32 = B.dd_uot_score(h32, 0)
+            finally:
+                B.dd_uot_destroy(h32)
+            res["fp32_vs_fp64"] = {
+                "step": fp32_step_error(h64, "grid256", args, stream, lam=lam),
+                "final_tracked_score_rel": abs(s32["tracked"] - s64["tracked"]) / abs(s64["tracked"]),
+                "final_dual_rel": abs(s32["dual"] - s64["dual"]) / abs(s64["dual"])}
+        finally:
+            B.dd_uot_destroy(h64)
+        out.append(res)
     return out
 
 
@@ -445,6 +484,8 @@ def run(args):
                 out["fp32_step_error"] = fp32_step_error(h2, args.workload, args, stream)
         finally:
             B.dd_uot_destroy(h2)
+    if args.config2:
+        out["eps_scaling_256"] = config2(args, stream)
     if args.forms:
         out["batched_form"] = batched_form(args.steps, args.warmup)
         out["differentiable_form"] = differentiable_form(args.steps)
@@ -467,6 +508,10 @@ def main():
                     help="half-iterations of the final stage of the FP32 solve, at most")
     ap.add_argument("--final64", type=int, default=24,
                     help="half-iterations of the final stage of the FP64 solve, at most")
+    ap.add_argument("--final256", type=int, default=48,
+                    help="half-iterations of the final stage of the 256^2 eps-scaling solves")
+    ap.add_argument("--config2", type=int, default=1,
+                    help="1: also the 256^2 eps-scaling solves at lambda 0.1, 1, 10")
     ap.add_argument("--err-ratio", type=float, default=0.01,
                     help="final stage: cell tolerance min(Err, ratio x certified gap)")
     ap.add_argument("--polish", type=int, default=10,
