@@ -6,7 +6,10 @@ Sinkhorn solves with the Newton Y-update and the PD stopping rule, re-split,
 score pieces, GetWeights, update), alternating A and B.  The metric counts
 grid points times inner Sinkhorn iterations: sum over the cells of
 |X_J| * (Y-halves of that cell), divided by the wall time of the timed steps.
-Every cell is solved in every step (the Y-box pools grow with the boxes).
+Every cell is solved in every step, whatever its Y-box size (variable-size
+pools; boxes wider than the in-LDS layout are solved by gangs of workgroups);
+`inner.overflow_cells` counts any cell that was not, and the headline `value`
+is null if it is not 0.
 
 Default run (the 1024 x 1024 workload, FP32 cells, FP64 reductions):
   1. the multiscale solve (Sec. 4.4: global Sinkhorn below 256^2, then DD
@@ -17,8 +20,12 @@ Default run (the 1024 x 1024 workload, FP32 cells, FP64 reductions):
      from the FP32 solve's final state, with the cell-solve launches timed
      by HIP events for the roofline;
   3. the FP32 error of one step against the FP64 step from the same state;
-  4. the batched and differentiable forms, and the CPU oracle timed on a
-     sample of the same state's cell solves (1 core and all cores).
+  4. the 256^2 workload at lambda 0.1, 1, 10 (eps from 64 h^2 to h^2), FP64
+     and FP32, with the time to each gap and the FP32 error against FP64;
+  5. the batched and differentiable forms (the latter from the grid
+     problem's converged state, gradients at a converged state), and the CPU
+     oracle timed on a sample of the headline state's cell solves (1 core
+     and all cores).
 
 Prints one JSON line on stdout, progress lines on stderr.  `--gpus` above 1
 is refused: the solver runs on a single device.
@@ -343,29 +350,42 @@ def batched_form(steps, warmup):
             "unit": "grid-pts*iters/s", "speedup": (pts / dt) / (ptss / dts)}
 
 
-def differentiable_form(halves):
+def differentiable_form(args, stream, halves):
     """The differentiable workload (512^2, Y points displaced by the seeded
     8x8 cubic B-spline field of amplitude 2h, lambda 1, eps = h^2, cells 4x4):
-    forward half-iterations, then the certificate and the gradients d/dmu,
-    d/dnu (dd_uot_backward) and d/dy' (dd_uot_backward_ypos), in FP32 and
-    FP64; the gradient difference between the two is reported relative to
-    the FP64 gradient."""
+    the FP64 multiscale solve of the grid problem, its state loaded into the
+    displaced problem's handles (same grid indices, boxes and cells) in FP32
+    and FP64, `halves` half-iterations there (the first greedy, since the
+    loaded tracked scores belong to the grid cost), then the certificate
+    (polished; its gap is reported: the gradients are those of that state)
+    and the gradients d/dmu, d/dnu (dd_uot_backward) and d/dy'
+    (dd_uot_backward_ypos); the FP32 gradients are compared with the FP64
+    ones from the same start, relative to the FP64 gradient."""
     import torch
-    w = WORKLOADS["grid512"]
+    name = "grid512"
+    w = WORKLOADS[name]
     n = w["n"]
-    mu, nu = workload_marginals("grid512")
+    nb = (n // w["cell"]) ** 2
+    mu, nu = workload_marginals(name)
     y = displaced_points(n, n, 1.0 / n, displacement_theta(53, 1.0 / n))
-    out, grads = {}, {}
+    t0 = time.perf_counter()
+    h0, ttg = multiscale_solve(name, 64, 32, args.polish, args, stream)
+    try:
+        st = B.dd_uot_get_state(h0, n, n, nb)
+    finally:
+        B.dd_uot_destroy(h0)
+    out = {"grid_solve": {"precision": 64, "ms": 1e3 * (time.perf_counter() - t0),
+                          "certified_gap": ttg["final"]["certified_gap"]}}
+    grads = {}
     for prec in (32, 64):
-        c = B.dd_uot_default_config(n1=n, n2=n, h=1.0 / n, eps=w["eps_h2"] / n ** 2, lam=w["lam"],
-                                    cell=w["cell"], precision=prec, init=B.INIT_BLOCK,
-                                    sinkhorn_max_iter=100, box_cap=32, getweights=B.GW_LINE,
-                                    lenience=0.0)
-        h = B.dd_uot_init_moved(c, mu, nu, y)
+        c = workload_config(name, prec, args.max_inner, args.err, GW_IDS[args.getweights])
+        h = B.dd_uot_init_moved(c, mu, nu, y, stream=stream)
         try:
+            B.dd_uot_set_state(h, st, force_greedy=True)
+            B.dd_uot_set_polish(h, args.polish)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            st = B.dd_uot_iterate(h, halves)
+            it = B.dd_uot_iterate(h, halves)
             torch.cuda.synchronize()
             tf = time.perf_counter() - t0
             t0 = time.perf_counter()
@@ -376,8 +396,9 @@ def differentiable_form(halves):
         finally:
             B.dd_uot_destroy(h)
         grads[prec] = (dmu, dnu, dy)
-        out[f"fp{prec}"] = {"forward_ms": 1e3 * tf, "forward_value": st["point_iters"] / tf,
-                            "backward_ms": 1e3 * tb, "certificate_gap": s["rel_pd_gap"],
+        out[f"fp{prec}"] = {"forward_ms": 1e3 * tf, "forward_value": it["point_iters"] / tf,
+                            "backward_ms": 1e3 * tb, "certified_gap": s["rel_gap_polished"],
+                            "certificate_gap": s["rel_pd_gap"],
                             "dd_plan_gap": (s["tracked"] - s["dual"]) / abs(s["dual"])}
     rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
     out["grad_fp32_vs_fp64"] = {"dmu": rel(grads[32][0], grads[64][0]),
@@ -385,8 +406,13 @@ def differentiable_form(halves):
                                 "dypos": rel(grads[32][2], grads[64][2])}
     out["half_iters"] = halves
     out["unit"] = "grid-pts*iters/s"
-    progress(f"differentiable form: forward FP32 {out['fp32']['forward_ms']:.0f} ms, backward "
-             f"{out['fp32']['backward_ms']:.0f} ms")
+    f32 = out["fp32"]
+    progress(f"differentiable form: grid solve {out['grid_solve']['ms']:.0f} ms, displaced FP32 "
+             f"{f32['forward_ms']:.0f} ms (certified gap {f32['certified_gap']:.2g}; FP64 "
+             f"{out['fp64']['certified_gap']:.2g}), backward "
+             f"{f32['backward_ms']:.0f} ms; FP32 vs FP64 gradients "
+             f"{out['grad_fp32_vs_fp64']['dmu']:.2g} / {out['grad_fp32_vs_fp64']['dnu']:.2g} / "
+             f"{out['grad_fp32_vs_fp64']['dypos']:.2g}")
     return out
 
 
@@ -433,7 +459,7 @@ def run(args):
     prof = profiled(args)
     out = {
         "metric": "grid-pts·iters/s and time to PD-gap 1e-6, 1024² UOT, FP32 vs FP64 on 1 GPU",
-        "value": point_iters / dt,
+        "value": point_iters / dt if hist[:, 7].sum() == 0 else None,
         "unit": "grid-pts·iters/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -488,7 +514,7 @@ def run(args):
         out["eps_scaling_256"] = config2(args, stream)
     if args.forms:
         out["batched_form"] = batched_form(args.steps, args.warmup)
-        out["differentiable_form"] = differentiable_form(args.steps)
+        out["differentiable_form"] = differentiable_form(args, stream, args.moved_halves)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(state, args.workload, args)
     return out
@@ -510,6 +536,8 @@ def main():
                     help="half-iterations of the final stage of the FP64 solve, at most")
     ap.add_argument("--final256", type=int, default=48,
                     help="half-iterations of the final stage of the 256^2 eps-scaling solves")
+    ap.add_argument("--moved-halves", type=int, default=8,
+                    help="half-iterations of the displaced problem from the grid solution")
     ap.add_argument("--config2", type=int, default=1,
                     help="1: also the 256^2 eps-scaling solves at lambda 0.1, 1, 10")
     ap.add_argument("--err-ratio", type=float, default=0.01,
