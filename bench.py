@@ -233,6 +233,51 @@ def config2(args, stream):
     return out
 
 
+def plateau_study(stream, cap=10000):
+    """The global GPU Sinkhorn (no decomposition) on the 256^2 marginals at
+    eps = (8h)^2 from beta = 0, for lambda in {0.01, ..., 1000}: iterations
+    and wall time until KL(P_X pi | e^{-alpha/lam} mu) / |mu| first reaches
+    1e-2 ... 1e-6, and that error at 10, 30, 100, ... iterations (at most `cap`
+    iterations per lambda).  Each call stops at the next target or milestone
+    and the next continues from its beta: the uninterrupted iteration."""
+    mu, nu = workload_marginals("grid256")
+    n = mu.shape[0]
+    mass = float(mu.sum())
+    marks = [m for m in (10, 30, 100, 300, 1000, 3000, 10000) if m <= cap]
+    out = []
+    for lam in (0.01, 0.1, 1.0, 10.0, 100.0, 1000.0):
+        cfg = B.dd_uot_default_config(n1=n, n2=n, h=1.0 / n, eps=64.0 / n ** 2, lam=lam, cell=4,
+                                      precision=64)
+        beta = np.zeros((n, n))
+        done, ms, pd = 0, 0.0, float("inf")
+        first, at = {}, {}
+        targets = [1e-2, 1e-3, 1e-4, 1e-5, 1e-6]
+        while done < cap:
+            nxt = min([m for m in marks if m > done] + [cap])
+            open_t = [t for t in targets if f"{t:g}" not in first]
+            tol = open_t[0] * mass if open_t else 0.0
+            t0 = time.perf_counter()
+            r = B.dd_uot_global_sinkhorn(cfg, mu, nu, beta0=beta, max_iter=nxt - done, tol=tol,
+                                         stream=stream)
+            ms += 1e3 * (time.perf_counter() - t0)
+            done += r["iters"]
+            beta = r["beta"]
+            pd = r["pd"] / mass
+            for t in targets:
+                if f"{t:g}" not in first and pd <= t:
+                    first[f"{t:g}"] = {"iters": done, "ms": ms}
+            if done in marks:
+                at[str(done)] = pd
+            if not open_t and done >= marks[-1]:
+                break
+        for t in targets:
+            first.setdefault(f"{t:g}", None)
+        out.append({"lambda": lam, "first_below": first, "error_at_iters": at, "iters": done,
+                    "ms": ms})
+        progress(f"plateau lambda {lam:g}: {done} iterations, error {pd:.2e}")
+    return {"workload": "grid256", "eps": "(8h)^2", "beta0": 0.0, "runs": out}
+
+
 def _oracle_cells(job):
     """Worker: the oracle's cell solves of `job["cells"]` on the exported
     state (the cells' basic boxes, the aggregated Y-marginal, the stored
@@ -330,6 +375,7 @@ def batched_form(steps, warmup):
     h = B.dd_uot_init_batch(cfgs, [q["mu"] for q in probs], [q["nu"] for q in probs])
     try:
         nt, _ = B.dd_uot_autotune(h)
+        gG, gW, _ = B.dd_uot_autotune_gang(h)
         B.dd_uot_set_graph(h, True)
         dt, pts = timed_iterate(h, steps, warmup)
     finally:
@@ -345,7 +391,8 @@ def batched_form(steps, warmup):
         ptss += p
     progress(f"batched form: {pts / dt:.3g} vs one by one {ptss / dts:.3g} grid-pts*iters/s")
     return {"problems": len(probs), "grid_points": int(sum(q["n"] ** 2 for q in probs)),
-            "steps": steps, "threads_per_cell": nt, "value": pts / dt, "ms_per_step": 1e3 * dt / steps,
+            "steps": steps, "threads_per_cell": nt, "gangs": [gG, gW], "value": pts / dt,
+            "ms_per_step": 1e3 * dt / steps,
             "one_by_one": {"value": ptss / dts, "ms_per_step": 1e3 * dts / steps},
             "unit": "grid-pts*iters/s", "speedup": (pts / dt) / (ptss / dts)}
 
@@ -443,6 +490,11 @@ def run(args):
     h, ttg_main = multiscale_solve(args.workload, args.precision, args.final32, args.polish, args,
                                    stream)
     try:
+        gG, gW, gms = B.dd_uot_autotune_gang(h)
+        gangs = {"G": gG, "wgs_per_cu": gW, "tuned_ms": {
+            k: float(v) for k, v in zip(("one_workgroup", "2x2", "4x1", "4x2", "8x1", "8x2", "16x2"),
+                                        gms)}}
+        progress(f"gang autotune: G {gG}, {gW} workgroups per CU")
         r = timed_steps(h, args.steps, args.warmup)
         progress(f"timed {args.steps} steps: {1e3 * r['dt'] / args.steps:.1f} ms per step")
         B.dd_uot_set_polish(h, args.polish)
@@ -476,7 +528,7 @@ def run(args):
                             f"final certified gap {ttg_main['final']['certified_gap']:.3g})",
                    "getweights": args.getweights, "lenience": 0.0, "cell_err": args.err,
                    "max_inner": args.max_inner, "translate_step": True, "balance": False,
-                   "box_margin": 2},
+                   "box_margin": 2, "wide_cell_gangs": gangs},
         "roofline": {"bound": "alu", "achieved": exp_rate / 1e12, "peak": EXP_PEAK / 1e12,
                      "unit": "Texp/s", "frac": exp_rate / EXP_PEAK,
                      "traffic": prof.get("traffic_bytes_per_launch"), "traffic_unit": "bytes/launch",
@@ -512,6 +564,8 @@ def run(args):
             B.dd_uot_destroy(h2)
     if args.config2:
         out["eps_scaling_256"] = config2(args, stream)
+    if args.plateau:
+        out["plateau"] = plateau_study(stream)
     if args.forms:
         out["batched_form"] = batched_form(args.steps, args.warmup)
         out["differentiable_form"] = differentiable_form(args, stream, args.moved_halves)
@@ -538,6 +592,8 @@ def main():
                     help="half-iterations of the final stage of the 256^2 eps-scaling solves")
     ap.add_argument("--moved-halves", type=int, default=8,
                     help="half-iterations of the displaced problem from the grid solution")
+    ap.add_argument("--plateau", type=int, default=0,
+                    help="1: also the global Sinkhorn plateau study (256^2, 6 lambdas)")
     ap.add_argument("--config2", type=int, default=1,
                     help="1: also the 256^2 eps-scaling solves at lambda 0.1, 1, 10")
     ap.add_argument("--err-ratio", type=float, default=0.01,

@@ -238,6 +238,15 @@ int dd_uot_iterate(dduot_handle* h, int32_t n_half_iters, dduot_iter_stats* stat
    128, 256 threads (-1: not admissible).  Synchronises. */
 int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms);
 
+/* Autotuner of the wide cells' launch (see dd_uot_set_gang): times the cell
+   solves of the next partition on the current state for one workgroup per
+   wide cell and for the gang shapes (G, workgroups per CU) = (2, 2), (4, 1),
+   (4, 2), (8, 1), (8, 2), (16, 2), and keeps the fastest; the state is
+   unchanged.  G and wgs_per_cu (nullable) receive the choice (0, 0: one
+   workgroup per wide cell), ms (nullable, 7 doubles) the times in that
+   order (-1: the shape does not apply).  Synchronises. */
+int dd_uot_autotune_gang(dduot_handle* h, int32_t* G, int32_t* wgs_per_cu, double* ms);
+
 /* Gangs for the wide cells (boxes wider than box_cap and at most 512
    columns, plain separable problems: no moved Y points, no balancing).  The
    wide cells of a step are listed heaviest first (box points times the

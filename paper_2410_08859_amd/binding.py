@@ -30,7 +30,7 @@ EXPORTED = (
     "dd_uot_backward_ypos", "dd_uot_set_graph", "dd_uot_autotune",
     "dd_uot_interpolate_potential", "dd_uot_global_sinkhorn", "dd_uot_init_duals",
     "dd_uot_launch_caps", "dd_uot_set_polish", "dd_uot_get_state", "dd_uot_set_state",
-    "dd_uot_set_err", "dd_uot_set_gang", "dd_uot_global_sinkhorn_noalloc",
+    "dd_uot_set_err", "dd_uot_set_gang", "dd_uot_global_sinkhorn_noalloc", "dd_uot_autotune_gang",
 )
 
 
@@ -126,6 +126,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "dd_uot_kernel_time": (C.c_int, [H, P(C.c_int64), dp, dp]),
         "dd_uot_cell_stats": (C.c_int, [H, C.c_int32, C.c_int32, P(C.c_int32), P(C.c_int32), dp]),
         "dd_uot_set_gang": (C.c_int, [H, C.c_int32, C.c_int32, P(C.c_int32)]),
+        "dd_uot_autotune_gang": (C.c_int, [H, P(C.c_int32), P(C.c_int32), dp]),
         "dd_uot_global_sinkhorn_noalloc": (C.c_int, [P(dduot_config), dp, dp, dp, dp, C.c_int32,
                                                      C.c_double, C.c_void_p, P(C.c_int32), dp]),
         "dd_uot_synchronize": (C.c_int, [H]),
@@ -514,6 +515,16 @@ def dd_uot_set_state(h, state, force_greedy=False):
                                    vals.size, _dptr(px), _dptr(hbar), _dptr(abar),
                                    warm.ctypes.data_as(C.POINTER(C.c_int32)), int(state["k"]),
                                    1 if force_greedy else 0))
+
+
+def dd_uot_autotune_gang(h):
+    """Returns (G, workgroups per CU chosen, [ms of one workgroup per wide cell,
+    then of (2,2), (4,1), (4,2), (8,1), (8,2), (16,2); -1 = does not apply])."""
+    g = C.c_int32()
+    w = C.c_int32()
+    ms = np.zeros(7)
+    _check(load().dd_uot_autotune_gang(h, C.byref(g), C.byref(w), _dptr(ms)))
+    return g.value, w.value, ms
 
 
 def dd_uot_autotune(h):

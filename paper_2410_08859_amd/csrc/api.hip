@@ -1157,16 +1157,19 @@ static int capture_pair(dduot_handle* h) {
 // point count) and keep the fastest.  The timed solves write only candidate
 // buffers and the stitched potentials; the potentials and their flags are
 // restored, so the state is unchanged.
-extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
-  if (!h) return fail(DDUOT_EINVAL, "null handle");
+// Times the cell solves of the next partition on the current state once per
+// candidate launch (threads per cell nts[c], gang shape gls[c]; nts[c] = 0:
+// not admissible, ms[c] = -1) with HIP events, every time from the same
+// stored potentials (their warm start); the state is left as it was.
+// *pick receives the fastest candidate.
+static int time_cell_solves(dduot_handle* h, int n, const int* nts, const GangLaunch* gls,
+                            double* ms, int* pick) {
   hipStream_t st = h->stream;
   const int part = (int)(h->k % 2);
   const int base = h->boff[part][0];
   CHK(check_pools(h, 1));
   HIPCHK(launch_aggregate(h->d, h->d_P, h->nbasic, h->ngrid, st));
   HIPCHK(launch_cell_prep(h->d, base, h->ncell[part], h->precision, st));
-  // every timed solve starts from the same stored potentials (their warm
-  // start), and the state is left as it was
   if (!h->d_abar_keep) CHK(dalloc(h, &h->d_abar_keep, h->ngrid));
   if (!h->d_awarm_keep) CHK(dalloc(h, &h->d_awarm_keep, h->nbasic));
   HIPCHK(hipMemcpyAsync(h->d_abar_keep, h->d_abar, sizeof(double) * h->ngrid, hipMemcpyDeviceToDevice, st));
@@ -1178,16 +1181,14 @@ extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
       e = hipMemcpyAsync(h->d_awarm, h->d_awarm_keep, sizeof(int) * h->nbasic, hipMemcpyDeviceToDevice, st);
     return e;
   };
-  const int cand[3] = {64, 128, 256};
   double best = 1e300;
-  int pick = 256;
+  *pick = -1;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  for (int c = 0; c < 3; ++c) {
-    const int nt = cand[c];
-    if (nt < h->max_tile) {
-      if (ms) ms[c] = -1.0;
+  for (int c = 0; c < n; ++c) {
+    if (nts[c] <= 0) {
+      ms[c] = -1.0;
       continue;
     }
     float t = 0.0f;
@@ -1195,7 +1196,7 @@ extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
     if (e == hipSuccess) e = hipEventRecord(e0, st);
     if (e == hipSuccess)
       e = launch_cell_solve(h->d, base, h->ncell[part], h->cap, h->tcap, h->precision, h->moved,
-                            h->balance, nt, h->gl, st);
+                            h->balance, nts[c], gls[c], st);
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
@@ -1204,22 +1205,78 @@ extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
       (void)hipEventDestroy(e1);
       return fail(DDUOT_EHIP, std::string("autotune: ") + hipGetErrorString(e));
     }
-    if (ms) ms[c] = t;
+    ms[c] = t;
     if (t < best) {
       best = t;
-      pick = nt;
+      *pick = c;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   HIPCHK(restore());
   HIPCHK(hipStreamSynchronize(st));
-  h->nt = pick;
-  if (h->gexec) {   // the captured step used the old size
+  int gab = 0;   // a gang wait that ran past its limit (not expected)
+  HIPCHK(hipMemcpy(&gab, h->d_gabort, sizeof(int), hipMemcpyDeviceToHost));
+  if (gab) {
+    HIPCHK(hipMemset(h->d_gabort, 0, sizeof(int)));
+    return fail(DDUOT_EHIP, "autotune: a gang kernel wait ran past its limit");
+  }
+  if (h->gexec) {   // a captured step keeps the old launch shape
     (void)hipGraphExecDestroy(h->gexec);
     h->gexec = nullptr;
   }
-  if (chosen) *chosen = pick;
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_autotune(dduot_handle* h, int32_t* chosen, double* ms) {
+  if (!h) return fail(DDUOT_EINVAL, "null handle");
+  const int cand[3] = {64, 128, 256};
+  int nts[3];
+  GangLaunch gls[3];
+  for (int c = 0; c < 3; ++c) {
+    nts[c] = cand[c] >= h->max_tile ? cand[c] : 0;
+    gls[c] = h->gl;
+  }
+  double t[3];
+  int pick = -1;
+  CHK(time_cell_solves(h, 3, nts, gls, t, &pick));
+  if (pick >= 0) h->nt = nts[pick];
+  if (ms)
+    for (int c = 0; c < 3; ++c) ms[c] = t[c];
+  if (chosen) *chosen = h->nt;
+  return DDUOT_OK;
+}
+
+extern "C" int dd_uot_autotune_gang(dduot_handle* h, int32_t* G, int32_t* wgs_per_cu, double* ms) {
+  if (!h) return fail(DDUOT_EINVAL, "null handle");
+  const int cg[7] = {0, 2, 4, 4, 8, 8, 16}, cw[7] = {2, 2, 1, 2, 1, 2, 2};
+  const int keep_g = h->gang_g, keep_w = h->gang_wpc;
+  int nts[7];
+  GangLaunch gls[7];
+  for (int c = 0; c < 7; ++c) {
+    h->gang_g = cg[c];
+    h->gang_wpc = cw[c];
+    gang_shape(h);
+    gls[c] = h->gl;
+    // a shape that does not apply (moved Y, balancing, too few workgroups)
+    // falls back to one workgroup per wide cell: timed once, as candidate 0
+    nts[c] = (c == 0 || h->gl.G == cg[c]) ? h->nt : 0;
+  }
+  h->gang_g = keep_g;
+  h->gang_wpc = keep_w;
+  gang_shape(h);
+  double t[7];
+  int pick = -1;
+  CHK(time_cell_solves(h, 7, nts, gls, t, &pick));
+  if (pick >= 0) {
+    h->gang_g = cg[pick];
+    h->gang_wpc = cw[pick];
+    gang_shape(h);
+  }
+  if (ms)
+    for (int c = 0; c < 7; ++c) ms[c] = t[c];
+  if (G) *G = h->gl.G;
+  if (wgs_per_cu) *wgs_per_cu = h->gl.G > 0 ? h->gang_wpc : 0;
   return DDUOT_OK;
 }
 

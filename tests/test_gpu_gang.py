@@ -141,3 +141,34 @@ def test_gang_setter_shapes_and_limits():
         assert B.dd_uot_set_gang(h, 8, 2) == (0, 0)
     finally:
         B.dd_uot_destroy(h)
+
+
+def test_gang_autotuner_keeps_the_trajectory():
+    # the autotuner times the wide cells' launch shapes on the current state,
+    # leaves the state as it was, and the tuned handle follows the untuned one
+    mu, nu = workload_marginals("grid256")
+    n = 256
+    cfg = B.dd_uot_default_config(n1=n, n2=n, h=1.0 / n, eps=1.0 / n ** 2, lam=1.0, cell=4,
+                                  precision=64, init=B.INIT_BLOCK, sinkhorn_err=1e-6,
+                                  sinkhorn_max_iter=300, lenience=0.0, box_cap=16, box_margin=2,
+                                  getweights=B.GW_LINE)
+    ha = B.dd_uot_init(cfg, mu, nu)
+    hb = B.dd_uot_init(cfg, mu, nu)
+    try:
+        B.dd_uot_iterate(ha, 3)
+        B.dd_uot_iterate(hb, 3)
+        g, w, ms = B.dd_uot_autotune_gang(hb)
+        print(f"[gang] autotune: G={g} per CU {w}; ms {np.round(ms, 2).tolist()}", flush=True)
+        assert ms[0] > 0 and (g, w) in [(0, 0), (2, 2), (4, 1), (4, 2), (8, 1), (8, 2), (16, 2)]
+        assert ms[[0, 1, 2, 3, 4, 5, 6].index(
+            [(0, 0), (2, 2), (4, 1), (4, 2), (8, 1), (8, 2), (16, 2)].index((g, w)))] == ms[ms > 0].min()
+        B.dd_uot_iterate(ha, 3)
+        B.dd_uot_iterate(hb, 3)
+        np.testing.assert_array_equal(B.dd_uot_history(hb, 0)[:, 3], B.dd_uot_history(ha, 0)[:, 3])
+        np.testing.assert_allclose(B.dd_uot_history(hb, 0)[:, :3], B.dd_uot_history(ha, 0)[:, :3],
+                                   rtol=1e-10)
+        for a, b in zip(B.dd_uot_marginals(hb, 0, n, n), B.dd_uot_marginals(ha, 0, n, n)):
+            assert max_rel(a, b) <= 1e-10
+    finally:
+        B.dd_uot_destroy(ha)
+        B.dd_uot_destroy(hb)
