@@ -48,6 +48,7 @@ struct M;
 template <>
 struct M<float> {
   static constexpr float kScale = 1.4426950408889634f;   // log2(e): exp(x) = 2^(x log2 e)
+  static constexpr double kScale64 = 1.4426950408889634;  // the same in FP64
   static __device__ __forceinline__ float ex2s(float x) { return __builtin_amdgcn_exp2f(x); }
   static __device__ __forceinline__ float ex(float x) { return __expf(x); }
   // hardware log2 times ln 2: the arguments are normal floats (shifted sums
@@ -67,6 +68,7 @@ struct M<float> {
 template <>
 struct M<double> {
   static constexpr double kScale = 1.0;
+  static constexpr double kScale64 = 1.0;
   static __device__ __forceinline__ double ex2s(double x) { return exp(x); }
   static __device__ __forceinline__ double ex(double x) { return exp(x); }
   static __device__ __forceinline__ double lg(double x) { return log(x); }
@@ -195,9 +197,11 @@ __device__ __forceinline__ double lse_pass(const double* base, int stride, int k
     // Terms are exp(base_k - shift - ch d^2) (d = k - c an integer): the
     // exponent in FP64, since base_k - shift and the cost ch d^2 can both be
     // large and cancel (a potential that pays for a long transport), then
-    // rounded to R for the exponential and the sum; the cost read from the
-    // FP64 table qc[d] = -ch d^2; four terms per trip with their reads
-    // issued together.
+    // rounded to R for the exponential and the sum.  FP32 kernels use the
+    // base-2 exponential: the exponent times log2 e, one FP64 fused
+    // multiply-add with the table qc[d] = -sc ch d^2 (sc = log2 e; 1 in FP64
+    // kernels); four terms per trip with their reads issued together.
+    constexpr double sc = M<R>::kScale64;
     R acc0 = R(0), acc1 = R(0);
     const int ci = (int)c;
     if (a - ci >= -qlim && b - 1 - ci <= qlim) {
@@ -206,18 +210,18 @@ __device__ __forceinline__ double lse_pass(const double* base, int stride, int k
       int k = a;
       for (; k + 4 <= b; k += 4, p += 4 * stride, q += 4) {
         const double v0 = p[0], v1 = p[stride], v2 = p[2 * stride], v3 = p[3 * stride];
-        acc0 += M<R>::ex(R((v0 - shift) + q[0]));
-        acc1 += M<R>::ex(R((v1 - shift) + q[1]));
-        acc0 += M<R>::ex(R((v2 - shift) + q[2]));
-        acc1 += M<R>::ex(R((v3 - shift) + q[3]));
+        acc0 += M<R>::ex2s(R(fma(v0 - shift, sc, q[0])));
+        acc1 += M<R>::ex2s(R(fma(v1 - shift, sc, q[1])));
+        acc0 += M<R>::ex2s(R(fma(v2 - shift, sc, q[2])));
+        acc1 += M<R>::ex2s(R(fma(v3 - shift, sc, q[3])));
       }
-      for (; k < b; ++k, p += stride, ++q) acc0 += M<R>::ex(R((p[0] - shift) + q[0]));
+      for (; k < b; ++k, p += stride, ++q) acc0 += M<R>::ex2s(R(fma(p[0] - shift, sc, q[0])));
     } else {
       // offsets beyond the table (a Y-box far from its tile): costs computed
       double dk = (double)(a - ci);
       const double* p = base + (long)a * stride;
       for (int k = a; k < b; ++k, p += stride, dk += 1.0)
-        acc0 += M<R>::ex(R((p[0] - shift) - ch * dk * dk));
+        acc0 += M<R>::ex2s(R(((p[0] - shift) - ch * dk * dk) * sc));
     }
     const R acc = acc0 + acc1;
     if (acc > R(2.8e-10) && acc < R(1.1e26)) return shift + (double)M<R>::lg(acc);   // e^-22 .. e^60
@@ -257,6 +261,7 @@ __device__ __forceinline__ double lse_full(const double* base, int stride, int k
                                            double shift, double& nfall) {
   constexpr R lo = sizeof(R) == 8 ? R(1e-304) : R(1.8e-35);
   constexpr R hi = sizeof(R) == 8 ? R(1e304) : R(5.5e34);
+  constexpr double sc = M<R>::kScale64;   // exponents and table as in lse_pass
   const int ci = (int)c;
   const bool tab = k0 - ci >= -qlim && k1 - 1 - ci <= qlim;
   for (int attempt = 0; have_shift && attempt < 2; ++attempt) {
@@ -267,16 +272,16 @@ __device__ __forceinline__ double lse_full(const double* base, int stride, int k
       const double* q = qc + (k0 - ci);
       for (; k + 4 <= k1; k += 4, p += 4 * stride, q += 4) {
         const double v0 = p[0], v1 = p[stride], v2 = p[2 * stride], v3 = p[3 * stride];
-        acc0 += M<R>::ex(R((v0 - shift) + q[0]));
-        acc1 += M<R>::ex(R((v1 - shift) + q[1]));
-        acc0 += M<R>::ex(R((v2 - shift) + q[2]));
-        acc1 += M<R>::ex(R((v3 - shift) + q[3]));
+        acc0 += M<R>::ex2s(R(fma(v0 - shift, sc, q[0])));
+        acc1 += M<R>::ex2s(R(fma(v1 - shift, sc, q[1])));
+        acc0 += M<R>::ex2s(R(fma(v2 - shift, sc, q[2])));
+        acc1 += M<R>::ex2s(R(fma(v3 - shift, sc, q[3])));
       }
-      for (; k < k1; ++k, p += stride, ++q) acc0 += M<R>::ex(R((p[0] - shift) + q[0]));
+      for (; k < k1; ++k, p += stride, ++q) acc0 += M<R>::ex2s(R(fma(p[0] - shift, sc, q[0])));
     } else {
       double dk = (double)(k0 - ci);
       for (; k < k1; ++k, p += stride, dk += 1.0)
-        acc0 += M<R>::ex(R((p[0] - shift) - ch * dk * dk));
+        acc0 += M<R>::ex2s(R(((p[0] - shift) - ch * dk * dk) * sc));
     }
     const R acc = acc0 + acc1;
     if (acc > lo && acc < hi) return shift + (double)M<R>::lg(acc);
@@ -315,7 +320,7 @@ struct CellLds {
   R* dl1;        // moved Y: displacement (pixels) on the box      [cmax^2]
   R* dl2;
   double* mx;    // moved Y: partial sums, shifts, flags           [3*256]
-  double* qtab;  // -ch d^2 for d = -cmax .. cmax (pass costs)      [2*cmax+1]
+  double* qtab;  // -sc ch d^2 for d = -cmax .. cmax (pass costs)   [2*cmax+1]
 };
 
 // cmax: largest box side of the launch; qmax: the largest box side of the
@@ -738,6 +743,7 @@ __device__ __forceinline__ R lse_partial(const double* base, int stride, int k0,
     a = max(k0, (int)ceilf(cf - rr));
     b = min(k1, (int)floorf(cf + rr) + 1);
   }
+  constexpr double sc = M<R>::kScale64;   // exponents and table as in lse_pass
   R acc0 = R(0), acc1 = R(0);
   const int ci = (int)c;
   if (a < b && a - ci >= -qlim && b - 1 - ci <= qlim) {
@@ -745,15 +751,15 @@ __device__ __forceinline__ R lse_partial(const double* base, int stride, int k0,
     const double* p = base + (long)a * stride;
     int k = a;
     for (; k + 2 <= b; k += 2, p += 2 * stride, q += 2) {
-      acc0 += M<R>::ex(R((p[0] - shift) + q[0]));
-      acc1 += M<R>::ex(R((p[stride] - shift) + q[1]));
+      acc0 += M<R>::ex2s(R(fma(p[0] - shift, sc, q[0])));
+      acc1 += M<R>::ex2s(R(fma(p[stride] - shift, sc, q[1])));
     }
-    if (k < b) acc0 += M<R>::ex(R((p[0] - shift) + q[0]));
+    if (k < b) acc0 += M<R>::ex2s(R(fma(p[0] - shift, sc, q[0])));
   } else {
     double dk = (double)(a - ci);
     const double* p = base + (long)a * stride;
     for (int k = a; k < b; ++k, p += stride, dk += 1.0)
-      acc0 += M<R>::ex(R((p[0] - shift) - ch * dk * dk));
+      acc0 += M<R>::ex2s(R(((p[0] - shift) - ch * dk * dk) * sc));
   }
   return acc0 + acc1;
 }
@@ -852,11 +858,12 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
 
   const double eps = P.eps, lam = P.lam, kap = P.kappa, K = P.K, ch = P.ch;
   const float ichf = ch > 0.0 ? (float)(1.0 / ch) : 0.0f;   // window: 1/ch (unused for ch = 0)
-  // cost table of the separable passes, centred: qc[d] = -ch d^2, |d| <= lcap
+  // cost table of the separable passes, centred: qc[d] = -sc ch d^2 (sc =
+  // log2 e in FP32 kernels, 1 in FP64 ones), |d| <= lcap
   const double* qc = S.qtab + lcap;
   for (int i = t; i <= 2 * lcap; i += NT) {
     const double dd = (double)(i - lcap);
-    S.qtab[i] = -ch * dd * dd;
+    S.qtab[i] = -M<R>::kScale64 * ch * dd * dd;
   }
   const int D1 = C.x1 - o1, D2 = C.x2 - o2;      // tile origin in box coordinates
   const double* nu = d.nu + P.grid_off;
@@ -944,6 +951,11 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
 
   // ---- X-half: S(i) = LSE_j [b(j) - ch |j - (D + i)|^2], in place over Tt ----
   // Returns S for the thread's point; sprev is that point's previous S.
+  // a gang member's LDS buffer of 16 x L2 doubles (L2 <= kGangUmax): the copy
+  // of the Y pass 1 outputs, and the staged rows of the X pass 1
+  double* Ul = nullptr;
+  if constexpr (kGang)
+    Ul = (double*)(smem_raw + cell_lds_layout<R>(0, lcap, false, true, nullptr, nullptr));
   bool have_x = false;
   double xext = 0.0;   // expected move of the X-half outputs since the last X-half
   bool gfail = false;  // a gang barrier failed (the cell is abandoned)
@@ -1010,15 +1022,34 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
       return sv;
     } else {
       // pass 1 over the rows [r0, r1) (a gang member's rows; all rows otherwise)
-      seg_max<NT, 8>(S.bd + ya, r1 - r0, L2, L2, 1, S.Mr + r0);
-      __syncthreads();
-      for (int o = r0 * lx2 + t; o < r1 * lx2; o += NT) {
-        const int j1 = o / lx2, i2 = o - j1 * lx2;
-        S.Tt[o] = lse_pass<R>(S.bd + j1 * L2, 1, 0, L2, (double)(D2 + i2), ch, ichf, qc, lcap, have_x,
-                              S.Tt[o] + xext,
-                              S.Mr[j1], nfall);
+      if constexpr (kGang) {
+        // 16 rows at a time through LDS (the Y pass 1 copy is not needed
+        // again before the next Y-half): each b value is read from global
+        // memory once, then by every window that covers it from LDS
+        for (int jb = r0; jb < r1; jb += kMaxTile) {
+          const int nr = min(kMaxTile, r1 - jb);
+          for (int q = t; q < nr * L2; q += NT) Ul[q] = S.bd[(long)jb * L2 + q];
+          __syncthreads();
+          seg_max<NT, 8>(Ul, nr, L2, L2, 1, S.Mr + jb);
+          __syncthreads();
+          for (int q = t; q < nr * lx2; q += NT) {
+            const int jl = q / lx2, i2 = q - jl * lx2;
+            const int o = (jb + jl) * lx2 + i2;
+            S.Tt[o] = lse_pass<R>(Ul + jl * L2, 1, 0, L2, (double)(D2 + i2), ch, ichf, qc, lcap,
+                                  have_x, S.Tt[o] + xext, S.Mr[jb + jl], nfall);
+          }
+          __syncthreads();
+        }
+      } else {
+        seg_max<NT, 8>(S.bd + ya, r1 - r0, L2, L2, 1, S.Mr + r0);
+        __syncthreads();
+        for (int o = r0 * lx2 + t; o < r1 * lx2; o += NT) {
+          const int j1 = o / lx2, i2 = o - j1 * lx2;
+          S.Tt[o] = lse_pass<R>(S.bd + j1 * L2, 1, 0, L2, (double)(D2 + i2), ch, ichf, qc, lcap,
+                                have_x, S.Tt[o] + xext, S.Mr[j1], nfall);
+        }
+        __syncthreads();
       }
-      __syncthreads();
       seg_max<NT, 16>(S.Tt + r0 * lx2, lx2, r1 - r0, 1, lx2, S.Mc);
       __syncthreads();
       double sv = 0.0;
@@ -1120,10 +1151,6 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
       __syncthreads();
     }
   };
-  // a gang member's LDS copy of the Y pass 1 outputs (L2 <= kGangUmax)
-  double* Ul = nullptr;
-  if constexpr (kGang)
-    Ul = (double*)(smem_raw + cell_lds_layout<R>(0, lcap, false, true, nullptr, nullptr));
   // Y pass 1 over tile columns [ib, ie): Uo(i1, j2) = LSE_i2 [a - ch (i2 - (j2 - D2))^2]
   // for the box columns [c0, c1) (a gang member's columns; all otherwise);
   // false when a gang barrier failed
