@@ -676,6 +676,30 @@ __device__ __forceinline__ double gang_ld(const double* p) {
   return __longlong_as_double((long long)v);
 }
 
+// dst[q] = src[q] for q < n, from global memory into LDS (kAgent: loads
+// as gang_ld).  Eight loads per thread are issued before the first write,
+// so their latencies overlap instead of adding up.
+template <int NT, bool kAgent>
+__device__ __forceinline__ void load_to_lds(double* dst, const double* src, int n) {
+  auto ld = [&](int i) { return kAgent ? gang_ld(src + i) : src[i]; };
+  int q = threadIdx.x;
+  for (; q + 7 * NT < n; q += 8 * NT) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ld(q + u * NT);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) dst[q + u * NT] = v[u];
+  }
+  if (q < n) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = q + u * NT < n ? ld(q + u * NT) : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (q + u * NT < n) dst[q + u * NT] = v[u];
+  }
+}
+
 // Barrier of the G workgroups of one gang.  The launch keeps every workgroup
 // resident (grid within the occupancy), so every wait ends; the wait is
 // still bounded: past `limit` ticks it flags the launch and returns false,
@@ -1026,17 +1050,20 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
         // 16 rows at a time through LDS (the Y pass 1 copy is not needed
         // again before the next Y-half): each b value is read from global
         // memory once, then by every window that covers it from LDS
+        // (row maxima of the staged rows in Mc, free until pass 2)
         for (int jb = r0; jb < r1; jb += kMaxTile) {
           const int nr = min(kMaxTile, r1 - jb);
-          for (int q = t; q < nr * L2; q += NT) Ul[q] = S.bd[(long)jb * L2 + q];
+          // the thread's first output's previous value, loaded with the rows
+          const double tp = t < nr * lx2 ? S.Tt[jb * lx2 + t] : 0.0;
+          load_to_lds<NT, false>(Ul, S.bd + (long)jb * L2, nr * L2);
           __syncthreads();
-          seg_max<NT, 8>(Ul, nr, L2, L2, 1, S.Mr + jb);
+          seg_max<NT, 8>(Ul, nr, L2, L2, 1, S.Mc);
           __syncthreads();
           for (int q = t; q < nr * lx2; q += NT) {
             const int jl = q / lx2, i2 = q - jl * lx2;
-            const int o = (jb + jl) * lx2 + i2;
+            const int o = jb * lx2 + q;
             S.Tt[o] = lse_pass<R>(Ul + jl * L2, 1, 0, L2, (double)(D2 + i2), ch, ichf, qc, lcap,
-                                  have_x, S.Tt[o] + xext, S.Mr[jb + jl], nfall);
+                                  have_x, (q == t ? tp : S.Tt[o]) + xext, S.Mc[jl], nfall);
           }
           __syncthreads();
         }
@@ -1156,16 +1183,21 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
   // false when a gang barrier failed
   auto y_pass1 = [&](double* Uo, int ib, int ie, bool have, double extra) -> bool {
     const int w = c1 - c0;
+    // each output's previous value (its shift) is loaded one trip ahead
+    auto at = [&](int q) { return (q / w) * L2 + c0 + q % w; };
+    double un = t < lx1 * w ? Uo[at(t)] : 0.0;
     for (int q = t; q < lx1 * w; q += NT) {
       const int i1 = q / w, j2 = c0 + (q - i1 * w);
       const int o = i1 * L2 + j2;
+      const double uo = un;
+      if (q + NT < lx1 * w) un = Uo[at(q + NT)];
       Uo[o] = lse_full<R>(S.adr + i1 * lx2, 1, ib, ie, (double)(j2 - D2), ch, qc, lcap, have,
-                          Uo[o] + extra, nfall);
+                          uo + extra, nfall);
     }
     if constexpr (kGang) {
       // every member reads all columns: a copy in LDS (agent-scope loads)
       if (!gang_sync(*g)) return false;
-      for (int q = t; q < lx1 * L2; q += NT) Ul[q] = gang_ld(Uo + q);
+      load_to_lds<NT, true>(Ul, Uo, lx1 * L2);
       __syncthreads();
       return true;
     } else {
@@ -1176,6 +1208,7 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
 
   for (;;) {
     ++it;
+    double ysh = 0.0;   // translation of b in this iteration (eps units)
     if (P.translate) {
       // exact maximisation of the cell dual along (alpha + s, beta - s):
       // e^{s/lam} = (R + sqrt(R^2 + 4AB)) / (2B), A = sum e^{-alpha/lam} mu,
@@ -1198,8 +1231,10 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
       aeps += sh;
       ushift += sh;
       xext -= sh;   // b = beta/eps + log nu moves by about -s/eps through the Y-half
-      for (int o = ya + t; o < yz; o += NT) S.bd[o] -= sh;
-      __syncthreads();
+      // b itself moves by -s/eps; the Y-update below rewrites b at every
+      // point of the Y-domain, and the translated value enters only its
+      // Newton warm start, which takes ysh instead of a pass over the box
+      ysh = sh;
     }
     // ---- Y-half: z by two passes, Newton per point --------------------------
     y_prepare();
@@ -1227,8 +1262,9 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
         lrr = wlrr[o];
       }
       const double qref = z * iK1;
-      // warm start: the previous beta/eps = bd - log nu, i.e. v0 = bd - lnv + K qref
-      const double v0 = S.bd[o] - lnv + K * qref;
+      // warm start: the previous beta/eps (translated) = bd - ysh - log nu,
+      // i.e. v0 = bd - ysh - lnv + K qref
+      const double v0 = (S.bd[o] - ysh) - lnv + K * qref;
       const double v = newton_v<R>(lrr - qref, v0, K, newton_tol, newton_max);
       S.bd[o] = -K * qref + v + lnv;
     }
