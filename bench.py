@@ -70,17 +70,17 @@ def progress(msg):
 
 
 def profiled(args):
-    """Counter figures that rocprofv3 measured for this bench configuration
-    and this kernel source (HBM traffic per launch scaled by a copy probe,
-    VALU issue fraction, VALU instructions per term), or {} otherwise."""
-    key = f"config: {args.workload} FP{args.precision} final {args.final32} steps {args.steps} " \
-          f"warmup {args.warmup}"
+    """Counter figures that rocprofv3 measured for this workload, precision
+    and final stage and this kernel source (HBM traffic per launch scaled by a
+    copy probe, VALU issue fraction, VALU instructions per term: averages per
+    launch over the profiled run's timed launches), or {} otherwise."""
+    key = f"config: {args.workload} FP{args.precision} final {args.final32}"
     try:
         txt = open(PROFILE).read()
         src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     except OSError:
         return {}
-    if src not in txt or key not in txt:
+    if src not in txt or not re.search(r"^" + re.escape(key) + r"$", txt, re.M):
         return {}
     out = {}
     for name in ("traffic_bytes_per_launch", "valu_issue_frac", "valu_instr_per_term"):
@@ -534,6 +534,7 @@ def run(args):
                      "traffic": prof.get("traffic_bytes_per_launch"), "traffic_unit": "bytes/launch",
                      "valu_issue_frac": prof.get("valu_issue_frac"),
                      "valu_instr_per_term": prof.get("valu_instr_per_term"),
+                     "counters_from": os.path.relpath(PROFILE, ROOT) if prof else None,
                      "kernel": "k_cell_solve (all launch tiers of a step)",
                      "terms_per_launch": terms / launches, "avg_launch_ms": avg_ms,
                      "hbm_algorithmic_GBps": hbm_rate / 1e9, "hbm_frac": hbm_rate / HBM_PEAK},
