@@ -351,6 +351,13 @@ def cpu_baseline(state, name, args):
                       f"iterations; wall time of the process pool including its start"}
 
 
+def gang_times(ms):
+    """The gang autotuner's times (ms, -1: the shape does not apply) by shape
+    (G x workgroups per CU; one workgroup per wide cell first)."""
+    names = ("one_workgroup", "2x2", "4x1", "4x2", "8x1", "8x2", "16x2")
+    return {k: float(v) for k, v in zip(names, ms)}
+
+
 def timed_iterate(h, steps, warmup):
     """(wall seconds, grid-pts*iters) of `steps` half-iterations after `warmup`."""
     import torch
@@ -366,20 +373,42 @@ def batched_form(steps, warmup):
     """The batched workload (64 problems, sides 64..512, lambda log-uniform in
     [0.1, 10], eps = h^2, FP32, cells 4x4): one handle whose launches cover
     every problem's cells, A+B pairs replayed from a hipGraph, threads per
-    cell autotuned; against the same problems stepped one handle at a time
-    (eager, 256 threads per cell)."""
+    cell and the wide cells' launch autotuned; against the same problems
+    stepped one handle at a time (eager, 256 threads per cell), and against
+    the same batch in FP64 (same start and half-iterations): per-problem
+    tracked scores and DD-plan gaps of both precisions."""
     probs = batched_problems(64)
-    cfgs = [B.dd_uot_default_config(n1=q["n"], n2=q["n"], h=1.0 / q["n"], eps=1.0 / q["n"] ** 2,
-                                    lam=q["lam"], cell=4, precision=32, sinkhorn_max_iter=100,
-                                    box_cap=48, getweights=B.GW_LINE, lenience=0.0) for q in probs]
+
+    def configs(precision):
+        return [B.dd_uot_default_config(n1=q["n"], n2=q["n"], h=1.0 / q["n"], eps=1.0 / q["n"] ** 2,
+                                        lam=q["lam"], cell=4, precision=precision,
+                                        sinkhorn_max_iter=100, box_cap=48, getweights=B.GW_LINE,
+                                        lenience=0.0) for q in probs]
+
+    def scores(h):
+        sc = [B.dd_uot_score(h, p) for p in range(len(probs))]
+        tracked = np.array([s["tracked"] for s in sc])
+        dual = np.array([s["dual"] for s in sc])
+        return tracked, (tracked - dual) / np.abs(dual)
+
+    cfgs = configs(32)
     h = B.dd_uot_init_batch(cfgs, [q["mu"] for q in probs], [q["nu"] for q in probs])
     try:
         nt, _ = B.dd_uot_autotune(h)
-        gG, gW, _ = B.dd_uot_autotune_gang(h)
+        gG, gW, gms = B.dd_uot_autotune_gang(h)
         B.dd_uot_set_graph(h, True)
         dt, pts = timed_iterate(h, steps, warmup)
+        tr32, gap32 = scores(h)
     finally:
         B.dd_uot_destroy(h)
+    h = B.dd_uot_init_batch(configs(64), [q["mu"] for q in probs], [q["nu"] for q in probs])
+    try:
+        B.dd_uot_set_graph(h, True)
+        dt64, pts64 = timed_iterate(h, steps, warmup)
+        tr64, gap64 = scores(h)
+    finally:
+        B.dd_uot_destroy(h)
+    dtr = np.abs(tr32 - tr64) / np.abs(tr64)
     dts, ptss = 0.0, 0.0
     for c, q in zip(cfgs, probs):
         hs = B.dd_uot_init(c, q["mu"], q["nu"])
@@ -389,12 +418,20 @@ def batched_form(steps, warmup):
             B.dd_uot_destroy(hs)
         dts += d
         ptss += p
-    progress(f"batched form: {pts / dt:.3g} vs one by one {ptss / dts:.3g} grid-pts*iters/s")
+    progress(f"batched form: {pts / dt:.3g} vs one by one {ptss / dts:.3g} grid-pts*iters/s; "
+             f"FP64 batch {pts64 / dt64:.3g}; FP32 vs FP64 tracked score max {dtr.max():.2e}")
     return {"problems": len(probs), "grid_points": int(sum(q["n"] ** 2 for q in probs)),
-            "steps": steps, "threads_per_cell": nt, "gangs": [gG, gW], "value": pts / dt,
-            "ms_per_step": 1e3 * dt / steps,
+            "steps": steps, "threads_per_cell": nt, "gangs": [gG, gW],
+            "gang_tuned_ms": gang_times(gms),
+            "value": pts / dt, "ms_per_step": 1e3 * dt / steps,
             "one_by_one": {"value": ptss / dts, "ms_per_step": 1e3 * dts / steps},
-            "unit": "grid-pts*iters/s", "speedup": (pts / dt) / (ptss / dts)}
+            "unit": "grid-pts*iters/s", "speedup": (pts / dt) / (ptss / dts),
+            "fp64": {"value": pts64 / dt64, "ms_per_step": 1e3 * dt64 / steps,
+                     "tracked_score_rel_diff": {"max": float(dtr.max()),
+                                                "median": float(np.median(dtr))},
+                     "dd_plan_gap_fp32": {"max": float(gap32.max()), "median": float(np.median(gap32))},
+                     "dd_plan_gap_fp64": {"max": float(gap64.max()), "median": float(np.median(gap64))},
+                     "note": "same start and half-iterations in both precisions"}}
 
 
 def differentiable_form(args, stream, halves):
@@ -491,9 +528,7 @@ def run(args):
                                    stream)
     try:
         gG, gW, gms = B.dd_uot_autotune_gang(h)
-        gangs = {"G": gG, "wgs_per_cu": gW, "tuned_ms": {
-            k: float(v) for k, v in zip(("one_workgroup", "2x2", "4x1", "4x2", "8x1", "8x2", "16x2"),
-                                        gms)}}
+        gangs = {"G": gG, "wgs_per_cu": gW, "tuned_ms": gang_times(gms)}
         progress(f"gang autotune: G {gG}, {gW} workgroups per CU")
         r = timed_steps(h, args.steps, args.warmup)
         progress(f"timed {args.steps} steps: {1e3 * r['dt'] / args.steps:.1f} ms per step")
