@@ -967,6 +967,32 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
     acc0[2] = acc0[4];
     __syncthreads();
   }
+  // The Y-domain's points of the rows [r0, r1), in order, at dom[ya ..
+  // ya + ndom): the domain is fixed for the solve (b = -inf outside it), and
+  // the Y-updates run over this list, so that every lane of a trip has a
+  // point.  Per trip of NT points: wave counts by ballot, offsets from the
+  // counts of the lower waves.
+  int* dom = (int*)(wsc + wl.dom);
+  int ndom = 0;
+  {
+    int* cnt = (int*)red;   // free until the first sum of the loop
+    const int lane = t & 63, wv = t >> 6;
+    for (int ob = ya; ob < yz; ob += NT) {
+      const int o = ob + t;
+      const bool in = o < yz && S.bd[o] > -INFINITY;
+      const unsigned long long m = __ballot(in);
+      if (lane == 0) cnt[wv] = __popcll(m);
+      __syncthreads();
+      int before = ndom, tot = ndom;
+      for (int w = 0; w < NT / 64; ++w) {
+        before += w < wv ? cnt[w] : 0;
+        tot += cnt[w];
+      }
+      if (in) dom[ya + before + __popcll(m & ((1ull << lane) - 1ull))] = o;
+      ndom = tot;
+      __syncthreads();
+    }
+  }
   const double muJ = acc0[0];
   const double Rmass = acc0[1];    // |nu_{-J}| on the domain
   const double B0mass = acc0[2];   // sum of e^{-beta0/lam} nu on the domain
@@ -1240,10 +1266,13 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
     y_prepare();
     if constexpr (!kMoved)
       if (!y_pass1(S.Ud, 0, lx2, have_y, ushift)) return false;
-    for (int o = ya + t; o < yz; o += NT) {
-      // outside the cell's Y-domain (b = -inf for the whole solve): no plan
-      // mass, and its z is never read
-      if (!(S.bd[o] > -INFINITY)) continue;
+    // over the Y-domain's points (outside it b = -inf for the whole solve:
+    // no plan mass, and z is never read); each point's index is loaded a
+    // trip ahead
+    int onext = t < ndom ? dom[ya + t] : 0;
+    for (int i = t; i < ndom; i += NT) {
+      const int o = onext;
+      if (i + NT < ndom) onext = dom[ya + i + NT];
       const int j1 = o / L2, j2 = o - j1 * L2;
       double z;
       if constexpr (kMoved)

@@ -132,11 +132,12 @@ struct GangLaunch {
 };
 
 // Per-cell workspace in global memory (byte offsets from the cell's base):
-// log r on the box (R), log nu (FP64 kernels: FP64); for a box wider than
+// log r on the box (R), log nu (FP64 kernels: FP64), the list of the
+// Y-domain's points (int32, at most the box); for a box wider than
 // the in-LDS layouts also b, z, log nu (FP32 kernels), the pass buffers, the
 // row / column maxima and the displacements.
 struct WsLayout {
-  size_t lrr, lnv, bd, zp, lnvf, Tt, Ud, Mr, MU, d1, d2, total;
+  size_t lrr, lnv, dom, bd, zp, lnvf, Tt, Ud, Mr, MU, d1, d2, total;
 };
 __host__ __device__ inline WsLayout cell_ws_layout(int rbytes, long ny, int cmax, bool moved,
                                                    bool big) {
@@ -150,6 +151,7 @@ __host__ __device__ inline WsLayout cell_ws_layout(int rbytes, long ny, int cmax
   const size_t n = (size_t)ny;
   w.lrr = take((size_t)rbytes * n);
   w.lnv = take(rbytes == 8 ? 8 * n : 0);
+  w.dom = take(4 * n);
   const size_t nb = big ? n : 0, nt = big ? (size_t)cmax * kMaxTile : 0, nc = big ? (size_t)cmax : 0;
   w.bd = take(8 * nb);
   w.zp = take((size_t)rbytes * nb);
