@@ -1274,14 +1274,11 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
       const int o = onext;
       if (i + NT < ndom) onext = dom[ya + i + NT];
       const int j1 = o / L2, j2 = o - j1 * L2;
-      double z;
-      if constexpr (kMoved)
-        z = dense_y_lse<R>(S.adr, S.Ma, lx1, lx2, (double)D1, (double)D2, j1 + (double)S.dl1[o],
-                           j2 + (double)S.dl2[o], ch, have_y, S.zp[o] + ushift, nfall);
-      else
-        z = lse_full<R>((kGang ? Ul : S.Ud) + j2, L2, 0, lx1, (double)(j1 - D1), ch, qc, lcap, have_y,
-                        S.zp[o] + ushift, nfall);
-      S.zp[o] = R(z);
+      // the point's inputs, loaded before the sum so that their latency
+      // (global memory in the wide kernels, and log r in every kernel)
+      // overlaps it
+      const double bo = S.bd[o];
+      const double zo = (double)S.zp[o];
       double lnv, lrr;
       if constexpr (sizeof(R) == 4) {
         lnv = (double)S.lnvf[o];
@@ -1290,10 +1287,18 @@ __device__ __forceinline__ bool cell_body(const Dev& d, int ci, int tcap, int ti
         lnv = wlnv[o];
         lrr = wlrr[o];
       }
+      double z;
+      if constexpr (kMoved)
+        z = dense_y_lse<R>(S.adr, S.Ma, lx1, lx2, (double)D1, (double)D2, j1 + (double)S.dl1[o],
+                           j2 + (double)S.dl2[o], ch, have_y, zo + ushift, nfall);
+      else
+        z = lse_full<R>((kGang ? Ul : S.Ud) + j2, L2, 0, lx1, (double)(j1 - D1), ch, qc, lcap, have_y,
+                        zo + ushift, nfall);
+      S.zp[o] = R(z);
       const double qref = z * iK1;
       // warm start: the previous beta/eps (translated) = bd - ysh - log nu,
       // i.e. v0 = bd - ysh - lnv + K qref
-      const double v0 = (S.bd[o] - ysh) - lnv + K * qref;
+      const double v0 = (bo - ysh) - lnv + K * qref;
       const double v = newton_v<R>(lrr - qref, v0, K, newton_tol, newton_max);
       S.bd[o] = -K * qref + v + lnv;
     }
