@@ -71,7 +71,7 @@ def test_autograd_on_device_tensors_matches_host_tensors():
         w = uot_value(m, v, c, 6)
         (3.0 * w).backward()
         assert m.grad.device.type == device
-        vals.append(float(w))
+        vals.append(float(w.detach()))
         grads.append((m.grad.cpu().numpy(), v.grad.cpu().numpy()))
     assert vals[1] == vals[0]
     for a, b in zip(grads[1], grads[0]):
