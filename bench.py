@@ -74,7 +74,8 @@ def profiled(args):
     and final stage and this kernel source (HBM traffic per launch scaled by a
     copy probe, VALU issue fraction, VALU instructions per term: averages per
     launch over the profiled run's timed launches), or {} otherwise."""
-    key = f"config: {args.workload} FP{args.precision} final {args.final32}"
+    key = f"config: {args.workload} FP{args.precision} final {args.final32} max-inner " \
+          f"{args.max_inner} err-ratio {args.err_ratio:g}"
     try:
         txt = open(PROFILE).read()
         src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
@@ -617,7 +618,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid1024", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
-    ap.add_argument("--max-inner", type=int, default=1000)
+    ap.add_argument("--max-inner", type=int, default=3000,
+                    help="inner iterations per cell solve at most")
     ap.add_argument("--err", type=float, default=2e-5, help="cell tolerance Err (Sec. 4.4)")
     ap.add_argument("--getweights", default="line", choices=("swift", "staggered", "line", "opt"))
     ap.add_argument("--final32", type=int, default=64,
@@ -632,7 +634,7 @@ def main():
                     help="1: also the global Sinkhorn plateau study (256^2, 6 lambdas)")
     ap.add_argument("--config2", type=int, default=1,
                     help="1: also the 256^2 eps-scaling solves at lambda 0.1, 1, 10")
-    ap.add_argument("--err-ratio", type=float, default=0.01,
+    ap.add_argument("--err-ratio", type=float, default=0.001,
                     help="final stage: cell tolerance min(Err, ratio x certified gap)")
     ap.add_argument("--polish", type=int, default=10,
                     help="global Sinkhorn iterations polishing each certificate")
