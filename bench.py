@@ -624,7 +624,7 @@ def main():
     ap.add_argument("--getweights", default="line", choices=("swift", "staggered", "line", "opt"))
     ap.add_argument("--final32", type=int, default=64,
                     help="half-iterations of the final stage of the FP32 solve, at most")
-    ap.add_argument("--final64", type=int, default=64,
+    ap.add_argument("--final64", type=int, default=128,
                     help="half-iterations of the final stage of the FP64 solve, at most")
     ap.add_argument("--final256", type=int, default=48,
                     help="half-iterations of the final stage of the 256^2 eps-scaling solves")
