@@ -626,7 +626,7 @@ def main():
                     help="half-iterations of the final stage of the FP32 solve, at most")
     ap.add_argument("--final64", type=int, default=128,
                     help="half-iterations of the final stage of the FP64 solve, at most")
-    ap.add_argument("--final256", type=int, default=48,
+    ap.add_argument("--final256", type=int, default=96,
                     help="half-iterations of the final stage of the 256^2 eps-scaling solves")
     ap.add_argument("--moved-halves", type=int, default=8,
                     help="half-iterations of the displaced problem from the grid solution")
